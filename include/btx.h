@@ -1,0 +1,129 @@
+/*
+ * btx.h -- C ABI of libbtx: one time step of the locally implicit
+ * Lax-Wendroff discrete-ordinate Boltzmann neutrino transport scheme of
+ * C. Chan and B. Mueller, "A Novel Multi-Dimensional Boltzmann Neutrino
+ * Transport Scheme for Core-Collapse Supernovae" (MNRAS 2020,
+ * arXiv:2003.02845), on an AMD Instinct MI355X (gfx950).
+ *
+ * Scheme (paper Sec. 3): the phase space is a spherical-polar grid in space
+ * (flat-faced cells, Sec. 3.1) times a comoving momentum grid of logarithmic
+ * energy groups, mu cells with Gauss quadrature widths and uniform Phi cells.
+ * One step computes, for every cell face, a Lax-Wendroff interface value with
+ * an implicit interface collision (Eq. halfstep) and a donor-cell upwind flux
+ * (Sec. 3.3.2), blends them with w = exp(-(ka+ks) dx) (Sec. 3.3.3), moves the
+ * resulting number content between cells through the momentum-space remap of
+ * Sec. 3.2 (Lorentz boost, conformally flat frame change, Hamiltonian kick,
+ * geometric rotation), and ends with the zone-local closed-form solve of
+ * absorption, emission and isotropic elastic scattering (Sec. 3.4).
+ *
+ * Conventions
+ *   Units: c = 1; lengths km; time km/c; energies MeV; opacities 1/km.  The
+ *   1/h^3 normalisation of moments is omitted.
+ *   State layout: f[zone][species][group][direction], zone = b*n_r + a
+ *   (theta index b, radius index a), direction = j*n_phi + k (mu index j,
+ *   Phi index k); occupations, FP64 in BTX_PREC_FP64 mode, FP32 in
+ *   BTX_PREC_MIXED mode.
+ *   Ownership: the library owns all device memory it allocates.  Host arrays
+ *   passed in are copied before the call returns.  A device pointer passed
+ *   with is_device_ptr = 1 is borrowed for the duration of the call only.
+ *   Streams: work is enqueued on the hipStream_t given at create time
+ *   (NULL = default stream).  btx_step is asynchronous; btx_get_state,
+ *   btx_moments and the timing query synchronise that stream.
+ *   Errors: every call returns a btx_status; nothing aborts or throws across
+ *   the ABI.  btx_last_error() returns a thread-local message for the last
+ *   failing call on that thread.
+ *   Threads: one context must not be used by two threads at once.
+ */
+#ifndef BTX_H
+#define BTX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BTX_OK = 0,
+  BTX_E_INVAL = 1,        /* invalid argument, size or layout                 */
+  BTX_E_NOMEM = 2,        /* device or host allocation failed                 */
+  BTX_E_DEVICE = 3,       /* HIP runtime error                                */
+  BTX_E_CFL = 4,          /* dt above the Courant limit (btx_max_dt, cfl = 1) */
+  BTX_E_STATE = 5,        /* background or state not set                      */
+  BTX_E_UNSUPPORTED = 6   /* valid input the library does not handle          */
+} btx_status;
+
+typedef enum { BTX_PREC_FP64 = 0, BTX_PREC_MIXED = 1 } btx_precision;
+/* 1D spherically symmetric column (one zone per radius at the equator, theta
+ * and phi periodic); 2D axisymmetric (r, theta) wedge periodic in phi; slab
+ * (planar, no momentum rotation) */
+typedef enum { BTX_GEOM_COLUMN = 0, BTX_GEOM_AXISYM2D = 1, BTX_GEOM_PLANAR = 2 } btx_geometry;
+typedef enum { BTX_MU_GAUSS_LEGENDRE = 0, BTX_MU_GAUSS_LOBATTO = 1 } btx_mu_rule;
+/* Phi split of the remap: keep the direction of the transverse momentum
+ * (weights ~ sin of the angular distances; needs n_phi >= 3) or linear in Phi */
+typedef enum { BTX_PHI_DIRECTION = 0, BTX_PHI_LINEAR = 1 } btx_phi_rule;
+/* radial boundary ghosts: specular mirror (mu -> -mu), outflow (empty, zero
+ * opacity at the face), equilibrium (the zone's own equilibrium occupation) */
+typedef enum { BTX_BC_REFLECT = 0, BTX_BC_OUTFLOW = 1, BTX_BC_EQUIL = 2 } btx_bc;
+
+typedef struct {
+  int32_t n_r, n_theta, n_eps, n_mu, n_phi, n_species;
+  int32_t geometry;          /* btx_geometry                                        */
+  int32_t mu_rule;           /* btx_mu_rule                                         */
+  int32_t phi_rule;          /* btx_phi_rule                                        */
+  int32_t inner_bc, outer_bc;/* btx_bc (outer: OUTFLOW or EQUIL)                     */
+  int32_t precision;         /* btx_precision                                       */
+  const double *r_edges;     /* n_r+1 ascending, >= 0 (z edges in slab geometry)    */
+  const double *theta_edges; /* 2D: n_theta+1 ascending from 0 to pi; else ignored  */
+  double dphi;               /* 2D: wedge width in phi (> 0); else ignored          */
+  const double *eps_edges;   /* n_eps+1 ascending, logarithmically spaced (> 0)     */
+  double fp64_threshold;     /* mixed mode: the collision solve of a (zone, species,
+                                group) runs in FP64 where dt_c (ka + ks) exceeds it;
+                                <= 0 selects the default 1.0                        */
+} btx_grid_desc;
+
+typedef struct {             /* host arrays, copied during the call                  */
+  const double *v_r;         /* [zone] radial fluid velocity (units of c, |v| < 1)   */
+  const double *v_theta;     /* [zone] polar fluid velocity                          */
+  const double *alpha;       /* [zone] lapse (> 0)                                   */
+  const double *psi;         /* [zone] conformal factor (> 0)                        */
+  const double *kappa_a;     /* [zone][species][group] absorption opacity (>= 0)     */
+  const double *kappa_s;     /* [zone][species][group] scattering opacity (>= 0)     */
+  const double *f_eq;        /* [zone][species][group] equilibrium occupation        */
+} btx_background;
+
+typedef struct btx_ctx btx_ctx;
+
+/* Validate the grid, compute geometry and quadrature (paper Sec. 3.1) in FP64
+ * on the host, allocate the device state.  hip_stream: a hipStream_t or NULL. */
+btx_status btx_create(const btx_grid_desc *desc, int hip_device, void *hip_stream,
+                      btx_ctx **out);
+/* Fluid velocity, metric (conformally flat, zero shift, Sec. 2.4) and
+ * opacities (Eq. sourceterms).  Static until the next call. */
+btx_status btx_set_background(btx_ctx *ctx, const btx_background *bg);
+/* Largest stable global step (Sec. 3.3): cfl times the smallest Courant
+ * length (zone volume over its largest face on an axis) of the grid. */
+btx_status btx_max_dt(const btx_ctx *ctx, double cfl, double *dt_out);
+/* State in the H-layout above, FP64 (FP64 mode) or FP32 (mixed mode);
+ * resets the cumulative boundary outflow. */
+btx_status btx_set_state(btx_ctx *ctx, const void *f, int is_device_ptr);
+btx_status btx_get_state(btx_ctx *ctx, void *f, int is_device_ptr);
+/* n_steps steps of size dt (Eq. fullstep + Sec. 3.4); BTX_E_CFL if dt exceeds
+ * btx_max_dt(cfl = 1). */
+btx_status btx_step(btx_ctx *ctx, double dt, int32_t n_steps);
+/* zone_moments[zone][species][5] = N (number), J, H, K, number flux (Sec. 4.1,
+ * 4.2); totals[species][3] = total number, cumulative boundary outflow, total
+ * energy.  Either pointer may be NULL.  Computed on the device in FP64. */
+btx_status btx_moments(btx_ctx *ctx, double *zone_moments, double *totals);
+/* Per-kernel GPU time: enable = 1 records HIP events around every kernel of
+ * btx_step on the context's stream; ms[k] / launches[k] (k = 0 face kernel,
+ * 1 zone-update kernel) receive the accumulated time and count since the last
+ * reset (reset = 1 clears them after reading). */
+btx_status btx_timing(btx_ctx *ctx, int enable, double *ms, int64_t *launches, int reset);
+btx_status btx_destroy(btx_ctx *ctx);
+const char *btx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

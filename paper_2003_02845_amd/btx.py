@@ -1,0 +1,162 @@
+"""Thin ctypes binding of libbtx (include/btx.h).
+
+Argument marshalling only: every step of the transport update runs in the HIP
+kernels of libbtx.so.  torch is imported first so that the library shares
+torch's HIP runtime (streams and device pointers are exchanged with it).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+try:                                   # share torch's HIP runtime when it is present
+    import torch                       # noqa: F401
+except Exception:                      # pragma: no cover - torch is part of the image
+    torch = None
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbtx.so")
+
+BTX_OK, BTX_E_INVAL, BTX_E_NOMEM, BTX_E_DEVICE, BTX_E_CFL, BTX_E_STATE, BTX_E_UNSUPPORTED = range(7)
+PREC_FP64, PREC_MIXED = 0, 1
+MU_LEGENDRE, MU_LOBATTO = 0, 1
+ABI_SYMBOLS = ["btx_create", "btx_set_background", "btx_max_dt", "btx_set_state",
+               "btx_get_state", "btx_step", "btx_moments", "btx_timing", "btx_destroy",
+               "btx_last_error"]
+
+_dp = C.POINTER(C.c_double)
+
+
+class BtxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libbtx status {status}: {msg}")
+        self.status = status
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("n_r", C.c_int32), ("n_theta", C.c_int32), ("n_eps", C.c_int32),
+                ("n_mu", C.c_int32), ("n_phi", C.c_int32), ("n_species", C.c_int32),
+                ("geometry", C.c_int32), ("mu_rule", C.c_int32), ("phi_rule", C.c_int32),
+                ("inner_bc", C.c_int32), ("outer_bc", C.c_int32), ("precision", C.c_int32),
+                ("r_edges", _dp), ("theta_edges", _dp), ("dphi", C.c_double),
+                ("eps_edges", _dp), ("fp64_threshold", C.c_double)]
+
+
+class Background(C.Structure):
+    _fields_ = [(n, _dp) for n in ("v_r", "v_theta", "alpha", "psi", "kappa_a", "kappa_s", "f_eq")]
+
+
+_lib = None
+
+
+def lib():
+    """load libbtx.so; raises if it has not been built (no fallback exists)"""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.btx_create.argtypes = [C.POINTER(GridDesc), C.c_int, vp, C.POINTER(vp)]
+        L.btx_set_background.argtypes = [vp, C.POINTER(Background)]
+        L.btx_max_dt.argtypes = [vp, C.c_double, _dp]
+        L.btx_set_state.argtypes = [vp, vp, C.c_int]
+        L.btx_get_state.argtypes = [vp, vp, C.c_int]
+        L.btx_step.argtypes = [vp, C.c_double, C.c_int32]
+        L.btx_moments.argtypes = [vp, _dp, _dp]
+        L.btx_timing.argtypes = [vp, C.c_int, _dp, C.POINTER(C.c_int64), C.c_int]
+        L.btx_destroy.argtypes = [vp]
+        L.btx_last_error.restype = C.c_char_p
+        for name in ABI_SYMBOLS:
+            if name != "btx_last_error":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != BTX_OK:
+        raise BtxError(status, lib().btx_last_error().decode())
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp)
+
+
+class Context:
+    """one transport grid on one GPU (btx_create ... btx_destroy)"""
+
+    def __init__(self, w, device=0, stream=None, precision=None, fp64_threshold=1.0):
+        self.w = w
+        self.precision = w.precision if precision is None else precision
+        self.dtype = np.float64 if self.precision == PREC_FP64 else np.float32
+        self._keep = [np.ascontiguousarray(w.r_edges, float), np.ascontiguousarray(w.theta_edges, float),
+                      np.ascontiguousarray(w.eps_edges, float)]
+        d = GridDesc(w.n_r, w.n_theta, w.n_eps, w.n_mu, w.n_phi, w.n_species, w.geometry,
+                     MU_LEGENDRE if w.mu_rule == "legendre" else MU_LOBATTO, w.phi_rule,
+                     w.inner_bc, w.outer_bc, self.precision, _p(self._keep[0]), _p(self._keep[1]),
+                     float(w.dphi), _p(self._keep[2]), float(fp64_threshold))
+        h = C.c_void_p()
+        _check(lib().btx_create(C.byref(d), device, C.c_void_p(stream or 0), C.byref(h)))
+        self.h = h
+        self.shape = (w.n_zones, w.n_species, w.n_eps, w.n_dir)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().btx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_background(self, w=None):
+        w = w or self.w
+        arrs = [np.ascontiguousarray(a, float) for a in
+                (w.v_r, w.v_theta, w.alpha, w.psi, w.kappa_a, w.kappa_s, w.f_eq)]
+        bg = Background(*[_p(a) for a in arrs])
+        _check(lib().btx_set_background(self.h, C.byref(bg)))
+
+    def max_dt(self, cfl=None):
+        out = C.c_double()
+        _check(lib().btx_max_dt(self.h, self.w.cfl if cfl is None else cfl, C.byref(out)))
+        return out.value
+
+    def set_state(self, f):
+        """f: numpy array (host) or torch tensor on the GPU, dtype of the precision"""
+        if torch is not None and isinstance(f, torch.Tensor):
+            assert f.is_cuda and f.is_contiguous() and f.numel() == int(np.prod(self.shape))
+            want = torch.float64 if self.dtype == np.float64 else torch.float32
+            assert f.dtype == want
+            _check(lib().btx_set_state(self.h, C.c_void_p(f.data_ptr()), 1))
+        else:
+            a = np.ascontiguousarray(f, dtype=self.dtype).reshape(-1)
+            assert a.size == int(np.prod(self.shape))
+            _check(lib().btx_set_state(self.h, C.c_void_p(a.ctypes.data), 0))
+
+    def get_state(self, out=None):
+        if out is not None:
+            _check(lib().btx_get_state(self.h, C.c_void_p(out.data_ptr()), 1))
+            return out
+        a = np.empty(self.shape, dtype=self.dtype)
+        _check(lib().btx_get_state(self.h, C.c_void_p(a.ctypes.data), 0))
+        return a
+
+    def step(self, dt, n=1):
+        _check(lib().btx_step(self.h, float(dt), int(n)))
+
+    def moments(self):
+        zm = np.zeros((self.w.n_zones, self.w.n_species, 5))
+        tot = np.zeros((self.w.n_species, 3))
+        _check(lib().btx_moments(self.h, _p(zm), _p(tot)))
+        return zm, tot
+
+    def timing(self, enable=True, reset=False):
+        ms = np.zeros(2)
+        n = (C.c_int64 * 2)()
+        _check(lib().btx_timing(self.h, int(enable), _p(ms), n, int(reset)))
+        return ms, np.array([n[0], n[1]])

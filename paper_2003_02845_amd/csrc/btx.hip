@@ -1,0 +1,1172 @@
+// libbtx: HIP (gfx950) implementation of one time step of the locally implicit
+// Lax-Wendroff discrete-ordinate neutrino transport scheme of Chan & Mueller
+// (arXiv:2003.02845), behind the C ABI of include/btx.h.
+//
+// One step = two kernels:
+//   face_kernel   one workgroup per cell face.  Builds the momentum-space remap
+//                 tables of the face in LDS (frame chain of Sec. 3.2 evaluated
+//                 once per direction, then inverted into per-target gather
+//                 lists), then per species: limited slopes of both sides,
+//                 Lax-Wendroff interface value with the implicit interface
+//                 collision (Eq. halfstep), donor-cell upwind content
+//                 (Sec. 3.3.2), smooth flux switching (Sec. 3.3.3) and the
+//                 remapped number-content change of both sides (Eq. fullstep).
+//   zone_kernel   one workgroup per zone: sums the content changes of its
+//                 faces, converts them to occupation and applies the
+//                 zone-local closed-form implicit collision solve (Sec. 3.4).
+// Precision: T = double (FP64 mode) or float (mixed mode: storage, remap and
+// fluxes in FP32; angle sums in FP64; the collision solve of a (zone, species,
+// group) in FP64 where dt_c (ka + ks) exceeds the threshold).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/btx.h"
+#include "btx_grid.h"
+
+using btx::FaceDesc;
+using btx::SideDesc;
+
+namespace {
+
+constexpr int kEC = 8;        // energy groups per gather work item
+constexpr int kTables = 8;    // remap tables per face
+constexpr int kMaxFaceThreads = 512;
+constexpr double kPi = 3.14159265358979323846;
+
+thread_local std::string g_err;
+
+btx_status fail(btx_status s, const std::string &msg)
+{
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(BTX_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+// ------------------------------------------------------------ device data
+
+struct DevGrid {
+  int nr, nth, ne, nmu, nphi, ns, ndir, nz, geom, phi_rule;
+  int eblk, blk, nch, nfaces;
+  double lnq, q, fp64_thr;
+  const double *mu, *Phi, *dOm, *nvec, *G, *eps, *vol;
+  const double *vr, *vth, *alp, *psi;
+};
+
+struct Frame {
+  double v[3];
+  double alpha, psi, th, ph;
+};
+
+__device__ inline double dsq(double x) { return x * x; }
+
+__device__ Frame side_frame(const DevGrid &g, const SideDesc &s)
+{
+  Frame f;
+  int z = s.z;
+  f.v[0] = g.vr[z];
+  f.v[1] = g.vth[z];
+  f.v[2] = 0.0;
+  if (s.kind == btx::SIDE_MIRROR) f.v[0] = -f.v[0];
+  f.alpha = g.alp[z];
+  f.psi = g.psi[z];
+  f.th = s.th;
+  f.ph = s.ph;
+  return f;
+}
+
+__device__ inline bool same_frame(const Frame &a, const Frame &b)
+{
+  return a.v[0] == b.v[0] && a.v[1] == b.v[1] && a.v[2] == b.v[2] && a.alpha == b.alpha &&
+         a.psi == b.psi && a.th == b.th && a.ph == b.ph;
+}
+
+// orthonormal basis (e_r, e_theta, e_phi) as columns
+__device__ void basis_cols(double th, double ph, double B[3][3])
+{
+  double st, ct, sp, cp;
+  sincos(th, &st, &ct);
+  sincos(ph, &sp, &cp);
+  B[0][0] = st * cp; B[1][0] = st * sp; B[2][0] = ct;
+  B[0][1] = ct * cp; B[1][1] = ct * sp; B[2][1] = -st;
+  B[0][2] = -sp;     B[1][2] = cp;      B[2][2] = 0.0;
+}
+
+// x given in the basis at (ta, pa) -> components in the basis at (tb, pb)
+__device__ void change_basis(double ta, double pa, double tb, double pb, const double x[3], double y[3])
+{
+  if (ta == tb && pa == pb) { y[0] = x[0]; y[1] = x[1]; y[2] = x[2]; return; }
+  double A[3][3], B[3][3], c[3];
+  basis_cols(ta, pa, A);
+  basis_cols(tb, pb, B);
+  for (int r = 0; r < 3; ++r) c[r] = A[r][0] * x[0] + A[r][1] * x[1] + A[r][2] * x[2];
+  for (int r = 0; r < 3; ++r) y[r] = B[0][r] * c[0] + B[1][r] * c[1] + B[2][r] * c[2];
+}
+
+// Lorentz boost by fluid velocity v (paper Sec. 3.2.2)
+__device__ void lorentz(const double v[3], const double u[4], double o[4])
+{
+  double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  double gam = 1.0 / sqrt(1.0 - v2);
+  double kv = gam * gam / (gam + 1.0);
+  double vu = v[0] * u[1] + v[1] * u[2] + v[2] * u[3];
+  double a = kv * vu + gam * u[0];
+  o[0] = gam * (u[0] + vu);
+  o[1] = u[1] + a * v[0];
+  o[2] = u[2] + a * v[1];
+  o[3] = u[3] + a * v[2];
+}
+
+// comoving(S) -> comoving(D) through Eulerian and coordinate frames, the
+// Hamiltonian kick on the axis of motion and the geometric rotation
+// (Eq. transformchain, Sec. 3.2.1-3.2.4; conformally flat, zero shift)
+__device__ void frame_chain(const Frame &S, const Frame &D, int axis, bool rot, const double u[4], double o[4])
+{
+  double e[4];
+  lorentz(S.v, u, e);
+  double u0 = -S.alpha * e[0];                       // covariant time component
+  double p2 = S.psi * S.psi;
+  double uc[3] = { p2 * e[1], p2 * e[2], p2 * e[3] };  // covariant spatial components
+  if (S.alpha != D.alpha || S.psi != D.psi) {
+    double tr = 0.0;
+    for (int i = 0; i < 3; ++i) if (i != axis) tr += uc[i] * uc[i];
+    double dp2 = D.psi * D.psi;
+    double rad = dp2 * dp2 * u0 * u0 / (D.alpha * D.alpha) - tr;
+    if (rad >= 0.0) {
+      uc[axis] = copysign(sqrt(rad), uc[axis] >= 0.0 ? 1.0 : -1.0);
+    } else {                                          // no real root: reflect along the axis
+      double sc = dp2 * fabs(u0) / D.alpha / sqrt(tr);
+      uc[axis] = 0.0;
+      for (int i = 0; i < 3; ++i) if (i != axis) uc[i] *= sc;
+    }
+  }
+  double ud[3];
+  if (rot) change_basis(S.th, S.ph, D.th, D.ph, uc, ud);
+  else { ud[0] = uc[0]; ud[1] = uc[1]; ud[2] = uc[2]; }
+  double dp2 = D.psi * D.psi;
+  double eD[4] = { -u0 / D.alpha, ud[0] / dp2, ud[1] / dp2, ud[2] / dp2 };
+  double mv[3] = { -D.v[0], -D.v[1], -D.v[2] };
+  lorentz(mv, eD, o);
+}
+
+__device__ inline double u0_dir(const Frame &f, const double *n)
+{
+  double v2 = f.v[0] * f.v[0] + f.v[1] * f.v[1] + f.v[2] * f.v[2];
+  double gam = 1.0 / sqrt(1.0 - v2);
+  return gam * (1.0 + f.v[0] * n[0] + f.v[1] * n[1] + f.v[2] * n[2]);
+}
+
+// ------------------------------------------------------------ LDS tables
+
+// Gather form of one remap T_{S->D}: for every source direction the energy
+// shift (di, tl, tr) and content weight aS; for every target direction the
+// inverse content weight and the list of (source, mu*Phi weight) entries.
+template <typename T>
+struct Tab {
+  int *di;
+  T *tl, *tr, *aS, *iaD;
+  int *start;        // ndir + 1
+  int *src;          // 4 * ndir
+  T *c;              // 4 * ndir
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+template <typename T>
+__device__ Tab<T> tab_at(char *base, int nd)
+{
+  Tab<T> t;
+  size_t off = 0;
+  t.tl = (T *)(base + off); off += nd * sizeof(T);
+  t.tr = (T *)(base + off); off += nd * sizeof(T);
+  t.aS = (T *)(base + off); off += nd * sizeof(T);
+  t.iaD = (T *)(base + off); off += nd * sizeof(T);
+  t.c = (T *)(base + off); off += 4 * nd * sizeof(T);
+  t.di = (int *)(base + off); off += nd * sizeof(int);
+  t.start = (int *)(base + off); off += (nd + 1) * sizeof(int);
+  t.src = (int *)(base + off); off += 4 * nd * sizeof(int);
+  return t;
+}
+
+__host__ __device__ inline size_t tab_stride(int nd, size_t szT)
+{
+  return align16(8 * (size_t)nd * szT + (size_t)nd * 4 + (size_t)(nd + 1) * 4 + 4 * (size_t)nd * 4);
+}
+
+// bytes of the table-build scratch (counts, cursors, record targets, weights)
+__host__ __device__ inline size_t scratch_bytes(int nd)
+{
+  return align16((size_t)kTables * nd * 4 * 6) + (size_t)kTables * nd * 4 * 8;
+}
+
+__host__ __device__ inline size_t data_bytes(int nd, int ne, size_t szT)
+{
+  size_t b = 4 * align16((size_t)nd * ne * szT), sc = scratch_bytes(nd);
+  return b > sc ? b : sc;
+}
+
+// ascending node bracket with edge clamping (all weight to the edge node)
+__device__ inline void node_bracket(const double *x, int n, double v, int &L, int &R, double &wR)
+{
+  if (n == 1 || v <= x[0]) { L = R = 0; wR = 0.0; return; }
+  if (v >= x[n - 1]) { L = R = n - 1; wR = 0.0; return; }
+  int l = 0;
+  while (x[l + 1] <= v) ++l;
+  L = l;
+  R = l + 1;
+  wR = (v - x[l]) / (x[l + 1] - x[l]);
+}
+
+// One source direction of one table: chain, brackets, records.
+// Writes the source info into the table and up to 4 (target, weight) records.
+template <typename T>
+__device__ int build_source(const DevGrid &g, const Frame &S, const Frame &D, int axis, bool rot,
+                            bool ident, int d, Tab<T> &tb, int *rt, double *rc)
+{
+  const double *n = g.nvec + 3 * d;
+  double aS = pow(S.psi, 6.0) * u0_dir(S, n) * g.dOm[d];
+  double aD = pow(D.psi, 6.0) * u0_dir(D, n) * g.dOm[d];
+  tb.aS[d] = (T)aS;
+  tb.iaD[d] = (T)(1.0 / aD);
+  if (ident) {
+    tb.di[d] = 0;
+    tb.tl[d] = (T)1.0;
+    tb.tr[d] = (T)0.0;
+    rt[0] = d; rc[0] = 1.0;
+    rt[1] = rt[2] = rt[3] = -1;
+    rc[1] = rc[2] = rc[3] = 0.0;
+    return 4;
+  }
+  double u[4] = { 1.0, n[0], n[1], n[2] }, o[4];
+  frame_chain(S, D, axis, rot, u, o);
+  // energy: eps* = rho eps_i with rho = o[0]; log groups -> one shift for all i
+  double rho = o[0];
+  double x = log(rho) / g.lnq;
+  int di = (int)floor(x);
+  double we = (rho * exp(-di * g.lnq) - 1.0) / (g.q - 1.0);
+  if (we < 0.0) we = 0.0;
+  if (we > 1.0) we = 1.0;
+  tb.di[d] = di;
+  tb.tl[d] = (T)(1.0 - we);
+  tb.tr[d] = (T)we;
+  // direction
+  double mus = o[1] / o[0];
+  mus = fmin(1.0, fmax(-1.0, mus));
+  int jL, jR;
+  double wj;
+  node_bracket(g.mu, g.nmu, mus, jL, jR, wj);
+  int k0 = d % g.nphi;
+  double P;
+  if (o[2] * o[2] + o[3] * o[3] <= 1e-12 * o[0] * o[0]) {
+    P = g.Phi[k0];                                  // on the mu = +-1 axis: keep the Phi label
+  } else {
+    P = atan2(o[3], o[2]);
+    if (P < 0.0) P += 2.0 * kPi;
+  }
+  int kL, kR;
+  double wk;
+  if (g.nphi == 1) { kL = kR = 0; wk = 0.0; }
+  else {
+    double dP = 2.0 * kPi / g.nphi;
+    int kl = (int)floor(P / dP - 0.5);
+    double PL = (kl + 0.5) * dP, PR = PL + dP;
+    if (g.phi_rule == 0) {
+      double a = sin(PR - P), b = sin(P - PL);
+      wk = b / (a + b);
+    } else {
+      wk = (P - PL) / dP;
+    }
+    kL = ((kl % g.nphi) + g.nphi) % g.nphi;
+    kR = (((kl + 1) % g.nphi) + g.nphi) % g.nphi;
+  }
+  // the four (mu, Phi) corners; coinciding brackets (clamped or one Phi bin)
+  // are merged so that every record has a distinct target
+  const bool oneJ = jL == jR, oneK = kL == kR;
+  const double wj0 = oneJ ? 1.0 : 1.0 - wj, wj1 = oneJ ? 0.0 : wj;
+  const double wk0 = oneK ? 1.0 : 1.0 - wk, wk1 = oneK ? 0.0 : wk;
+  double c00 = wj0 * wk0, c01 = wj0 * wk1, c10 = wj1 * wk0, c11 = wj1 * wk1;
+  rt[0] = c00 != 0.0 ? jL * g.nphi + kL : -1; rc[0] = c00;
+  rt[1] = c01 != 0.0 ? jL * g.nphi + kR : -1; rc[1] = c01;
+  rt[2] = c10 != 0.0 ? jR * g.nphi + kL : -1; rc[2] = c10;
+  rt[3] = c11 != 0.0 ? jR * g.nphi + kR : -1; rc[3] = c11;
+  return 4;
+}
+
+// Gather of one remap for target direction dp and groups i0..i0+kEC-1.
+// Density tables: X holds occupation x G_i and the result is an occupation;
+// content tables: X holds content and the result is content.
+template <typename T>
+__device__ void gather(const DevGrid &g, const Tab<T> &tb, const T *X, bool dens, int dp, int i0,
+                       const double *Gs, T out[kEC])
+{
+  const int ne = g.ne, nd = g.ndir;
+  T acc[kEC];
+#pragma unroll
+  for (int k = 0; k < kEC; ++k) acc[k] = (T)0;
+  const int e0 = tb.start[dp], e1 = tb.start[dp + 1];
+  const bool low = (i0 == 0), top = (ne - 1 < i0 + kEC);
+  const int kt = ne - 1 - i0;
+  for (int e = e0; e < e1; ++e) {
+    const int d = tb.src[e];
+    T c = tb.c[e];
+    if (dens) c *= tb.aS[d];
+    const int di = tb.di[d];
+    const T tl = tb.tl[d] * c, tr = tb.tr[d] * c;
+    const T *col = X + d;
+#pragma unroll
+    for (int k = 0; k < kEC; ++k) {
+      int i = i0 + k;
+      if (i >= ne) break;
+      int iL = i - di, iR = iL - 1;
+      T v = (T)0;
+      if (iL >= 0 && iL < ne) v += tl * col[iL * nd];
+      if (iR >= 0 && iR < ne) v += tr * col[iR * nd];
+      acc[k] += v;
+    }
+    if (low) {                                       // sources pushed below the lowest group
+      for (int i = 0; i < ne && i + di < 0; ++i) acc[0] += tl * col[i * nd];
+      for (int i = 0; i < ne && i + di + 1 < 0; ++i) acc[0] += tr * col[i * nd];
+    }
+    if (top) {                                       // sources pushed above the highest group
+      T v = (T)0;
+      for (int i = max(0, ne - di); i < ne; ++i) v += tl * col[i * nd];
+      for (int i = max(0, ne - 1 - di); i < ne; ++i) v += tr * col[i * nd];
+#pragma unroll
+      for (int k = 0; k < kEC; ++k)
+        if (k == kt) acc[k] += v;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kEC; ++k) {
+    int i = i0 + k;
+    if (dens && i < ne) out[k] = (T)((double)acc[k] * (double)tb.iaD[dp] / Gs[i]);
+    else out[k] = acc[k];
+  }
+}
+
+template <typename T>
+__device__ inline T mc_limiter(T dm, T dp)
+{
+  T a = (T)2 * dm, b = (T)2 * dp, m = (T)0.5 * (dm + dp);
+  if (a > (T)0 && b > (T)0 && m > (T)0) return fmin(a, fmin(b, m));
+  if (a < (T)0 && b < (T)0 && m < (T)0) return fmax(a, fmax(b, m));
+  return (T)0;
+}
+
+// one side's data of species s, scaled by the shell volume G_i, into LDS
+template <typename T>
+__device__ void load_side(const DevGrid &g, const SideDesc &sd, const T *f, const T *feq, int s,
+                          const double *Gs, T *dst)
+{
+  const int nd = g.ndir, n = g.eblk;
+  const T *src = f + (size_t)sd.z * g.blk + (size_t)s * n;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    int i = q / nd, d = q - i * nd;
+    T v;
+    if (sd.kind == btx::SIDE_ZONE) v = src[q];
+    else if (sd.kind == btx::SIDE_MIRROR) {
+      int j = d / g.nphi, k = d - j * g.nphi;
+      v = src[i * nd + (g.nmu - 1 - j) * g.nphi + k];
+    } else if (sd.kind == btx::SIDE_EQ) v = feq[((size_t)sd.z * g.ns + s) * g.ne + i];
+    else v = (T)0;
+    dst[q] = (T)((double)v * Gs[i]);
+  }
+}
+
+__device__ inline double wave_sum(double v)
+{
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------ face kernel
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxFaceThreads)
+face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const T *__restrict__ f,
+            const T *__restrict__ ka, const T *__restrict__ ks, const T *__restrict__ feq,
+            T *__restrict__ dN, double *__restrict__ tally, double dt, int face0)
+{
+  extern __shared__ __align__(16) char lds[];
+  const int fid = face0 + blockIdx.x;
+  const FaceDesc &F = faces[fid];
+  const int nd = g.ndir, ne = g.ne, n = g.eblk, tid = threadIdx.x;
+  T *outL = dN + (size_t)fid * 2 * g.blk, *outR = outL + g.blk;
+  if (!F.active) {
+    for (int q = tid; q < 2 * g.blk; q += blockDim.x) outL[q] = (T)0;
+    return;
+  }
+  // ---- LDS carve-up
+  const size_t tstride = tab_stride(nd, sizeof(T));
+  char *p = lds;
+  char *tabs = p;            p += kTables * tstride;
+  T *buf[4];
+  char *data = p;
+  for (int b = 0; b < 4; ++b) buf[b] = (T *)(data + b * align16((size_t)n * sizeof(T)));
+  p += data_bytes(nd, ne, sizeof(T));
+  double *Gs = (double *)p;  p += align16(ne * sizeof(double));
+  double *Urad = (double *)p; p += align16(nd * sizeof(double));
+  double *Vn = (double *)p;  p += align16(nd * sizeof(double));
+  double *UL = (double *)p;  p += align16(nd * sizeof(double));
+  double *UR = (double *)p;  p += align16(nd * sizeof(double));
+  double *sav = (double *)p; p += align16(ne * sizeof(double));
+  double *red = (double *)p; p += align16(32 * sizeof(double));
+  // scratch for the table build lives in the data buffers
+  int *cnt = (int *)data;                            // kTables * nd
+  int *cur = cnt + kTables * nd;                     // kTables * nd
+  int *rtg = cur + kTables * nd;                     // kTables * nd * 4
+  double *rcw = (double *)(data + align16((size_t)kTables * nd * 4 * 6));
+
+#define TB(t) tab_at<T>(tabs + (t) * tstride, nd)
+
+  // ---- frames: L, R, interface (mean, velocities in the interface basis), slope neighbours
+  const Frame fL = side_frame(g, F.L), fR = side_frame(g, F.R);
+  const Frame fLm = side_frame(g, F.Lm), fRp = side_frame(g, F.Rp);
+  Frame fs;
+  {
+    double vl[3], vr[3];
+    change_basis(fL.th, fL.ph, F.ths, F.phs, fL.v, vl);
+    change_basis(fR.th, fR.ph, F.ths, F.phs, fR.v, vr);
+    for (int i = 0; i < 3; ++i) fs.v[i] = 0.5 * (vl[i] + vr[i]);
+    fs.alpha = 0.5 * (fL.alpha + fR.alpha);
+    fs.psi = 0.5 * (fL.psi + fR.psi);
+    fs.th = F.ths;
+    fs.ph = F.phs;
+  }
+  const bool rot = g.geom != 2;
+  const int ax = F.axis;
+  const bool slopeL = F.L.slope, slopeR = F.R.slope && !F.self;
+  // table t: 0 Lm->L, 1 R->L, 2 L->R, 3 Rp->R, 4 L->s, 5 R->s, 6 s->L, 7 s->R
+
+  for (int q = tid; q < kTables * nd; q += blockDim.x) cnt[q] = 0;
+  for (int i = tid; i < ne; i += blockDim.x) Gs[i] = g.G[i];
+  __syncthreads();
+  // pass 1: chain per (table, source direction), records, counts
+  for (int q = tid; q < kTables * nd; q += blockDim.x) {
+    int t = q / nd, d = q - t * nd;
+    int rt[4];
+    double rw[4];
+    const Frame &S = t == 0 ? fLm : (t == 1 || t == 5) ? fR : (t == 2 || t == 4) ? fL : t == 3 ? fRp : fs;
+    const Frame &D = (t == 0 || t == 1 || t == 6) ? fL : (t == 2 || t == 3 || t == 7) ? fR : fs;
+    Tab<T> tt = TB(t);
+    int nr = build_source<T>(g, S, D, ax, rot, same_frame(S, D), d, tt, rt, rw);
+    (void)nr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      rtg[q * 4 + r] = rt[r];
+      rcw[q * 4 + r] = rw[r];
+      if (rt[r] >= 0) atomicAdd(&cnt[t * nd + rt[r]], 1);
+    }
+  }
+  // interface speeds of each bin (flux integral, zero shift): U = alpha psi^4 uhat^n
+  const double gs = 1.0 / sqrt(1.0 - (fs.v[0] * fs.v[0] + fs.v[1] * fs.v[1] + fs.v[2] * fs.v[2]));
+  const double kvs = gs * gs / (gs + 1.0);
+  const double ap4 = fs.alpha * dsq(fs.psi * fs.psi);
+  const double vn = fs.v[ax];
+  const double Uadv = ap4 * gs * vn;
+  for (int d = tid; d < nd; d += blockDim.x) {
+    const double *nv = g.nvec + 3 * d;
+    double vdn = fs.v[0] * nv[0] + fs.v[1] * nv[1] + fs.v[2] * nv[2];
+    double u0 = gs * (1.0 + vdn);
+    double un = nv[ax] + (kvs * vdn + gs) * vn;
+    Urad[d] = ap4 * (nv[ax] + kvs * vdn * vn);
+    Vn[d] = fs.alpha * un / (fs.psi * fs.psi * u0);
+    // donor speeds: the side's own comoving direction, in the interface basis
+    double u[4] = { 1.0, nv[0], nv[1], nv[2] }, e[4], y[3];
+    lorentz(fL.v, u, e);
+    if (rot) change_basis(fL.th, fL.ph, fs.th, fs.ph, e + 1, y); else { y[0] = e[1]; y[1] = e[2]; y[2] = e[3]; }
+    UL[d] = ap4 * y[ax];
+    lorentz(fR.v, u, e);
+    if (rot) change_basis(fR.th, fR.ph, fs.th, fs.ph, e + 1, y); else { y[0] = e[1]; y[1] = e[2]; y[2] = e[3]; }
+    UR[d] = ap4 * y[ax];
+  }
+  __syncthreads();
+  // pass 2: exclusive scan of the counts (one thread per table)
+  if (tid < kTables) {
+    Tab<T> tt = TB(tid);
+    int acc = 0;
+    for (int d = 0; d < nd; ++d) {
+      tt.start[d] = acc;
+      cur[tid * nd + d] = acc;
+      acc += cnt[tid * nd + d];
+    }
+    tt.start[nd] = acc;
+  }
+  __syncthreads();
+  // pass 3: scatter records into their target lists
+  for (int q = tid; q < kTables * nd; q += blockDim.x) {
+    int t = q / nd, d = q - t * nd;
+    Tab<T> tt = TB(t);
+    for (int r = 0; r < 4; ++r) {
+      int tg = rtg[q * 4 + r];
+      if (tg < 0) continue;
+      int slot = atomicAdd(&cur[t * nd + tg], 1);
+      tt.src[slot] = d;
+      tt.c[slot] = (T)rcw[q * 4 + r];
+    }
+  }
+  __syncthreads();
+  // pass 4: sort each list by source so that the summation order is fixed
+  for (int q = tid; q < kTables * nd; q += blockDim.x) {
+    int t = q / nd, d = q - t * nd;
+    Tab<T> tt = TB(t);
+    int a = tt.start[d], b = tt.start[d + 1];
+    for (int x = a + 1; x < b; ++x) {
+      int ks_ = tt.src[x];
+      T kc = tt.c[x];
+      int y = x - 1;
+      while (y >= a && tt.src[y] > ks_) {
+        tt.src[y + 1] = tt.src[y];
+        tt.c[y + 1] = tt.c[y];
+        --y;
+      }
+      tt.src[y + 1] = ks_;
+      tt.c[y + 1] = kc;
+    }
+  }
+  __syncthreads();
+
+  // ---- per species
+  const int nitems = nd * g.nch;
+  const bool own = tid < nitems;
+  const int dp = own ? tid % nd : 0;
+  const int i0 = own ? (tid / nd) * kEC : 0;
+  const double cA = dt * F.area;
+  const double tau = 0.5 * fs.alpha * dt / gs;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = (blockDim.x + 63) >> 6;
+  for (int s = 0; s < g.ns; ++s) {
+    load_side<T>(g, F.Lm, f, feq, s, Gs, buf[0]);
+    load_side<T>(g, F.L, f, feq, s, Gs, buf[1]);
+    load_side<T>(g, F.R, f, feq, s, Gs, buf[2]);
+    load_side<T>(g, F.Rp, f, feq, s, Gs, buf[3]);
+    __syncthreads();
+    // phase 1: limited slopes and reconstructed donor values (own frames)
+    T EL[kEC], ER[kEC];
+    if (own) {
+      T a[kEC], b[kEC];
+      T fl[kEC], fr[kEC], sl[kEC];
+      for (int k = 0; k < kEC; ++k) {
+        int i = i0 + k;
+        fl[k] = i < ne ? (T)((double)buf[1][i * nd + dp] / Gs[i]) : (T)0;
+        fr[k] = i < ne ? (T)((double)buf[2][i * nd + dp] / Gs[i]) : (T)0;
+        sl[k] = (T)0;
+      }
+      if (slopeL) {
+        gather<T>(g, TB(0), buf[0], true, dp, i0, Gs, a);
+        gather<T>(g, TB(1), buf[2], true, dp, i0, Gs, b);
+        for (int k = 0; k < kEC; ++k)
+          sl[k] = mc_limiter<T>((fl[k] - a[k]) / (T)F.hLm, (b[k] - fl[k]) / (T)F.h);
+      }
+      for (int k = 0; k < kEC; ++k) EL[k] = fl[k] + (T)F.dL * sl[k];
+      if (slopeR) {
+        gather<T>(g, TB(2), buf[1], true, dp, i0, Gs, a);
+        gather<T>(g, TB(3), buf[3], true, dp, i0, Gs, b);
+        for (int k = 0; k < kEC; ++k)
+          ER[k] = fr[k] + (T)F.dR * mc_limiter<T>((fr[k] - a[k]) / (T)F.h, (b[k] - fr[k]) / (T)F.hRp);
+      } else if (F.self) {
+        for (int k = 0; k < kEC; ++k) ER[k] = fr[k] + (T)F.dR * sl[k];
+      } else {
+        for (int k = 0; k < kEC; ++k) ER[k] = fr[k];
+      }
+    }
+    __syncthreads();                                   // Lm and Rp data no longer read
+    if (own) {
+      for (int k = 0; k < kEC; ++k) {
+        int i = i0 + k;
+        if (i < ne) {
+          buf[0][i * nd + dp] = (T)((double)EL[k] * Gs[i]);
+          buf[3][i * nd + dp] = (T)((double)ER[k] * Gs[i]);
+        }
+      }
+    }
+    // phase 2a: Lax-Wendroff half step source S in the interface frame
+    T Sv[kEC];
+    if (own) {
+      T A[kEC], B[kEC];
+      gather<T>(g, TB(4), buf[1], true, dp, i0, Gs, A);
+      gather<T>(g, TB(5), buf[2], true, dp, i0, Gs, B);
+      const T cv = (T)(-0.5 * dt * Vn[dp] / F.h);
+      for (int k = 0; k < kEC; ++k) {
+        int i = i0 + k;
+        double kf = 0.0;
+        if (i < ne && !F.zero_opacity) {
+          size_t l = ((size_t)F.L.z * g.ns + s) * ne + i, r = ((size_t)F.R.z * g.ns + s) * ne + i;
+          kf = 0.5 * ((double)ka[l] + (double)ka[r]) * 0.5 * ((double)feq[l] + (double)feq[r]);
+        }
+        Sv[k] = (T)0.5 * (A[k] + B[k]) + cv * (B[k] - A[k]) + (T)(tau * kf);
+      }
+    }
+    __syncthreads();                                   // all reads of L and R data done
+    if (own) {
+      for (int k = 0; k < kEC; ++k) {
+        int i = i0 + k;
+        if (i < ne) buf[2][i * nd + dp] = Sv[k];
+      }
+    }
+    __syncthreads();
+    // angle integral <S> per group (FP64, fixed order)
+    for (int i = wave; i < ne; i += nwaves) {
+      double acc = 0.0;
+      for (int d = lane; d < nd; d += 64) acc += (double)buf[2][i * nd + d] * g.dOm[d];
+      acc = wave_sum(acc);
+      if (lane == 0) sav[i] = acc / (4.0 * kPi);
+    }
+    __syncthreads();
+    // phase 2b: interface collision, blend weights, content fluxes
+    if (own) {
+      for (int k = 0; k < kEC; ++k) {
+        int i = i0 + k;
+        if (i >= ne) break;
+        double ka_ = 0.0, ks_ = 0.0;
+        if (!F.zero_opacity) {
+          size_t l = ((size_t)F.L.z * g.ns + s) * ne + i, r = ((size_t)F.R.z * g.ns + s) * ne + i;
+          ka_ = 0.5 * ((double)ka[l] + (double)ka[r]);
+          ks_ = 0.5 * ((double)ks[l] + (double)ks[r]);
+        }
+        double flw;
+        if (sizeof(T) == 8 || tau * (ka_ + ks_) > g.fp64_thr) {
+          flw = ((double)Sv[k] + tau * ks_ * sav[i] / (1.0 + tau * ka_)) / (1.0 + tau * (ka_ + ks_));
+        } else {
+          float t = (float)tau, a = (float)ka_, b = (float)ks_;
+          flw = ((float)Sv[k] + t * b * (float)sav[i] / (1.0f + t * a)) / (1.0f + t * (a + b));
+        }
+        double w = exp(-(ka_ + ks_) * F.h);
+        double gw = Gs[i] * g.dOm[dp] * cA;
+        buf[1][i * nd + dp] = (T)((1.0 - w) * Urad[dp] * flw * gw);
+        double eL = w * fmax(UL[dp], 0.0) + (1.0 - w) * fmax(Uadv, 0.0);
+        double eR = w * fmax(-UR[dp], 0.0) + (1.0 - w) * fmax(-Uadv, 0.0);
+        buf[0][i * nd + dp] = (T)(eL * g.dOm[dp] * cA * (double)buf[0][i * nd + dp]);
+        buf[3][i * nd + dp] = (T)(eR * g.dOm[dp] * cA * (double)buf[3][i * nd + dp]);
+      }
+    }
+    __syncthreads();
+    // phase 3: content changes of both sides
+    double sumL = 0.0, sumR = 0.0;
+    if (own) {
+      T a[kEC], b[kEC], c2[kEC];
+      gather<T>(g, TB(6), buf[1], false, dp, i0, Gs, a);
+      gather<T>(g, TB(1), buf[3], false, dp, i0, Gs, b);
+      T *oL = outL + (size_t)s * n, *oR = outR + (size_t)s * n;
+      for (int k = 0; k < kEC; ++k) {
+        int i = i0 + k;
+        if (i >= ne) break;
+        T v = -a[k] - buf[0][i * nd + dp] + b[k];
+        oL[i * nd + dp] = v;
+        sumL += (double)v;
+      }
+      gather<T>(g, TB(7), buf[1], false, dp, i0, Gs, a);
+      gather<T>(g, TB(2), buf[0], false, dp, i0, Gs, c2);
+      for (int k = 0; k < kEC; ++k) {
+        int i = i0 + k;
+        if (i >= ne) break;
+        T v = a[k] - buf[3][i * nd + dp] + c2[k];
+        oR[i * nd + dp] = v;
+        sumR += (double)v;
+      }
+    }
+    if (F.L.kind != btx::SIDE_ZONE || F.R.kind != btx::SIDE_ZONE) {
+      double v = (F.L.kind != btx::SIDE_ZONE) ? sumL : sumR;
+      v = wave_sum(v);
+      if (lane == 0) red[wave] = v;
+      __syncthreads();
+      if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < nwaves; ++w) t += red[w];
+        tally[(size_t)fid * g.ns + s] += t;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ zone kernel
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+zone_kernel(DevGrid g, const btx::ZoneFaces *__restrict__ zf, const T *__restrict__ f,
+            const T *__restrict__ dN, const T *__restrict__ ka, const T *__restrict__ ks,
+            const T *__restrict__ feq, T *__restrict__ fout, double dt)
+{
+  const int z = blockIdx.x;
+  const int nd = g.ndir, ne = g.ne, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const btx::ZoneFaces L = zf[z];
+  const double vr = g.vr[z], vt = g.vth[z];
+  const double gam = 1.0 / sqrt(1.0 - (vr * vr + vt * vt));
+  const double p6v = pow(g.psi[z], 6.0) * g.vol[z];
+  const double tau = g.alp[z] * dt / gam;
+  for (int row = wave; row < g.ns * ne; row += nwaves) {
+    int s = row / ne, i = row - s * ne;
+    size_t kidx = ((size_t)z * g.ns + s) * ne + i;
+    double ka_ = (double)ka[kidx], ks_ = (double)ks[kidx], fe_ = (double)feq[kidx];
+    bool wide = (sizeof(T) == 8) || tau * (ka_ + ks_) > g.fp64_thr;
+    double Sd[4];
+    double part = 0.0;
+    for (int r = 0; r < 4; ++r) {
+      int d = lane + 64 * r;
+      Sd[r] = 0.0;
+      if (d >= nd) continue;
+      size_t off = (size_t)s * g.eblk + (size_t)i * nd + d;
+      double acc = 0.0;
+      for (int q = 0; q < L.n; ++q)
+        acc += (double)dN[((size_t)L.fid[q] * 2 + L.side[q]) * g.blk + off];
+      const double *nv = g.nvec + 3 * d;
+      double W = p6v * gam * (1.0 + vr * nv[0] + vt * nv[1]) * g.G[i] * g.dOm[d];
+      double S = (double)f[(size_t)z * g.blk + off] + tau * ka_ * fe_ + acc / W;
+      if (!wide) S = (double)(float)S;
+      Sd[r] = S;
+      part += S * g.dOm[d];
+    }
+    double avg = wave_sum(part) / (4.0 * kPi);
+    for (int r = 0; r < 4; ++r) {
+      int d = lane + 64 * r;
+      if (d >= nd) continue;
+      size_t off = (size_t)s * g.eblk + (size_t)i * nd + d;
+      double out;
+      if (wide) out = (Sd[r] + tau * ks_ * avg / (1.0 + tau * ka_)) / (1.0 + tau * (ka_ + ks_));
+      else {
+        float t = (float)tau, a = (float)ka_, b = (float)ks_;
+        out = ((float)Sd[r] + t * b * (float)avg / (1.0f + t * a)) / (1.0f + t * (a + b));
+      }
+      fout[(size_t)z * g.blk + off] = (T)out;
+    }
+  }
+}
+
+// per-zone moments in FP64 (paper Sec. 4.1-4.2, without 1/h^3):
+// zm[z][s][0..4] = N, J, H, K, number flux; ze[z][s] = energy content
+template <typename T>
+__global__ void __launch_bounds__(256)
+moments_kernel(DevGrid g, const T *__restrict__ f, double *__restrict__ zm, double *__restrict__ ze)
+{
+  const int z = blockIdx.x;
+  __shared__ double red[6][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const double vr = g.vr[z], vt = g.vth[z];
+  const double gam = 1.0 / sqrt(1.0 - (vr * vr + vt * vt));
+  const double p6v = pow(g.psi[z], 6.0) * g.vol[z];
+  for (int s = 0; s < g.ns; ++s) {
+    double m[6] = { 0, 0, 0, 0, 0, 0 };
+    for (int q = threadIdx.x; q < g.eblk; q += blockDim.x) {
+      int i = q / g.ndir, d = q - i * g.ndir;
+      double fv = (double)f[(size_t)z * g.blk + (size_t)s * g.eblk + q];
+      const double *nv = g.nvec + 3 * d;
+      double dG = g.G[i] * g.dOm[d], mu = nv[0], e = g.eps[i];
+      double nn = p6v * gam * (1.0 + vr * nv[0] + vt * nv[1]) * dG * fv;
+      m[0] += nn;
+      m[1] += fv * e * dG;
+      m[2] += fv * mu * e * dG;
+      m[3] += fv * mu * mu * e * dG;
+      m[4] += fv * mu * dG;
+      m[5] += nn * e;
+    }
+    for (int k = 0; k < 6; ++k) {
+      double v = wave_sum(m[k]);
+      if (lane == 0) red[k][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t[6];
+      for (int k = 0; k < 6; ++k) {
+        t[k] = 0.0;
+        for (int w = 0; w < nwaves; ++w) t[k] += red[k][w];
+      }
+      double *o = zm + ((size_t)z * g.ns + s) * 5;
+      o[0] = t[0];
+      for (int k = 1; k < 5; ++k) o[k] = t[k] / (4.0 * kPi);
+      ze[(size_t)z * g.ns + s] = t[5];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ void cast_kernel(const double *__restrict__ src, T *__restrict__ dst, size_t n)
+{
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (T)src[i];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- the ABI
+
+struct btx_ctx {
+  btx::Grid g;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t tsize = 8;                 // bytes per stored value
+  // device buffers
+  double *d_mu = nullptr, *d_Phi = nullptr, *d_dOm = nullptr, *d_nvec = nullptr, *d_G = nullptr,
+         *d_eps = nullptr, *d_vol = nullptr;
+  double *d_vr = nullptr, *d_vth = nullptr, *d_alp = nullptr, *d_psi = nullptr;
+  void *d_ka = nullptr, *d_ks = nullptr, *d_feq = nullptr;
+  void *d_f = nullptr, *d_fn = nullptr, *d_dN = nullptr;
+  double *d_tally = nullptr, *d_zm = nullptr, *d_ze = nullptr, *d_stage = nullptr;
+  FaceDesc *d_faces = nullptr;
+  btx::ZoneFaces *d_zf = nullptr;
+  bool have_bg = false, have_state = false;
+  double dt_max1 = 0.0;
+  size_t lds_bytes = 0;
+  int face_threads = 0;
+  // timing
+  bool timing = false;
+  double t_ms[2] = { 0, 0 };
+  int64_t t_n[2] = { 0, 0 };
+  std::vector<hipEvent_t> ev;
+};
+
+namespace {
+
+DevGrid dev_grid(const btx_ctx *c)
+{
+  const btx::Grid &g = c->g;
+  DevGrid d;
+  d.nr = g.nr; d.nth = g.nth; d.ne = g.ne; d.nmu = g.nmu; d.nphi = g.nphi; d.ns = g.ns;
+  d.ndir = g.ndir; d.nz = g.nz; d.geom = g.geom; d.phi_rule = g.phi_rule;
+  d.eblk = g.ne * g.ndir; d.blk = g.ns * d.eblk;
+  d.nch = (g.ne + kEC - 1) / kEC;
+  d.nfaces = (int)g.faces.size();
+  d.lnq = g.lnq; d.q = g.q; d.fp64_thr = g.fp64_thr;
+  d.mu = c->d_mu; d.Phi = c->d_Phi; d.dOm = c->d_dOm; d.nvec = c->d_nvec; d.G = c->d_G;
+  d.eps = c->d_eps; d.vol = c->d_vol;
+  d.vr = c->d_vr; d.vth = c->d_vth; d.alp = c->d_alp; d.psi = c->d_psi;
+  return d;
+}
+
+template <typename X>
+btx_status upload(X **dst, const X *src, size_t n)
+{
+  HIP_TRY(hipMalloc((void **)dst, sizeof(X) * std::max<size_t>(n, 1)));
+  if (n) HIP_TRY(hipMemcpy(*dst, src, sizeof(X) * n, hipMemcpyHostToDevice));
+  return BTX_OK;
+}
+
+size_t face_lds(const btx::Grid &g, size_t szT)
+{
+  int nd = g.ndir, ne = g.ne, n = nd * ne;
+  (void)n;
+  size_t b = kTables * tab_stride(nd, szT);
+  b += data_bytes(nd, ne, szT);
+  b += align16(ne * 8) + 4 * align16(nd * 8) + align16(ne * 8) + align16(32 * 8);
+  return b;
+}
+
+void free_ctx(btx_ctx *c)
+{
+  void *ptrs[] = { c->d_mu, c->d_Phi, c->d_dOm, c->d_nvec, c->d_G, c->d_eps, c->d_vol, c->d_vr,
+                   c->d_vth, c->d_alp, c->d_psi, c->d_ka, c->d_ks, c->d_feq, c->d_f, c->d_fn,
+                   c->d_dN, c->d_tally, c->d_zm, c->d_ze, c->d_stage, c->d_faces, c->d_zf };
+  for (void *p : ptrs) if (p) (void)hipFree(p);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+template <typename T>
+btx_status launch_step(btx_ctx *c, double dt)
+{
+  DevGrid dg = dev_grid(c);
+  int nf = dg.nfaces;
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+  if (c->timing) { e0 = c->ev[0]; e1 = c->ev[1]; e2 = c->ev[2]; HIP_TRY(hipEventRecord(e0, c->stream)); }
+  const int maxgrid = 1 << 30;
+  for (int f0 = 0; f0 < nf; f0 += maxgrid) {
+    int nb = std::min(nf - f0, maxgrid);
+    hipLaunchKernelGGL((face_kernel<T>), dim3(nb), dim3(c->face_threads), c->lds_bytes, c->stream, dg,
+                       c->d_faces, (const T *)c->d_f, (const T *)c->d_ka, (const T *)c->d_ks,
+                       (const T *)c->d_feq, (T *)c->d_dN, c->d_tally, dt, f0);
+  }
+  HIP_TRY(hipGetLastError());
+  if (c->timing) HIP_TRY(hipEventRecord(e1, c->stream));
+  hipLaunchKernelGGL((zone_kernel<T>), dim3(dg.nz), dim3(256), 0, c->stream, dg, c->d_zf,
+                     (const T *)c->d_f, (const T *)c->d_dN, (const T *)c->d_ka, (const T *)c->d_ks,
+                     (const T *)c->d_feq, (T *)c->d_fn, dt);
+  HIP_TRY(hipGetLastError());
+  if (c->timing) {
+    HIP_TRY(hipEventRecord(e2, c->stream));
+    HIP_TRY(hipEventSynchronize(e2));
+    float a = 0.f, b = 0.f;
+    HIP_TRY(hipEventElapsedTime(&a, e0, e1));
+    HIP_TRY(hipEventElapsedTime(&b, e1, e2));
+    c->t_ms[0] += a; c->t_ms[1] += b;
+    c->t_n[0] += 1; c->t_n[1] += 1;
+  }
+  std::swap(c->d_f, c->d_fn);
+  return BTX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *btx_last_error(void) { return g_err.c_str(); }
+
+btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, btx_ctx **out)
+{
+  if (!d || !out) return fail(BTX_E_INVAL, "null argument");
+  *out = nullptr;
+  if (d->n_r < 1 || d->n_eps < 1 || d->n_mu < 2 || d->n_phi < 1 || d->n_species < 1)
+    return fail(BTX_E_INVAL, "sizes must be positive (n_mu >= 2)");
+  if (d->geometry < 0 || d->geometry > 2) return fail(BTX_E_INVAL, "unknown geometry");
+  if (d->mu_rule < 0 || d->mu_rule > 1) return fail(BTX_E_INVAL, "unknown mu rule");
+  if (d->phi_rule < 0 || d->phi_rule > 1) return fail(BTX_E_INVAL, "unknown phi rule");
+  if (d->phi_rule == BTX_PHI_DIRECTION && d->n_phi > 1 && d->n_phi < 3)
+    return fail(BTX_E_INVAL, "direction-preserving Phi split needs n_phi >= 3");
+  if (d->inner_bc < 0 || d->inner_bc > 2 || d->outer_bc < 1 || d->outer_bc > 2)
+    return fail(BTX_E_INVAL, "bad boundary condition");
+  if (d->precision != BTX_PREC_FP64 && d->precision != BTX_PREC_MIXED)
+    return fail(BTX_E_INVAL, "unknown precision");
+  if (!d->r_edges || !d->eps_edges) return fail(BTX_E_INVAL, "null edge array");
+  int nth = d->geometry == BTX_GEOM_AXISYM2D ? d->n_theta : 1;
+  if (nth < 1) return fail(BTX_E_INVAL, "n_theta must be positive");
+  if (d->n_mu * d->n_phi > 255) return fail(BTX_E_UNSUPPORTED, "at most 255 directions");
+  int nch = (d->n_eps + kEC - 1) / kEC;
+  if (d->n_mu * d->n_phi * nch > kMaxFaceThreads) return fail(BTX_E_UNSUPPORTED, "too many directions x groups per face");
+  for (int a = 0; a < d->n_r; ++a)
+    if (!(d->r_edges[a + 1] > d->r_edges[a])) return fail(BTX_E_INVAL, "r edges must ascend");
+  if (d->geometry != BTX_GEOM_PLANAR && !(d->r_edges[0] >= 0.0)) return fail(BTX_E_INVAL, "r edges must be >= 0");
+  for (int i = 0; i < d->n_eps; ++i)
+    if (!(d->eps_edges[i + 1] > d->eps_edges[i]) || !(d->eps_edges[i] > 0.0))
+      return fail(BTX_E_INVAL, "energy edges must be positive and ascend");
+  if (d->geometry == BTX_GEOM_AXISYM2D) {
+    if (!d->theta_edges) return fail(BTX_E_INVAL, "null theta edges");
+    if (d->theta_edges[0] != 0.0 || std::fabs(d->theta_edges[nth] - kPi) > 1e-12)
+      return fail(BTX_E_UNSUPPORTED, "2D theta edges must span [0, pi]");
+    for (int b = 0; b < nth; ++b)
+      if (!(d->theta_edges[b + 1] > d->theta_edges[b])) return fail(BTX_E_INVAL, "theta edges must ascend");
+    if (!(d->dphi > 0.0) || d->dphi > kPi) return fail(BTX_E_INVAL, "dphi must be in (0, pi]");
+  }
+  btx_ctx *c = new btx_ctx();
+  btx::Grid &g = c->g;
+  g.nr = d->n_r; g.nth = nth; g.ne = d->n_eps; g.nmu = d->n_mu; g.nphi = d->n_phi; g.ns = d->n_species;
+  g.geom = d->geometry; g.mu_rule = d->mu_rule; g.phi_rule = d->phi_rule;
+  g.inner_bc = d->inner_bc; g.outer_bc = d->outer_bc; g.prec = d->precision;
+  g.dphi = d->dphi;
+  g.fp64_thr = d->fp64_threshold > 0.0 ? d->fp64_threshold : 1.0;
+  g.r_e.assign(d->r_edges, d->r_edges + g.nr + 1);
+  g.eps_e.assign(d->eps_edges, d->eps_edges + g.ne + 1);
+  if (g.geom == BTX_GEOM_AXISYM2D) g.th_e.assign(d->theta_edges, d->theta_edges + nth + 1);
+  else g.th_e = { 0.0, kPi };
+  std::string why = btx::build_grid(g);
+  if (!why.empty()) { delete c; return fail(BTX_E_UNSUPPORTED, why); }
+  c->device = hip_device;
+  c->stream = (hipStream_t)hip_stream;
+  c->tsize = g.prec == BTX_PREC_FP64 ? 8 : 4;
+  c->dt_max1 = btx::max_dt(g, 1.0);
+  c->lds_bytes = face_lds(g, c->tsize);
+  int items = g.ndir * ((g.ne + kEC - 1) / kEC);
+  c->face_threads = std::max(64, ((items + 63) / 64) * 64);
+  btx_status st = BTX_OK;
+  hipError_t he = hipSetDevice(hip_device);
+  if (he != hipSuccess) { delete c; return fail(BTX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(he)); }
+  hipDeviceProp_t prop;
+  he = hipGetDeviceProperties(&prop, hip_device);
+  if (he != hipSuccess) { delete c; return fail(BTX_E_DEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(he)); }
+  if (c->tsize == 8)
+    he = hipFuncSetAttribute((const void *)face_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)c->lds_bytes);
+  else
+    he = hipFuncSetAttribute((const void *)face_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)c->lds_bytes);
+  (void)he;
+  size_t lds_cap = std::max<size_t>((size_t)prop.sharedMemPerBlock, (size_t)prop.maxSharedMemoryPerMultiProcessor);
+  if (c->lds_bytes > lds_cap) {
+    size_t need = c->lds_bytes;
+    delete c;
+    return fail(BTX_E_UNSUPPORTED, "face workgroup needs " + std::to_string(need) + " B of LDS");
+  }
+  size_t nz = g.nz, blk = (size_t)g.ns * g.ne * g.ndir, nk = nz * g.ns * g.ne;
+  size_t nf = g.faces.size();
+#define TRY(x) do { st = (x); if (st != BTX_OK) { free_ctx(c); return st; } } while (0)
+  TRY(upload(&c->d_mu, g.mu.data(), g.mu.size()));
+  TRY(upload(&c->d_Phi, g.Phi.data(), g.Phi.size()));
+  TRY(upload(&c->d_dOm, g.dOm.data(), g.dOm.size()));
+  TRY(upload(&c->d_nvec, g.nvec.data(), g.nvec.size()));
+  TRY(upload(&c->d_G, g.G.data(), g.G.size()));
+  TRY(upload(&c->d_eps, g.eps.data(), g.eps.size()));
+  TRY(upload(&c->d_vol, g.vol.data(), g.vol.size()));
+  TRY(upload(&c->d_faces, g.faces.data(), nf));
+  TRY(upload(&c->d_zf, g.zfaces.data(), g.zfaces.size()));
+  std::vector<double> zero(nz, 0.0), one(nz, 1.0);
+  TRY(upload(&c->d_vr, zero.data(), nz));
+  TRY(upload(&c->d_vth, zero.data(), nz));
+  TRY(upload(&c->d_alp, one.data(), nz));
+  TRY(upload(&c->d_psi, one.data(), nz));
+#undef TRY
+  auto dmalloc = [&](void **p, size_t bytes) -> bool {
+    if (hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) return false;
+    return hipMemset(*p, 0, std::max<size_t>(bytes, 16)) == hipSuccess;
+  };
+  if (!dmalloc(&c->d_ka, nk * c->tsize) || !dmalloc(&c->d_ks, nk * c->tsize) ||
+      !dmalloc(&c->d_feq, nk * c->tsize) || !dmalloc(&c->d_f, nz * blk * c->tsize) ||
+      !dmalloc(&c->d_fn, nz * blk * c->tsize) || !dmalloc(&c->d_dN, nf * 2 * blk * c->tsize) ||
+      !dmalloc((void **)&c->d_tally, nf * g.ns * 8) || !dmalloc((void **)&c->d_zm, nz * g.ns * 5 * 8) ||
+      !dmalloc((void **)&c->d_ze, nz * g.ns * 8) ||
+      !dmalloc((void **)&c->d_stage, std::max(nz * blk, nk) * 8)) {
+    free_ctx(c);
+    return fail(BTX_E_NOMEM, "device allocation failed");
+  }
+  c->ev.resize(3);
+  for (auto &e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) { free_ctx(c); return fail(BTX_E_DEVICE, "hipEventCreate failed"); }
+  *out = c;
+  return BTX_OK;
+}
+
+btx_status btx_set_background(btx_ctx *c, const btx_background *bg)
+{
+  if (!c || !bg) return fail(BTX_E_INVAL, "null argument");
+  if (!bg->v_r || !bg->v_theta || !bg->alpha || !bg->psi || !bg->kappa_a || !bg->kappa_s || !bg->f_eq)
+    return fail(BTX_E_INVAL, "null background array");
+  const btx::Grid &g = c->g;
+  size_t nz = g.nz, nk = nz * g.ns * g.ne;
+  for (size_t z = 0; z < nz; ++z) {
+    double v2 = bg->v_r[z] * bg->v_r[z] + bg->v_theta[z] * bg->v_theta[z];
+    if (!(v2 < 1.0) || !(bg->alpha[z] > 0.0) || !(bg->psi[z] > 0.0) || !std::isfinite(bg->alpha[z]) ||
+        !std::isfinite(bg->psi[z]))
+      return fail(BTX_E_INVAL, "background velocity/metric out of range at zone " + std::to_string(z));
+  }
+  for (size_t k = 0; k < nk; ++k)
+    if (!(bg->kappa_a[k] >= 0.0) || !(bg->kappa_s[k] >= 0.0) || !std::isfinite(bg->kappa_a[k]) ||
+        !std::isfinite(bg->kappa_s[k]) || !std::isfinite(bg->f_eq[k]))
+      return fail(BTX_E_INVAL, "opacities must be finite and >= 0 (entry " + std::to_string(k) + ")");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipMemcpy(c->d_vr, bg->v_r, nz * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_vth, bg->v_theta, nz * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_alp, bg->alpha, nz * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_psi, bg->psi, nz * 8, hipMemcpyHostToDevice));
+  const double *src[3] = { bg->kappa_a, bg->kappa_s, bg->f_eq };
+  void *dst[3] = { c->d_ka, c->d_ks, c->d_feq };
+  for (int k = 0; k < 3; ++k) {
+    if (c->tsize == 8) {
+      HIP_TRY(hipMemcpy(dst[k], src[k], nk * 8, hipMemcpyHostToDevice));
+    } else {
+      HIP_TRY(hipMemcpy(c->d_stage, src[k], nk * 8, hipMemcpyHostToDevice));
+      hipLaunchKernelGGL((cast_kernel<float>), dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, 0,
+                         c->d_stage, (float *)dst[k], nk);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipDeviceSynchronize());
+    }
+  }
+  c->have_bg = true;
+  return BTX_OK;
+}
+
+btx_status btx_max_dt(const btx_ctx *c, double cfl, double *dt_out)
+{
+  if (!c || !dt_out) return fail(BTX_E_INVAL, "null argument");
+  if (!(cfl > 0.0)) return fail(BTX_E_INVAL, "cfl must be positive");
+  *dt_out = c->dt_max1 * cfl;
+  return BTX_OK;
+}
+
+btx_status btx_set_state(btx_ctx *c, const void *f, int is_device_ptr)
+{
+  if (!c || !f) return fail(BTX_E_INVAL, "null argument");
+  const btx::Grid &g = c->g;
+  size_t bytes = (size_t)g.nz * g.ns * g.ne * g.ndir * c->tsize;
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipMemcpyAsync(c->d_f, f, bytes, is_device_ptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMemsetAsync(c->d_tally, 0, g.faces.size() * g.ns * 8, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->have_state = true;
+  return BTX_OK;
+}
+
+btx_status btx_get_state(btx_ctx *c, void *f, int is_device_ptr)
+{
+  if (!c || !f) return fail(BTX_E_INVAL, "null argument");
+  if (!c->have_state) return fail(BTX_E_STATE, "no state set");
+  const btx::Grid &g = c->g;
+  size_t bytes = (size_t)g.nz * g.ns * g.ne * g.ndir * c->tsize;
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipMemcpyAsync(f, c->d_f, bytes, is_device_ptr ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return BTX_OK;
+}
+
+btx_status btx_step(btx_ctx *c, double dt, int32_t n_steps)
+{
+  if (!c) return fail(BTX_E_INVAL, "null context");
+  if (!c->have_bg || !c->have_state) return fail(BTX_E_STATE, "background and state must be set");
+  if (n_steps < 0) return fail(BTX_E_INVAL, "n_steps must be >= 0");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(BTX_E_INVAL, "dt must be positive and finite");
+  if (dt > c->dt_max1 * (1.0 + 1e-12)) return fail(BTX_E_CFL, "dt exceeds the Courant limit");
+  HIP_TRY(hipSetDevice(c->device));
+  for (int t = 0; t < n_steps; ++t) {
+    btx_status s = c->tsize == 8 ? launch_step<double>(c, dt) : launch_step<float>(c, dt);
+    if (s != BTX_OK) return s;
+  }
+  return BTX_OK;
+}
+
+btx_status btx_moments(btx_ctx *c, double *zone_moments, double *totals)
+{
+  if (!c) return fail(BTX_E_INVAL, "null context");
+  if (!c->have_bg || !c->have_state) return fail(BTX_E_STATE, "background and state must be set");
+  const btx::Grid &g = c->g;
+  HIP_TRY(hipSetDevice(c->device));
+  DevGrid dg = dev_grid(c);
+  if (c->tsize == 8)
+    hipLaunchKernelGGL((moments_kernel<double>), dim3(g.nz), dim3(256), 0, c->stream, dg,
+                       (const double *)c->d_f, c->d_zm, c->d_ze);
+  else
+    hipLaunchKernelGGL((moments_kernel<float>), dim3(g.nz), dim3(256), 0, c->stream, dg,
+                       (const float *)c->d_f, c->d_zm, c->d_ze);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> zm((size_t)g.nz * g.ns * 5), ze((size_t)g.nz * g.ns), tally(g.faces.size() * g.ns);
+  HIP_TRY(hipMemcpyAsync(zm.data(), c->d_zm, zm.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(ze.data(), c->d_ze, ze.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(tally.data(), c->d_tally, tally.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (zone_moments) std::memcpy(zone_moments, zm.data(), zm.size() * 8);
+  if (totals) {
+    for (int s = 0; s < g.ns; ++s) {
+      double N = 0.0, E = 0.0, out = 0.0;
+      for (int z = 0; z < g.nz; ++z) {
+        N += zm[((size_t)z * g.ns + s) * 5];
+        E += ze[(size_t)z * g.ns + s];
+      }
+      for (int f : g.bface) out += tally[(size_t)f * g.ns + s];
+      totals[3 * s] = N;
+      totals[3 * s + 1] = out;
+      totals[3 * s + 2] = E;
+    }
+  }
+  return BTX_OK;
+}
+
+btx_status btx_timing(btx_ctx *c, int enable, double *ms, int64_t *launches, int reset)
+{
+  if (!c) return fail(BTX_E_INVAL, "null context");
+  if (ms) { ms[0] = c->t_ms[0]; ms[1] = c->t_ms[1]; }
+  if (launches) { launches[0] = c->t_n[0]; launches[1] = c->t_n[1]; }
+  if (reset) { c->t_ms[0] = c->t_ms[1] = 0.0; c->t_n[0] = c->t_n[1] = 0; }
+  c->timing = enable != 0;
+  return BTX_OK;
+}
+
+btx_status btx_destroy(btx_ctx *c)
+{
+  if (!c) return BTX_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  free_ctx(c);
+  return BTX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+"""GPU (libbtx, HIP on gfx950) against the FP64 CPU reference.
+
+FP64 mode: ||f_gpu - f_ref||_inf / ||f_ref||_inf <= 1e-12 after several steps;
+moments to 1e-12 where they are not negligible.  Mixed mode: per-zone number
+and J within 1e-5 relative where J > 1e-8 max J.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2003_02845_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RNG = np.random.default_rng(7)
+
+
+def _btx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2003_02845_amd import btx
+    return btx
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _perturb(w, amp=0.3):
+    w.f0 = w.f0 * (1.0 + amp * RNG.random(w.f0.shape)) + 1e-3 * RNG.random(w.f0.shape)
+    return w
+
+
+CASES = {
+    "column_sphere": lambda: W.radiating_sphere(n_r=12, n_eps=4, n_mu=6, n_phi=4, n_steps=4),
+    "column_lobatto_v": lambda: _perturb(W.batch_models(n_models=1, size_scale=0.03)[0]),
+    "axisym": lambda: _perturb(W.axisym_2d(n_r=10, n_theta=6, n_eps=6, n_mu=4, n_phi=4)),
+    "shock_3species": lambda: _perturb(W.shock_2d(n_r=12, n_theta=5, n_eps=9, n_mu=4, n_phi=4,
+                                                  precision=W.PREC_FP64)),
+    "planar": lambda: W.planar(n_z=20, n_eps=3, n_mu=6, kappa_a=2.0, kappa_s=5.0, f_eq=0.3,
+                               inner_bc=W.BC_EQUIL, outer_bc=W.BC_OUTFLOW),
+}
+
+
+def _run_pair(w, steps, precision, oracle_mod):
+    btx = _btx()
+    o = oracle_mod.Oracle(w)
+    dt = o.max_dt(0.4)
+    ctx = btx.Context(w, precision=precision)
+    assert abs(ctx.max_dt(0.4) - dt) <= 1e-13 * dt
+    ctx.set_background()
+    ctx.set_state(w.f0)
+    o.step(dt, steps)
+    ctx.step(dt, steps)
+    return o, ctx
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_fp64_parity(case, oracle_mod):
+    w = CASES[case]()
+    _say(f"[gpu] fp64 parity {case}: zones {w.n_zones} block {w.block}")
+    o, ctx = _run_pair(w, 3, W.PREC_FP64, oracle_mod)
+    ref, got = o.state(), ctx.get_state()
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _say(f"[gpu]   rel err {err:.3e}")
+    assert err <= 1e-12
+    zr, tr = o.moments()
+    zg, tg = ctx.moments()
+    for k in range(5):
+        m = np.abs(zr[..., k]).max()
+        mask = np.abs(zr[..., k]) > 1e-30 * m
+        if mask.any():
+            assert np.max(np.abs(zg[..., k] - zr[..., k])[mask]) <= 1e-12 * m
+    assert np.allclose(tg, tr, rtol=1e-12, atol=1e-12 * np.abs(tr).max())
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", ["shock_3species", "column_lobatto_v"])
+def test_mixed_moments(case, oracle_mod):
+    w = CASES[case]()
+    _say(f"[gpu] mixed moments {case}")
+    o, ctx = _run_pair(w, 3, W.PREC_MIXED, oracle_mod)
+    zr, _ = o.moments()
+    zg, _ = ctx.moments()
+    for k in (0, 1):
+        m = zr[..., k]
+        mask = np.abs(zr[..., 1]) > 1e-8 * np.abs(zr[..., 1]).max()
+        rel = np.max(np.abs(zg[..., k] - m)[mask] / np.abs(m[mask]))
+        _say(f"[gpu]   moment {k} rel err {rel:.3e}")
+        assert rel <= 1e-5
+    ctx.close()
+
+
+def test_number_conservation_gpu(oracle_mod):
+    btx = _btx()
+    w = W.shock_2d(n_r=12, n_theta=5, n_eps=6, n_mu=4, n_phi=4, precision=W.PREC_FP64)
+    w.kappa_a[:] = 0.0
+    w.kappa_s[:] = 0.0
+    w.f0 = RNG.random(w.f0.shape)
+    _say("[gpu] number conservation")
+    ctx = btx.Context(w)
+    ctx.set_background()
+    ctx.set_state(w.f0)
+    _, t0 = ctx.moments()
+    ctx.step(ctx.max_dt(0.4), 3)
+    _, t1 = ctx.moments()
+    for s in range(w.n_species):
+        assert abs(t1[s, 0] - t0[s, 0] + t1[s, 1]) < 1e-13 * t0[s, 0]
+    ctx.close()
+
+
+def test_errors_gpu():
+    btx = _btx()
+    w = W.axisym_2d(n_r=6, n_theta=4, n_eps=4, n_mu=4, n_phi=4)
+    ctx = btx.Context(w)
+    with pytest.raises(btx.BtxError) as e:
+        ctx.step(1e-3, 1)
+    assert e.value.status == btx.BTX_E_STATE
+    ctx.set_background()
+    ctx.set_state(w.f0)
+    with pytest.raises(btx.BtxError) as e:
+        ctx.step(ctx.max_dt(1.0) * 1.5, 1)
+    assert e.value.status == btx.BTX_E_CFL
+    w.kappa_a[0, 0, 0] = float("nan")
+    with pytest.raises(btx.BtxError) as e:
+        ctx.set_background(w)
+    assert e.value.status == btx.BTX_E_INVAL
+    ctx.close()

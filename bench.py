@@ -1,0 +1,176 @@
+"""Throughput of the transport step on one MI355X.
+
+Workload: the high-resolution axisymmetric profile (600 r x 256 theta zones,
+3 species, 24 logarithmic groups 2-300 MeV, 12 Gauss-Lobatto mu x 8 Phi =
+96 directions, ~1.06e9 phase-space values) with seeded shock and l = 1-8
+density perturbations, in mixed precision; the same grid is then stepped in
+FP64 for the mixed-vs-FP64 speedup and the moment error of the mixed run.
+Inputs are synthetic (paper_2003_02845_amd.workloads) and resident in HBM
+before timing starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--n-r", type=int, default=600)
+    ap.add_argument("--n-theta", type=int, default=256)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def device_state(torch, w, dtype):
+    feq = torch.from_numpy(np.ascontiguousarray(w.f_eq)).cuda().to(dtype)
+    return feq[..., None].expand(w.n_zones, w.n_species, w.n_eps, w.n_dir).contiguous()
+
+
+def run_gpu(torch, btx, w, precision, steps, warmup):
+    stream = torch.cuda.current_stream()
+    ctx = btx.Context(w, device=0, stream=stream.cuda_stream, precision=precision)
+    ctx.set_background()
+    dtype = torch.float32 if precision == 1 else torch.float64
+    f0 = device_state(torch, w, dtype)
+    ctx.set_state(f0)
+    del f0
+    dt = ctx.max_dt(w.cfl)
+    ctx.step(dt, warmup)
+    torch.cuda.synchronize()
+    ctx.timing(enable=True, reset=True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter()
+    t0.record(stream)
+    ctx.step(dt, steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall
+    ms = t0.elapsed_time(t1)
+    kms, kn = ctx.timing(enable=False, reset=True)
+    zm, tot = ctx.moments()
+    ctx.close()
+    return {"ms": ms, "wall": wall, "kernel_ms": kms / np.maximum(kn, 1), "zm": zm, "tot": tot,
+            "dt": dt}
+
+
+def cpu_baseline(steps_note):
+    """the CPU reference on a bounded sample of the same workload shape"""
+    from oracle import oracle
+    from paper_2003_02845_amd import workloads as W
+    w = W.hires_2d(n_theta=32)
+    o = oracle.Oracle(w)
+    dt = o.max_dt(w.cfl)
+    t = time.perf_counter()
+    o.step(dt, 1)
+    el = time.perf_counter() - t
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": w.n_values / el, "unit": "zone*group*direction updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"one FP64 step of the same profile and momentum grid on 600 r x 32 theta "
+                      f"zones ({w.n_values:.3g} values, {el:.1f} s)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
+              f"(the spatial decomposition across GPUs is a design, not a build)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2003_02845_amd import btx, workloads as W
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    w = W.hires_2d(n_r=a.n_r, n_theta=a.n_theta)
+    print(f"[bench] workload {w.name}: {w.n_zones} zones x {w.block} = {w.n_values:.4g} values",
+          file=sys.stderr, flush=True)
+    mixed = run_gpu(torch, btx, w, W.PREC_MIXED, a.steps, a.warmup)
+    upd = w.n_values * a.steps
+    value = upd / (mixed["ms"] * 1e-3)
+    print(f"[bench] mixed: {mixed['ms'] / a.steps:.3f} ms/step, {value:.4g} updates/s, "
+          f"kernels {mixed['kernel_ms']}", file=sys.stderr, flush=True)
+    res64 = None
+    if not a.no_fp64:
+        k64 = a.fp64_steps if a.fp64_steps is not None else a.steps
+        res64 = run_gpu(torch, btx, w, W.PREC_FP64, k64, a.warmup)
+        v64 = w.n_values * k64 / (res64["ms"] * 1e-3)
+        print(f"[bench] fp64: {res64['ms'] / k64:.3f} ms/step, {v64:.4g} updates/s, "
+              f"kernels {res64['kernel_ms']}", file=sys.stderr, flush=True)
+    if a.copy_probe:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+    # algorithmic bytes (mixed): f read + f written (4 B each) + ka, ks, feq per group (FP32)
+    # + v_r, v_theta, alpha, psi per zone (FP64)
+    nz, nsg = w.n_zones, w.n_zones * w.n_species * w.n_eps
+    b_step = w.n_values * 8 + nsg * 3 * 4 + nz * 4 * 8
+    # the face kernel's algorithmic share: it must read f and the opacities once
+    b_face = w.n_values * 4 + nsg * 3 * 4 + nz * 4 * 8
+    t_face = mixed["kernel_ms"][0] * 1e-3
+    achieved = b_face / t_face / 1e9
+    out = {
+        "metric": "zone*group*direction updates/s (mixed FP32/FP64), with FP64 speedup and % HBM peak",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": mixed["ms"] / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "hires_2d: 600 r x 256 theta zones, 3 species, 24 groups, "
+                               "12 mu x 8 Phi directions, mixed precision",
+                   "zones": nz, "values": w.n_values, "dt": mixed["dt"]},
+        "step_hbm_frac": b_step / (mixed["ms"] / a.steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": "face_kernel<float>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None},
+    }
+    if res64 is not None:
+        k64 = a.fp64_steps if a.fp64_steps is not None else a.steps
+        v64 = w.n_values * k64 / (res64["ms"] * 1e-3)
+        out["fp64_value"] = v64
+        out["speedup_vs_fp64"] = value / v64
+        # moment error of the mixed run against the FP64 GPU run (same steps only if equal)
+        if k64 == a.steps:
+            zm, z64 = mixed["zm"], res64["zm"]
+            J64 = z64[..., 1]
+            mask = np.abs(J64) > 1e-8 * np.abs(J64).max()
+            out["mixed_vs_fp64_rel_err"] = {
+                "N": float(np.max(np.abs(zm[..., 0] - z64[..., 0])[mask] / np.abs(z64[..., 0][mask]))),
+                "J": float(np.max(np.abs(zm[..., 1] - J64)[mask] / np.abs(J64[mask])))}
+        tot = mixed["tot"]
+        if k64 == a.steps:
+                out["number_drift_mixed"] = float(np.max(np.abs(tot[:, 0] + tot[:, 1] - res64["tot"][:, 0]
+                                                            - res64["tot"][:, 1]) / res64["tot"][:, 0]))
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(a.steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -115,10 +115,11 @@ btx_status btx_step(btx_ctx *ctx, double dt, int32_t n_steps);
  * 4.2); totals[species][3] = total number, cumulative boundary outflow, total
  * energy.  Either pointer may be NULL.  Computed on the device in FP64. */
 btx_status btx_moments(btx_ctx *ctx, double *zone_moments, double *totals);
-/* Per-kernel GPU time: enable = 1 records HIP events around every kernel of
- * btx_step on the context's stream; ms[k] / launches[k] (k = 0 face kernel,
- * 1 zone-update kernel) receive the accumulated time and count since the last
- * reset (reset = 1 clears them after reading). */
+/* Per-kernel GPU time: enable = 1 records HIP events around the kernels of
+ * each btx_step step on the context's stream (no synchronisation; up to 256
+ * steps between two queries).  The query synchronises the recorded events and
+ * returns in ms[k] / launches[k] (k = 0 face kernel, 1 zone-update kernel) the
+ * accumulated time and count since the last reset (reset = 1 clears them). */
 btx_status btx_timing(btx_ctx *ctx, int enable, double *ms, int64_t *launches, int reset);
 btx_status btx_destroy(btx_ctx *ctx);
 const char *btx_last_error(void);

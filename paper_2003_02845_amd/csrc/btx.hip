@@ -820,11 +820,12 @@ struct btx_ctx {
   double dt_max1 = 0.0;
   size_t lds_bytes = 0;
   int face_threads = 0;
-  // timing
+  // timing: three events per step recorded on the stream, resolved on query
   bool timing = false;
   double t_ms[2] = { 0, 0 };
   int64_t t_n[2] = { 0, 0 };
-  std::vector<hipEvent_t> ev;
+  std::vector<hipEvent_t> ev;      // pool, 3 per recorded step
+  size_t ev_used = 0;              // events recorded and not yet resolved
 };
 
 namespace {
@@ -879,7 +880,12 @@ btx_status launch_step(btx_ctx *c, double dt)
   DevGrid dg = dev_grid(c);
   int nf = dg.nfaces;
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-  if (c->timing) { e0 = c->ev[0]; e1 = c->ev[1]; e2 = c->ev[2]; HIP_TRY(hipEventRecord(e0, c->stream)); }
+  bool rec = c->timing && c->ev_used + 3 <= c->ev.size();
+  if (rec) {
+    e0 = c->ev[c->ev_used]; e1 = c->ev[c->ev_used + 1]; e2 = c->ev[c->ev_used + 2];
+    c->ev_used += 3;
+    HIP_TRY(hipEventRecord(e0, c->stream));
+  }
   const int maxgrid = 1 << 30;
   for (int f0 = 0; f0 < nf; f0 += maxgrid) {
     int nb = std::min(nf - f0, maxgrid);
@@ -888,20 +894,12 @@ btx_status launch_step(btx_ctx *c, double dt)
                        (const T *)c->d_feq, (T *)c->d_dN, c->d_tally, dt, f0);
   }
   HIP_TRY(hipGetLastError());
-  if (c->timing) HIP_TRY(hipEventRecord(e1, c->stream));
+  if (rec) HIP_TRY(hipEventRecord(e1, c->stream));
   hipLaunchKernelGGL((zone_kernel<T>), dim3(dg.nz), dim3(256), 0, c->stream, dg, c->d_zf,
                      (const T *)c->d_f, (const T *)c->d_dN, (const T *)c->d_ka, (const T *)c->d_ks,
                      (const T *)c->d_feq, (T *)c->d_fn, dt);
   HIP_TRY(hipGetLastError());
-  if (c->timing) {
-    HIP_TRY(hipEventRecord(e2, c->stream));
-    HIP_TRY(hipEventSynchronize(e2));
-    float a = 0.f, b = 0.f;
-    HIP_TRY(hipEventElapsedTime(&a, e0, e1));
-    HIP_TRY(hipEventElapsedTime(&b, e1, e2));
-    c->t_ms[0] += a; c->t_ms[1] += b;
-    c->t_n[0] += 1; c->t_n[1] += 1;
-  }
+  if (rec) HIP_TRY(hipEventRecord(e2, c->stream));
   std::swap(c->d_f, c->d_fn);
   return BTX_OK;
 }
@@ -1013,11 +1011,11 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
       !dmalloc(&c->d_fn, nz * blk * c->tsize) || !dmalloc(&c->d_dN, nf * 2 * blk * c->tsize) ||
       !dmalloc((void **)&c->d_tally, nf * g.ns * 8) || !dmalloc((void **)&c->d_zm, nz * g.ns * 5 * 8) ||
       !dmalloc((void **)&c->d_ze, nz * g.ns * 8) ||
-      !dmalloc((void **)&c->d_stage, std::max(nz * blk, nk) * 8)) {
+      !dmalloc((void **)&c->d_stage, nk * 8)) {
     free_ctx(c);
     return fail(BTX_E_NOMEM, "device allocation failed");
   }
-  c->ev.resize(3);
+  c->ev.resize(3 * 256);
   for (auto &e : c->ev)
     if (hipEventCreate(&e) != hipSuccess) { free_ctx(c); return fail(BTX_E_DEVICE, "hipEventCreate failed"); }
   *out = c;
@@ -1152,6 +1150,16 @@ btx_status btx_moments(btx_ctx *c, double *zone_moments, double *totals)
 btx_status btx_timing(btx_ctx *c, int enable, double *ms, int64_t *launches, int reset)
 {
   if (!c) return fail(BTX_E_INVAL, "null context");
+  HIP_TRY(hipSetDevice(c->device));
+  for (size_t k = 0; k + 3 <= c->ev_used; k += 3) {
+    HIP_TRY(hipEventSynchronize(c->ev[k + 2]));
+    float a = 0.f, b = 0.f;
+    HIP_TRY(hipEventElapsedTime(&a, c->ev[k], c->ev[k + 1]));
+    HIP_TRY(hipEventElapsedTime(&b, c->ev[k + 1], c->ev[k + 2]));
+    c->t_ms[0] += a; c->t_ms[1] += b;
+    c->t_n[0] += 1; c->t_n[1] += 1;
+  }
+  c->ev_used = 0;
   if (ms) { ms[0] = c->t_ms[0]; ms[1] = c->t_ms[1]; }
   if (launches) { launches[0] = c->t_n[0]; launches[1] = c->t_n[1]; }
   if (reset) { c->t_ms[0] = c->t_ms[1] = 0.0; c->t_n[0] = c->t_n[1] = 0; }

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -34,9 +35,8 @@ using btx::SideDesc;
 
 namespace {
 
-constexpr int kEC = 8;        // energy groups per gather work item
 constexpr int kTables = 8;    // remap tables per face
-constexpr int kMaxFaceThreads = 512;
+constexpr int kMaxFaceThreads = 1024;
 constexpr double kPi = 3.14159265358979323846;
 
 thread_local std::string g_err;
@@ -67,6 +67,15 @@ struct DevGrid {
 struct Frame {
   double v[3];
   double alpha, psi, th, ph;
+};
+
+// Per-face frame data computed once per background by table_kernel: the five
+// frames (0 Lm, 1 L, 2 R, 3 Rp, 4 interface) with their Lorentz factor and
+// psi^6, and the basis changes L -> interface and R -> interface.
+struct FaceAux {
+  double v[5][3];
+  double alpha[5], psi[5], gam[5], p6[5];
+  double M[2][9];
 };
 
 __device__ inline double dsq(double x) { return x * x; }
@@ -169,51 +178,63 @@ __device__ inline double u0_dir(const Frame &f, const double *n)
 
 // ------------------------------------------------------------ LDS tables
 
-// Gather form of one remap T_{S->D}: for every source direction the energy
-// shift (di, tl, tr) and content weight aS; for every target direction the
-// inverse content weight and the list of (source, mu*Phi weight) entries.
+// A remap T_{S->D} of one face in gather form.  For every target direction d'
+// the entries [start[d'], start[d'+1]) hold the source direction and its
+// energy shift packed in 16 bits (src | (di + 128) << 8) and the two energy-tap
+// weights multiplied by the (mu, Phi) corner weight.  Tables act on number
+// content; occupations are turned into content before (x G_i aS(d)) and back
+// after (/ (G_i aD(d'))) by the caller.
 template <typename T>
 struct Tab {
-  int *di;
-  T *tl, *tr, *aS, *iaD;
-  int *start;        // ndir + 1
-  int *src;          // 4 * ndir
-  T *c;              // 4 * ndir
+  T *coef;             // 2 * 4nd: (cL, cR) per entry
+  unsigned short *key; // 4nd
+  unsigned short *start;  // nd + 1
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
+__host__ __device__ inline size_t tab_stride(int nd, size_t szT)
+{
+  return align16(8 * (size_t)nd * szT + 4 * (size_t)nd * 2 + (size_t)(nd + 1) * 2);
+}
+
 template <typename T>
-__device__ Tab<T> tab_at(char *base, int nd)
+__device__ inline Tab<T> tab_at(char *base, int nd)
 {
   Tab<T> t;
-  size_t off = 0;
-  t.tl = (T *)(base + off); off += nd * sizeof(T);
-  t.tr = (T *)(base + off); off += nd * sizeof(T);
-  t.aS = (T *)(base + off); off += nd * sizeof(T);
-  t.iaD = (T *)(base + off); off += nd * sizeof(T);
-  t.c = (T *)(base + off); off += 4 * nd * sizeof(T);
-  t.di = (int *)(base + off); off += nd * sizeof(int);
-  t.start = (int *)(base + off); off += (nd + 1) * sizeof(int);
-  t.src = (int *)(base + off); off += 4 * nd * sizeof(int);
+  t.coef = (T *)base;
+  t.key = (unsigned short *)(base + 8 * (size_t)nd * sizeof(T));
+  t.start = t.key + 4 * nd;
   return t;
 }
 
-__host__ __device__ inline size_t tab_stride(int nd, size_t szT)
+// LDS row stride of the data buffers: odd, so that one source column read
+// across rows by neighbouring lanes hits distinct banks
+__host__ __device__ inline int row_stride(int nd) { return nd | 1; }
+
+// one data buffer: rows -2 .. ne+ce-1 (rows -2, -1, ne, ne+1 zero)
+__host__ __device__ inline size_t buf_bytes(int nd, int ne, int ce, size_t szT)
 {
-  return align16(8 * (size_t)nd * szT + (size_t)nd * 4 + (size_t)(nd + 1) * 4 + 4 * (size_t)nd * 4);
+  return align16((size_t)(ne + ce + 2) * row_stride(nd) * szT);
 }
 
-// bytes of the table-build scratch (counts, cursors, record targets, weights)
-__host__ __device__ inline size_t scratch_bytes(int nd)
+// table-build scratch for one round of 4 tables
+__host__ __device__ inline size_t scratch_bytes(int nd, size_t szT)
 {
-  return align16((size_t)kTables * nd * 4 * 6) + (size_t)kTables * nd * 4 * 8;
+  return (size_t)4 * nd * 4 * 2 + (size_t)16 * nd * 4 + (size_t)32 * nd * szT;
 }
 
-__host__ __device__ inline size_t data_bytes(int nd, int ne, size_t szT)
+__host__ __device__ inline size_t data_bytes(int nd, int ne, int ce, size_t szT)
 {
-  size_t b = 4 * align16((size_t)nd * ne * szT), sc = scratch_bytes(nd);
-  return b > sc ? b : sc;
+  return 3 * buf_bytes(nd, ne, ce, szT);
+}
+
+// small per-face arrays: G, 1/G, frame weights (5 frames), 4 speeds, interface
+// opacities (3), angle averages, reduction scratch
+__host__ __device__ inline size_t small_bytes(int nd, int ne)
+{
+  return 2 * align16(ne * 8) + 5 * align16(nd * 8) + 4 * align16(nd * 8) + 4 * align16(ne * 8) +
+         align16(32 * 8) + align16(5 * sizeof(Frame));
 }
 
 // ascending node bracket with edge clamping (all weight to the edge node)
@@ -228,41 +249,31 @@ __device__ inline void node_bracket(const double *x, int n, double v, int &L, in
   wR = (v - x[l]) / (x[l + 1] - x[l]);
 }
 
-// One source direction of one table: chain, brackets, records.
-// Writes the source info into the table and up to 4 (target, weight) records.
-template <typename T>
-__device__ int build_source(const DevGrid &g, const Frame &S, const Frame &D, int axis, bool rot,
-                            bool ident, int d, Tab<T> &tb, int *rt, double *rc)
+// One source direction of one remap: frame chain, energy shift and taps,
+// (mu, Phi) corners.  rt[4] receive the targets (-1 unused), rl/rr the tap
+// weights times the corner weight.
+__device__ void remap_source(const DevGrid &g, const Frame &S, const Frame &D, int axis, bool rot,
+                             bool ident, int d, int rt[4], double rl[4], double rr[4], int &di_out)
 {
   const double *n = g.nvec + 3 * d;
-  double aS = pow(S.psi, 6.0) * u0_dir(S, n) * g.dOm[d];
-  double aD = pow(D.psi, 6.0) * u0_dir(D, n) * g.dOm[d];
-  tb.aS[d] = (T)aS;
-  tb.iaD[d] = (T)(1.0 / aD);
+  rt[1] = rt[2] = rt[3] = -1;
+  rl[1] = rl[2] = rl[3] = rr[1] = rr[2] = rr[3] = 0.0;
   if (ident) {
-    tb.di[d] = 0;
-    tb.tl[d] = (T)1.0;
-    tb.tr[d] = (T)0.0;
-    rt[0] = d; rc[0] = 1.0;
-    rt[1] = rt[2] = rt[3] = -1;
-    rc[1] = rc[2] = rc[3] = 0.0;
-    return 4;
+    di_out = 0;
+    rt[0] = d; rl[0] = 1.0; rr[0] = 0.0;
+    return;
   }
   double u[4] = { 1.0, n[0], n[1], n[2] }, o[4];
   frame_chain(S, D, axis, rot, u, o);
-  // energy: eps* = rho eps_i with rho = o[0]; log groups -> one shift for all i
+  // energy: eps* = rho eps_i; logarithmic groups -> one shift for every i
   double rho = o[0];
-  double x = log(rho) / g.lnq;
-  int di = (int)floor(x);
+  int di = (int)floor(log(rho) / g.lnq);
   double we = (rho * exp(-di * g.lnq) - 1.0) / (g.q - 1.0);
-  if (we < 0.0) we = 0.0;
-  if (we > 1.0) we = 1.0;
-  tb.di[d] = di;
-  tb.tl[d] = (T)(1.0 - we);
-  tb.tr[d] = (T)we;
+  we = fmin(1.0, fmax(0.0, we));
+  di = max(-127, min(127, di));
+  di_out = di;
   // direction
-  double mus = o[1] / o[0];
-  mus = fmin(1.0, fmax(-1.0, mus));
+  double mus = fmin(1.0, fmax(-1.0, o[1] / o[0]));
   int jL, jR;
   double wj;
   node_bracket(g.mu, g.nmu, mus, jL, jR, wj);
@@ -290,69 +301,91 @@ __device__ int build_source(const DevGrid &g, const Frame &S, const Frame &D, in
     kL = ((kl % g.nphi) + g.nphi) % g.nphi;
     kR = (((kl + 1) % g.nphi) + g.nphi) % g.nphi;
   }
-  // the four (mu, Phi) corners; coinciding brackets (clamped or one Phi bin)
-  // are merged so that every record has a distinct target
+  // coinciding brackets (clamped or a single Phi bin) are merged so that the
+  // four records of a source have distinct targets
   const bool oneJ = jL == jR, oneK = kL == kR;
   const double wj0 = oneJ ? 1.0 : 1.0 - wj, wj1 = oneJ ? 0.0 : wj;
   const double wk0 = oneK ? 1.0 : 1.0 - wk, wk1 = oneK ? 0.0 : wk;
-  double c00 = wj0 * wk0, c01 = wj0 * wk1, c10 = wj1 * wk0, c11 = wj1 * wk1;
-  rt[0] = c00 != 0.0 ? jL * g.nphi + kL : -1; rc[0] = c00;
-  rt[1] = c01 != 0.0 ? jL * g.nphi + kR : -1; rc[1] = c01;
-  rt[2] = c10 != 0.0 ? jR * g.nphi + kL : -1; rc[2] = c10;
-  rt[3] = c11 != 0.0 ? jR * g.nphi + kR : -1; rc[3] = c11;
-  return 4;
+  const double c[4] = { wj0 * wk0, wj0 * wk1, wj1 * wk0, wj1 * wk1 };
+  const int tg[4] = { jL * g.nphi + kL, jL * g.nphi + kR, jR * g.nphi + kL, jR * g.nphi + kR };
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    // corner weights at rounding level (a direction that lands on a node up
+    // to the last bit) are dropped: they move less than 1e-15 of a bin
+    rt[r] = c[r] > 1e-15 ? tg[r] : -1;
+    rl[r] = c[r] * (1.0 - we);
+    rr[r] = c[r] * we;
+  }
 }
 
-// Gather of one remap for target direction dp and groups i0..i0+kEC-1.
-// Density tables: X holds occupation x G_i and the result is an occupation;
-// content tables: X holds content and the result is content.
-template <typename T>
-__device__ void gather(const DevGrid &g, const Tab<T> &tb, const T *X, bool dens, int dp, int i0,
-                       const double *Gs, T out[kEC])
+// One gather-list entry (source column, energy shift, two tap weights) added
+// into the groups i0 .. i0+CE-1 of a target.  X points at row 0 of a buffer
+// with row stride rs whose rows -2, -1, ne, ne+1 are zero.
+template <typename T, int CE>
+__device__ __forceinline__ void entry_acc(const T *__restrict__ X, int rs, int ne, int i0, unsigned key,
+                                          T cl, T cr, bool low, bool top, int kt, T acc[CE])
 {
-  const int ne = g.ne, nd = g.ndir;
-  T acc[kEC];
+  const int d = key & 0xff, di = (int)(key >> 8) - 128;
+  const T *col = X + d;
+  if (di >= -1 && di <= 1) {
+    const T *base = col + (i0 - di - 1) * rs;
+    T x[CE + 1];
 #pragma unroll
-  for (int k = 0; k < kEC; ++k) acc[k] = (T)0;
-  const int e0 = tb.start[dp], e1 = tb.start[dp + 1];
-  const bool low = (i0 == 0), top = (ne - 1 < i0 + kEC);
-  const int kt = ne - 1 - i0;
-  for (int e = e0; e < e1; ++e) {
-    const int d = tb.src[e];
-    T c = tb.c[e];
-    if (dens) c *= tb.aS[d];
-    const int di = tb.di[d];
-    const T tl = tb.tl[d] * c, tr = tb.tr[d] * c;
-    const T *col = X + d;
+    for (int k = 0; k <= CE; ++k) x[k] = base[k * rs];
 #pragma unroll
-    for (int k = 0; k < kEC; ++k) {
-      int i = i0 + k;
-      if (i >= ne) break;
-      int iL = i - di, iR = iL - 1;
+    for (int k = 0; k < CE; ++k) acc[k] += cl * x[k + 1] + cr * x[k];
+    // sources pushed beyond the lowest / highest group stay in it
+    if (low && di < 0) acc[0] += cl * col[0];
+    if (top && di >= 0) {
+      T x1 = col[(ne - 1) * rs];
+      T v = di == 0 ? cr * x1 : cl * x1 + cr * (x1 + col[(ne - 2) * rs]);
+#pragma unroll
+      for (int k = 0; k < CE; ++k)
+        if (k == kt) acc[k] += v;
+    }
+  } else {                                           // shifts of two or more groups
+#pragma unroll
+    for (int k = 0; k < CE; ++k) {
+      int iL = i0 + k - di, iR = iL - 1;
       T v = (T)0;
-      if (iL >= 0 && iL < ne) v += tl * col[iL * nd];
-      if (iR >= 0 && iR < ne) v += tr * col[iR * nd];
+      if (iL >= 0 && iL < ne) v += cl * col[iL * rs];
+      if (iR >= 0 && iR < ne) v += cr * col[iR * rs];
       acc[k] += v;
     }
-    if (low) {                                       // sources pushed below the lowest group
-      for (int i = 0; i < ne && i + di < 0; ++i) acc[0] += tl * col[i * nd];
-      for (int i = 0; i < ne && i + di + 1 < 0; ++i) acc[0] += tr * col[i * nd];
+    if (low && di < 0) {
+      for (int i = 0; i < ne && i < -di; ++i) acc[0] += cl * col[i * rs];
+      for (int i = 0; i < ne && i < -di - 1; ++i) acc[0] += cr * col[i * rs];
     }
-    if (top) {                                       // sources pushed above the highest group
+    if (top && di >= 0) {
       T v = (T)0;
-      for (int i = max(0, ne - di); i < ne; ++i) v += tl * col[i * nd];
-      for (int i = max(0, ne - 1 - di); i < ne; ++i) v += tr * col[i * nd];
+      for (int i = max(0, ne - di); i < ne; ++i) v += cl * col[i * rs];
+      for (int i = max(0, ne - 1 - di); i < ne; ++i) v += cr * col[i * rs];
 #pragma unroll
-      for (int k = 0; k < kEC; ++k)
+      for (int k = 0; k < CE; ++k)
         if (k == kt) acc[k] += v;
     }
   }
-#pragma unroll
-  for (int k = 0; k < kEC; ++k) {
-    int i = i0 + k;
-    if (dens && i < ne) out[k] = (T)((double)acc[k] * (double)tb.iaD[dp] / Gs[i]);
-    else out[k] = acc[k];
+}
+
+// Gather of one remap for target direction dp and groups i0 .. i0+CE-1 into acc
+// (accumulates), two entries per iteration.  X points at row 0 of a buffer
+// whose rows -2, -1, ne, ne+1 are zero.
+template <typename T, int CE>
+__device__ __forceinline__ void gather_acc(const Tab<T> &tb, const T *__restrict__ X, int rs, int ne,
+                                           int dp, int i0, T acc[CE])
+{
+  const int e0 = tb.start[dp], e1 = tb.start[dp + 1];
+  const bool low = i0 == 0;
+  const int kt = ne - 1 - i0;
+  const bool top = kt < CE;
+  int e = e0;
+  for (; e + 1 < e1; e += 2) {
+    const unsigned k0 = tb.key[e], k1 = tb.key[e + 1];
+    const T a0 = tb.coef[2 * e], b0 = tb.coef[2 * e + 1], a1 = tb.coef[2 * e + 2], b1 = tb.coef[2 * e + 3];
+    entry_acc<T, CE>(X, rs, ne, i0, k0, a0, b0, low, top, kt, acc);
+    entry_acc<T, CE>(X, rs, ne, i0, k1, a1, b1, low, top, kt, acc);
   }
+  if (e < e1) entry_acc<T, CE>(X, rs, ne, i0, tb.key[e], tb.coef[2 * e], tb.coef[2 * e + 1], low, top, kt, acc);
 }
 
 template <typename T>
@@ -364,276 +397,396 @@ __device__ inline T mc_limiter(T dm, T dp)
   return (T)0;
 }
 
-// one side's data of species s, scaled by the shell volume G_i, into LDS
-template <typename T>
-__device__ void load_side(const DevGrid &g, const SideDesc &sd, const T *f, const T *feq, int s,
-                          const double *Gs, T *dst)
-{
-  const int nd = g.ndir, n = g.eblk;
-  const T *src = f + (size_t)sd.z * g.blk + (size_t)s * n;
-  for (int q = threadIdx.x; q < n; q += blockDim.x) {
-    int i = q / nd, d = q - i * nd;
-    T v;
-    if (sd.kind == btx::SIDE_ZONE) v = src[q];
-    else if (sd.kind == btx::SIDE_MIRROR) {
-      int j = d / g.nphi, k = d - j * g.nphi;
-      v = src[i * nd + (g.nmu - 1 - j) * g.nphi + k];
-    } else if (sd.kind == btx::SIDE_EQ) v = feq[((size_t)sd.z * g.ns + s) * g.ne + i];
-    else v = (T)0;
-    dst[q] = (T)((double)v * Gs[i]);
-  }
-}
-
 __device__ inline double wave_sum(double v)
 {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-// ------------------------------------------------------------ face kernel
+// column dp of one side's species-s data as content density x G_i aS(dp),
+// rows i = ch, ch + nch, ...; guard rows are zeroed by the caller
+template <typename T>
+__device__ inline void load_column(const DevGrid &g, const SideDesc &sd, const T *__restrict__ f,
+                                   const T *__restrict__ feq, int s, const double *Gs, double aS,
+                                   int dp, int ch, int nch, T *X)
+{
+  const int nd = g.ndir, ne = g.ne, rs = row_stride(nd);
+  const T *src = f + (size_t)sd.z * g.blk + (size_t)s * g.eblk;
+  int sd_col = dp;
+  if (sd.kind == btx::SIDE_MIRROR) {
+    int j = dp / g.nphi, k = dp - j * g.nphi;
+    sd_col = (g.nmu - 1 - j) * g.nphi + k;
+  }
+  for (int i = ch; i < ne; i += nch) {
+    double v;
+    if (sd.kind == btx::SIDE_ZONE || sd.kind == btx::SIDE_MIRROR) v = (double)src[i * nd + sd_col];
+    else if (sd.kind == btx::SIDE_EQ) v = (double)feq[((size_t)sd.z * g.ns + s) * ne + i];
+    else v = 0.0;
+    X[i * rs + dp] = (T)(v * Gs[i] * aS);
+  }
+}
 
 template <typename T>
-__global__ void __launch_bounds__(kMaxFaceThreads)
-face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const T *__restrict__ f,
-            const T *__restrict__ ka, const T *__restrict__ ks, const T *__restrict__ feq,
-            T *__restrict__ dN, double *__restrict__ tally, double dt, int face0)
+__device__ inline void zero_guards(T *X, int nd, int ne, int tid, int nthr)
+{
+  const int rs = row_stride(nd);
+  for (int q = tid; q < 4 * nd; q += nthr) {
+    int r = q / nd, d = q - r * nd;
+    int row = r < 2 ? r - 2 : ne + (r - 2);
+    X[row * rs + d] = (T)0;
+  }
+}
+
+// ------------------------------------------------------------ table kernel
+
+// Builds the eight remap tables of one face (frame chain once per direction,
+// inverted into sorted per-target gather lists) and stores them in global
+// memory; run once per background.
+// table t: 0 Lm->L, 1 R->L, 2 L->R, 3 Rp->R, 4 L->s, 5 R->s, 6 s->L, 7 s->R
+template <typename T>
+__global__ void __launch_bounds__(256)
+table_kernel(DevGrid g, const FaceDesc *__restrict__ faces, char *__restrict__ tabs_g,
+             FaceAux *__restrict__ aux, int face0)
 {
   extern __shared__ __align__(16) char lds[];
   const int fid = face0 + blockIdx.x;
   const FaceDesc &F = faces[fid];
-  const int nd = g.ndir, ne = g.ne, n = g.eblk, tid = threadIdx.x;
+  const int nd = g.ndir, tid = threadIdx.x, nthr = blockDim.x;
+  const size_t tstride = tab_stride(nd, sizeof(T));
+  char *p = lds;
+  char *tabs = p;              p += kTables * tstride;
+  Frame *frm = (Frame *)p;     p += align16(5 * sizeof(Frame));
+  char *data = p;
+  int *cnt = (int *)data;                      // 4 nd
+  int *cur = cnt + 4 * nd;                     // 4 nd
+  int *rtg = cur + 4 * nd;                     // 16 nd
+  T *rcf = (T *)(rtg + 16 * nd);               // 32 nd
+#define TB(t) tab_at<T>(tabs + (t) * tstride, nd)
+  if (tid == 0) {
+    Frame a = side_frame(g, F.L), b = side_frame(g, F.R);
+    frm[0] = side_frame(g, F.Lm);
+    frm[1] = a;
+    frm[2] = b;
+    frm[3] = side_frame(g, F.Rp);
+    Frame fs_;
+    double vl[3], vr[3];
+    change_basis(a.th, a.ph, F.ths, F.phs, a.v, vl);
+    change_basis(b.th, b.ph, F.ths, F.phs, b.v, vr);
+    for (int i = 0; i < 3; ++i) fs_.v[i] = 0.5 * (vl[i] + vr[i]);
+    fs_.alpha = 0.5 * (a.alpha + b.alpha);
+    fs_.psi = 0.5 * (a.psi + b.psi);
+    fs_.th = F.ths;
+    fs_.ph = F.phs;
+    frm[4] = fs_;
+  }
+  const bool rot = g.geom != 2;
+  const int ax = F.axis;
+  // table t: 0 Lm->L, 1 R->L, 2 L->R, 3 Rp->R, 4 L->s, 5 R->s, 6 s->L, 7 s->R
+  for (int round = 0; round < 2; ++round) {
+    __syncthreads();
+    for (int q = tid; q < 4 * nd; q += nthr) cnt[q] = 0;
+    __syncthreads();
+    for (int q = tid; q < 4 * nd; q += nthr) {
+      int tl = q / nd, d = q - tl * nd, t = 4 * round + tl;
+      const int si = t == 0 ? 0 : (t == 1 || t == 5) ? 2 : (t == 2 || t == 4) ? 1 : t == 3 ? 3 : 4;
+      const int di_ = (t == 0 || t == 1 || t == 6) ? 1 : (t == 2 || t == 3 || t == 7) ? 2 : 4;
+      const Frame S = frm[si], D = frm[di_];
+      int rt[4], di;
+      double rl[4], rr[4];
+      remap_source(g, S, D, ax, rot, same_frame(S, D), d, rt, rl, rr, di);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        rtg[q * 4 + r] = rt[r] >= 0 ? (rt[r] | ((di + 128) << 16)) : -1;
+        rcf[(q * 4 + r) * 2] = (T)rl[r];
+        rcf[(q * 4 + r) * 2 + 1] = (T)rr[r];
+        if (rt[r] >= 0) atomicAdd(&cnt[tl * nd + rt[r]], 1);
+      }
+    }
+    __syncthreads();
+    if (tid < 4) {                                     // exclusive scan per table
+      Tab<T> tt = TB(4 * round + tid);
+      int acc = 0;
+      for (int d = 0; d < nd; ++d) {
+        tt.start[d] = (unsigned short)acc;
+        cur[tid * nd + d] = acc;
+        acc += cnt[tid * nd + d];
+      }
+      tt.start[nd] = (unsigned short)acc;
+    }
+    __syncthreads();
+    for (int q = tid; q < 4 * nd; q += nthr) {         // records into their target lists
+      int tl = q / nd, d = q - tl * nd;
+      Tab<T> tt = TB(4 * round + tl);
+      for (int r = 0; r < 4; ++r) {
+        int v = rtg[q * 4 + r];
+        if (v < 0) continue;
+        int tg = v & 0xffff, dib = v >> 16;
+        int slot = atomicAdd(&cur[tl * nd + tg], 1);
+        tt.key[slot] = (unsigned short)(d | (dib << 8));
+        tt.coef[2 * slot] = rcf[(q * 4 + r) * 2];
+        tt.coef[2 * slot + 1] = rcf[(q * 4 + r) * 2 + 1];
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < 4 * nd; q += nthr) {         // fixed summation order: sort by key
+      int tl = q / nd, d = q - tl * nd;
+      Tab<T> tt = TB(4 * round + tl);
+      int a = tt.start[d], b = tt.start[d + 1];
+      for (int x = a + 1; x < b; ++x) {
+        unsigned short kx = tt.key[x];
+        T c0 = tt.coef[2 * x], c1 = tt.coef[2 * x + 1];
+        int y = x - 1;
+        while (y >= a && tt.key[y] > kx) {
+          tt.key[y + 1] = tt.key[y];
+          tt.coef[2 * y + 2] = tt.coef[2 * y];
+          tt.coef[2 * y + 3] = tt.coef[2 * y + 1];
+          --y;
+        }
+        tt.key[y + 1] = kx;
+        tt.coef[2 * y + 2] = c0;
+        tt.coef[2 * y + 3] = c1;
+      }
+    }
+  }
+  __syncthreads();
+
+  if (tid == 0) {
+    FaceAux A;
+    for (int k = 0; k < 5; ++k) {
+      const Frame &fr = frm[k];
+      for (int i = 0; i < 3; ++i) A.v[k][i] = fr.v[i];
+      A.alpha[k] = fr.alpha;
+      A.psi[k] = fr.psi;
+      A.gam[k] = 1.0 / sqrt(1.0 - (fr.v[0] * fr.v[0] + fr.v[1] * fr.v[1] + fr.v[2] * fr.v[2]));
+      A.p6[k] = pow(fr.psi, 6.0);
+    }
+    for (int side = 0; side < 2; ++side) {
+      const Frame &fr = frm[1 + side];
+      for (int c = 0; c < 3; ++c) {
+        double e[3] = { c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, c == 2 ? 1.0 : 0.0 }, y[3];
+        if (rot) change_basis(fr.th, fr.ph, F.ths, F.phs, e, y);
+        else { y[0] = e[0]; y[1] = e[1]; y[2] = e[2]; }
+        for (int r = 0; r < 3; ++r) A.M[side][3 * r + c] = y[r];
+      }
+    }
+    aux[fid] = A;
+  }
+  __syncthreads();
+  uint4 *dst = (uint4 *)(tabs_g + (size_t)fid * kTables * tstride);
+  const uint4 *src = (const uint4 *)tabs;
+  const int n16 = (int)(kTables * tstride / 16);
+  for (int q = tid; q < n16; q += nthr) dst[q] = src[q];
+#undef TB
+}
+
+// ------------------------------------------------------------ face kernel
+
+template <typename T, int CE>
+__global__ void __launch_bounds__(kMaxFaceThreads)
+face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restrict__ tabs_g,
+            const FaceAux *__restrict__ aux,
+            const T *__restrict__ f, const T *__restrict__ ka, const T *__restrict__ ks,
+            const T *__restrict__ feq, T *__restrict__ dN, double *__restrict__ tally, double dt,
+            int face0)
+{
+  extern __shared__ __align__(16) char lds[];
+  const int fid = face0 + blockIdx.x;
+  const FaceDesc &F = faces[fid];
+  const int nd = g.ndir, ne = g.ne, tid = threadIdx.x, nthr = blockDim.x;
   T *outL = dN + (size_t)fid * 2 * g.blk, *outR = outL + g.blk;
   if (!F.active) {
-    for (int q = tid; q < 2 * g.blk; q += blockDim.x) outL[q] = (T)0;
+    for (size_t q = tid; q < 2 * (size_t)g.blk; q += nthr) outL[q] = (T)0;
     return;
   }
   // ---- LDS carve-up
   const size_t tstride = tab_stride(nd, sizeof(T));
   char *p = lds;
-  char *tabs = p;            p += kTables * tstride;
-  T *buf[4];
-  char *data = p;
-  for (int b = 0; b < 4; ++b) buf[b] = (T *)(data + b * align16((size_t)n * sizeof(T)));
-  p += data_bytes(nd, ne, sizeof(T));
-  double *Gs = (double *)p;  p += align16(ne * sizeof(double));
-  double *Urad = (double *)p; p += align16(nd * sizeof(double));
-  double *Vn = (double *)p;  p += align16(nd * sizeof(double));
-  double *UL = (double *)p;  p += align16(nd * sizeof(double));
-  double *UR = (double *)p;  p += align16(nd * sizeof(double));
-  double *sav = (double *)p; p += align16(ne * sizeof(double));
-  double *red = (double *)p; p += align16(32 * sizeof(double));
-  // scratch for the table build lives in the data buffers
-  int *cnt = (int *)data;                            // kTables * nd
-  int *cur = cnt + kTables * nd;                     // kTables * nd
-  int *rtg = cur + kTables * nd;                     // kTables * nd * 4
-  double *rcw = (double *)(data + align16((size_t)kTables * nd * 4 * 6));
+  char *tabs = p;              p += kTables * tstride;
+  char *data = p;              p += data_bytes(nd, ne, CE, sizeof(T));
+  const size_t bb = buf_bytes(nd, ne, CE, sizeof(T));
+  const int rs = row_stride(nd);
+  T *X0 = (T *)(data) + 2 * rs, *X1 = (T *)(data + bb) + 2 * rs, *X2 = (T *)(data + 2 * bb) + 2 * rs;
+  double *Gs = (double *)p;    p += align16(ne * 8);
+  double *iG = (double *)p;    p += align16(ne * 8);
+  double *aF = (double *)p;    p += 5 * align16(nd * 8);   // frames Lm, L, R, Rp, s
+  double *Urad = (double *)p;  p += align16(nd * 8);
+  double *Vn = (double *)p;    p += align16(nd * 8);
+  double *UL = (double *)p;    p += align16(nd * 8);
+  double *UR = (double *)p;    p += align16(nd * 8);
+  double *kas = (double *)p;   p += align16(ne * 8);
+  double *kss = (double *)p;   p += align16(ne * 8);
+  double *fes = (double *)p;   p += align16(ne * 8);
+  double *sav = (double *)p;   p += align16(ne * 8);
+  double *red = (double *)p;   p += align16(32 * 8);
+  const size_t nda = align16(nd * 8) / 8;
 
 #define TB(t) tab_at<T>(tabs + (t) * tstride, nd)
 
-  // ---- frames: L, R, interface (mean, velocities in the interface basis), slope neighbours
-  const Frame fL = side_frame(g, F.L), fR = side_frame(g, F.R);
-  const Frame fLm = side_frame(g, F.Lm), fRp = side_frame(g, F.Rp);
-  Frame fs;
-  {
-    double vl[3], vr[3];
-    change_basis(fL.th, fL.ph, F.ths, F.phs, fL.v, vl);
-    change_basis(fR.th, fR.ph, F.ths, F.phs, fR.v, vr);
-    for (int i = 0; i < 3; ++i) fs.v[i] = 0.5 * (vl[i] + vr[i]);
-    fs.alpha = 0.5 * (fL.alpha + fR.alpha);
-    fs.psi = 0.5 * (fL.psi + fR.psi);
-    fs.th = F.ths;
-    fs.ph = F.phs;
-  }
-  const bool rot = g.geom != 2;
+  // ---- frame data of this face (precomputed once per background)
+  const FaceAux &A = aux[fid];
+  for (int i = tid; i < ne; i += nthr) { Gs[i] = g.G[i]; iG[i] = 1.0 / g.G[i]; }
   const int ax = F.axis;
   const bool slopeL = F.L.slope, slopeR = F.R.slope && !F.self;
-  // table t: 0 Lm->L, 1 R->L, 2 L->R, 3 Rp->R, 4 L->s, 5 R->s, 6 s->L, 7 s->R
-
-  for (int q = tid; q < kTables * nd; q += blockDim.x) cnt[q] = 0;
-  for (int i = tid; i < ne; i += blockDim.x) Gs[i] = g.G[i];
-  __syncthreads();
-  // pass 1: chain per (table, source direction), records, counts
-  for (int q = tid; q < kTables * nd; q += blockDim.x) {
-    int t = q / nd, d = q - t * nd;
-    int rt[4];
-    double rw[4];
-    const Frame &S = t == 0 ? fLm : (t == 1 || t == 5) ? fR : (t == 2 || t == 4) ? fL : t == 3 ? fRp : fs;
-    const Frame &D = (t == 0 || t == 1 || t == 6) ? fL : (t == 2 || t == 3 || t == 7) ? fR : fs;
-    Tab<T> tt = TB(t);
-    int nr = build_source<T>(g, S, D, ax, rot, same_frame(S, D), d, tt, rt, rw);
-    (void)nr;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      rtg[q * 4 + r] = rt[r];
-      rcw[q * 4 + r] = rw[r];
-      if (rt[r] >= 0) atomicAdd(&cnt[t * nd + rt[r]], 1);
-    }
-  }
-  // interface speeds of each bin (flux integral, zero shift): U = alpha psi^4 uhat^n
-  const double gs = 1.0 / sqrt(1.0 - (fs.v[0] * fs.v[0] + fs.v[1] * fs.v[1] + fs.v[2] * fs.v[2]));
-  const double kvs = gs * gs / (gs + 1.0);
-  const double ap4 = fs.alpha * dsq(fs.psi * fs.psi);
-  const double vn = fs.v[ax];
+  const double gs = A.gam[4];
+  const double ap4 = A.alpha[4] * dsq(A.psi[4] * A.psi[4]);
+  const double vn = A.v[4][ax];
   const double Uadv = ap4 * gs * vn;
-  for (int d = tid; d < nd; d += blockDim.x) {
+  const double tau = 0.5 * A.alpha[4] * dt / gs;
+  // per-direction frame weights psi^6 u0 dOmega and interface speeds
+  for (int q = tid; q < 6 * nd; q += nthr) {
+    int kind = q / nd, d = q - kind * nd;
     const double *nv = g.nvec + 3 * d;
-    double vdn = fs.v[0] * nv[0] + fs.v[1] * nv[1] + fs.v[2] * nv[2];
-    double u0 = gs * (1.0 + vdn);
-    double un = nv[ax] + (kvs * vdn + gs) * vn;
-    Urad[d] = ap4 * (nv[ax] + kvs * vdn * vn);
-    Vn[d] = fs.alpha * un / (fs.psi * fs.psi * u0);
-    // donor speeds: the side's own comoving direction, in the interface basis
-    double u[4] = { 1.0, nv[0], nv[1], nv[2] }, e[4], y[3];
-    lorentz(fL.v, u, e);
-    if (rot) change_basis(fL.th, fL.ph, fs.th, fs.ph, e + 1, y); else { y[0] = e[1]; y[1] = e[2]; y[2] = e[3]; }
-    UL[d] = ap4 * y[ax];
-    lorentz(fR.v, u, e);
-    if (rot) change_basis(fR.th, fR.ph, fs.th, fs.ph, e + 1, y); else { y[0] = e[1]; y[1] = e[2]; y[2] = e[3]; }
-    UR[d] = ap4 * y[ax];
-  }
-  __syncthreads();
-  // pass 2: exclusive scan of the counts (one thread per table)
-  if (tid < kTables) {
-    Tab<T> tt = TB(tid);
-    int acc = 0;
-    for (int d = 0; d < nd; ++d) {
-      tt.start[d] = acc;
-      cur[tid * nd + d] = acc;
-      acc += cnt[tid * nd + d];
-    }
-    tt.start[nd] = acc;
-  }
-  __syncthreads();
-  // pass 3: scatter records into their target lists
-  for (int q = tid; q < kTables * nd; q += blockDim.x) {
-    int t = q / nd, d = q - t * nd;
-    Tab<T> tt = TB(t);
-    for (int r = 0; r < 4; ++r) {
-      int tg = rtg[q * 4 + r];
-      if (tg < 0) continue;
-      int slot = atomicAdd(&cur[t * nd + tg], 1);
-      tt.src[slot] = d;
-      tt.c[slot] = (T)rcw[q * 4 + r];
-    }
-  }
-  __syncthreads();
-  // pass 4: sort each list by source so that the summation order is fixed
-  for (int q = tid; q < kTables * nd; q += blockDim.x) {
-    int t = q / nd, d = q - t * nd;
-    Tab<T> tt = TB(t);
-    int a = tt.start[d], b = tt.start[d + 1];
-    for (int x = a + 1; x < b; ++x) {
-      int ks_ = tt.src[x];
-      T kc = tt.c[x];
-      int y = x - 1;
-      while (y >= a && tt.src[y] > ks_) {
-        tt.src[y + 1] = tt.src[y];
-        tt.c[y + 1] = tt.c[y];
-        --y;
+    if (kind < 5) {
+      double vdn = A.v[kind][0] * nv[0] + A.v[kind][1] * nv[1] + A.v[kind][2] * nv[2];
+      aF[kind * nda + d] = A.p6[kind] * A.gam[kind] * (1.0 + vdn) * g.dOm[d];
+    } else {
+      const double kvs = gs * gs / (gs + 1.0);
+      double vdn = A.v[4][0] * nv[0] + A.v[4][1] * nv[1] + A.v[4][2] * nv[2];
+      double u0 = gs * (1.0 + vdn);
+      double un = nv[ax] + (kvs * vdn + gs) * vn;
+      Urad[d] = ap4 * (nv[ax] + kvs * vdn * vn);
+      Vn[d] = A.alpha[4] * un / (A.psi[4] * A.psi[4] * u0);
+      // donor speeds: each side's own comoving direction, in the interface basis
+      for (int side = 0; side < 2; ++side) {
+        const double *v = A.v[1 + side];
+        double gm = A.gam[1 + side], kv = gm * gm / (gm + 1.0);
+        double vu = v[0] * nv[0] + v[1] * nv[1] + v[2] * nv[2];
+        double a_ = kv * vu + gm;
+        double e0 = nv[0] + a_ * v[0], e1 = nv[1] + a_ * v[1], e2 = nv[2] + a_ * v[2];
+        const double *M = A.M[side];
+        double y = M[3 * ax] * e0 + M[3 * ax + 1] * e1 + M[3 * ax + 2] * e2;
+        (side ? UR : UL)[d] = ap4 * y;
       }
-      tt.src[y + 1] = ks_;
-      tt.c[y + 1] = kc;
     }
+  }
+
+  // ---- remap tables of this face (built once per background by table_kernel)
+  {
+    const uint4 *src = (const uint4 *)(tabs_g + (size_t)fid * kTables * tstride);
+    uint4 *dst = (uint4 *)tabs;
+    const int n16 = (int)(kTables * tstride / 16);
+    for (int q = tid; q < n16; q += nthr) dst[q] = src[q];
   }
   __syncthreads();
 
   // ---- per species
-  const int nitems = nd * g.nch;
+  const int nch = g.nch;
+  const int nitems = nd * nch;
   const bool own = tid < nitems;
-  const int dp = own ? tid % nd : 0;
-  const int i0 = own ? (tid / nd) * kEC : 0;
+  const int dp = own ? tid / nch : 0;                 // neighbouring lanes share a target list
+  const int ch = own ? tid - dp * nch : 0;
+  const int i0 = ch * CE;
   const double cA = dt * F.area;
-  const double tau = 0.5 * fs.alpha * dt / gs;
-  const int lane = tid & 63, wave = tid >> 6, nwaves = (blockDim.x + 63) >> 6;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = (nthr + 63) >> 6;
+  const double aLd = aF[1 * nda + dp], aRd = aF[2 * nda + dp], aSd = aF[4 * nda + dp];
+#pragma unroll 1
   for (int s = 0; s < g.ns; ++s) {
-    load_side<T>(g, F.Lm, f, feq, s, Gs, buf[0]);
-    load_side<T>(g, F.L, f, feq, s, Gs, buf[1]);
-    load_side<T>(g, F.R, f, feq, s, Gs, buf[2]);
-    load_side<T>(g, F.Rp, f, feq, s, Gs, buf[3]);
+    if (own) {
+      load_column<T>(g, F.L, f, feq, s, Gs, aLd, dp, ch, nch, X1);
+      load_column<T>(g, F.R, f, feq, s, Gs, aRd, dp, ch, nch, X2);
+      if (slopeL) load_column<T>(g, F.Lm, f, feq, s, Gs, aF[0 * nda + dp], dp, ch, nch, X0);
+    }
+    zero_guards<T>(X0, nd, ne, tid, nthr);
+    zero_guards<T>(X1, nd, ne, tid, nthr);
+    zero_guards<T>(X2, nd, ne, tid, nthr);
+    for (int i = tid; i < ne; i += nthr) {
+      double a_ = 0.0, b_ = 0.0, e_ = 0.0;
+      if (!F.zero_opacity) {
+        size_t l = ((size_t)F.L.z * g.ns + s) * ne + i, r = ((size_t)F.R.z * g.ns + s) * ne + i;
+        a_ = 0.5 * ((double)ka[l] + (double)ka[r]);
+        b_ = 0.5 * ((double)ks[l] + (double)ks[r]);
+        e_ = 0.5 * ((double)feq[l] + (double)feq[r]);
+      }
+      kas[i] = a_; kss[i] = b_; fes[i] = e_;
+    }
     __syncthreads();
     // phase 1: limited slopes and reconstructed donor values (own frames)
-    T EL[kEC], ER[kEC];
+    T fl[CE], fr[CE], sl[CE], EL[CE], ER[CE];
     if (own) {
-      T a[kEC], b[kEC];
-      T fl[kEC], fr[kEC], sl[kEC];
-      for (int k = 0; k < kEC; ++k) {
+#pragma unroll
+      for (int k = 0; k < CE; ++k) {
         int i = i0 + k;
-        fl[k] = i < ne ? (T)((double)buf[1][i * nd + dp] / Gs[i]) : (T)0;
-        fr[k] = i < ne ? (T)((double)buf[2][i * nd + dp] / Gs[i]) : (T)0;
+        bool in = i < ne;
+        fl[k] = in ? (T)((double)X1[i * rs + dp] * iG[i] / aLd) : (T)0;
+        fr[k] = in ? (T)((double)X2[i * rs + dp] * iG[i] / aRd) : (T)0;
         sl[k] = (T)0;
       }
       if (slopeL) {
-        gather<T>(g, TB(0), buf[0], true, dp, i0, Gs, a);
-        gather<T>(g, TB(1), buf[2], true, dp, i0, Gs, b);
-        for (int k = 0; k < kEC; ++k)
-          sl[k] = mc_limiter<T>((fl[k] - a[k]) / (T)F.hLm, (b[k] - fl[k]) / (T)F.h);
-      }
-      for (int k = 0; k < kEC; ++k) EL[k] = fl[k] + (T)F.dL * sl[k];
-      if (slopeR) {
-        gather<T>(g, TB(2), buf[1], true, dp, i0, Gs, a);
-        gather<T>(g, TB(3), buf[3], true, dp, i0, Gs, b);
-        for (int k = 0; k < kEC; ++k)
-          ER[k] = fr[k] + (T)F.dR * mc_limiter<T>((fr[k] - a[k]) / (T)F.h, (b[k] - fr[k]) / (T)F.hRp);
-      } else if (F.self) {
-        for (int k = 0; k < kEC; ++k) ER[k] = fr[k] + (T)F.dR * sl[k];
-      } else {
-        for (int k = 0; k < kEC; ++k) ER[k] = fr[k];
-      }
-    }
-    __syncthreads();                                   // Lm and Rp data no longer read
-    if (own) {
-      for (int k = 0; k < kEC; ++k) {
-        int i = i0 + k;
-        if (i < ne) {
-          buf[0][i * nd + dp] = (T)((double)EL[k] * Gs[i]);
-          buf[3][i * nd + dp] = (T)((double)ER[k] * Gs[i]);
+        T a[CE], b[CE];
+#pragma unroll
+        for (int k = 0; k < CE; ++k) a[k] = b[k] = (T)0;
+        gather_acc<T, CE>(TB(0), X0, rs, ne, dp, i0, a);
+        gather_acc<T, CE>(TB(1), X2, rs, ne, dp, i0, b);
+#pragma unroll
+        for (int k = 0; k < CE; ++k) {
+          int i = min(i0 + k, ne - 1);
+          T sc = (T)(iG[i] / aLd);
+          sl[k] = mc_limiter<T>((fl[k] - a[k] * sc) / (T)F.hLm, (b[k] * sc - fl[k]) / (T)F.h);
         }
       }
+#pragma unroll
+      for (int k = 0; k < CE; ++k) EL[k] = fl[k] + (T)F.dL * sl[k];
     }
-    // phase 2a: Lax-Wendroff half step source S in the interface frame
-    T Sv[kEC];
+    if (slopeR) {
+      __syncthreads();                                 // X0 (Lm) no longer read
+      if (own) load_column<T>(g, F.Rp, f, feq, s, Gs, aF[3 * nda + dp], dp, ch, nch, X0);
+      __syncthreads();
+      if (own) {
+        T a[CE], b[CE];
+#pragma unroll
+        for (int k = 0; k < CE; ++k) a[k] = b[k] = (T)0;
+        gather_acc<T, CE>(TB(2), X1, rs, ne, dp, i0, a);
+        gather_acc<T, CE>(TB(3), X0, rs, ne, dp, i0, b);
+#pragma unroll
+        for (int k = 0; k < CE; ++k) {
+          int i = min(i0 + k, ne - 1);
+          T sc = (T)(iG[i] / aRd);
+          ER[k] = fr[k] + (T)F.dR * mc_limiter<T>((fr[k] - a[k] * sc) / (T)F.h, (b[k] * sc - fr[k]) / (T)F.hRp);
+        }
+      }
+    } else if (own) {
+#pragma unroll
+      for (int k = 0; k < CE; ++k) ER[k] = F.self ? fr[k] + (T)F.dR * sl[k] : fr[k];
+    }
+    // phase 2a: Lax-Wendroff half-step source S in the interface frame
+    T Sv[CE];
     if (own) {
-      T A[kEC], B[kEC];
-      gather<T>(g, TB(4), buf[1], true, dp, i0, Gs, A);
-      gather<T>(g, TB(5), buf[2], true, dp, i0, Gs, B);
+      T A[CE], B[CE];
+#pragma unroll
+      for (int k = 0; k < CE; ++k) A[k] = B[k] = (T)0;
+      gather_acc<T, CE>(TB(4), X1, rs, ne, dp, i0, A);
+      gather_acc<T, CE>(TB(5), X2, rs, ne, dp, i0, B);
       const T cv = (T)(-0.5 * dt * Vn[dp] / F.h);
-      for (int k = 0; k < kEC; ++k) {
-        int i = i0 + k;
-        double kf = 0.0;
-        if (i < ne && !F.zero_opacity) {
-          size_t l = ((size_t)F.L.z * g.ns + s) * ne + i, r = ((size_t)F.R.z * g.ns + s) * ne + i;
-          kf = 0.5 * ((double)ka[l] + (double)ka[r]) * 0.5 * ((double)feq[l] + (double)feq[r]);
-        }
-        Sv[k] = (T)0.5 * (A[k] + B[k]) + cv * (B[k] - A[k]) + (T)(tau * kf);
+#pragma unroll
+      for (int k = 0; k < CE; ++k) {
+        int i = min(i0 + k, ne - 1);
+        T sc = (T)(iG[i] / aSd);
+        T a = A[k] * sc, b = B[k] * sc;
+        Sv[k] = (T)0.5 * (a + b) + cv * (b - a) + (T)(tau * kas[i] * fes[i]);
       }
     }
-    __syncthreads();                                   // all reads of L and R data done
+    __syncthreads();                                   // all reads of X0..X2 done
     if (own) {
-      for (int k = 0; k < kEC; ++k) {
-        int i = i0 + k;
-        if (i < ne) buf[2][i * nd + dp] = Sv[k];
-      }
+#pragma unroll
+      for (int k = 0; k < CE; ++k)
+        if (i0 + k < ne) X0[(i0 + k) * rs + dp] = Sv[k];
     }
     __syncthreads();
-    // angle integral <S> per group (FP64, fixed order)
-    for (int i = wave; i < ne; i += nwaves) {
+    for (int i = wave; i < ne; i += nwaves) {          // <S> per group, FP64, fixed order
       double acc = 0.0;
-      for (int d = lane; d < nd; d += 64) acc += (double)buf[2][i * nd + d] * g.dOm[d];
+      for (int d = lane; d < nd; d += 64) acc += (double)X0[i * rs + d] * g.dOm[d];
       acc = wave_sum(acc);
       if (lane == 0) sav[i] = acc / (4.0 * kPi);
     }
     __syncthreads();
-    // phase 2b: interface collision, blend weights, content fluxes
+    // phase 2b: interface collision, blend weights and content fluxes
     if (own) {
-      for (int k = 0; k < kEC; ++k) {
+      const double dO = g.dOm[dp];
+#pragma unroll
+      for (int k = 0; k < CE; ++k) {
         int i = i0 + k;
         if (i >= ne) break;
-        double ka_ = 0.0, ks_ = 0.0;
-        if (!F.zero_opacity) {
-          size_t l = ((size_t)F.L.z * g.ns + s) * ne + i, r = ((size_t)F.R.z * g.ns + s) * ne + i;
-          ka_ = 0.5 * ((double)ka[l] + (double)ka[r]);
-          ks_ = 0.5 * ((double)ks[l] + (double)ks[r]);
-        }
+        double ka_ = kas[i], ks_ = kss[i];
         double flw;
         if (sizeof(T) == 8 || tau * (ka_ + ks_) > g.fp64_thr) {
           flw = ((double)Sv[k] + tau * ks_ * sav[i] / (1.0 + tau * ka_)) / (1.0 + tau * (ka_ + ks_));
@@ -642,35 +795,41 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const T *__restrict__
           flw = ((float)Sv[k] + t * b * (float)sav[i] / (1.0f + t * a)) / (1.0f + t * (a + b));
         }
         double w = exp(-(ka_ + ks_) * F.h);
-        double gw = Gs[i] * g.dOm[dp] * cA;
-        buf[1][i * nd + dp] = (T)((1.0 - w) * Urad[dp] * flw * gw);
+        double gw = Gs[i] * dO * cA;
+        X1[i * rs + dp] = (T)((1.0 - w) * Urad[dp] * flw * gw);
         double eL = w * fmax(UL[dp], 0.0) + (1.0 - w) * fmax(Uadv, 0.0);
         double eR = w * fmax(-UR[dp], 0.0) + (1.0 - w) * fmax(-Uadv, 0.0);
-        buf[0][i * nd + dp] = (T)(eL * g.dOm[dp] * cA * (double)buf[0][i * nd + dp]);
-        buf[3][i * nd + dp] = (T)(eR * g.dOm[dp] * cA * (double)buf[3][i * nd + dp]);
+        X0[i * rs + dp] = (T)(eL * gw * (double)EL[k]);
+        X2[i * rs + dp] = (T)(eR * gw * (double)ER[k]);
       }
     }
     __syncthreads();
     // phase 3: content changes of both sides
     double sumL = 0.0, sumR = 0.0;
     if (own) {
-      T a[kEC], b[kEC], c2[kEC];
-      gather<T>(g, TB(6), buf[1], false, dp, i0, Gs, a);
-      gather<T>(g, TB(1), buf[3], false, dp, i0, Gs, b);
-      T *oL = outL + (size_t)s * n, *oR = outR + (size_t)s * n;
-      for (int k = 0; k < kEC; ++k) {
+      T a[CE], b[CE];
+#pragma unroll
+      for (int k = 0; k < CE; ++k) a[k] = b[k] = (T)0;
+      gather_acc<T, CE>(TB(6), X1, rs, ne, dp, i0, a);
+      gather_acc<T, CE>(TB(1), X2, rs, ne, dp, i0, b);
+      T *oL = outL + (size_t)s * g.eblk, *oR = outR + (size_t)s * g.eblk;
+#pragma unroll
+      for (int k = 0; k < CE; ++k) {
         int i = i0 + k;
         if (i >= ne) break;
-        T v = -a[k] - buf[0][i * nd + dp] + b[k];
+        T v = -a[k] - X0[i * rs + dp] + b[k];
         oL[i * nd + dp] = v;
         sumL += (double)v;
       }
-      gather<T>(g, TB(7), buf[1], false, dp, i0, Gs, a);
-      gather<T>(g, TB(2), buf[0], false, dp, i0, Gs, c2);
-      for (int k = 0; k < kEC; ++k) {
+#pragma unroll
+      for (int k = 0; k < CE; ++k) a[k] = b[k] = (T)0;
+      gather_acc<T, CE>(TB(7), X1, rs, ne, dp, i0, a);
+      gather_acc<T, CE>(TB(2), X0, rs, ne, dp, i0, b);
+#pragma unroll
+      for (int k = 0; k < CE; ++k) {
         int i = i0 + k;
         if (i >= ne) break;
-        T v = a[k] - buf[3][i * nd + dp] + c2[k];
+        T v = a[k] - X2[i * rs + dp] + b[k];
         oR[i * nd + dp] = v;
         sumR += (double)v;
       }
@@ -688,6 +847,7 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const T *__restrict__
     }
     __syncthreads();
   }
+#undef TB
 }
 
 // ------------------------------------------------------------ zone kernel
@@ -813,6 +973,9 @@ struct btx_ctx {
   double *d_vr = nullptr, *d_vth = nullptr, *d_alp = nullptr, *d_psi = nullptr;
   void *d_ka = nullptr, *d_ks = nullptr, *d_feq = nullptr;
   void *d_f = nullptr, *d_fn = nullptr, *d_dN = nullptr;
+  char *d_tabs = nullptr;            // remap tables of every face (per background)
+  FaceAux *d_aux = nullptr;          // frame data of every face (per background)
+  size_t tab_lds = 0;
   double *d_tally = nullptr, *d_zm = nullptr, *d_ze = nullptr, *d_stage = nullptr;
   FaceDesc *d_faces = nullptr;
   btx::ZoneFaces *d_zf = nullptr;
@@ -830,6 +993,13 @@ struct btx_ctx {
 
 namespace {
 
+// groups per face-kernel work item: 4 while the workgroup stays within 1024
+// threads, else 8
+int face_ce(const btx::Grid &g)
+{
+  return g.ndir * ((g.ne + 3) / 4) <= kMaxFaceThreads ? 4 : 8;
+}
+
 DevGrid dev_grid(const btx_ctx *c)
 {
   const btx::Grid &g = c->g;
@@ -837,7 +1007,7 @@ DevGrid dev_grid(const btx_ctx *c)
   d.nr = g.nr; d.nth = g.nth; d.ne = g.ne; d.nmu = g.nmu; d.nphi = g.nphi; d.ns = g.ns;
   d.ndir = g.ndir; d.nz = g.nz; d.geom = g.geom; d.phi_rule = g.phi_rule;
   d.eblk = g.ne * g.ndir; d.blk = g.ns * d.eblk;
-  d.nch = (g.ne + kEC - 1) / kEC;
+  d.nch = (g.ne + face_ce(g) - 1) / face_ce(g);
   d.nfaces = (int)g.faces.size();
   d.lnq = g.lnq; d.q = g.q; d.fp64_thr = g.fp64_thr;
   d.mu = c->d_mu; d.Phi = c->d_Phi; d.dOm = c->d_dOm; d.nvec = c->d_nvec; d.G = c->d_G;
@@ -856,19 +1026,15 @@ btx_status upload(X **dst, const X *src, size_t n)
 
 size_t face_lds(const btx::Grid &g, size_t szT)
 {
-  int nd = g.ndir, ne = g.ne, n = nd * ne;
-  (void)n;
-  size_t b = kTables * tab_stride(nd, szT);
-  b += data_bytes(nd, ne, szT);
-  b += align16(ne * 8) + 4 * align16(nd * 8) + align16(ne * 8) + align16(32 * 8);
-  return b;
+  int nd = g.ndir, ne = g.ne, ce = face_ce(g);
+  return kTables * tab_stride(nd, szT) + data_bytes(nd, ne, ce, szT) + small_bytes(nd, ne);
 }
 
 void free_ctx(btx_ctx *c)
 {
   void *ptrs[] = { c->d_mu, c->d_Phi, c->d_dOm, c->d_nvec, c->d_G, c->d_eps, c->d_vol, c->d_vr,
                    c->d_vth, c->d_alp, c->d_psi, c->d_ka, c->d_ks, c->d_feq, c->d_f, c->d_fn,
-                   c->d_dN, c->d_tally, c->d_zm, c->d_ze, c->d_stage, c->d_faces, c->d_zf };
+                   c->d_dN, c->d_tally, c->d_zm, c->d_ze, c->d_stage, c->d_faces, c->d_zf, c->d_tabs, c->d_aux };
   for (void *p : ptrs) if (p) (void)hipFree(p);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   delete c;
@@ -889,9 +1055,14 @@ btx_status launch_step(btx_ctx *c, double dt)
   const int maxgrid = 1 << 30;
   for (int f0 = 0; f0 < nf; f0 += maxgrid) {
     int nb = std::min(nf - f0, maxgrid);
-    hipLaunchKernelGGL((face_kernel<T>), dim3(nb), dim3(c->face_threads), c->lds_bytes, c->stream, dg,
-                       c->d_faces, (const T *)c->d_f, (const T *)c->d_ka, (const T *)c->d_ks,
-                       (const T *)c->d_feq, (T *)c->d_dN, c->d_tally, dt, f0);
+    if (face_ce(c->g) == 4)
+      hipLaunchKernelGGL((face_kernel<T, 4>), dim3(nb), dim3(c->face_threads), c->lds_bytes, c->stream, dg,
+                         c->d_faces, c->d_tabs, c->d_aux, (const T *)c->d_f, (const T *)c->d_ka, (const T *)c->d_ks,
+                         (const T *)c->d_feq, (T *)c->d_dN, c->d_tally, dt, f0);
+    else
+      hipLaunchKernelGGL((face_kernel<T, 8>), dim3(nb), dim3(c->face_threads), c->lds_bytes, c->stream, dg,
+                         c->d_faces, c->d_tabs, c->d_aux, (const T *)c->d_f, (const T *)c->d_ka, (const T *)c->d_ks,
+                         (const T *)c->d_feq, (T *)c->d_dN, c->d_tally, dt, f0);
   }
   HIP_TRY(hipGetLastError());
   if (rec) HIP_TRY(hipEventRecord(e1, c->stream));
@@ -928,9 +1099,10 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
   if (!d->r_edges || !d->eps_edges) return fail(BTX_E_INVAL, "null edge array");
   int nth = d->geometry == BTX_GEOM_AXISYM2D ? d->n_theta : 1;
   if (nth < 1) return fail(BTX_E_INVAL, "n_theta must be positive");
-  if (d->n_mu * d->n_phi > 255) return fail(BTX_E_UNSUPPORTED, "at most 255 directions");
-  int nch = (d->n_eps + kEC - 1) / kEC;
-  if (d->n_mu * d->n_phi * nch > kMaxFaceThreads) return fail(BTX_E_UNSUPPORTED, "too many directions x groups per face");
+  if (d->n_mu * d->n_phi > 256) return fail(BTX_E_UNSUPPORTED, "at most 256 directions");
+  if (d->n_mu * d->n_phi * ((d->n_eps + 7) / 8) > kMaxFaceThreads)
+    return fail(BTX_E_UNSUPPORTED, "too many directions x groups per face");
+  if (d->n_mu * d->n_phi * 4 > 65535) return fail(BTX_E_UNSUPPORTED, "too many directions");
   for (int a = 0; a < d->n_r; ++a)
     if (!(d->r_edges[a + 1] > d->r_edges[a])) return fail(BTX_E_INVAL, "r edges must ascend");
   if (d->geometry != BTX_GEOM_PLANAR && !(d->r_edges[0] >= 0.0)) return fail(BTX_E_INVAL, "r edges must be >= 0");
@@ -963,7 +1135,9 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
   c->tsize = g.prec == BTX_PREC_FP64 ? 8 : 4;
   c->dt_max1 = btx::max_dt(g, 1.0);
   c->lds_bytes = face_lds(g, c->tsize);
-  int items = g.ndir * ((g.ne + kEC - 1) / kEC);
+  c->tab_lds = kTables * tab_stride(g.ndir, c->tsize) + align16(5 * sizeof(Frame)) +
+               align16(scratch_bytes(g.ndir, c->tsize));
+  int items = g.ndir * ((g.ne + face_ce(g) - 1) / face_ce(g));
   c->face_threads = std::max(64, ((items + 63) / 64) * 64);
   btx_status st = BTX_OK;
   hipError_t he = hipSetDevice(hip_device);
@@ -971,13 +1145,15 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
   hipDeviceProp_t prop;
   he = hipGetDeviceProperties(&prop, hip_device);
   if (he != hipSuccess) { delete c; return fail(BTX_E_DEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(he)); }
-  if (c->tsize == 8)
-    he = hipFuncSetAttribute((const void *)face_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)c->lds_bytes);
-  else
-    he = hipFuncSetAttribute((const void *)face_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)c->lds_bytes);
-  (void)he;
+  {
+    const void *fk = c->tsize == 8 ? (face_ce(g) == 4 ? (const void *)face_kernel<double, 4> : (const void *)face_kernel<double, 8>)
+                                   : (face_ce(g) == 4 ? (const void *)face_kernel<float, 4> : (const void *)face_kernel<float, 8>);
+    he = hipFuncSetAttribute(fk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes);
+    (void)he;
+    const void *tk = c->tsize == 8 ? (const void *)table_kernel<double> : (const void *)table_kernel<float>;
+    he = hipFuncSetAttribute(tk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->tab_lds);
+    (void)he;
+  }
   size_t lds_cap = std::max<size_t>((size_t)prop.sharedMemPerBlock, (size_t)prop.maxSharedMemoryPerMultiProcessor);
   if (c->lds_bytes > lds_cap) {
     size_t need = c->lds_bytes;
@@ -1011,7 +1187,9 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
       !dmalloc(&c->d_fn, nz * blk * c->tsize) || !dmalloc(&c->d_dN, nf * 2 * blk * c->tsize) ||
       !dmalloc((void **)&c->d_tally, nf * g.ns * 8) || !dmalloc((void **)&c->d_zm, nz * g.ns * 5 * 8) ||
       !dmalloc((void **)&c->d_ze, nz * g.ns * 8) ||
-      !dmalloc((void **)&c->d_stage, nk * 8)) {
+      !dmalloc((void **)&c->d_stage, nk * 8) ||
+      !dmalloc((void **)&c->d_tabs, nf * kTables * tab_stride(g.ndir, c->tsize)) ||
+      !dmalloc((void **)&c->d_aux, nf * sizeof(FaceAux))) {
     free_ctx(c);
     return fail(BTX_E_NOMEM, "device allocation failed");
   }
@@ -1056,6 +1234,23 @@ btx_status btx_set_background(btx_ctx *c, const btx_background *bg)
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipDeviceSynchronize());
     }
+  }
+  // remap tables of every face for this background
+  {
+    DevGrid dg = dev_grid(c);
+    int nf = dg.nfaces;
+    const int maxgrid = 1 << 30;
+    for (int f0 = 0; f0 < nf; f0 += maxgrid) {
+      int nb = std::min(nf - f0, maxgrid);
+      if (c->tsize == 8)
+        hipLaunchKernelGGL((table_kernel<double>), dim3(nb), dim3(256), c->tab_lds, c->stream, dg, c->d_faces,
+                           c->d_tabs, c->d_aux, f0);
+      else
+        hipLaunchKernelGGL((table_kernel<float>), dim3(nb), dim3(256), c->tab_lds, c->stream, dg, c->d_faces,
+                           c->d_tabs, c->d_aux, f0);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
   }
   c->have_bg = true;
   return BTX_OK;

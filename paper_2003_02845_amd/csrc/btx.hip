@@ -37,6 +37,7 @@ namespace {
 
 constexpr int kTables = 8;    // remap tables per face
 constexpr int kMaxFaceThreads = 1024;
+constexpr int kCE = 6;        // groups per face-kernel work item (16 for very wide grids)
 constexpr double kPi = 3.14159265358979323846;
 
 thread_local std::string g_err;
@@ -208,14 +209,15 @@ __device__ inline Tab<T> tab_at(char *base, int nd)
   return t;
 }
 
-// LDS row stride of the data buffers: odd, so that one source column read
-// across rows by neighbouring lanes hits distinct banks
-__host__ __device__ inline int row_stride(int nd) { return nd | 1; }
+// Data buffers in LDS are direction-major: column d holds groups -2 .. ne+ce-1
+// contiguously (groups -2, -1, ne, ne+1 zero), so a gather reads a window of
+// consecutive groups of one source column.  The column stride is odd so that
+// neighbouring lanes reading different columns hit distinct banks.
+__host__ __device__ inline int col_stride(int ne, int ce) { return (ne + ce + 2) | 1; }
 
-// one data buffer: rows -2 .. ne+ce-1 (rows -2, -1, ne, ne+1 zero)
 __host__ __device__ inline size_t buf_bytes(int nd, int ne, int ce, size_t szT)
 {
-  return align16((size_t)(ne + ce + 2) * row_stride(nd) * szT);
+  return align16((size_t)nd * col_stride(ne, ce) * szT + 16);
 }
 
 // table-build scratch for one round of 4 tables
@@ -233,8 +235,8 @@ __host__ __device__ inline size_t data_bytes(int nd, int ne, int ce, size_t szT)
 // opacities (3), angle averages, reduction scratch
 __host__ __device__ inline size_t small_bytes(int nd, int ne)
 {
-  return 2 * align16(ne * 8) + 5 * align16(nd * 8) + 4 * align16(nd * 8) + 4 * align16(ne * 8) +
-         align16(32 * 8) + align16(5 * sizeof(Frame));
+  (void)nd;
+  return 2 * align16(ne * 8) + 4 * align16(ne * 8) + align16(32 * 8);
 }
 
 // ascending node bracket with edge clamping (all weight to the edge node)
@@ -318,74 +320,60 @@ __device__ void remap_source(const DevGrid &g, const Frame &S, const Frame &D, i
   }
 }
 
-// One gather-list entry (source column, energy shift, two tap weights) added
-// into the groups i0 .. i0+CE-1 of a target.  X points at row 0 of a buffer
-// with row stride rs whose rows -2, -1, ne, ne+1 are zero.
+// Gather of one remap for target direction dp and groups i0 .. i0+CE-1,
+// accumulated into acc.  X points at group 0 of column 0 of a direction-major
+// buffer with column stride cs.  Content that the energy shift pushes below
+// group 0 or above group ne-1 stays in that group.
 template <typename T, int CE>
-__device__ __forceinline__ void entry_acc(const T *__restrict__ X, int rs, int ne, int i0, unsigned key,
-                                          T cl, T cr, bool low, bool top, int kt, T acc[CE])
-{
-  const int d = key & 0xff, di = (int)(key >> 8) - 128;
-  const T *col = X + d;
-  if (di >= -1 && di <= 1) {
-    const T *base = col + (i0 - di - 1) * rs;
-    T x[CE + 1];
-#pragma unroll
-    for (int k = 0; k <= CE; ++k) x[k] = base[k * rs];
-#pragma unroll
-    for (int k = 0; k < CE; ++k) acc[k] += cl * x[k + 1] + cr * x[k];
-    // sources pushed beyond the lowest / highest group stay in it
-    if (low && di < 0) acc[0] += cl * col[0];
-    if (top && di >= 0) {
-      T x1 = col[(ne - 1) * rs];
-      T v = di == 0 ? cr * x1 : cl * x1 + cr * (x1 + col[(ne - 2) * rs]);
-#pragma unroll
-      for (int k = 0; k < CE; ++k)
-        if (k == kt) acc[k] += v;
-    }
-  } else {                                           // shifts of two or more groups
-#pragma unroll
-    for (int k = 0; k < CE; ++k) {
-      int iL = i0 + k - di, iR = iL - 1;
-      T v = (T)0;
-      if (iL >= 0 && iL < ne) v += cl * col[iL * rs];
-      if (iR >= 0 && iR < ne) v += cr * col[iR * rs];
-      acc[k] += v;
-    }
-    if (low && di < 0) {
-      for (int i = 0; i < ne && i < -di; ++i) acc[0] += cl * col[i * rs];
-      for (int i = 0; i < ne && i < -di - 1; ++i) acc[0] += cr * col[i * rs];
-    }
-    if (top && di >= 0) {
-      T v = (T)0;
-      for (int i = max(0, ne - di); i < ne; ++i) v += cl * col[i * rs];
-      for (int i = max(0, ne - 1 - di); i < ne; ++i) v += cr * col[i * rs];
-#pragma unroll
-      for (int k = 0; k < CE; ++k)
-        if (k == kt) acc[k] += v;
-    }
-  }
-}
-
-// Gather of one remap for target direction dp and groups i0 .. i0+CE-1 into acc
-// (accumulates), two entries per iteration.  X points at row 0 of a buffer
-// whose rows -2, -1, ne, ne+1 are zero.
-template <typename T, int CE>
-__device__ __forceinline__ void gather_acc(const Tab<T> &tb, const T *__restrict__ X, int rs, int ne,
+__device__ __forceinline__ void gather_acc(const Tab<T> &tb, const T *__restrict__ X, int cs, int ne,
                                            int dp, int i0, T acc[CE])
 {
   const int e0 = tb.start[dp], e1 = tb.start[dp + 1];
   const bool low = i0 == 0;
   const int kt = ne - 1 - i0;
   const bool top = kt < CE;
-  int e = e0;
-  for (; e + 1 < e1; e += 2) {
-    const unsigned k0 = tb.key[e], k1 = tb.key[e + 1];
-    const T a0 = tb.coef[2 * e], b0 = tb.coef[2 * e + 1], a1 = tb.coef[2 * e + 2], b1 = tb.coef[2 * e + 3];
-    entry_acc<T, CE>(X, rs, ne, i0, k0, a0, b0, low, top, kt, acc);
-    entry_acc<T, CE>(X, rs, ne, i0, k1, a1, b1, low, top, kt, acc);
+  T accLow = (T)0, accTop = (T)0;
+#pragma unroll 2
+  for (int e = e0; e < e1; ++e) {
+    const unsigned key = tb.key[e];
+    const int d = key & 0xff, di = (int)(key >> 8) - 128;
+    const T cl = tb.coef[2 * e], cr = tb.coef[2 * e + 1];
+    const T *col = X + d * cs;
+    if (di >= -1 && di <= 1) {
+      const T *w = col + (i0 - di - 1);
+      T x[CE + 1];
+#pragma unroll
+      for (int k = 0; k <= CE; ++k) x[k] = w[k];
+#pragma unroll
+      for (int k = 0; k < CE; ++k) acc[k] += cl * x[k + 1] + cr * x[k];
+      accLow += (low && di < 0) ? cl * x[0] : (T)0;        // group 0 of the source
+      if (top && di >= 0) {
+        T x1 = col[ne - 1];
+        accTop += di == 0 ? cr * x1 : cl * x1 + cr * (x1 + col[ne - 2]);
+      }
+    } else {                                           // shifts of two or more groups
+#pragma unroll
+      for (int k = 0; k < CE; ++k) {
+        int iL = i0 + k - di, iR = iL - 1;
+        T v = (T)0;
+        if (iL >= 0 && iL < ne) v += cl * col[iL];
+        if (iR >= 0 && iR < ne) v += cr * col[iR];
+        acc[k] += v;
+      }
+      if (low && di < 0) {
+        for (int i = 0; i < ne && i < -di; ++i) accLow += cl * col[i];
+        for (int i = 0; i < ne && i < -di - 1; ++i) accLow += cr * col[i];
+      }
+      if (top && di >= 0) {
+        for (int i = max(0, ne - di); i < ne; ++i) accTop += cl * col[i];
+        for (int i = max(0, ne - 1 - di); i < ne; ++i) accTop += cr * col[i];
+      }
+    }
   }
-  if (e < e1) entry_acc<T, CE>(X, rs, ne, i0, tb.key[e], tb.coef[2 * e], tb.coef[2 * e + 1], low, top, kt, acc);
+  acc[0] += accLow;
+#pragma unroll
+  for (int k = 0; k < CE; ++k)
+    if (k == kt) acc[k] += accTop;
 }
 
 template <typename T>
@@ -408,9 +396,9 @@ __device__ inline double wave_sum(double v)
 template <typename T>
 __device__ inline void load_column(const DevGrid &g, const SideDesc &sd, const T *__restrict__ f,
                                    const T *__restrict__ feq, int s, const double *Gs, double aS,
-                                   int dp, int ch, int nch, T *X)
+                                   int dp, int ch, int nch, int cs, T *X)
 {
-  const int nd = g.ndir, ne = g.ne, rs = row_stride(nd);
+  const int nd = g.ndir, ne = g.ne;
   const T *src = f + (size_t)sd.z * g.blk + (size_t)s * g.eblk;
   int sd_col = dp;
   if (sd.kind == btx::SIDE_MIRROR) {
@@ -422,18 +410,17 @@ __device__ inline void load_column(const DevGrid &g, const SideDesc &sd, const T
     if (sd.kind == btx::SIDE_ZONE || sd.kind == btx::SIDE_MIRROR) v = (double)src[i * nd + sd_col];
     else if (sd.kind == btx::SIDE_EQ) v = (double)feq[((size_t)sd.z * g.ns + s) * ne + i];
     else v = 0.0;
-    X[i * rs + dp] = (T)(v * Gs[i] * aS);
+    X[dp * cs + i] = (T)(v * Gs[i] * aS);
   }
 }
 
 template <typename T>
-__device__ inline void zero_guards(T *X, int nd, int ne, int tid, int nthr)
+__device__ inline void zero_guards(T *X, int nd, int ne, int cs, int tid, int nthr)
 {
-  const int rs = row_stride(nd);
   for (int q = tid; q < 4 * nd; q += nthr) {
-    int r = q / nd, d = q - r * nd;
+    int d = q >> 2, r = q & 3;
     int row = r < 2 ? r - 2 : ne + (r - 2);
-    X[row * rs + d] = (T)0;
+    X[d * cs + row] = (T)0;
   }
 }
 
@@ -604,21 +591,15 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
   char *tabs = p;              p += kTables * tstride;
   char *data = p;              p += data_bytes(nd, ne, CE, sizeof(T));
   const size_t bb = buf_bytes(nd, ne, CE, sizeof(T));
-  const int rs = row_stride(nd);
-  T *X0 = (T *)(data) + 2 * rs, *X1 = (T *)(data + bb) + 2 * rs, *X2 = (T *)(data + 2 * bb) + 2 * rs;
+  const int cs = col_stride(ne, CE);
+  T *X0 = (T *)(data) + 2, *X1 = (T *)(data + bb) + 2, *X2 = (T *)(data + 2 * bb) + 2;
   double *Gs = (double *)p;    p += align16(ne * 8);
   double *iG = (double *)p;    p += align16(ne * 8);
-  double *aF = (double *)p;    p += 5 * align16(nd * 8);   // frames Lm, L, R, Rp, s
-  double *Urad = (double *)p;  p += align16(nd * 8);
-  double *Vn = (double *)p;    p += align16(nd * 8);
-  double *UL = (double *)p;    p += align16(nd * 8);
-  double *UR = (double *)p;    p += align16(nd * 8);
   double *kas = (double *)p;   p += align16(ne * 8);
   double *kss = (double *)p;   p += align16(ne * 8);
   double *fes = (double *)p;   p += align16(ne * 8);
   double *sav = (double *)p;   p += align16(ne * 8);
   double *red = (double *)p;   p += align16(32 * 8);
-  const size_t nda = align16(nd * 8) / 8;
 
 #define TB(t) tab_at<T>(tabs + (t) * tstride, nd)
 
@@ -632,34 +613,6 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
   const double vn = A.v[4][ax];
   const double Uadv = ap4 * gs * vn;
   const double tau = 0.5 * A.alpha[4] * dt / gs;
-  // per-direction frame weights psi^6 u0 dOmega and interface speeds
-  for (int q = tid; q < 6 * nd; q += nthr) {
-    int kind = q / nd, d = q - kind * nd;
-    const double *nv = g.nvec + 3 * d;
-    if (kind < 5) {
-      double vdn = A.v[kind][0] * nv[0] + A.v[kind][1] * nv[1] + A.v[kind][2] * nv[2];
-      aF[kind * nda + d] = A.p6[kind] * A.gam[kind] * (1.0 + vdn) * g.dOm[d];
-    } else {
-      const double kvs = gs * gs / (gs + 1.0);
-      double vdn = A.v[4][0] * nv[0] + A.v[4][1] * nv[1] + A.v[4][2] * nv[2];
-      double u0 = gs * (1.0 + vdn);
-      double un = nv[ax] + (kvs * vdn + gs) * vn;
-      Urad[d] = ap4 * (nv[ax] + kvs * vdn * vn);
-      Vn[d] = A.alpha[4] * un / (A.psi[4] * A.psi[4] * u0);
-      // donor speeds: each side's own comoving direction, in the interface basis
-      for (int side = 0; side < 2; ++side) {
-        const double *v = A.v[1 + side];
-        double gm = A.gam[1 + side], kv = gm * gm / (gm + 1.0);
-        double vu = v[0] * nv[0] + v[1] * nv[1] + v[2] * nv[2];
-        double a_ = kv * vu + gm;
-        double e0 = nv[0] + a_ * v[0], e1 = nv[1] + a_ * v[1], e2 = nv[2] + a_ * v[2];
-        const double *M = A.M[side];
-        double y = M[3 * ax] * e0 + M[3 * ax + 1] * e1 + M[3 * ax + 2] * e2;
-        (side ? UR : UL)[d] = ap4 * y;
-      }
-    }
-  }
-
   // ---- remap tables of this face (built once per background by table_kernel)
   {
     const uint4 *src = (const uint4 *)(tabs_g + (size_t)fid * kTables * tstride);
@@ -675,20 +628,53 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
   const bool own = tid < nitems;
   const int dp = own ? tid / nch : 0;                 // neighbouring lanes share a target list
   const int ch = own ? tid - dp * nch : 0;
+  // this thread's direction: frame weights psi^6 u0 dOmega (frames Lm, L, R,
+  // Rp, interface), interface speeds (flux integral with zero shift) and the
+  // donor speeds of both sides (cell-centre direction in the interface basis)
+  double aFr[5];
+  double Urad_d, Vn_d, UL_d, UR_d;
+  {
+    const double *nv = g.nvec + 3 * dp;
+    const double dO = g.dOm[dp];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      double vdn = A.v[k][0] * nv[0] + A.v[k][1] * nv[1] + A.v[k][2] * nv[2];
+      aFr[k] = A.p6[k] * A.gam[k] * (1.0 + vdn) * dO;
+    }
+    const double kvs = gs * gs / (gs + 1.0);
+    double vdn = A.v[4][0] * nv[0] + A.v[4][1] * nv[1] + A.v[4][2] * nv[2];
+    double u0 = gs * (1.0 + vdn);
+    double un = nv[ax] + (kvs * vdn + gs) * vn;
+    Urad_d = ap4 * (nv[ax] + kvs * vdn * vn);
+    Vn_d = A.alpha[4] * un / (A.psi[4] * A.psi[4] * u0);
+    double Us[2];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const double *v = A.v[1 + side];
+      double gm = A.gam[1 + side], kv = gm * gm / (gm + 1.0);
+      double vu = v[0] * nv[0] + v[1] * nv[1] + v[2] * nv[2];
+      double a_ = kv * vu + gm;
+      double e0 = nv[0] + a_ * v[0], e1 = nv[1] + a_ * v[1], e2 = nv[2] + a_ * v[2];
+      const double *M = A.M[side];
+      Us[side] = ap4 * (M[3 * ax] * e0 + M[3 * ax + 1] * e1 + M[3 * ax + 2] * e2);
+    }
+    UL_d = Us[0];
+    UR_d = Us[1];
+  }
   const int i0 = ch * CE;
   const double cA = dt * F.area;
   const int lane = tid & 63, wave = tid >> 6, nwaves = (nthr + 63) >> 6;
-  const double aLd = aF[1 * nda + dp], aRd = aF[2 * nda + dp], aSd = aF[4 * nda + dp];
+  const double aLd = aFr[1], aRd = aFr[2], aSd = aFr[4];
 #pragma unroll 1
   for (int s = 0; s < g.ns; ++s) {
     if (own) {
-      load_column<T>(g, F.L, f, feq, s, Gs, aLd, dp, ch, nch, X1);
-      load_column<T>(g, F.R, f, feq, s, Gs, aRd, dp, ch, nch, X2);
-      if (slopeL) load_column<T>(g, F.Lm, f, feq, s, Gs, aF[0 * nda + dp], dp, ch, nch, X0);
+      load_column<T>(g, F.L, f, feq, s, Gs, aLd, dp, ch, nch, cs, X1);
+      load_column<T>(g, F.R, f, feq, s, Gs, aRd, dp, ch, nch, cs, X2);
+      if (slopeL) load_column<T>(g, F.Lm, f, feq, s, Gs, aFr[0], dp, ch, nch, cs, X0);
     }
-    zero_guards<T>(X0, nd, ne, tid, nthr);
-    zero_guards<T>(X1, nd, ne, tid, nthr);
-    zero_guards<T>(X2, nd, ne, tid, nthr);
+    zero_guards<T>(X0, nd, ne, cs, tid, nthr);
+    zero_guards<T>(X1, nd, ne, cs, tid, nthr);
+    zero_guards<T>(X2, nd, ne, cs, tid, nthr);
     for (int i = tid; i < ne; i += nthr) {
       double a_ = 0.0, b_ = 0.0, e_ = 0.0;
       if (!F.zero_opacity) {
@@ -707,16 +693,16 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
       for (int k = 0; k < CE; ++k) {
         int i = i0 + k;
         bool in = i < ne;
-        fl[k] = in ? (T)((double)X1[i * rs + dp] * iG[i] / aLd) : (T)0;
-        fr[k] = in ? (T)((double)X2[i * rs + dp] * iG[i] / aRd) : (T)0;
+        fl[k] = in ? (T)((double)X1[dp * cs + i] * iG[i] / aLd) : (T)0;
+        fr[k] = in ? (T)((double)X2[dp * cs + i] * iG[i] / aRd) : (T)0;
         sl[k] = (T)0;
       }
       if (slopeL) {
         T a[CE], b[CE];
 #pragma unroll
         for (int k = 0; k < CE; ++k) a[k] = b[k] = (T)0;
-        gather_acc<T, CE>(TB(0), X0, rs, ne, dp, i0, a);
-        gather_acc<T, CE>(TB(1), X2, rs, ne, dp, i0, b);
+        gather_acc<T, CE>(TB(0), X0, cs, ne, dp, i0, a);
+        gather_acc<T, CE>(TB(1), X2, cs, ne, dp, i0, b);
 #pragma unroll
         for (int k = 0; k < CE; ++k) {
           int i = min(i0 + k, ne - 1);
@@ -729,14 +715,14 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
     }
     if (slopeR) {
       __syncthreads();                                 // X0 (Lm) no longer read
-      if (own) load_column<T>(g, F.Rp, f, feq, s, Gs, aF[3 * nda + dp], dp, ch, nch, X0);
+      if (own) load_column<T>(g, F.Rp, f, feq, s, Gs, aFr[3], dp, ch, nch, cs, X0);
       __syncthreads();
       if (own) {
         T a[CE], b[CE];
 #pragma unroll
         for (int k = 0; k < CE; ++k) a[k] = b[k] = (T)0;
-        gather_acc<T, CE>(TB(2), X1, rs, ne, dp, i0, a);
-        gather_acc<T, CE>(TB(3), X0, rs, ne, dp, i0, b);
+        gather_acc<T, CE>(TB(2), X1, cs, ne, dp, i0, a);
+        gather_acc<T, CE>(TB(3), X0, cs, ne, dp, i0, b);
 #pragma unroll
         for (int k = 0; k < CE; ++k) {
           int i = min(i0 + k, ne - 1);
@@ -754,9 +740,9 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
       T A[CE], B[CE];
 #pragma unroll
       for (int k = 0; k < CE; ++k) A[k] = B[k] = (T)0;
-      gather_acc<T, CE>(TB(4), X1, rs, ne, dp, i0, A);
-      gather_acc<T, CE>(TB(5), X2, rs, ne, dp, i0, B);
-      const T cv = (T)(-0.5 * dt * Vn[dp] / F.h);
+      gather_acc<T, CE>(TB(4), X1, cs, ne, dp, i0, A);
+      gather_acc<T, CE>(TB(5), X2, cs, ne, dp, i0, B);
+      const T cv = (T)(-0.5 * dt * Vn_d / F.h);
 #pragma unroll
       for (int k = 0; k < CE; ++k) {
         int i = min(i0 + k, ne - 1);
@@ -769,12 +755,12 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
     if (own) {
 #pragma unroll
       for (int k = 0; k < CE; ++k)
-        if (i0 + k < ne) X0[(i0 + k) * rs + dp] = Sv[k];
+        if (i0 + k < ne) X0[dp * cs + i0 + k] = Sv[k];
     }
     __syncthreads();
     for (int i = wave; i < ne; i += nwaves) {          // <S> per group, FP64, fixed order
       double acc = 0.0;
-      for (int d = lane; d < nd; d += 64) acc += (double)X0[i * rs + d] * g.dOm[d];
+      for (int d = lane; d < nd; d += 64) acc += (double)X0[d * cs + i] * g.dOm[d];
       acc = wave_sum(acc);
       if (lane == 0) sav[i] = acc / (4.0 * kPi);
     }
@@ -796,11 +782,11 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
         }
         double w = exp(-(ka_ + ks_) * F.h);
         double gw = Gs[i] * dO * cA;
-        X1[i * rs + dp] = (T)((1.0 - w) * Urad[dp] * flw * gw);
-        double eL = w * fmax(UL[dp], 0.0) + (1.0 - w) * fmax(Uadv, 0.0);
-        double eR = w * fmax(-UR[dp], 0.0) + (1.0 - w) * fmax(-Uadv, 0.0);
-        X0[i * rs + dp] = (T)(eL * gw * (double)EL[k]);
-        X2[i * rs + dp] = (T)(eR * gw * (double)ER[k]);
+        X1[dp * cs + i] = (T)((1.0 - w) * Urad_d * flw * gw);
+        double eL = w * fmax(UL_d, 0.0) + (1.0 - w) * fmax(Uadv, 0.0);
+        double eR = w * fmax(-UR_d, 0.0) + (1.0 - w) * fmax(-Uadv, 0.0);
+        X0[dp * cs + i] = (T)(eL * gw * (double)EL[k]);
+        X2[dp * cs + i] = (T)(eR * gw * (double)ER[k]);
       }
     }
     __syncthreads();
@@ -810,26 +796,26 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
       T a[CE], b[CE];
 #pragma unroll
       for (int k = 0; k < CE; ++k) a[k] = b[k] = (T)0;
-      gather_acc<T, CE>(TB(6), X1, rs, ne, dp, i0, a);
-      gather_acc<T, CE>(TB(1), X2, rs, ne, dp, i0, b);
+      gather_acc<T, CE>(TB(6), X1, cs, ne, dp, i0, a);
+      gather_acc<T, CE>(TB(1), X2, cs, ne, dp, i0, b);
       T *oL = outL + (size_t)s * g.eblk, *oR = outR + (size_t)s * g.eblk;
 #pragma unroll
       for (int k = 0; k < CE; ++k) {
         int i = i0 + k;
         if (i >= ne) break;
-        T v = -a[k] - X0[i * rs + dp] + b[k];
+        T v = -a[k] - X0[dp * cs + i] + b[k];
         oL[i * nd + dp] = v;
         sumL += (double)v;
       }
 #pragma unroll
       for (int k = 0; k < CE; ++k) a[k] = b[k] = (T)0;
-      gather_acc<T, CE>(TB(7), X1, rs, ne, dp, i0, a);
-      gather_acc<T, CE>(TB(2), X0, rs, ne, dp, i0, b);
+      gather_acc<T, CE>(TB(7), X1, cs, ne, dp, i0, a);
+      gather_acc<T, CE>(TB(2), X0, cs, ne, dp, i0, b);
 #pragma unroll
       for (int k = 0; k < CE; ++k) {
         int i = i0 + k;
         if (i >= ne) break;
-        T v = a[k] - X2[i * rs + dp] + b[k];
+        T v = a[k] - X2[dp * cs + i] + b[k];
         oR[i * nd + dp] = v;
         sumR += (double)v;
       }
@@ -993,11 +979,11 @@ struct btx_ctx {
 
 namespace {
 
-// groups per face-kernel work item: 4 while the workgroup stays within 1024
-// threads, else 8
+// groups per face-kernel work item: kCE while the workgroup stays within
+// 1024 threads, else 16
 int face_ce(const btx::Grid &g)
 {
-  return g.ndir * ((g.ne + 3) / 4) <= kMaxFaceThreads ? 4 : 8;
+  return g.ndir * ((g.ne + kCE - 1) / kCE) <= kMaxFaceThreads ? kCE : 16;
 }
 
 DevGrid dev_grid(const btx_ctx *c)
@@ -1055,12 +1041,12 @@ btx_status launch_step(btx_ctx *c, double dt)
   const int maxgrid = 1 << 30;
   for (int f0 = 0; f0 < nf; f0 += maxgrid) {
     int nb = std::min(nf - f0, maxgrid);
-    if (face_ce(c->g) == 4)
-      hipLaunchKernelGGL((face_kernel<T, 4>), dim3(nb), dim3(c->face_threads), c->lds_bytes, c->stream, dg,
+    if (face_ce(c->g) == kCE)
+      hipLaunchKernelGGL((face_kernel<T, kCE>), dim3(nb), dim3(c->face_threads), c->lds_bytes, c->stream, dg,
                          c->d_faces, c->d_tabs, c->d_aux, (const T *)c->d_f, (const T *)c->d_ka, (const T *)c->d_ks,
                          (const T *)c->d_feq, (T *)c->d_dN, c->d_tally, dt, f0);
     else
-      hipLaunchKernelGGL((face_kernel<T, 8>), dim3(nb), dim3(c->face_threads), c->lds_bytes, c->stream, dg,
+      hipLaunchKernelGGL((face_kernel<T, 16>), dim3(nb), dim3(c->face_threads), c->lds_bytes, c->stream, dg,
                          c->d_faces, c->d_tabs, c->d_aux, (const T *)c->d_f, (const T *)c->d_ka, (const T *)c->d_ks,
                          (const T *)c->d_feq, (T *)c->d_dN, c->d_tally, dt, f0);
   }
@@ -1100,7 +1086,7 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
   int nth = d->geometry == BTX_GEOM_AXISYM2D ? d->n_theta : 1;
   if (nth < 1) return fail(BTX_E_INVAL, "n_theta must be positive");
   if (d->n_mu * d->n_phi > 256) return fail(BTX_E_UNSUPPORTED, "at most 256 directions");
-  if (d->n_mu * d->n_phi * ((d->n_eps + 7) / 8) > kMaxFaceThreads)
+  if (d->n_mu * d->n_phi * ((d->n_eps + 15) / 16) > kMaxFaceThreads)
     return fail(BTX_E_UNSUPPORTED, "too many directions x groups per face");
   if (d->n_mu * d->n_phi * 4 > 65535) return fail(BTX_E_UNSUPPORTED, "too many directions");
   for (int a = 0; a < d->n_r; ++a)
@@ -1146,8 +1132,8 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
   he = hipGetDeviceProperties(&prop, hip_device);
   if (he != hipSuccess) { delete c; return fail(BTX_E_DEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(he)); }
   {
-    const void *fk = c->tsize == 8 ? (face_ce(g) == 4 ? (const void *)face_kernel<double, 4> : (const void *)face_kernel<double, 8>)
-                                   : (face_ce(g) == 4 ? (const void *)face_kernel<float, 4> : (const void *)face_kernel<float, 8>);
+    const void *fk = c->tsize == 8 ? (face_ce(g) == kCE ? (const void *)face_kernel<double, kCE> : (const void *)face_kernel<double, 16>)
+                                   : (face_ce(g) == kCE ? (const void *)face_kernel<float, kCE> : (const void *)face_kernel<float, 16>);
     he = hipFuncSetAttribute(fk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes);
     (void)he;
     const void *tk = c->tsize == 8 ? (const void *)table_kernel<double> : (const void *)table_kernel<float>;

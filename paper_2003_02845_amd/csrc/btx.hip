@@ -36,8 +36,6 @@ using btx::SideDesc;
 namespace {
 
 constexpr int kTables = 8;    // remap tables per face
-constexpr int kMaxFaceThreads = 1024;
-constexpr int kCE = 6;        // groups per face-kernel work item (16 for very wide grids)
 constexpr double kPi = 3.14159265358979323846;
 
 thread_local std::string g_err;
@@ -59,7 +57,7 @@ btx_status fail(btx_status s, const std::string &msg)
 
 struct DevGrid {
   int nr, nth, ne, nmu, nphi, ns, ndir, nz, geom, phi_rule;
-  int eblk, blk, nch, nfaces;
+  int eblk, blk, nfaces;
   double lnq, q, fp64_thr;
   const double *mu, *Phi, *dOm, *nvec, *G, *eps, *vol;
   const double *vr, *vth, *alp, *psi;
@@ -180,63 +178,71 @@ __device__ inline double u0_dir(const Frame &f, const double *n)
 // ------------------------------------------------------------ LDS tables
 
 // A remap T_{S->D} of one face in gather form.  For every target direction d'
-// the entries [start[d'], start[d'+1]) hold the source direction and its
-// energy shift packed in 16 bits (src | (di + 128) << 8) and the two energy-tap
-// weights multiplied by the (mu, Phi) corner weight.  Tables act on number
-// content; occupations are turned into content before (x G_i aS(d)) and back
-// after (/ (G_i aD(d'))) by the caller.
+// the entries [start[d'], start[d'+1]) hold the source direction and its energy
+// shift packed in 16 bits (src | (di + 128) << 8) and the (mu, Phi) corner
+// weight c.  On a logarithmic energy grid one shift serves every group: source
+// group i sends c (1 - we[src]) to group i + di and c we[src] to i + di + 1.
+// start[nd + 1] holds flags: bit 0 is set when some entry shifts by two or
+// more groups.  Tables act on number content; occupations are turned into
+// content before (x G_i a(d)) and back after (/ (G_i a(d'))) by the caller.
 template <typename T>
 struct Tab {
-  T *coef;             // 2 * 4nd: (cL, cR) per entry
-  unsigned short *key; // 4nd
-  unsigned short *start;  // nd + 1
+  const T *c;                    // 4 nd corner weights
+  const T *we;                   // nd: upper energy-tap weight per source direction
+  const unsigned short *key;     // 4 nd
+  const unsigned short *start;   // nd + 2
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 __host__ __device__ inline size_t tab_stride(int nd, size_t szT)
 {
-  return align16(8 * (size_t)nd * szT + 4 * (size_t)nd * 2 + (size_t)(nd + 1) * 2);
+  return align16(5 * (size_t)nd * szT + (5 * (size_t)nd + 2) * 2);
 }
 
 template <typename T>
-__device__ inline Tab<T> tab_at(char *base, int nd)
+__device__ inline Tab<T> tab_at(const char *base, int nd)
 {
   Tab<T> t;
-  t.coef = (T *)base;
-  t.key = (unsigned short *)(base + 8 * (size_t)nd * sizeof(T));
+  t.c = (const T *)base;
+  t.we = t.c + 4 * nd;
+  t.key = (const unsigned short *)(t.we + nd);
   t.start = t.key + 4 * nd;
   return t;
 }
 
-// Data buffers in LDS are direction-major: column d holds groups -2 .. ne+ce-1
-// contiguously (groups -2, -1, ne, ne+1 zero), so a gather reads a window of
-// consecutive groups of one source column.  The column stride is odd so that
-// neighbouring lanes reading different columns hit distinct banks.
-__host__ __device__ inline int col_stride(int ne, int ce) { return (ne + ce + 2) | 1; }
+// Work items of the face kernel: kNch per target direction, each owning CE
+// consecutive rows (energy groups).  The kNch * CE rows of a direction end at
+// group ne + 1, so that the rows ne and ne + 1, which collect the content an
+// upward shift pushes past the top group, share a work item with group ne - 1,
+// and they start at or below group -1.
+constexpr int kNch = 4;
 
-__host__ __device__ inline size_t buf_bytes(int nd, int ne, int ce, size_t szT)
+// Data buffers in LDS are direction-major: column d holds the rows
+// ne - kNch CE .. ne + 2 contiguously; rows outside 0 .. ne-1 are zero.  The
+// stride kNch CE + 3 is odd, so neighbouring lanes reading different columns
+// hit distinct banks.
+__host__ __device__ inline int col_rows(int ce) { return kNch * ce + 3; }
+
+__host__ __device__ inline size_t buf_bytes(int nd, int ce, size_t szT)
 {
-  return align16((size_t)nd * col_stride(ne, ce) * szT + 16);
+  return align16((size_t)nd * col_rows(ce) * szT);
 }
 
 // table-build scratch for one round of 4 tables
 __host__ __device__ inline size_t scratch_bytes(int nd, size_t szT)
 {
-  return (size_t)4 * nd * 4 * 2 + (size_t)16 * nd * 4 + (size_t)32 * nd * szT;
+  return (size_t)4 * nd * 4 * 2 + (size_t)16 * nd * 4 + (size_t)16 * nd * szT;
 }
 
-__host__ __device__ inline size_t data_bytes(int nd, int ne, int ce, size_t szT)
+// LDS of one face workgroup: 8 tables, 4 data buffers (Lm, L, R, Rp), per-row
+// constants (G, 1/G, source, blend weight as T; two collision coefficients as
+// FP64; a precision flag) and the wave partials of the angle sums and tally
+__host__ __device__ inline size_t face_lds_bytes(int nd, int ce, size_t szT)
 {
-  return 3 * buf_bytes(nd, ne, ce, szT);
-}
-
-// small per-face arrays: G, 1/G, frame weights (5 frames), 4 speeds, interface
-// opacities (3), angle averages, reduction scratch
-__host__ __device__ inline size_t small_bytes(int nd, int ne)
-{
-  (void)nd;
-  return 2 * align16(ne * 8) + 4 * align16(ne * 8) + align16(32 * 8);
+  const size_t nrow = col_rows(ce);
+  return kTables * tab_stride(nd, szT) + 4 * buf_bytes(nd, ce, szT) + 4 * align16(nrow * szT) +
+         2 * align16(nrow * 8) + align16(nrow * 4) + align16(16 * nrow * 8) + align16(16 * 8);
 }
 
 // ascending node bracket with edge clamping (all weight to the edge node)
@@ -251,18 +257,19 @@ __device__ inline void node_bracket(const double *x, int n, double v, int &L, in
   wR = (v - x[l]) / (x[l + 1] - x[l]);
 }
 
-// One source direction of one remap: frame chain, energy shift and taps,
-// (mu, Phi) corners.  rt[4] receive the targets (-1 unused), rl/rr the tap
-// weights times the corner weight.
+// One source direction of one remap: frame chain, energy shift and upper tap
+// weight, (mu, Phi) corners.  rt[4] receive the targets (-1 unused), cw[4]
+// the corner weights.
 __device__ void remap_source(const DevGrid &g, const Frame &S, const Frame &D, int axis, bool rot,
-                             bool ident, int d, int rt[4], double rl[4], double rr[4], int &di_out)
+                             bool ident, int d, int rt[4], double cw[4], double &we_out, int &di_out)
 {
   const double *n = g.nvec + 3 * d;
   rt[1] = rt[2] = rt[3] = -1;
-  rl[1] = rl[2] = rl[3] = rr[1] = rr[2] = rr[3] = 0.0;
+  cw[1] = cw[2] = cw[3] = 0.0;
   if (ident) {
     di_out = 0;
-    rt[0] = d; rl[0] = 1.0; rr[0] = 0.0;
+    we_out = 0.0;
+    rt[0] = d; cw[0] = 1.0;
     return;
   }
   double u[4] = { 1.0, n[0], n[1], n[2] }, o[4];
@@ -274,6 +281,7 @@ __device__ void remap_source(const DevGrid &g, const Frame &S, const Frame &D, i
   we = fmin(1.0, fmax(0.0, we));
   di = max(-127, min(127, di));
   di_out = di;
+  we_out = we;
   // direction
   double mus = fmin(1.0, fmax(-1.0, o[1] / o[0]));
   int jL, jR;
@@ -315,65 +323,67 @@ __device__ void remap_source(const DevGrid &g, const Frame &S, const Frame &D, i
     // corner weights at rounding level (a direction that lands on a node up
     // to the last bit) are dropped: they move less than 1e-15 of a bin
     rt[r] = c[r] > 1e-15 ? tg[r] : -1;
-    rl[r] = c[r] * (1.0 - we);
-    rr[r] = c[r] * we;
+    cw[r] = c[r];
   }
 }
 
-// Gather of one remap for target direction dp and groups i0 .. i0+CE-1,
-// accumulated into acc.  X points at group 0 of column 0 of a direction-major
-// buffer with column stride cs.  Content that the energy shift pushes below
-// group 0 or above group ne-1 stays in that group.
+// Gather of one remap for target direction dp over the rows r0 .. r0+CE-1 of
+// a work item.  X points at group 0 of column 0 of a direction-major buffer
+// (column stride cs, zero outside groups 0 .. ne-1).  Content that the energy
+// shift pushes below group 0 or above group ne-1 stays in that group: for
+// shifts of at most one group it lands on row -1 (kb: its position in this
+// item, folded into group 0) or on rows ne, ne+1 (the last two rows of the
+// top item, folded into group ne-1); tables with larger shifts take the
+// explicit path.
 template <typename T, int CE>
-__device__ __forceinline__ void gather_acc(const Tab<T> &tb, const T *__restrict__ X, int cs, int ne,
-                                           int dp, int i0, T acc[CE])
+__device__ __forceinline__ void gather(const Tab<T> &tb, int nd, const T *__restrict__ X, int cs, int ne,
+                                       int dp, int r0, bool top, int kb, T acc[CE])
 {
+#pragma unroll
+  for (int k = 0; k < CE; ++k) acc[k] = (T)0;
   const int e0 = tb.start[dp], e1 = tb.start[dp + 1];
-  const bool low = i0 == 0;
-  const int kt = ne - 1 - i0;
-  const bool top = kt < CE;
-  T accLow = (T)0, accTop = (T)0;
+  if ((tb.start[nd + 1] & 1) == 0) {
 #pragma unroll 2
-  for (int e = e0; e < e1; ++e) {
-    const unsigned key = tb.key[e];
-    const int d = key & 0xff, di = (int)(key >> 8) - 128;
-    const T cl = tb.coef[2 * e], cr = tb.coef[2 * e + 1];
-    const T *col = X + d * cs;
-    if (di >= -1 && di <= 1) {
-      const T *w = col + (i0 - di - 1);
+    for (int e = e0; e < e1; ++e) {
+      const unsigned key = tb.key[e];
+      const int d = key & 0xff, di = (int)(key >> 8) - 128;
+      const T c = tb.c[e], cr = c * tb.we[d], cl = c - cr;
+      const T *w = X + d * cs + (r0 - di - 1);
       T x[CE + 1];
 #pragma unroll
       for (int k = 0; k <= CE; ++k) x[k] = w[k];
 #pragma unroll
       for (int k = 0; k < CE; ++k) acc[k] += cl * x[k + 1] + cr * x[k];
-      accLow += (low && di < 0) ? cl * x[0] : (T)0;        // group 0 of the source
-      if (top && di >= 0) {
-        T x1 = col[ne - 1];
-        accTop += di == 0 ? cr * x1 : cl * x1 + cr * (x1 + col[ne - 2]);
-      }
-    } else {                                           // shifts of two or more groups
+    }
+    if (top) acc[CE - 3] += acc[CE - 2] + acc[CE - 1];
+#pragma unroll
+    for (int k = 0; k + 1 < CE; ++k) acc[k + 1] += k == kb ? acc[k] : (T)0;
+  } else {
+    for (int e = e0; e < e1; ++e) {
+      const unsigned key = tb.key[e];
+      const int d = key & 0xff, di = (int)(key >> 8) - 128;
+      const T c = tb.c[e], cr = c * tb.we[d], cl = c - cr;
+      const T *col = X + d * cs;
 #pragma unroll
       for (int k = 0; k < CE; ++k) {
-        int iL = i0 + k - di, iR = iL - 1;
+        const int i = r0 + k;
+        if (i < 0 || i >= ne) continue;
+        const int iL = i - di, iR = iL - 1;
         T v = (T)0;
         if (iL >= 0 && iL < ne) v += cl * col[iL];
         if (iR >= 0 && iR < ne) v += cr * col[iR];
+        if (i == 0) {                                   // sent below group 0
+          for (int j = 0; j < ne && j + di < 0; ++j) v += cl * col[j];
+          for (int j = 0; j < ne && j + di + 1 < 0; ++j) v += cr * col[j];
+        }
+        if (i == ne - 1) {                              // sent above group ne-1
+          for (int j = max(0, ne - di); j < ne; ++j) v += cl * col[j];
+          for (int j = max(0, ne - 1 - di); j < ne; ++j) v += cr * col[j];
+        }
         acc[k] += v;
-      }
-      if (low && di < 0) {
-        for (int i = 0; i < ne && i < -di; ++i) accLow += cl * col[i];
-        for (int i = 0; i < ne && i < -di - 1; ++i) accLow += cr * col[i];
-      }
-      if (top && di >= 0) {
-        for (int i = max(0, ne - di); i < ne; ++i) accTop += cl * col[i];
-        for (int i = max(0, ne - 1 - di); i < ne; ++i) accTop += cr * col[i];
       }
     }
   }
-  acc[0] += accLow;
-#pragma unroll
-  for (int k = 0; k < CE; ++k)
-    if (k == kt) acc[k] += accTop;
 }
 
 template <typename T>
@@ -391,37 +401,12 @@ __device__ inline double wave_sum(double v)
   return v;
 }
 
-// column dp of one side's species-s data as content density x G_i aS(dp),
-// rows i = ch, ch + nch, ...; guard rows are zeroed by the caller
-template <typename T>
-__device__ inline void load_column(const DevGrid &g, const SideDesc &sd, const T *__restrict__ f,
-                                   const T *__restrict__ feq, int s, const double *Gs, double aS,
-                                   int dp, int ch, int nch, int cs, T *X)
+// frame weight psi^6 u0 dOmega of direction d in frame k of a face
+__device__ inline double frame_weight(const DevGrid &g, const FaceAux &A, int k, int d)
 {
-  const int nd = g.ndir, ne = g.ne;
-  const T *src = f + (size_t)sd.z * g.blk + (size_t)s * g.eblk;
-  int sd_col = dp;
-  if (sd.kind == btx::SIDE_MIRROR) {
-    int j = dp / g.nphi, k = dp - j * g.nphi;
-    sd_col = (g.nmu - 1 - j) * g.nphi + k;
-  }
-  for (int i = ch; i < ne; i += nch) {
-    double v;
-    if (sd.kind == btx::SIDE_ZONE || sd.kind == btx::SIDE_MIRROR) v = (double)src[i * nd + sd_col];
-    else if (sd.kind == btx::SIDE_EQ) v = (double)feq[((size_t)sd.z * g.ns + s) * ne + i];
-    else v = 0.0;
-    X[dp * cs + i] = (T)(v * Gs[i] * aS);
-  }
-}
-
-template <typename T>
-__device__ inline void zero_guards(T *X, int nd, int ne, int cs, int tid, int nthr)
-{
-  for (int q = tid; q < 4 * nd; q += nthr) {
-    int d = q >> 2, r = q & 3;
-    int row = r < 2 ? r - 2 : ne + (r - 2);
-    X[d * cs + row] = (T)0;
-  }
+  const double *nv = g.nvec + 3 * d;
+  double vdn = A.v[k][0] * nv[0] + A.v[k][1] * nv[1] + A.v[k][2] * nv[2];
+  return A.p6[k] * A.gam[k] * (1.0 + vdn) * g.dOm[d];
 }
 
 // ------------------------------------------------------------ table kernel
@@ -436,6 +421,7 @@ table_kernel(DevGrid g, const FaceDesc *__restrict__ faces, char *__restrict__ t
              FaceAux *__restrict__ aux, int face0)
 {
   extern __shared__ __align__(16) char lds[];
+  __shared__ int flg[kTables];
   const int fid = face0 + blockIdx.x;
   const FaceDesc &F = faces[fid];
   const int nd = g.ndir, tid = threadIdx.x, nthr = blockDim.x;
@@ -447,8 +433,15 @@ table_kernel(DevGrid g, const FaceDesc *__restrict__ faces, char *__restrict__ t
   int *cnt = (int *)data;                      // 4 nd
   int *cur = cnt + 4 * nd;                     // 4 nd
   int *rtg = cur + 4 * nd;                     // 16 nd
-  T *rcf = (T *)(rtg + 16 * nd);               // 32 nd
-#define TB(t) tab_at<T>(tabs + (t) * tstride, nd)
+  T *rcf = (T *)(rtg + 16 * nd);               // 16 nd
+  auto tw = [&](int t, T *&c, T *&we, unsigned short *&key, unsigned short *&start) {
+    char *b = tabs + t * tstride;
+    c = (T *)b;
+    we = c + 4 * nd;
+    key = (unsigned short *)(we + nd);
+    start = key + 4 * nd;
+  };
+  if (tid < kTables) flg[tid] = 0;
   if (tid == 0) {
     Frame a = side_frame(g, F.L), b = side_frame(g, F.R);
     frm[0] = side_frame(g, F.Lm);
@@ -468,7 +461,6 @@ table_kernel(DevGrid g, const FaceDesc *__restrict__ faces, char *__restrict__ t
   }
   const bool rot = g.geom != 2;
   const int ax = F.axis;
-  // table t: 0 Lm->L, 1 R->L, 2 L->R, 3 Rp->R, 4 L->s, 5 R->s, 6 s->L, 7 s->R
   for (int round = 0; round < 2; ++round) {
     __syncthreads();
     for (int q = tid; q < 4 * nd; q += nthr) cnt[q] = 0;
@@ -479,59 +471,67 @@ table_kernel(DevGrid g, const FaceDesc *__restrict__ faces, char *__restrict__ t
       const int di_ = (t == 0 || t == 1 || t == 6) ? 1 : (t == 2 || t == 3 || t == 7) ? 2 : 4;
       const Frame S = frm[si], D = frm[di_];
       int rt[4], di;
-      double rl[4], rr[4];
-      remap_source(g, S, D, ax, rot, same_frame(S, D), d, rt, rl, rr, di);
+      double cw[4], we;
+      remap_source(g, S, D, ax, rot, same_frame(S, D), d, rt, cw, we, di);
+      T *c, *wev;
+      unsigned short *key, *start;
+      tw(t, c, wev, key, start);
+      wev[d] = (T)we;
+      if (di < -1 || di > 1) atomicOr(&flg[t], 1);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         rtg[q * 4 + r] = rt[r] >= 0 ? (rt[r] | ((di + 128) << 16)) : -1;
-        rcf[(q * 4 + r) * 2] = (T)rl[r];
-        rcf[(q * 4 + r) * 2 + 1] = (T)rr[r];
+        rcf[q * 4 + r] = (T)cw[r];
         if (rt[r] >= 0) atomicAdd(&cnt[tl * nd + rt[r]], 1);
       }
     }
     __syncthreads();
     if (tid < 4) {                                     // exclusive scan per table
-      Tab<T> tt = TB(4 * round + tid);
+      T *c, *wev;
+      unsigned short *key, *start;
+      tw(4 * round + tid, c, wev, key, start);
       int acc = 0;
       for (int d = 0; d < nd; ++d) {
-        tt.start[d] = (unsigned short)acc;
+        start[d] = (unsigned short)acc;
         cur[tid * nd + d] = acc;
         acc += cnt[tid * nd + d];
       }
-      tt.start[nd] = (unsigned short)acc;
+      start[nd] = (unsigned short)acc;
+      start[nd + 1] = (unsigned short)flg[4 * round + tid];
     }
     __syncthreads();
     for (int q = tid; q < 4 * nd; q += nthr) {         // records into their target lists
       int tl = q / nd, d = q - tl * nd;
-      Tab<T> tt = TB(4 * round + tl);
+      T *c, *wev;
+      unsigned short *key, *start;
+      tw(4 * round + tl, c, wev, key, start);
       for (int r = 0; r < 4; ++r) {
         int v = rtg[q * 4 + r];
         if (v < 0) continue;
         int tg = v & 0xffff, dib = v >> 16;
         int slot = atomicAdd(&cur[tl * nd + tg], 1);
-        tt.key[slot] = (unsigned short)(d | (dib << 8));
-        tt.coef[2 * slot] = rcf[(q * 4 + r) * 2];
-        tt.coef[2 * slot + 1] = rcf[(q * 4 + r) * 2 + 1];
+        key[slot] = (unsigned short)(d | (dib << 8));
+        c[slot] = rcf[q * 4 + r];
       }
     }
     __syncthreads();
     for (int q = tid; q < 4 * nd; q += nthr) {         // fixed summation order: sort by key
       int tl = q / nd, d = q - tl * nd;
-      Tab<T> tt = TB(4 * round + tl);
-      int a = tt.start[d], b = tt.start[d + 1];
+      T *c, *wev;
+      unsigned short *key, *start;
+      tw(4 * round + tl, c, wev, key, start);
+      int a = start[d], b = start[d + 1];
       for (int x = a + 1; x < b; ++x) {
-        unsigned short kx = tt.key[x];
-        T c0 = tt.coef[2 * x], c1 = tt.coef[2 * x + 1];
+        unsigned short kx = key[x];
+        T c0 = c[x];
         int y = x - 1;
-        while (y >= a && tt.key[y] > kx) {
-          tt.key[y + 1] = tt.key[y];
-          tt.coef[2 * y + 2] = tt.coef[2 * y];
-          tt.coef[2 * y + 3] = tt.coef[2 * y + 1];
+        while (y >= a && key[y] > kx) {
+          key[y + 1] = key[y];
+          c[y + 1] = c[y];
           --y;
         }
-        tt.key[y + 1] = kx;
-        tt.coef[2 * y + 2] = c0;
-        tt.coef[2 * y + 3] = c1;
+        key[y + 1] = kx;
+        c[y + 1] = c0;
       }
     }
   }
@@ -563,18 +563,56 @@ table_kernel(DevGrid g, const FaceDesc *__restrict__ faces, char *__restrict__ t
   const uint4 *src = (const uint4 *)tabs;
   const int n16 = (int)(kTables * tstride / 16);
   for (int q = tid; q < n16; q += nthr) dst[q] = src[q];
-#undef TB
 }
 
 // ------------------------------------------------------------ face kernel
 
+// one side's species-s values of a work item's load rows (li, li + kNch, ...)
 template <typename T, int CE>
-__global__ void __launch_bounds__(kMaxFaceThreads)
+__device__ __forceinline__ void fetch_side(const DevGrid &g, const SideDesc &sd, const T *__restrict__ f,
+                                           const T *__restrict__ feq, int s, int li, int ld, T v[CE])
+{
+  const int nd = g.ndir, ne = g.ne;
+  const T *src = f + (size_t)sd.z * g.blk + (size_t)s * g.eblk + ld;
+  const T *eq = feq + ((size_t)sd.z * g.ns + s) * ne;
+#pragma unroll
+  for (int m = 0; m < CE; ++m) {
+    const int i = li + kNch * m;
+    T x = (T)0;
+    if (i < ne) {
+      if (sd.kind == btx::SIDE_ZONE || sd.kind == btx::SIDE_MIRROR) x = src[(size_t)i * nd];
+      else if (sd.kind == btx::SIDE_EQ) x = eq[i];
+    }
+    v[m] = x;
+  }
+}
+
+template <typename T, int CE>
+__device__ __forceinline__ void store_side(const T v[CE], const T gl[CE], T a, int col, int li, int ne, int cs,
+                                           T *X)
+{
+#pragma unroll
+  for (int m = 0; m < CE; ++m) {
+    const int i = li + kNch * m;
+    if (i < ne) X[col * cs + i] = v[m] * gl[m] * a;
+  }
+}
+
+// One workgroup per face, kNch work items per direction.  Per species:
+//   load    the four stencil zones' blocks (coalesced rows, transposed into
+//           direction-major LDS columns as number content)
+//   phase 1 MC-limited slopes of both sides in their own frames (Sec. 3.3.2)
+//           and the reconstructed donor values
+//   phase 2 Lax-Wendroff half-step source in the interface frame; angle sums
+//           by wave shuffles; implicit interface collision (Eq. halfstep);
+//           blend (Sec. 3.3.3) into flux and donor contents
+//   phase 3 remapped content change of both sides (Eq. fullstep)
+template <typename T, int CE, int MAXT>
+__global__ void __launch_bounds__(MAXT)
 face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restrict__ tabs_g,
-            const FaceAux *__restrict__ aux,
-            const T *__restrict__ f, const T *__restrict__ ka, const T *__restrict__ ks,
-            const T *__restrict__ feq, T *__restrict__ dN, double *__restrict__ tally, double dt,
-            int face0)
+            const FaceAux *__restrict__ aux, const T *__restrict__ f, const T *__restrict__ ka,
+            const T *__restrict__ ks, const T *__restrict__ feq, T *__restrict__ dN,
+            double *__restrict__ tally, double dt, int face0)
 {
   extern __shared__ __align__(16) char lds[];
   const int fid = face0 + blockIdx.x;
@@ -585,68 +623,104 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
     for (size_t q = tid; q < 2 * (size_t)g.blk; q += nthr) outL[q] = (T)0;
     return;
   }
+  const int nrow = col_rows(CE), cs = nrow, gb = kNch * CE - ne;
   // ---- LDS carve-up
   const size_t tstride = tab_stride(nd, sizeof(T));
+  const size_t bb = buf_bytes(nd, CE, sizeof(T));
   char *p = lds;
-  char *tabs = p;              p += kTables * tstride;
-  char *data = p;              p += data_bytes(nd, ne, CE, sizeof(T));
-  const size_t bb = buf_bytes(nd, ne, CE, sizeof(T));
-  const int cs = col_stride(ne, CE);
-  T *X0 = (T *)(data) + 2, *X1 = (T *)(data + bb) + 2, *X2 = (T *)(data + 2 * bb) + 2;
-  double *Gs = (double *)p;    p += align16(ne * 8);
-  double *iG = (double *)p;    p += align16(ne * 8);
-  double *kas = (double *)p;   p += align16(ne * 8);
-  double *kss = (double *)p;   p += align16(ne * 8);
-  double *fes = (double *)p;   p += align16(ne * 8);
-  double *sav = (double *)p;   p += align16(ne * 8);
-  double *red = (double *)p;   p += align16(32 * 8);
+  const char *tabs = p;         p += kTables * tstride;
+  char *bufs = p;               p += 4 * bb;
+  T *XLm = (T *)(bufs) + gb, *XL = (T *)(bufs + bb) + gb, *XR = (T *)(bufs + 2 * bb) + gb,
+    *XRp = (T *)(bufs + 3 * bb) + gb;
+  T *rG = (T *)p + gb;          p += align16(nrow * sizeof(T));
+  T *riG = (T *)p + gb;         p += align16(nrow * sizeof(T));
+  T *rsrc = (T *)p + gb;        p += align16(nrow * sizeof(T));
+  T *rw = (T *)p + gb;          p += align16(nrow * sizeof(T));
+  double *rc0 = (double *)p + gb;  p += align16(nrow * 8);
+  double *rc1 = (double *)p + gb;  p += align16(nrow * 8);
+  int *rthick = (int *)p + gb;  p += align16(nrow * 4);
+  double *spart = (double *)p;  p += align16(16 * nrow * 8);
+  double *tpart = (double *)p;
 
 #define TB(t) tab_at<T>(tabs + (t) * tstride, nd)
 
-  // ---- frame data of this face (precomputed once per background)
+  // ---- remap tables of this face (built once per background by table_kernel)
+  {
+    const uint4 *src = (const uint4 *)(tabs_g + (size_t)fid * kTables * tstride);
+    uint4 *dst = (uint4 *)lds;
+    const int n16 = (int)(kTables * tstride / 16);
+    for (int q = tid; q < n16; q += nthr) dst[q] = src[q];
+  }
+  // ---- zero rows of the data buffers, per-row constants outside 0 .. ne-1
+  {
+    const int ng = nrow - ne;
+    for (int q = tid; q < 4 * nd * ng; q += nthr) {
+      int b = q / (nd * ng), rem = q - b * nd * ng, d = rem / ng, r = rem - d * ng;
+      ((T *)(bufs + b * bb))[d * cs + (r < gb ? r : r + ne)] = (T)0;
+    }
+    for (int q = tid; q < nrow; q += nthr) {
+      const int r = q - gb;
+      const bool in = r >= 0 && r < ne;
+      rG[r] = in ? (T)g.G[r] : (T)0;
+      riG[r] = in ? (T)(1.0 / g.G[r]) : (T)0;
+      if (!in) { rsrc[r] = (T)0; rw[r] = (T)0; rc0[r] = 0.0; rc1[r] = 0.0; rthick[r] = 0; }
+    }
+  }
   const FaceAux &A = aux[fid];
-  for (int i = tid; i < ne; i += nthr) { Gs[i] = g.G[i]; iG[i] = 1.0 / g.G[i]; }
   const int ax = F.axis;
   const bool slopeL = F.L.slope, slopeR = F.R.slope && !F.self;
+  const bool ghost = F.L.kind != btx::SIDE_ZONE || F.R.kind != btx::SIDE_ZONE;
   const double gs = A.gam[4];
   const double ap4 = A.alpha[4] * dsq(A.psi[4] * A.psi[4]);
   const double vn = A.v[4][ax];
   const double Uadv = ap4 * gs * vn;
   const double tau = 0.5 * A.alpha[4] * dt / gs;
-  // ---- remap tables of this face (built once per background by table_kernel)
-  {
-    const uint4 *src = (const uint4 *)(tabs_g + (size_t)fid * kTables * tstride);
-    uint4 *dst = (uint4 *)tabs;
-    const int n16 = (int)(kTables * tstride / 16);
-    for (int q = tid; q < n16; q += nthr) dst[q] = src[q];
-  }
-  __syncthreads();
 
-  // ---- per species
-  const int nch = g.nch;
-  const int nitems = nd * nch;
-  const bool own = tid < nitems;
-  const int dp = own ? tid / nch : 0;                 // neighbouring lanes share a target list
-  const int ch = own ? tid - dp * nch : 0;
-  // this thread's direction: frame weights psi^6 u0 dOmega (frames Lm, L, R,
-  // Rp, interface), interface speeds (flux integral with zero shift) and the
-  // donor speeds of both sides (cell-centre direction in the interface basis)
-  double aFr[5];
-  double Urad_d, Vn_d, UL_d, UR_d;
+  // ---- load mapping: direction ld, rows li, li + kNch, ...
+  const bool ldown = tid < kNch * nd;
+  const int ld = ldown ? tid % nd : 0, li = ldown ? tid / nd : ne;
+  T gl[CE];
+#pragma unroll
+  for (int m = 0; m < CE; ++m) {
+    const int i = li + kNch * m;
+    gl[m] = i < ne ? (T)g.G[i] : (T)0;
+  }
+  const SideDesc *sides[4] = { &F.Lm, &F.L, &F.R, &F.Rp };
+  int colS[4];
+  T aS_[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int col = ld;
+    if (sides[k]->kind == btx::SIDE_MIRROR) {
+      int j = ld / g.nphi, kk = ld - j * g.nphi;
+      col = (g.nmu - 1 - j) * g.nphi + kk;
+    }
+    colS[k] = col;
+    aS_[k] = (T)frame_weight(g, A, k, col);
+  }
+
+  // ---- compute mapping: target direction dp, rows r0 .. r0 + CE - 1
+  const bool own = tid < kNch * nd;
+  const int dp = own ? tid / kNch : 0, ch = tid % kNch;
+  const int r0 = ne + 2 - (kNch - ch) * CE;
+  const bool top = ch == kNch - 1;
+  const int kb = -1 - r0;
+  T iaL, iaR, iaS, cv, kF, uLp, uap, uRn, uan;
+  double dOd;
   {
     const double *nv = g.nvec + 3 * dp;
     const double dO = g.dOm[dp];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      double vdn = A.v[k][0] * nv[0] + A.v[k][1] * nv[1] + A.v[k][2] * nv[2];
-      aFr[k] = A.p6[k] * A.gam[k] * (1.0 + vdn) * dO;
-    }
+    iaL = (T)(1.0 / frame_weight(g, A, 1, dp));
+    iaR = (T)(1.0 / frame_weight(g, A, 2, dp));
+    iaS = (T)(1.0 / frame_weight(g, A, 4, dp));
+    // interface speeds (flux integral with zero shift) and the donor speeds of
+    // both sides (cell-centre direction expressed in the interface basis)
     const double kvs = gs * gs / (gs + 1.0);
     double vdn = A.v[4][0] * nv[0] + A.v[4][1] * nv[1] + A.v[4][2] * nv[2];
     double u0 = gs * (1.0 + vdn);
     double un = nv[ax] + (kvs * vdn + gs) * vn;
-    Urad_d = ap4 * (nv[ax] + kvs * vdn * vn);
-    Vn_d = A.alpha[4] * un / (A.psi[4] * A.psi[4] * u0);
+    const double Urad = ap4 * (nv[ax] + kvs * vdn * vn);
+    const double Vn = A.alpha[4] * un / (A.psi[4] * A.psi[4] * u0);
     double Us[2];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
@@ -658,23 +732,34 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
       const double *M = A.M[side];
       Us[side] = ap4 * (M[3 * ax] * e0 + M[3 * ax + 1] * e1 + M[3 * ax + 2] * e2);
     }
-    UL_d = Us[0];
-    UR_d = Us[1];
+    const double gwd = dO * dt * F.area;
+    cv = (T)(-0.5 * dt * Vn / F.h);
+    kF = (T)(Urad * gwd);
+    uLp = (T)(fmax(Us[0], 0.0) * gwd);
+    uRn = (T)(fmax(-Us[1], 0.0) * gwd);
+    uap = (T)(fmax(Uadv, 0.0) * gwd);
+    uan = (T)(fmax(-Uadv, 0.0) * gwd);
+    dOd = own ? dO : 0.0;
   }
-  const int i0 = ch * CE;
-  const double cA = dt * F.area;
-  const int lane = tid & 63, wave = tid >> 6, nwaves = (nthr + 63) >> 6;
-  const double aLd = aFr[1], aRd = aFr[2], aSd = aFr[4];
+  const T dL = (T)F.dL, dR = (T)F.dR, ih = (T)(1.0 / F.h);
+  const T ihLm = (T)(1.0 / F.hLm), ihRp = (T)(1.0 / F.hRp);
+  const int lane = tid & 63, wave = tid >> 6, nw = (nthr + 63) >> 6;
+
 #pragma unroll 1
   for (int s = 0; s < g.ns; ++s) {
-    if (own) {
-      load_column<T>(g, F.L, f, feq, s, Gs, aLd, dp, ch, nch, cs, X1);
-      load_column<T>(g, F.R, f, feq, s, Gs, aRd, dp, ch, nch, cs, X2);
-      if (slopeL) load_column<T>(g, F.Lm, f, feq, s, Gs, aFr[0], dp, ch, nch, cs, X0);
+    // ---- load the stencil blocks as content densities
+    {
+      T v0[CE], v1[CE], v2[CE], v3[CE];
+      if (slopeL) fetch_side<T, CE>(g, F.Lm, f, feq, s, li, ld, v0);
+      fetch_side<T, CE>(g, F.L, f, feq, s, li, ld, v1);
+      fetch_side<T, CE>(g, F.R, f, feq, s, li, ld, v2);
+      if (slopeR) fetch_side<T, CE>(g, F.Rp, f, feq, s, li, ld, v3);
+      if (slopeL) store_side<T, CE>(v0, gl, aS_[0], colS[0], li, ne, cs, XLm);
+      store_side<T, CE>(v1, gl, aS_[1], colS[1], li, ne, cs, XL);
+      store_side<T, CE>(v2, gl, aS_[2], colS[2], li, ne, cs, XR);
+      if (slopeR) store_side<T, CE>(v3, gl, aS_[3], colS[3], li, ne, cs, XRp);
     }
-    zero_guards<T>(X0, nd, ne, cs, tid, nthr);
-    zero_guards<T>(X1, nd, ne, cs, tid, nthr);
-    zero_guards<T>(X2, nd, ne, cs, tid, nthr);
+    // ---- per-group interface opacities and collision coefficients
     for (int i = tid; i < ne; i += nthr) {
       double a_ = 0.0, b_ = 0.0, e_ = 0.0;
       if (!F.zero_opacity) {
@@ -683,155 +768,129 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
         b_ = 0.5 * ((double)ks[l] + (double)ks[r]);
         e_ = 0.5 * ((double)feq[l] + (double)feq[r]);
       }
-      kas[i] = a_; kss[i] = b_; fes[i] = e_;
+      const double den = 1.0 + tau * (a_ + b_);
+      rc0[i] = 1.0 / den;
+      rc1[i] = tau * b_ / (1.0 + tau * a_) / den;
+      rsrc[i] = (T)(tau * a_ * e_);
+      rw[i] = (T)exp(-(a_ + b_) * F.h);
+      rthick[i] = sizeof(T) == 8 || tau * (a_ + b_) > g.fp64_thr;
     }
     __syncthreads();
-    // phase 1: limited slopes and reconstructed donor values (own frames)
-    T fl[CE], fr[CE], sl[CE], EL[CE], ER[CE];
-    if (own) {
+    // ---- phase 1: limited slopes and reconstructed donor values
+    T EL[CE], ER[CE], Sv[CE];
+    {
+      T fl[CE], fr[CE], sl[CE];
 #pragma unroll
       for (int k = 0; k < CE; ++k) {
-        int i = i0 + k;
-        bool in = i < ne;
-        fl[k] = in ? (T)((double)X1[dp * cs + i] * iG[i] / aLd) : (T)0;
-        fr[k] = in ? (T)((double)X2[dp * cs + i] * iG[i] / aRd) : (T)0;
+        const int r = r0 + k;
+        fl[k] = XL[dp * cs + r] * riG[r] * iaL;
+        fr[k] = XR[dp * cs + r] * riG[r] * iaR;
         sl[k] = (T)0;
       }
       if (slopeL) {
         T a[CE], b[CE];
-#pragma unroll
-        for (int k = 0; k < CE; ++k) a[k] = b[k] = (T)0;
-        gather_acc<T, CE>(TB(0), X0, cs, ne, dp, i0, a);
-        gather_acc<T, CE>(TB(1), X2, cs, ne, dp, i0, b);
+        gather<T, CE>(TB(0), nd, XLm, cs, ne, dp, r0, top, kb, a);
+        gather<T, CE>(TB(1), nd, XR, cs, ne, dp, r0, top, kb, b);
 #pragma unroll
         for (int k = 0; k < CE; ++k) {
-          int i = min(i0 + k, ne - 1);
-          T sc = (T)(iG[i] / aLd);
-          sl[k] = mc_limiter<T>((fl[k] - a[k] * sc) / (T)F.hLm, (b[k] * sc - fl[k]) / (T)F.h);
+          const T sc = riG[r0 + k] * iaL;
+          sl[k] = mc_limiter<T>((fl[k] - a[k] * sc) * ihLm, (b[k] * sc - fl[k]) * ih);
         }
       }
 #pragma unroll
-      for (int k = 0; k < CE; ++k) EL[k] = fl[k] + (T)F.dL * sl[k];
-    }
-    if (slopeR) {
-      __syncthreads();                                 // X0 (Lm) no longer read
-      if (own) load_column<T>(g, F.Rp, f, feq, s, Gs, aFr[3], dp, ch, nch, cs, X0);
-      __syncthreads();
-      if (own) {
+      for (int k = 0; k < CE; ++k) EL[k] = fl[k] + dL * sl[k];
+      if (slopeR) {
         T a[CE], b[CE];
-#pragma unroll
-        for (int k = 0; k < CE; ++k) a[k] = b[k] = (T)0;
-        gather_acc<T, CE>(TB(2), X1, cs, ne, dp, i0, a);
-        gather_acc<T, CE>(TB(3), X0, cs, ne, dp, i0, b);
+        gather<T, CE>(TB(2), nd, XL, cs, ne, dp, r0, top, kb, a);
+        gather<T, CE>(TB(3), nd, XRp, cs, ne, dp, r0, top, kb, b);
 #pragma unroll
         for (int k = 0; k < CE; ++k) {
-          int i = min(i0 + k, ne - 1);
-          T sc = (T)(iG[i] / aRd);
-          ER[k] = fr[k] + (T)F.dR * mc_limiter<T>((fr[k] - a[k] * sc) / (T)F.h, (b[k] * sc - fr[k]) / (T)F.hRp);
+          const T sc = riG[r0 + k] * iaR;
+          ER[k] = fr[k] + dR * mc_limiter<T>((fr[k] - a[k] * sc) * ih, (b[k] * sc - fr[k]) * ihRp);
         }
-      }
-    } else if (own) {
+      } else {
 #pragma unroll
-      for (int k = 0; k < CE; ++k) ER[k] = F.self ? fr[k] + (T)F.dR * sl[k] : fr[k];
-    }
-    // phase 2a: Lax-Wendroff half-step source S in the interface frame
-    T Sv[CE];
-    if (own) {
-      T A[CE], B[CE];
-#pragma unroll
-      for (int k = 0; k < CE; ++k) A[k] = B[k] = (T)0;
-      gather_acc<T, CE>(TB(4), X1, cs, ne, dp, i0, A);
-      gather_acc<T, CE>(TB(5), X2, cs, ne, dp, i0, B);
-      const T cv = (T)(-0.5 * dt * Vn_d / F.h);
-#pragma unroll
-      for (int k = 0; k < CE; ++k) {
-        int i = min(i0 + k, ne - 1);
-        T sc = (T)(iG[i] / aSd);
-        T a = A[k] * sc, b = B[k] * sc;
-        Sv[k] = (T)0.5 * (a + b) + cv * (b - a) + (T)(tau * kas[i] * fes[i]);
+        for (int k = 0; k < CE; ++k) ER[k] = F.self ? fr[k] + dR * sl[k] : fr[k];
       }
     }
-    __syncthreads();                                   // all reads of X0..X2 done
-    if (own) {
-#pragma unroll
-      for (int k = 0; k < CE; ++k)
-        if (i0 + k < ne) X0[dp * cs + i0 + k] = Sv[k];
-    }
-    __syncthreads();
-    for (int i = wave; i < ne; i += nwaves) {          // <S> per group, FP64, fixed order
-      double acc = 0.0;
-      for (int d = lane; d < nd; d += 64) acc += (double)X0[d * cs + i] * g.dOm[d];
-      acc = wave_sum(acc);
-      if (lane == 0) sav[i] = acc / (4.0 * kPi);
-    }
-    __syncthreads();
-    // phase 2b: interface collision, blend weights and content fluxes
-    if (own) {
-      const double dO = g.dOm[dp];
-#pragma unroll
-      for (int k = 0; k < CE; ++k) {
-        int i = i0 + k;
-        if (i >= ne) break;
-        double ka_ = kas[i], ks_ = kss[i];
-        double flw;
-        if (sizeof(T) == 8 || tau * (ka_ + ks_) > g.fp64_thr) {
-          flw = ((double)Sv[k] + tau * ks_ * sav[i] / (1.0 + tau * ka_)) / (1.0 + tau * (ka_ + ks_));
-        } else {
-          float t = (float)tau, a = (float)ka_, b = (float)ks_;
-          flw = ((float)Sv[k] + t * b * (float)sav[i] / (1.0f + t * a)) / (1.0f + t * (a + b));
-        }
-        double w = exp(-(ka_ + ks_) * F.h);
-        double gw = Gs[i] * dO * cA;
-        X1[dp * cs + i] = (T)((1.0 - w) * Urad_d * flw * gw);
-        double eL = w * fmax(UL_d, 0.0) + (1.0 - w) * fmax(Uadv, 0.0);
-        double eR = w * fmax(-UR_d, 0.0) + (1.0 - w) * fmax(-Uadv, 0.0);
-        X0[dp * cs + i] = (T)(eL * gw * (double)EL[k]);
-        X2[dp * cs + i] = (T)(eR * gw * (double)ER[k]);
-      }
-    }
-    __syncthreads();
-    // phase 3: content changes of both sides
-    double sumL = 0.0, sumR = 0.0;
-    if (own) {
+    // ---- phase 2: Lax-Wendroff half-step source S in the interface frame
+    {
       T a[CE], b[CE];
-#pragma unroll
-      for (int k = 0; k < CE; ++k) a[k] = b[k] = (T)0;
-      gather_acc<T, CE>(TB(6), X1, cs, ne, dp, i0, a);
-      gather_acc<T, CE>(TB(1), X2, cs, ne, dp, i0, b);
-      T *oL = outL + (size_t)s * g.eblk, *oR = outR + (size_t)s * g.eblk;
+      gather<T, CE>(TB(4), nd, XL, cs, ne, dp, r0, top, kb, a);
+      gather<T, CE>(TB(5), nd, XR, cs, ne, dp, r0, top, kb, b);
 #pragma unroll
       for (int k = 0; k < CE; ++k) {
-        int i = i0 + k;
-        if (i >= ne) break;
-        T v = -a[k] - X0[dp * cs + i] + b[k];
-        oL[i * nd + dp] = v;
+        const int r = r0 + k;
+        const T sc = riG[r] * iaS;
+        const T x = a[k] * sc, y = b[k] * sc;
+        Sv[k] = (T)0.5 * (x + y) + cv * (y - x) + rsrc[r];
+      }
+    }
+    // angle sums of S per group (FP64): lanes kNch apart share rows
+#pragma unroll
+    for (int k = 0; k < CE; ++k) {
+      double v = (double)Sv[k] * dOd;
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 8, 64);
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      if (lane < kNch) spart[wave * nrow + r0 + k + gb] = v;
+    }
+    __syncthreads();                                   // partial sums visible, buffers free
+    if (own) {
+#pragma unroll
+      for (int k = 0; k < CE; ++k) {
+        const int r = r0 + k;
+        if (r < 0 || r >= ne) continue;
+        double sav = 0.0;
+        for (int w = 0; w < nw; ++w) sav += spart[w * nrow + r + gb];
+        sav *= 1.0 / (4.0 * kPi);
+        T flw;
+        if (rthick[r]) flw = (T)((double)Sv[k] * rc0[r] + rc1[r] * sav);
+        else flw = (T)((float)Sv[k] * (float)rc0[r] + (float)rc1[r] * (float)sav);
+        const T w = rw[r], G = rG[r];
+        XLm[dp * cs + r] = ((T)1 - w) * kF * G * flw;
+        XL[dp * cs + r] = (w * (uLp - uap) + uap) * G * EL[k];
+        XR[dp * cs + r] = (w * (uRn - uan) + uan) * G * ER[k];
+      }
+    }
+    __syncthreads();
+    // ---- phase 3: content changes of both sides
+    double sumL = 0.0, sumR = 0.0;
+    {
+      T a[CE], b[CE];
+      T *oL = outL + (size_t)s * g.eblk, *oR = outR + (size_t)s * g.eblk;
+      gather<T, CE>(TB(6), nd, XLm, cs, ne, dp, r0, top, kb, a);
+      gather<T, CE>(TB(1), nd, XR, cs, ne, dp, r0, top, kb, b);
+#pragma unroll
+      for (int k = 0; k < CE; ++k) {
+        const int r = r0 + k;
+        if (!own || r < 0 || r >= ne) continue;
+        const T v = -a[k] - XL[dp * cs + r] + b[k];
+        oL[r * nd + dp] = v;
         sumL += (double)v;
       }
-#pragma unroll
-      for (int k = 0; k < CE; ++k) a[k] = b[k] = (T)0;
-      gather_acc<T, CE>(TB(7), X1, cs, ne, dp, i0, a);
-      gather_acc<T, CE>(TB(2), X0, cs, ne, dp, i0, b);
+      gather<T, CE>(TB(7), nd, XLm, cs, ne, dp, r0, top, kb, a);
+      gather<T, CE>(TB(2), nd, XL, cs, ne, dp, r0, top, kb, b);
 #pragma unroll
       for (int k = 0; k < CE; ++k) {
-        int i = i0 + k;
-        if (i >= ne) break;
-        T v = a[k] - X2[dp * cs + i] + b[k];
-        oR[i * nd + dp] = v;
+        const int r = r0 + k;
+        if (!own || r < 0 || r >= ne) continue;
+        const T v = a[k] - XR[dp * cs + r] + b[k];
+        oR[r * nd + dp] = v;
         sumR += (double)v;
       }
     }
-    if (F.L.kind != btx::SIDE_ZONE || F.R.kind != btx::SIDE_ZONE) {
-      double v = (F.L.kind != btx::SIDE_ZONE) ? sumL : sumR;
-      v = wave_sum(v);
-      if (lane == 0) red[wave] = v;
-      __syncthreads();
-      if (tid == 0) {
-        double t = 0.0;
-        for (int w = 0; w < nwaves; ++w) t += red[w];
-        tally[(size_t)fid * g.ns + s] += t;
-      }
+    if (ghost) {
+      double v = wave_sum(F.L.kind != btx::SIDE_ZONE ? sumL : sumR);
+      if (lane == 0) tpart[wave] = v;
     }
-    __syncthreads();
+    __syncthreads();                                   // buffers and partials free for the next species
+    if (ghost && tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < nw; ++w) t += tpart[w];
+      tally[(size_t)fid * g.ns + s] += t;
+    }
   }
 #undef TB
 }
@@ -979,11 +1038,41 @@ struct btx_ctx {
 
 namespace {
 
-// groups per face-kernel work item: kCE while the workgroup stays within
-// 1024 threads, else 16
+// groups per face work item: the smallest instantiated CE with kNch CE >=
+// ne + 3 whose chunking keeps groups -1 and 0 in one item ((ne + 2) not a
+// multiple of CE); 0 if there is none
+constexpr int kCEs[] = { 4, 5, 6, 7, 8, 12, 16 };
+
 int face_ce(const btx::Grid &g)
 {
-  return g.ndir * ((g.ne + kCE - 1) / kCE) <= kMaxFaceThreads ? kCE : 16;
+  for (int ce : kCEs)
+    if (kNch * ce >= g.ne + 3 && (g.ne + 2) % ce != 0) return ce;
+  return 0;
+}
+
+// kNch threads per direction: workgroups of up to 512 threads (up to 128
+// directions), else up to 1024
+bool face_wide(const btx::Grid &g) { return kNch * g.ndir > 512; }
+
+template <typename T, int MAXT>
+const void *face_fn_t(int ce)
+{
+  switch (ce) {
+  case 4: return (const void *)face_kernel<T, 4, MAXT>;
+  case 5: return (const void *)face_kernel<T, 5, MAXT>;
+  case 6: return (const void *)face_kernel<T, 6, MAXT>;
+  case 7: return (const void *)face_kernel<T, 7, MAXT>;
+  case 8: return (const void *)face_kernel<T, 8, MAXT>;
+  case 12: return (const void *)face_kernel<T, 12, MAXT>;
+  case 16: return (const void *)face_kernel<T, 16, MAXT>;
+  default: return nullptr;
+  }
+}
+
+template <typename T>
+const void *face_fn(const btx::Grid &g)
+{
+  return face_wide(g) ? face_fn_t<T, 1024>(face_ce(g)) : face_fn_t<T, 512>(face_ce(g));
 }
 
 DevGrid dev_grid(const btx_ctx *c)
@@ -993,7 +1082,6 @@ DevGrid dev_grid(const btx_ctx *c)
   d.nr = g.nr; d.nth = g.nth; d.ne = g.ne; d.nmu = g.nmu; d.nphi = g.nphi; d.ns = g.ns;
   d.ndir = g.ndir; d.nz = g.nz; d.geom = g.geom; d.phi_rule = g.phi_rule;
   d.eblk = g.ne * g.ndir; d.blk = g.ns * d.eblk;
-  d.nch = (g.ne + face_ce(g) - 1) / face_ce(g);
   d.nfaces = (int)g.faces.size();
   d.lnq = g.lnq; d.q = g.q; d.fp64_thr = g.fp64_thr;
   d.mu = c->d_mu; d.Phi = c->d_Phi; d.dOm = c->d_dOm; d.nvec = c->d_nvec; d.G = c->d_G;
@@ -1010,11 +1098,7 @@ btx_status upload(X **dst, const X *src, size_t n)
   return BTX_OK;
 }
 
-size_t face_lds(const btx::Grid &g, size_t szT)
-{
-  int nd = g.ndir, ne = g.ne, ce = face_ce(g);
-  return kTables * tab_stride(nd, szT) + data_bytes(nd, ne, ce, szT) + small_bytes(nd, ne);
-}
+size_t face_lds(const btx::Grid &g, size_t szT) { return face_lds_bytes(g.ndir, face_ce(g), szT); }
 
 void free_ctx(btx_ctx *c)
 {
@@ -1038,17 +1122,18 @@ btx_status launch_step(btx_ctx *c, double dt)
     c->ev_used += 3;
     HIP_TRY(hipEventRecord(e0, c->stream));
   }
+  const void *fn = face_fn<T>(c->g);
+  const FaceDesc *faces = c->d_faces;
+  const char *tabs = c->d_tabs;
+  const FaceAux *aux = c->d_aux;
+  const T *f = (const T *)c->d_f, *ka = (const T *)c->d_ka, *ks = (const T *)c->d_ks, *feq = (const T *)c->d_feq;
+  T *dN = (T *)c->d_dN;
+  double *tally = c->d_tally;
   const int maxgrid = 1 << 30;
   for (int f0 = 0; f0 < nf; f0 += maxgrid) {
     int nb = std::min(nf - f0, maxgrid);
-    if (face_ce(c->g) == kCE)
-      hipLaunchKernelGGL((face_kernel<T, kCE>), dim3(nb), dim3(c->face_threads), c->lds_bytes, c->stream, dg,
-                         c->d_faces, c->d_tabs, c->d_aux, (const T *)c->d_f, (const T *)c->d_ka, (const T *)c->d_ks,
-                         (const T *)c->d_feq, (T *)c->d_dN, c->d_tally, dt, f0);
-    else
-      hipLaunchKernelGGL((face_kernel<T, 16>), dim3(nb), dim3(c->face_threads), c->lds_bytes, c->stream, dg,
-                         c->d_faces, c->d_tabs, c->d_aux, (const T *)c->d_f, (const T *)c->d_ka, (const T *)c->d_ks,
-                         (const T *)c->d_feq, (T *)c->d_dN, c->d_tally, dt, f0);
+    void *args[] = { &dg, &faces, &tabs, &aux, &f, &ka, &ks, &feq, &dN, &tally, &dt, &f0 };
+    HIP_TRY(hipLaunchKernel(fn, dim3(nb), dim3(c->face_threads), args, c->lds_bytes, c->stream));
   }
   HIP_TRY(hipGetLastError());
   if (rec) HIP_TRY(hipEventRecord(e1, c->stream));
@@ -1086,8 +1171,6 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
   int nth = d->geometry == BTX_GEOM_AXISYM2D ? d->n_theta : 1;
   if (nth < 1) return fail(BTX_E_INVAL, "n_theta must be positive");
   if (d->n_mu * d->n_phi > 256) return fail(BTX_E_UNSUPPORTED, "at most 256 directions");
-  if (d->n_mu * d->n_phi * ((d->n_eps + 15) / 16) > kMaxFaceThreads)
-    return fail(BTX_E_UNSUPPORTED, "too many directions x groups per face");
   if (d->n_mu * d->n_phi * 4 > 65535) return fail(BTX_E_UNSUPPORTED, "too many directions");
   for (int a = 0; a < d->n_r; ++a)
     if (!(d->r_edges[a + 1] > d->r_edges[a])) return fail(BTX_E_INVAL, "r edges must ascend");
@@ -1123,8 +1206,11 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
   c->lds_bytes = face_lds(g, c->tsize);
   c->tab_lds = kTables * tab_stride(g.ndir, c->tsize) + align16(5 * sizeof(Frame)) +
                align16(scratch_bytes(g.ndir, c->tsize));
-  int items = g.ndir * ((g.ne + face_ce(g) - 1) / face_ce(g));
-  c->face_threads = std::max(64, ((items + 63) / 64) * 64);
+  if (face_ce(g) == 0) {
+    delete c;
+    return fail(BTX_E_UNSUPPORTED, "no face work-item shape for n_eps = " + std::to_string(d->n_eps));
+  }
+  c->face_threads = ((kNch * g.ndir + 63) / 64) * 64;
   btx_status st = BTX_OK;
   hipError_t he = hipSetDevice(hip_device);
   if (he != hipSuccess) { delete c; return fail(BTX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(he)); }
@@ -1132,8 +1218,7 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
   he = hipGetDeviceProperties(&prop, hip_device);
   if (he != hipSuccess) { delete c; return fail(BTX_E_DEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(he)); }
   {
-    const void *fk = c->tsize == 8 ? (face_ce(g) == kCE ? (const void *)face_kernel<double, kCE> : (const void *)face_kernel<double, 16>)
-                                   : (face_ce(g) == kCE ? (const void *)face_kernel<float, kCE> : (const void *)face_kernel<float, 16>);
+    const void *fk = c->tsize == 8 ? face_fn<double>(g) : face_fn<float>(g);
     he = hipFuncSetAttribute(fk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes);
     (void)he;
     const void *tk = c->tsize == 8 ? (const void *)table_kernel<double> : (const void *)table_kernel<float>;

@@ -57,7 +57,7 @@ btx_status fail(btx_status s, const std::string &msg)
 
 struct DevGrid {
   int nr, nth, ne, nmu, nphi, ns, ndir, nz, geom, phi_rule;
-  int eblk, blk, nfaces;
+  int eblk, blk, nfaces, nch, ce;   // face work items per direction, groups per item
   double lnq, q, fp64_thr;
   const double *mu, *Phi, *dOm, *nvec, *G, *eps, *vol;
   const double *vr, *vth, *alp, *psi;
@@ -178,17 +178,18 @@ __device__ inline double u0_dir(const Frame &f, const double *n)
 // ------------------------------------------------------------ LDS tables
 
 // A remap T_{S->D} of one face in gather form.  For every target direction d'
-// the entries [start[d'], start[d'+1]) hold the source direction and its energy
-// shift packed in 16 bits (src | (di + 128) << 8) and the (mu, Phi) corner
-// weight c.  On a logarithmic energy grid one shift serves every group: source
-// group i sends c (1 - we[src]) to group i + di and c we[src] to i + di + 1.
-// start[nd + 1] holds flags: bit 0 is set when some entry shifts by two or
-// more groups.  Tables act on number content; occupations are turned into
-// content before (x G_i a(d)) and back after (/ (G_i a(d'))) by the caller.
+// the entries [start[d'], start[d'+1]) hold the two energy-tap weights
+// (cl, cr) and a 16-bit key: on a logarithmic energy grid one shift di serves
+// every group, and source group i of direction src sends cl to group i + di and
+// cr to group i + di + 1.  Keys are first built as src | (di + 128) << 8 and
+// sorted; when every shift of the table is within one group (flag bit 0 of
+// start[nd + 1] clear) they are then replaced by the source window offset
+// src * cs - di + 2 in the direction-major data buffers.  Tables act on number
+// content; occupations are turned into content before (x G_i a(d)) and back
+// after (/ (G_i a(d'))) by the caller.
 template <typename T>
 struct Tab {
-  const T *c;                    // 4 nd corner weights
-  const T *we;                   // nd: upper energy-tap weight per source direction
+  const T *cw;                   // 2 x 4 nd tap weights (cl, cr)
   const unsigned short *key;     // 4 nd
   const unsigned short *start;   // nd + 2
 };
@@ -197,51 +198,49 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t
 
 __host__ __device__ inline size_t tab_stride(int nd, size_t szT)
 {
-  return align16(5 * (size_t)nd * szT + (5 * (size_t)nd + 2) * 2);
+  return align16(8 * (size_t)nd * szT + (5 * (size_t)nd + 2) * 2);
 }
 
 template <typename T>
 __device__ inline Tab<T> tab_at(const char *base, int nd)
 {
   Tab<T> t;
-  t.c = (const T *)base;
-  t.we = t.c + 4 * nd;
-  t.key = (const unsigned short *)(t.we + nd);
+  t.cw = (const T *)base;
+  t.key = (const unsigned short *)(t.cw + 8 * nd);
   t.start = t.key + 4 * nd;
   return t;
 }
 
-// Work items of the face kernel: kNch per target direction, each owning CE
-// consecutive rows (energy groups).  The kNch * CE rows of a direction end at
-// group ne + 1, so that the rows ne and ne + 1, which collect the content an
-// upward shift pushes past the top group, share a work item with group ne - 1,
-// and they start at or below group -1.
-constexpr int kNch = 4;
+// Work items of the face kernel: nch (a power of two) per target direction,
+// each owning CE consecutive rows (energy groups).  The nch * CE rows of a
+// direction end at group ne + 1, so that the rows ne and ne + 1, which collect
+// the content an upward shift pushes past the top group, share a work item
+// with group ne - 1, and they start at or below group -1.
 
 // Data buffers in LDS are direction-major: column d holds the rows
-// ne - kNch CE .. ne + 2 contiguously; rows outside 0 .. ne-1 are zero.  The
-// stride kNch CE + 3 is odd, so neighbouring lanes reading different columns
+// ne - nch CE .. ne + 2 contiguously; rows outside 0 .. ne-1 are zero.  The
+// stride nch CE + 3 is odd, so neighbouring lanes reading different columns
 // hit distinct banks.
-__host__ __device__ inline int col_rows(int ce) { return kNch * ce + 3; }
+__host__ __device__ inline int col_rows(int nch, int ce) { return nch * ce + 3; }
 
-__host__ __device__ inline size_t buf_bytes(int nd, int ce, size_t szT)
+__host__ __device__ inline size_t buf_bytes(int nd, int nch, int ce, size_t szT)
 {
-  return align16((size_t)nd * col_rows(ce) * szT);
+  return align16((size_t)nd * col_rows(nch, ce) * szT);
 }
 
 // table-build scratch for one round of 4 tables
 __host__ __device__ inline size_t scratch_bytes(int nd, size_t szT)
 {
-  return (size_t)4 * nd * 4 * 2 + (size_t)16 * nd * 4 + (size_t)16 * nd * szT;
+  return (size_t)4 * nd * 4 * 2 + (size_t)16 * nd * 4 + (size_t)32 * nd * szT;
 }
 
 // LDS of one face workgroup: 8 tables, 4 data buffers (Lm, L, R, Rp), per-row
 // constants (G, 1/G, source, blend weight as T; two collision coefficients as
 // FP64; a precision flag) and the wave partials of the angle sums and tally
-__host__ __device__ inline size_t face_lds_bytes(int nd, int ce, size_t szT)
+__host__ __device__ inline size_t face_lds_bytes(int nd, int nch, int ce, size_t szT)
 {
-  const size_t nrow = col_rows(ce);
-  return kTables * tab_stride(nd, szT) + 4 * buf_bytes(nd, ce, szT) + 4 * align16(nrow * szT) +
+  const size_t nrow = col_rows(nch, ce);
+  return kTables * tab_stride(nd, szT) + 4 * buf_bytes(nd, nch, ce, szT) + 4 * align16(nrow * szT) +
          2 * align16(nrow * 8) + align16(nrow * 4) + align16(16 * nrow * 8) + align16(16 * 8);
 }
 
@@ -257,19 +256,18 @@ __device__ inline void node_bracket(const double *x, int n, double v, int &L, in
   wR = (v - x[l]) / (x[l + 1] - x[l]);
 }
 
-// One source direction of one remap: frame chain, energy shift and upper tap
-// weight, (mu, Phi) corners.  rt[4] receive the targets (-1 unused), cw[4]
-// the corner weights.
+// One source direction of one remap: frame chain, energy shift and taps,
+// (mu, Phi) corners.  rt[4] receive the targets (-1 unused), rl/rr the tap
+// weights times the corner weight.
 __device__ void remap_source(const DevGrid &g, const Frame &S, const Frame &D, int axis, bool rot,
-                             bool ident, int d, int rt[4], double cw[4], double &we_out, int &di_out)
+                             bool ident, int d, int rt[4], double rl[4], double rr[4], int &di_out)
 {
   const double *n = g.nvec + 3 * d;
   rt[1] = rt[2] = rt[3] = -1;
-  cw[1] = cw[2] = cw[3] = 0.0;
+  rl[1] = rl[2] = rl[3] = rr[1] = rr[2] = rr[3] = 0.0;
   if (ident) {
     di_out = 0;
-    we_out = 0.0;
-    rt[0] = d; cw[0] = 1.0;
+    rt[0] = d; rl[0] = 1.0; rr[0] = 0.0;
     return;
   }
   double u[4] = { 1.0, n[0], n[1], n[2] }, o[4];
@@ -281,7 +279,6 @@ __device__ void remap_source(const DevGrid &g, const Frame &S, const Frame &D, i
   we = fmin(1.0, fmax(0.0, we));
   di = max(-127, min(127, di));
   di_out = di;
-  we_out = we;
   // direction
   double mus = fmin(1.0, fmax(-1.0, o[1] / o[0]));
   int jL, jR;
@@ -323,7 +320,8 @@ __device__ void remap_source(const DevGrid &g, const Frame &S, const Frame &D, i
     // corner weights at rounding level (a direction that lands on a node up
     // to the last bit) are dropped: they move less than 1e-15 of a bin
     rt[r] = c[r] > 1e-15 ? tg[r] : -1;
-    cw[r] = c[r];
+    rl[r] = c[r] * (1.0 - we);
+    rr[r] = c[r] * we;
   }
 }
 
@@ -332,10 +330,11 @@ __device__ void remap_source(const DevGrid &g, const Frame &S, const Frame &D, i
 // (column stride cs, zero outside groups 0 .. ne-1).  Content that the energy
 // shift pushes below group 0 or above group ne-1 stays in that group: for
 // shifts of at most one group it lands on row -1 (kb: its position in this
-// item, folded into group 0) or on rows ne, ne+1 (the last two rows of the
-// top item, folded into group ne-1); tables with larger shifts take the
-// explicit path.
-template <typename T, int CE>
+// item, folded into group 0; with SPLIT, row -1 ends the previous item,
+// the neighbouring lane, and is carried over) or on rows ne, ne+1 (the last
+// two rows of the top item, folded into group ne-1); tables with larger
+// shifts take the explicit path.  Called by all lanes of a wave together.
+template <typename T, int CE, bool SPLIT>
 __device__ __forceinline__ void gather(const Tab<T> &tb, int nd, const T *__restrict__ X, int cs, int ne,
                                        int dp, int r0, bool top, int kb, T acc[CE])
 {
@@ -343,17 +342,16 @@ __device__ __forceinline__ void gather(const Tab<T> &tb, int nd, const T *__rest
   for (int k = 0; k < CE; ++k) acc[k] = (T)0;
   const int e0 = tb.start[dp], e1 = tb.start[dp + 1];
   if ((tb.start[nd + 1] & 1) == 0) {
+    const T *base = X + (r0 - 3);
 #pragma unroll 2
     for (int e = e0; e < e1; ++e) {
-      const unsigned key = tb.key[e];
-      const int d = key & 0xff, di = (int)(key >> 8) - 128;
-      const T c = tb.c[e], cr = c * tb.we[d], cl = c - cr;
-      const T *w = X + d * cs + (r0 - di - 1);
+      const T *w = base + tb.key[e];                 // window of rows r0-di-1 .. r0-di+CE-1
+      const T cl = tb.cw[2 * e], cr = tb.cw[2 * e + 1];
       T x[CE + 1];
 #pragma unroll
       for (int k = 0; k <= CE; ++k) x[k] = w[k];
 #pragma unroll
-      for (int k = 0; k < CE; ++k) acc[k] += cl * x[k + 1] + cr * x[k];
+      for (int k = 0; k < CE; ++k) acc[k] = fma(cl, x[k + 1], fma(cr, x[k], acc[k]));
     }
     if (top) acc[CE - 3] += acc[CE - 2] + acc[CE - 1];
 #pragma unroll
@@ -362,7 +360,7 @@ __device__ __forceinline__ void gather(const Tab<T> &tb, int nd, const T *__rest
     for (int e = e0; e < e1; ++e) {
       const unsigned key = tb.key[e];
       const int d = key & 0xff, di = (int)(key >> 8) - 128;
-      const T c = tb.c[e], cr = c * tb.we[d], cl = c - cr;
+      const T cl = tb.cw[2 * e], cr = tb.cw[2 * e + 1];
       const T *col = X + d * cs;
 #pragma unroll
       for (int k = 0; k < CE; ++k) {
@@ -383,6 +381,10 @@ __device__ __forceinline__ void gather(const Tab<T> &tb, int nd, const T *__rest
         acc[k] += v;
       }
     }
+  }
+  if constexpr (SPLIT) {
+    const T carry = __shfl_up(acc[CE - 1], 1, 64);
+    if (r0 == 0) acc[0] += carry;
   }
 }
 
@@ -433,12 +435,12 @@ table_kernel(DevGrid g, const FaceDesc *__restrict__ faces, char *__restrict__ t
   int *cnt = (int *)data;                      // 4 nd
   int *cur = cnt + 4 * nd;                     // 4 nd
   int *rtg = cur + 4 * nd;                     // 16 nd
-  T *rcf = (T *)(rtg + 16 * nd);               // 16 nd
-  auto tw = [&](int t, T *&c, T *&we, unsigned short *&key, unsigned short *&start) {
+  T *rcf = (T *)(rtg + 16 * nd);               // 32 nd
+  const int cs = col_rows(g.nch, g.ce);
+  auto tw = [&](int t, T *&cw, unsigned short *&key, unsigned short *&start) {
     char *b = tabs + t * tstride;
-    c = (T *)b;
-    we = c + 4 * nd;
-    key = (unsigned short *)(we + nd);
+    cw = (T *)b;
+    key = (unsigned short *)(cw + 8 * nd);
     start = key + 4 * nd;
   };
   if (tid < kTables) flg[tid] = 0;
@@ -471,25 +473,22 @@ table_kernel(DevGrid g, const FaceDesc *__restrict__ faces, char *__restrict__ t
       const int di_ = (t == 0 || t == 1 || t == 6) ? 1 : (t == 2 || t == 3 || t == 7) ? 2 : 4;
       const Frame S = frm[si], D = frm[di_];
       int rt[4], di;
-      double cw[4], we;
-      remap_source(g, S, D, ax, rot, same_frame(S, D), d, rt, cw, we, di);
-      T *c, *wev;
-      unsigned short *key, *start;
-      tw(t, c, wev, key, start);
-      wev[d] = (T)we;
+      double rl[4], rr[4];
+      remap_source(g, S, D, ax, rot, same_frame(S, D), d, rt, rl, rr, di);
       if (di < -1 || di > 1) atomicOr(&flg[t], 1);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         rtg[q * 4 + r] = rt[r] >= 0 ? (rt[r] | ((di + 128) << 16)) : -1;
-        rcf[q * 4 + r] = (T)cw[r];
+        rcf[(q * 4 + r) * 2] = (T)rl[r];
+        rcf[(q * 4 + r) * 2 + 1] = (T)rr[r];
         if (rt[r] >= 0) atomicAdd(&cnt[tl * nd + rt[r]], 1);
       }
     }
     __syncthreads();
     if (tid < 4) {                                     // exclusive scan per table
-      T *c, *wev;
+      T *cw;
       unsigned short *key, *start;
-      tw(4 * round + tid, c, wev, key, start);
+      tw(4 * round + tid, cw, key, start);
       int acc = 0;
       for (int d = 0; d < nd; ++d) {
         start[d] = (unsigned short)acc;
@@ -502,37 +501,46 @@ table_kernel(DevGrid g, const FaceDesc *__restrict__ faces, char *__restrict__ t
     __syncthreads();
     for (int q = tid; q < 4 * nd; q += nthr) {         // records into their target lists
       int tl = q / nd, d = q - tl * nd;
-      T *c, *wev;
+      T *cw;
       unsigned short *key, *start;
-      tw(4 * round + tl, c, wev, key, start);
+      tw(4 * round + tl, cw, key, start);
       for (int r = 0; r < 4; ++r) {
         int v = rtg[q * 4 + r];
         if (v < 0) continue;
         int tg = v & 0xffff, dib = v >> 16;
         int slot = atomicAdd(&cur[tl * nd + tg], 1);
         key[slot] = (unsigned short)(d | (dib << 8));
-        c[slot] = rcf[q * 4 + r];
+        cw[2 * slot] = rcf[(q * 4 + r) * 2];
+        cw[2 * slot + 1] = rcf[(q * 4 + r) * 2 + 1];
       }
     }
     __syncthreads();
     for (int q = tid; q < 4 * nd; q += nthr) {         // fixed summation order: sort by key
       int tl = q / nd, d = q - tl * nd;
-      T *c, *wev;
+      T *cw;
       unsigned short *key, *start;
-      tw(4 * round + tl, c, wev, key, start);
+      tw(4 * round + tl, cw, key, start);
       int a = start[d], b = start[d + 1];
       for (int x = a + 1; x < b; ++x) {
         unsigned short kx = key[x];
-        T c0 = c[x];
+        T c0 = cw[2 * x], c1 = cw[2 * x + 1];
         int y = x - 1;
         while (y >= a && key[y] > kx) {
           key[y + 1] = key[y];
-          c[y + 1] = c[y];
+          cw[2 * y + 2] = cw[2 * y];
+          cw[2 * y + 3] = cw[2 * y + 1];
           --y;
         }
         key[y + 1] = kx;
-        c[y + 1] = c0;
+        cw[2 * y + 2] = c0;
+        cw[2 * y + 3] = c1;
       }
+      // shifts within one group: keys become source window offsets
+      if (!(start[nd + 1] & 1))
+        for (int x = a; x < b; ++x) {
+          const int src = key[x] & 0xff, di = (key[x] >> 8) - 128;
+          key[x] = (unsigned short)(src * cs - di + 2);
+        }
     }
   }
   __syncthreads();
@@ -567,8 +575,8 @@ table_kernel(DevGrid g, const FaceDesc *__restrict__ faces, char *__restrict__ t
 
 // ------------------------------------------------------------ face kernel
 
-// one side's species-s values of a work item's load rows (li, li + kNch, ...)
-template <typename T, int CE>
+// one side's species-s values of a work item's load rows (li, li + NCH, ...)
+template <typename T, int NCH, int CE>
 __device__ __forceinline__ void fetch_side(const DevGrid &g, const SideDesc &sd, const T *__restrict__ f,
                                            const T *__restrict__ feq, int s, int li, int ld, T v[CE])
 {
@@ -577,7 +585,7 @@ __device__ __forceinline__ void fetch_side(const DevGrid &g, const SideDesc &sd,
   const T *eq = feq + ((size_t)sd.z * g.ns + s) * ne;
 #pragma unroll
   for (int m = 0; m < CE; ++m) {
-    const int i = li + kNch * m;
+    const int i = li + NCH * m;
     T x = (T)0;
     if (i < ne) {
       if (sd.kind == btx::SIDE_ZONE || sd.kind == btx::SIDE_MIRROR) x = src[(size_t)i * nd];
@@ -587,18 +595,18 @@ __device__ __forceinline__ void fetch_side(const DevGrid &g, const SideDesc &sd,
   }
 }
 
-template <typename T, int CE>
+template <typename T, int NCH, int CE>
 __device__ __forceinline__ void store_side(const T v[CE], const T gl[CE], T a, int col, int li, int ne, int cs,
                                            T *X)
 {
 #pragma unroll
   for (int m = 0; m < CE; ++m) {
-    const int i = li + kNch * m;
+    const int i = li + NCH * m;
     if (i < ne) X[col * cs + i] = v[m] * gl[m] * a;
   }
 }
 
-// One workgroup per face, kNch work items per direction.  Per species:
+// One workgroup per face, NCH work items per direction.  Per species:
 //   load    the four stencil zones' blocks (coalesced rows, transposed into
 //           direction-major LDS columns as number content)
 //   phase 1 MC-limited slopes of both sides in their own frames (Sec. 3.3.2)
@@ -607,7 +615,7 @@ __device__ __forceinline__ void store_side(const T v[CE], const T gl[CE], T a, i
 //           by wave shuffles; implicit interface collision (Eq. halfstep);
 //           blend (Sec. 3.3.3) into flux and donor contents
 //   phase 3 remapped content change of both sides (Eq. fullstep)
-template <typename T, int CE, int MAXT>
+template <typename T, int NCH, int CE, int MAXT, bool SPLIT>
 __global__ void __launch_bounds__(MAXT)
 face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restrict__ tabs_g,
             const FaceAux *__restrict__ aux, const T *__restrict__ f, const T *__restrict__ ka,
@@ -623,10 +631,10 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
     for (size_t q = tid; q < 2 * (size_t)g.blk; q += nthr) outL[q] = (T)0;
     return;
   }
-  const int nrow = col_rows(CE), cs = nrow, gb = kNch * CE - ne;
+  const int nrow = col_rows(NCH, CE), cs = nrow, gb = NCH * CE - ne;
   // ---- LDS carve-up
   const size_t tstride = tab_stride(nd, sizeof(T));
-  const size_t bb = buf_bytes(nd, CE, sizeof(T));
+  const size_t bb = buf_bytes(nd, NCH, CE, sizeof(T));
   char *p = lds;
   const char *tabs = p;         p += kTables * tstride;
   char *bufs = p;               p += 4 * bb;
@@ -676,13 +684,13 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
   const double Uadv = ap4 * gs * vn;
   const double tau = 0.5 * A.alpha[4] * dt / gs;
 
-  // ---- load mapping: direction ld, rows li, li + kNch, ...
-  const bool ldown = tid < kNch * nd;
+  // ---- load mapping: direction ld, rows li, li + NCH, ...
+  const bool ldown = tid < NCH * nd;
   const int ld = ldown ? tid % nd : 0, li = ldown ? tid / nd : ne;
   T gl[CE];
 #pragma unroll
   for (int m = 0; m < CE; ++m) {
-    const int i = li + kNch * m;
+    const int i = li + NCH * m;
     gl[m] = i < ne ? (T)g.G[i] : (T)0;
   }
   const SideDesc *sides[4] = { &F.Lm, &F.L, &F.R, &F.Rp };
@@ -700,10 +708,10 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
   }
 
   // ---- compute mapping: target direction dp, rows r0 .. r0 + CE - 1
-  const bool own = tid < kNch * nd;
-  const int dp = own ? tid / kNch : 0, ch = tid % kNch;
-  const int r0 = ne + 2 - (kNch - ch) * CE;
-  const bool top = ch == kNch - 1;
+  const bool own = tid < NCH * nd;
+  const int dp = own ? tid / NCH : 0, ch = tid % NCH;
+  const int r0 = ne + 2 - (NCH - ch) * CE;
+  const bool top = ch == NCH - 1;
   const int kb = -1 - r0;
   T iaL, iaR, iaS, cv, kF, uLp, uap, uRn, uan;
   double dOd;
@@ -750,14 +758,14 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
     // ---- load the stencil blocks as content densities
     {
       T v0[CE], v1[CE], v2[CE], v3[CE];
-      if (slopeL) fetch_side<T, CE>(g, F.Lm, f, feq, s, li, ld, v0);
-      fetch_side<T, CE>(g, F.L, f, feq, s, li, ld, v1);
-      fetch_side<T, CE>(g, F.R, f, feq, s, li, ld, v2);
-      if (slopeR) fetch_side<T, CE>(g, F.Rp, f, feq, s, li, ld, v3);
-      if (slopeL) store_side<T, CE>(v0, gl, aS_[0], colS[0], li, ne, cs, XLm);
-      store_side<T, CE>(v1, gl, aS_[1], colS[1], li, ne, cs, XL);
-      store_side<T, CE>(v2, gl, aS_[2], colS[2], li, ne, cs, XR);
-      if (slopeR) store_side<T, CE>(v3, gl, aS_[3], colS[3], li, ne, cs, XRp);
+      if (slopeL) fetch_side<T, NCH, CE>(g, F.Lm, f, feq, s, li, ld, v0);
+      fetch_side<T, NCH, CE>(g, F.L, f, feq, s, li, ld, v1);
+      fetch_side<T, NCH, CE>(g, F.R, f, feq, s, li, ld, v2);
+      if (slopeR) fetch_side<T, NCH, CE>(g, F.Rp, f, feq, s, li, ld, v3);
+      if (slopeL) store_side<T, NCH, CE>(v0, gl, aS_[0], colS[0], li, ne, cs, XLm);
+      store_side<T, NCH, CE>(v1, gl, aS_[1], colS[1], li, ne, cs, XL);
+      store_side<T, NCH, CE>(v2, gl, aS_[2], colS[2], li, ne, cs, XR);
+      if (slopeR) store_side<T, NCH, CE>(v3, gl, aS_[3], colS[3], li, ne, cs, XRp);
     }
     // ---- per-group interface opacities and collision coefficients
     for (int i = tid; i < ne; i += nthr) {
@@ -776,109 +784,104 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
       rthick[i] = sizeof(T) == 8 || tau * (a_ + b_) > g.fp64_thr;
     }
     __syncthreads();
-    // ---- phase 1: limited slopes and reconstructed donor values
-    T EL[CE], ER[CE], Sv[CE];
-    {
-      T fl[CE], fr[CE], sl[CE];
-#pragma unroll
-      for (int k = 0; k < CE; ++k) {
-        const int r = r0 + k;
-        fl[k] = XL[dp * cs + r] * riG[r] * iaL;
-        fr[k] = XR[dp * cs + r] * riG[r] * iaR;
-        sl[k] = (T)0;
-      }
-      if (slopeL) {
-        T a[CE], b[CE];
-        gather<T, CE>(TB(0), nd, XLm, cs, ne, dp, r0, top, kb, a);
-        gather<T, CE>(TB(1), nd, XR, cs, ne, dp, r0, top, kb, b);
-#pragma unroll
-        for (int k = 0; k < CE; ++k) {
-          const T sc = riG[r0 + k] * iaL;
-          sl[k] = mc_limiter<T>((fl[k] - a[k] * sc) * ihLm, (b[k] * sc - fl[k]) * ih);
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < CE; ++k) EL[k] = fl[k] + dL * sl[k];
-      if (slopeR) {
-        T a[CE], b[CE];
-        gather<T, CE>(TB(2), nd, XL, cs, ne, dp, r0, top, kb, a);
-        gather<T, CE>(TB(3), nd, XRp, cs, ne, dp, r0, top, kb, b);
-#pragma unroll
-        for (int k = 0; k < CE; ++k) {
-          const T sc = riG[r0 + k] * iaR;
-          ER[k] = fr[k] + dR * mc_limiter<T>((fr[k] - a[k] * sc) * ih, (b[k] * sc - fr[k]) * ihRp);
-        }
-      } else {
-#pragma unroll
-        for (int k = 0; k < CE; ++k) ER[k] = F.self ? fr[k] + dR * sl[k] : fr[k];
-      }
-    }
-    // ---- phase 2: Lax-Wendroff half-step source S in the interface frame
-    {
-      T a[CE], b[CE];
-      gather<T, CE>(TB(4), nd, XL, cs, ne, dp, r0, top, kb, a);
-      gather<T, CE>(TB(5), nd, XR, cs, ne, dp, r0, top, kb, b);
-#pragma unroll
-      for (int k = 0; k < CE; ++k) {
-        const int r = r0 + k;
-        const T sc = riG[r] * iaS;
-        const T x = a[k] * sc, y = b[k] * sc;
-        Sv[k] = (T)0.5 * (x + y) + cv * (y - x) + rsrc[r];
-      }
-    }
-    // angle sums of S per group (FP64): lanes kNch apart share rows
-#pragma unroll
-    for (int k = 0; k < CE; ++k) {
-      double v = (double)Sv[k] * dOd;
-      v += __shfl_xor(v, 4, 64);
-      v += __shfl_xor(v, 8, 64);
-      v += __shfl_xor(v, 16, 64);
-      v += __shfl_xor(v, 32, 64);
-      if (lane < kNch) spart[wave * nrow + r0 + k + gb] = v;
-    }
-    __syncthreads();                                   // partial sums visible, buffers free
-    if (own) {
-#pragma unroll
-      for (int k = 0; k < CE; ++k) {
-        const int r = r0 + k;
-        if (r < 0 || r >= ne) continue;
-        double sav = 0.0;
-        for (int w = 0; w < nw; ++w) sav += spart[w * nrow + r + gb];
-        sav *= 1.0 / (4.0 * kPi);
-        T flw;
-        if (rthick[r]) flw = (T)((double)Sv[k] * rc0[r] + rc1[r] * sav);
-        else flw = (T)((float)Sv[k] * (float)rc0[r] + (float)rc1[r] * (float)sav);
-        const T w = rw[r], G = rG[r];
-        XLm[dp * cs + r] = ((T)1 - w) * kF * G * flw;
-        XL[dp * cs + r] = (w * (uLp - uap) + uap) * G * EL[k];
-        XR[dp * cs + r] = (w * (uRn - uan) + uan) * G * ER[k];
-      }
-    }
-    __syncthreads();
-    // ---- phase 3: content changes of both sides
+    // ---- five remap stages, each the sum of two gathers a = Ta . Xa, b = Tb . Xb
+    //   0 slopes of L      T0 . Lm,  T1 . R
+    //   1 slopes of R      T2 . L,   T3 . Rp
+    //   2 interface        T4 . L,   T5 . R    -> S, <S>, collision, blend
+    //   3 content to L     T6 . FL,  T1 . ER
+    //   4 content to R     T7 . FL,  T2 . EL
+    // (buffers: 0 Lm (FL after stage 2), 1 L (EL content), 2 R (ER content), 3 Rp)
+    T EL[CE], ER[CE];
     double sumL = 0.0, sumR = 0.0;
-    {
+#pragma unroll 1
+    for (int st = 0; st < 5; ++st) {
       T a[CE], b[CE];
-      T *oL = outL + (size_t)s * g.eblk, *oR = outR + (size_t)s * g.eblk;
-      gather<T, CE>(TB(6), nd, XLm, cs, ne, dp, r0, top, kb, a);
-      gather<T, CE>(TB(1), nd, XR, cs, ne, dp, r0, top, kb, b);
 #pragma unroll
-      for (int k = 0; k < CE; ++k) {
-        const int r = r0 + k;
-        if (!own || r < 0 || r >= ne) continue;
-        const T v = -a[k] - XL[dp * cs + r] + b[k];
-        oL[r * nd + dp] = v;
-        sumL += (double)v;
+      for (int k = 0; k < CE; ++k) a[k] = b[k] = (T)0;
+      const int nj = (st == 0 && !slopeL) || (st == 1 && !slopeR) ? 0 : 2;
+#pragma unroll 1
+      for (int j = 0; j < nj; ++j) {
+        const int t = (int)((0x2716543210ull >> (4 * (2 * st + j))) & 0xf);
+        const int x = (int)((0x1020213120ull >> (4 * (2 * st + j))) & 0xf);
+        T c[CE];
+        gather<T, CE, SPLIT>(TB(t), nd, (const T *)(bufs + x * bb) + gb, cs, ne, dp, r0, top, kb, c);
+#pragma unroll
+        for (int k = 0; k < CE; ++k) {
+          a[k] = j == 0 ? c[k] : a[k];
+          b[k] = j == 0 ? b[k] : c[k];
+        }
       }
-      gather<T, CE>(TB(7), nd, XLm, cs, ne, dp, r0, top, kb, a);
-      gather<T, CE>(TB(2), nd, XL, cs, ne, dp, r0, top, kb, b);
+      if (st == 0) {                                   // MC-limited slope of L (Sec. 3.3.2)
 #pragma unroll
-      for (int k = 0; k < CE; ++k) {
-        const int r = r0 + k;
-        if (!own || r < 0 || r >= ne) continue;
-        const T v = a[k] - XR[dp * cs + r] + b[k];
-        oR[r * nd + dp] = v;
-        sumR += (double)v;
+        for (int k = 0; k < CE; ++k) {
+          const int r = r0 + k;
+          const T sc = riG[r] * iaL, fl = XL[dp * cs + r] * sc;
+          const T sl = slopeL ? mc_limiter<T>((fl - a[k] * sc) * ihLm, (b[k] * sc - fl) * ih) : (T)0;
+          EL[k] = fl + dL * sl;
+          if (F.self) ER[k] = XR[dp * cs + r] * riG[r] * iaR + dR * sl;
+        }
+      } else if (st == 1) {                            // MC-limited slope of R
+        if (!F.self) {
+#pragma unroll
+          for (int k = 0; k < CE; ++k) {
+            const int r = r0 + k;
+            const T sc = riG[r] * iaR, fr = XR[dp * cs + r] * sc;
+            ER[k] = slopeR ? fr + dR * mc_limiter<T>((fr - a[k] * sc) * ih, (b[k] * sc - fr) * ihRp) : fr;
+          }
+        }
+      } else if (st == 2) {
+        // Lax-Wendroff half-step source S in the interface frame
+        T Sv[CE];
+#pragma unroll
+        for (int k = 0; k < CE; ++k) {
+          const int r = r0 + k;
+          const T sc = riG[r] * iaS;
+          const T x = a[k] * sc, y = b[k] * sc;
+          Sv[k] = (T)0.5 * (x + y) + cv * (y - x) + rsrc[r];
+        }
+        // angle sums of S per group (FP64): lanes NCH apart share rows
+#pragma unroll
+        for (int k = 0; k < CE; ++k) {
+          double v = (double)Sv[k] * dOd;
+#pragma unroll
+          for (int o = NCH; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+          if (lane < NCH) spart[wave * nrow + r0 + k + gb] = v;
+        }
+        __syncthreads();                               // partial sums visible, buffers free
+        // implicit interface collision, blend weights and content fluxes
+        if (own) {
+#pragma unroll
+          for (int k = 0; k < CE; ++k) {
+            const int r = r0 + k;
+            if (r < 0 || r >= ne) continue;
+            double sav = 0.0;
+            for (int w = 0; w < nw; ++w) sav += spart[w * nrow + r + gb];
+            sav *= 1.0 / (4.0 * kPi);
+            T flw;
+            if (rthick[r]) flw = (T)((double)Sv[k] * rc0[r] + rc1[r] * sav);
+            else flw = (T)((float)Sv[k] * (float)rc0[r] + (float)rc1[r] * (float)sav);
+            const T w = rw[r], G = rG[r];
+            XLm[dp * cs + r] = ((T)1 - w) * kF * G * flw;
+            XL[dp * cs + r] = (w * (uLp - uap) + uap) * G * EL[k];
+            XR[dp * cs + r] = (w * (uRn - uan) + uan) * G * ER[k];
+          }
+        }
+        __syncthreads();
+      } else {                                         // remapped content changes
+        T *o = (st == 3 ? outL : outR) + (size_t)s * g.eblk;
+        const T *own_c = st == 3 ? XL : XR;
+        const T sg = st == 3 ? (T)-1 : (T)1;
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < CE; ++k) {
+          const int r = r0 + k;
+          if (!own || r < 0 || r >= ne) continue;
+          const T v = sg * a[k] - own_c[dp * cs + r] + b[k];
+          o[r * nd + dp] = v;
+          sum += (double)v;
+        }
+        if (st == 3) sumL = sum;
+        else sumR = sum;
       }
     }
     if (ghost) {
@@ -1038,41 +1041,73 @@ struct btx_ctx {
 
 namespace {
 
-// groups per face work item: the smallest instantiated CE with kNch CE >=
-// ne + 3 whose chunking keeps groups -1 and 0 in one item ((ne + 2) not a
-// multiple of CE); 0 if there is none
-constexpr int kCEs[] = { 4, 5, 6, 7, 8, 12, 16 };
+// Face work-item shape.  FP32: 8 items per direction (up to 96 directions in
+// workgroups of up to 768 threads, up to 128 in 1024); FP64: 4 items per
+// direction (up to 128 directions, 512 threads), which keeps its larger LDS
+// buffers within one CU.  CE is the smallest instantiated value with
+// nch CE >= ne + 3; 0 if there is none (more than 61 groups).
+struct FaceShape {
+  int nch = 0, ce = 0, maxt = 0;
+};
 
-int face_ce(const btx::Grid &g)
+constexpr int kCE8[] = { 3, 4, 5, 6, 8 };
+constexpr int kCE4[] = { 4, 5, 6, 7, 8, 12, 16 };
+
+FaceShape face_shape(const btx::Grid &g)
 {
-  for (int ce : kCEs)
-    if (kNch * ce >= g.ne + 3 && (g.ne + 2) % ce != 0) return ce;
-  return 0;
+  FaceShape f;
+  if (g.ndir > 128) return f;
+  f.nch = g.prec == BTX_PREC_FP64 ? 4 : 8;
+  f.maxt = f.nch == 4 ? 512 : (g.ndir <= 96 ? 768 : 1024);
+  auto pick = [&](const int *c, int n) {
+    for (int k = 0; k < n; ++k)
+      if (f.nch * c[k] >= g.ne + 3) return c[k];
+    return 0;
+  };
+  f.ce = f.nch == 8 ? pick(kCE8, 5) : pick(kCE4, 7);
+  return f;
 }
 
-// kNch threads per direction: workgroups of up to 512 threads (up to 128
-// directions), else up to 1024
-bool face_wide(const btx::Grid &g) { return kNch * g.ndir > 512; }
-
-template <typename T, int MAXT>
+template <typename T, int NCH, int MAXT, bool SPLIT>
 const void *face_fn_t(int ce)
 {
-  switch (ce) {
-  case 4: return (const void *)face_kernel<T, 4, MAXT>;
-  case 5: return (const void *)face_kernel<T, 5, MAXT>;
-  case 6: return (const void *)face_kernel<T, 6, MAXT>;
-  case 7: return (const void *)face_kernel<T, 7, MAXT>;
-  case 8: return (const void *)face_kernel<T, 8, MAXT>;
-  case 12: return (const void *)face_kernel<T, 12, MAXT>;
-  case 16: return (const void *)face_kernel<T, 16, MAXT>;
-  default: return nullptr;
+  if constexpr (NCH == 8) {
+    switch (ce) {
+    case 3: return (const void *)face_kernel<T, 8, 3, MAXT, SPLIT>;
+    case 4: return (const void *)face_kernel<T, 8, 4, MAXT, SPLIT>;
+    case 5: return (const void *)face_kernel<T, 8, 5, MAXT, SPLIT>;
+    case 6: return (const void *)face_kernel<T, 8, 6, MAXT, SPLIT>;
+    case 8: return (const void *)face_kernel<T, 8, 8, MAXT, SPLIT>;
+    default: return nullptr;
+    }
+  } else {
+    switch (ce) {
+    case 4: return (const void *)face_kernel<T, 4, 4, MAXT, SPLIT>;
+    case 5: return (const void *)face_kernel<T, 4, 5, MAXT, SPLIT>;
+    case 6: return (const void *)face_kernel<T, 4, 6, MAXT, SPLIT>;
+    case 7: return (const void *)face_kernel<T, 4, 7, MAXT, SPLIT>;
+    case 8: return (const void *)face_kernel<T, 4, 8, MAXT, SPLIT>;
+    case 12: return (const void *)face_kernel<T, 4, 12, MAXT, SPLIT>;
+    case 16: return (const void *)face_kernel<T, 4, 16, MAXT, SPLIT>;
+    default: return nullptr;
+    }
   }
 }
 
+// the instance for this grid; SPLIT when group -1 ends a work item
+// ((ne + 2) a multiple of CE)
 template <typename T>
 const void *face_fn(const btx::Grid &g)
 {
-  return face_wide(g) ? face_fn_t<T, 1024>(face_ce(g)) : face_fn_t<T, 512>(face_ce(g));
+  const FaceShape f = face_shape(g);
+  if (f.ce == 0) return nullptr;
+  const bool split = (g.ne + 2) % f.ce == 0;
+  if constexpr (sizeof(T) == 8) {
+    return split ? face_fn_t<T, 4, 512, true>(f.ce) : face_fn_t<T, 4, 512, false>(f.ce);
+  } else {
+    if (f.maxt == 768) return split ? face_fn_t<T, 8, 768, true>(f.ce) : face_fn_t<T, 8, 768, false>(f.ce);
+    return split ? face_fn_t<T, 8, 1024, true>(f.ce) : face_fn_t<T, 8, 1024, false>(f.ce);
+  }
 }
 
 DevGrid dev_grid(const btx_ctx *c)
@@ -1084,6 +1119,8 @@ DevGrid dev_grid(const btx_ctx *c)
   d.eblk = g.ne * g.ndir; d.blk = g.ns * d.eblk;
   d.nfaces = (int)g.faces.size();
   d.lnq = g.lnq; d.q = g.q; d.fp64_thr = g.fp64_thr;
+  d.nch = face_shape(g).nch;
+  d.ce = face_shape(g).ce;
   d.mu = c->d_mu; d.Phi = c->d_Phi; d.dOm = c->d_dOm; d.nvec = c->d_nvec; d.G = c->d_G;
   d.eps = c->d_eps; d.vol = c->d_vol;
   d.vr = c->d_vr; d.vth = c->d_vth; d.alp = c->d_alp; d.psi = c->d_psi;
@@ -1098,7 +1135,11 @@ btx_status upload(X **dst, const X *src, size_t n)
   return BTX_OK;
 }
 
-size_t face_lds(const btx::Grid &g, size_t szT) { return face_lds_bytes(g.ndir, face_ce(g), szT); }
+size_t face_lds(const btx::Grid &g, size_t szT)
+{
+  const FaceShape f = face_shape(g);
+  return face_lds_bytes(g.ndir, f.nch, f.ce, szT);
+}
 
 void free_ctx(btx_ctx *c)
 {
@@ -1170,7 +1211,7 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
   if (!d->r_edges || !d->eps_edges) return fail(BTX_E_INVAL, "null edge array");
   int nth = d->geometry == BTX_GEOM_AXISYM2D ? d->n_theta : 1;
   if (nth < 1) return fail(BTX_E_INVAL, "n_theta must be positive");
-  if (d->n_mu * d->n_phi > 256) return fail(BTX_E_UNSUPPORTED, "at most 256 directions");
+  if (d->n_mu * d->n_phi > 128) return fail(BTX_E_UNSUPPORTED, "at most 128 directions");
   if (d->n_mu * d->n_phi * 4 > 65535) return fail(BTX_E_UNSUPPORTED, "too many directions");
   for (int a = 0; a < d->n_r; ++a)
     if (!(d->r_edges[a + 1] > d->r_edges[a])) return fail(BTX_E_INVAL, "r edges must ascend");
@@ -1206,11 +1247,11 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
   c->lds_bytes = face_lds(g, c->tsize);
   c->tab_lds = kTables * tab_stride(g.ndir, c->tsize) + align16(5 * sizeof(Frame)) +
                align16(scratch_bytes(g.ndir, c->tsize));
-  if (face_ce(g) == 0) {
+  if (face_shape(g).ce == 0) {
     delete c;
     return fail(BTX_E_UNSUPPORTED, "no face work-item shape for n_eps = " + std::to_string(d->n_eps));
   }
-  c->face_threads = ((kNch * g.ndir + 63) / 64) * 64;
+  c->face_threads = ((face_shape(g).nch * g.ndir + 63) / 64) * 64;
   btx_status st = BTX_OK;
   hipError_t he = hipSetDevice(hip_device);
   if (he != hipSuccess) { delete c; return fail(BTX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(he)); }

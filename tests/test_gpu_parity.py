@@ -43,7 +43,23 @@ CASES = {
                                                   precision=W.PREC_FP64)),
     "planar": lambda: W.planar(n_z=20, n_eps=3, n_mu=6, kappa_a=2.0, kappa_s=5.0, f_eq=0.3,
                                inner_bc=W.BC_EQUIL, outer_bc=W.BC_OUTFLOW),
+    # 10 groups: group -1 of the work-item chunking ends one item and group 0
+    # starts the next (both precisions)
+    "split_groups": lambda: _perturb(W.axisym_2d(n_r=7, n_theta=5, n_eps=10, n_mu=4, n_phi=4)),
+    # a single energy group
+    "one_group": lambda: _perturb(W.axisym_2d(n_r=6, n_theta=4, n_eps=1, n_mu=4, n_phi=3)),
+    # steep velocity jumps on a fine energy grid: energy shifts of two or more
+    # groups between neighbouring frames
+    "large_shift": lambda: _steep(W.planar(n_z=6, n_eps=12, n_mu=6, kappa_a=0.5, kappa_s=1.0,
+                                           f_eq=0.3, inner_bc=W.BC_EQUIL, outer_bc=W.BC_OUTFLOW)),
 }
+
+
+def _steep(w):
+    w.v_r = np.linspace(-0.6, 0.6, w.n_zones)
+    w.alpha = np.linspace(0.7, 1.0, w.n_zones)
+    w.psi = w.alpha ** -0.5
+    return _perturb(w)
 
 
 def _run_pair(w, steps, precision, oracle_mod):
@@ -79,7 +95,7 @@ def test_fp64_parity(case, oracle_mod):
     ctx.close()
 
 
-@pytest.mark.parametrize("case", ["shock_3species", "column_lobatto_v"])
+@pytest.mark.parametrize("case", ["shock_3species", "column_lobatto_v", "split_groups", "large_shift"])
 def test_mixed_moments(case, oracle_mod):
     w = CASES[case]()
     _say(f"[gpu] mixed moments {case}")

@@ -11,8 +11,10 @@ before timing starts.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -77,7 +79,7 @@ def cpu_baseline(steps_note):
     """the CPU reference on a bounded sample of the same workload shape"""
     from oracle import oracle
     from paper_2003_02845_amd import workloads as W
-    w = W.hires_2d(n_theta=32)
+    w = W.hires_2d(n_theta=96)
     o = oracle.Oracle(w)
     dt = o.max_dt(w.cfl)
     t = time.perf_counter()
@@ -86,8 +88,24 @@ def cpu_baseline(steps_note):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": w.n_values / el, "unit": "zone*group*direction updates/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"one FP64 step of the same profile and momentum grid on 600 r x 32 theta "
+            "sample": f"one FP64 step of the same profile and momentum grid on 600 r x 96 theta "
                       f"zones ({w.n_values:.3g} values, {el:.1f} s)"}
+
+
+def face_traffic():
+    """HBM bytes per face-kernel launch from the committed counter summary, or None when the
+    kernel source has changed since the counters were taken"""
+    prof = os.path.join(ROOT, "profiles", "face_kernel_hires_2d_mixed_hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_2003_02845_amd", "csrc", "btx.hip")
+    try:
+        text = open(prof).read()
+        want = re.search(r"btx\.hip: ([0-9a-f]{16})", text).group(1)
+        have = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if want != have:
+            return None
+        return float(re.search(r"face_traffic_bytes ([0-9.e+]+)", text).group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
 
 
 def main():
@@ -129,6 +147,7 @@ def main():
     b_face = w.n_values * 4 + nsg * 3 * 4 + nz * 4 * 8
     t_face = mixed["kernel_ms"][0] * 1e-3
     achieved = b_face / t_face / 1e9
+    traffic = face_traffic() if (a.n_r, a.n_theta) == (600, 256) else None
     out = {
         "metric": "zone*group*direction updates/s (mixed FP32/FP64), with FP64 speedup and % HBM peak",
         "value": value,
@@ -148,7 +167,9 @@ def main():
         "step_hbm_frac": b_step / (mixed["ms"] / a.steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": "face_kernel<float>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+                     "traffic": None if traffic is None else traffic / 1e9,
+                     "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic": b_face / 1e9, "algorithmic_unit": "GB per launch"},
     }
     if res64 is not None:
         k64 = a.fp64_steps if a.fp64_steps is not None else a.steps

@@ -1,0 +1,87 @@
+"""The C ABI without a GPU: libbtx.so loads and exports every function that
+include/btx.h declares, the Python binding names the same set, and the
+argument structs have the layout of the header.  No compute call is made."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "btx.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(btx_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib_path():
+    from paper_2003_02845_amd import btx
+    from paper_2003_02845_amd import build
+    if not os.path.exists(btx.LIB_PATH):
+        build.build()
+    return btx.LIB_PATH
+
+
+def test_header_declares_the_step_interface():
+    names = _declared()
+    for need in ("btx_create", "btx_set_background", "btx_max_dt", "btx_set_state",
+                 "btx_get_state", "btx_step", "btx_moments", "btx_destroy", "btx_last_error"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol(lib_path):
+    out = subprocess.run(["nm", "-D", "--defined-only", lib_path], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (btx_[a-z_]+)$", out, flags=re.M))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, f"declared but not exported: {missing}"
+
+
+def test_library_loads_and_resolves(lib_path):
+    L = C.CDLL(lib_path)
+    for n in _declared():
+        assert getattr(L, n) is not None
+    L.btx_last_error.restype = C.c_char_p
+    assert isinstance(L.btx_last_error(), bytes)
+
+
+def test_binding_names_match_header():
+    from paper_2003_02845_amd import btx
+    assert sorted(btx.ABI_SYMBOLS) == _declared()
+
+
+def test_struct_layout_matches_header():
+    """the ctypes structs follow the field order and widths of the header"""
+    from paper_2003_02845_amd import btx
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    for cname, pyname in (("btx_grid_desc", "GridDesc"), ("btx_background", "Background")):
+        body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + ";", text).group(1)
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            is_ptr = "*" in decl
+            words = decl.replace("*", " ").replace("const ", " ").split(None, 1)
+            for nm in words[1].split(","):
+                fields.append((nm.strip(), is_ptr))
+        py = getattr(btx, pyname)._fields_
+        assert [f[0] for f in py] == [f[0] for f in fields], cname
+        for (nm, ctype), (_, is_ptr) in zip(py, fields):
+            assert (C.sizeof(ctype) == 8) if is_ptr else True, nm
+
+
+def test_null_arguments_rejected_without_device(lib_path):
+    """argument checks that run before any HIP call"""
+    L = C.CDLL(lib_path)
+    L.btx_create.restype = C.c_int
+    assert L.btx_create(None, 0, None, None) == 1            # BTX_E_INVAL
+    L.btx_max_dt.restype = C.c_int
+    assert L.btx_max_dt(None, C.c_double(0.4), None) == 1
+    L.btx_destroy.restype = C.c_int
+    assert L.btx_destroy(None) == 0

@@ -33,6 +33,7 @@
  *   the ABI.  btx_last_error() returns a thread-local message for the last
  *   failing call on that thread.
  *   Threads: one context must not be used by two threads at once.
+ *   Limits: at most 128 directions (n_mu n_phi) and 61 energy groups.
  */
 #ifndef BTX_H
 #define BTX_H
@@ -123,6 +124,37 @@ btx_status btx_moments(btx_ctx *ctx, double *zone_moments, double *totals);
 btx_status btx_timing(btx_ctx *ctx, int enable, double *ms, int64_t *launches, int reset);
 btx_status btx_destroy(btx_ctx *ctx);
 const char *btx_last_error(void);
+
+/* ---- Batches: many independent models (grids of uneven sizes, one shared
+ * precision) stepped together.  Each step is one face-kernel launch per face
+ * shape class plus one zone-update launch over every zone of every model,
+ * replayed from a HIP graph captured at the first step (the same kernels and
+ * arithmetic as btx_step; per-model results equal those of btx_step up to the
+ * summation order of the angle sums when the face shapes differ).  The face
+ * shape of each model class (precision, directions, groups) is chosen by a
+ * built-in autotuner at the first step, timed on the batch's own faces;
+ * choices persist as a JSON object in tune_cache_path (NULL: no cache).
+ * Models are indexed 0 .. n_models-1 in the order of descs.  Streams,
+ * ownership and errors as for the single-model calls above. */
+typedef struct btx_batch btx_batch;
+btx_status btx_batch_create(const btx_grid_desc *descs, int32_t n_models, int hip_device, void *hip_stream,
+                            const char *tune_cache_path, btx_batch **out);
+btx_status btx_batch_set_background(btx_batch *b, int32_t model, const btx_background *bg);
+btx_status btx_batch_max_dt(const btx_batch *b, int32_t model, double cfl, double *dt_out);
+btx_status btx_batch_set_state(btx_batch *b, int32_t model, const void *f, int is_device_ptr);
+btx_status btx_batch_get_state(btx_batch *b, int32_t model, void *f, int is_device_ptr);
+/* n_steps steps; dt_per_model[n_models] (each within its model's Courant
+ * limit).  The first call tunes and captures (synchronising the stream). */
+btx_status btx_batch_step(btx_batch *b, const double *dt_per_model, int32_t n_steps);
+/* enable = 0: launch the kernels of each step directly instead of replaying
+ * the captured graph (same work, same results) */
+btx_status btx_batch_use_graph(btx_batch *b, int enable);
+/* the face shape the autotuner chose for a model: work items per direction
+ * and energy groups per work item (valid after the first step) */
+btx_status btx_batch_shape(const btx_batch *b, int32_t model, int32_t *items_per_direction,
+                           int32_t *groups_per_item);
+btx_status btx_batch_moments(btx_batch *b, int32_t model, double *zone_moments, double *totals);
+btx_status btx_batch_destroy(btx_batch *b);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,9 @@ PREC_FP64, PREC_MIXED = 0, 1
 MU_LEGENDRE, MU_LOBATTO = 0, 1
 ABI_SYMBOLS = ["btx_create", "btx_set_background", "btx_max_dt", "btx_set_state",
                "btx_get_state", "btx_step", "btx_moments", "btx_timing", "btx_destroy",
-               "btx_last_error"]
+               "btx_last_error", "btx_batch_create", "btx_batch_set_background",
+               "btx_batch_max_dt", "btx_batch_set_state", "btx_batch_get_state", "btx_batch_step",
+               "btx_batch_use_graph", "btx_batch_shape", "btx_batch_moments", "btx_batch_destroy"]
 
 _dp = C.POINTER(C.c_double)
 
@@ -68,6 +70,17 @@ def lib():
         L.btx_moments.argtypes = [vp, _dp, _dp]
         L.btx_timing.argtypes = [vp, C.c_int, _dp, C.POINTER(C.c_int64), C.c_int]
         L.btx_destroy.argtypes = [vp]
+        L.btx_batch_create.argtypes = [C.POINTER(GridDesc), C.c_int32, C.c_int, vp, C.c_char_p,
+                                       C.POINTER(vp)]
+        L.btx_batch_set_background.argtypes = [vp, C.c_int32, C.POINTER(Background)]
+        L.btx_batch_max_dt.argtypes = [vp, C.c_int32, C.c_double, _dp]
+        L.btx_batch_set_state.argtypes = [vp, C.c_int32, vp, C.c_int]
+        L.btx_batch_get_state.argtypes = [vp, C.c_int32, vp, C.c_int]
+        L.btx_batch_step.argtypes = [vp, _dp, C.c_int32]
+        L.btx_batch_use_graph.argtypes = [vp, C.c_int]
+        L.btx_batch_shape.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.btx_batch_moments.argtypes = [vp, C.c_int32, _dp, _dp]
+        L.btx_batch_destroy.argtypes = [vp]
         L.btx_last_error.restype = C.c_char_p
         for name in ABI_SYMBOLS:
             if name != "btx_last_error":
@@ -83,6 +96,22 @@ def _check(status):
 
 def _p(a):
     return a.ctypes.data_as(_dp)
+
+
+def _desc(w, precision, fp64_threshold):
+    keep = [np.ascontiguousarray(w.r_edges, float), np.ascontiguousarray(w.theta_edges, float),
+            np.ascontiguousarray(w.eps_edges, float)]
+    d = GridDesc(w.n_r, w.n_theta, w.n_eps, w.n_mu, w.n_phi, w.n_species, w.geometry,
+                 MU_LEGENDRE if w.mu_rule == "legendre" else MU_LOBATTO, w.phi_rule,
+                 w.inner_bc, w.outer_bc, precision, _p(keep[0]), _p(keep[1]),
+                 float(w.dphi), _p(keep[2]), float(fp64_threshold))
+    return d, keep
+
+
+def _background(w):
+    arrs = [np.ascontiguousarray(a, float) for a in
+            (w.v_r, w.v_theta, w.alpha, w.psi, w.kappa_a, w.kappa_s, w.f_eq)]
+    return Background(*[_p(a) for a in arrs]), arrs
 
 
 class Context:
@@ -160,3 +189,75 @@ class Context:
         n = (C.c_int64 * 2)()
         _check(lib().btx_timing(self.h, int(enable), _p(ms), n, int(reset)))
         return ms, np.array([n[0], n[1]])
+
+
+class Batch:
+    """independent models stepped together (btx_batch_create ... btx_batch_destroy)"""
+
+    def __init__(self, workloads, device=0, stream=None, precision=None, tune_cache=None,
+                 fp64_threshold=1.0):
+        self.ws = list(workloads)
+        self.precision = self.ws[0].precision if precision is None else precision
+        self.dtype = np.float64 if self.precision == PREC_FP64 else np.float32
+        descs = (GridDesc * len(self.ws))()
+        self._keep = []
+        for k, w in enumerate(self.ws):
+            d, keep = _desc(w, self.precision, fp64_threshold)
+            descs[k] = d
+            self._keep.append(keep)
+        h = C.c_void_p()
+        path = None if tune_cache is None else str(tune_cache).encode()
+        _check(lib().btx_batch_create(descs, len(self.ws), device, C.c_void_p(stream or 0), path,
+                                      C.byref(h)))
+        self.h = h
+        self.shapes = [(w.n_zones, w.n_species, w.n_eps, w.n_dir) for w in self.ws]
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().btx_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_background(self, m, w=None):
+        bg, keep = _background(w or self.ws[m])
+        _check(lib().btx_batch_set_background(self.h, m, C.byref(bg)))
+
+    def max_dt(self, m, cfl=None):
+        out = C.c_double()
+        _check(lib().btx_batch_max_dt(self.h, m, self.ws[m].cfl if cfl is None else cfl, C.byref(out)))
+        return out.value
+
+    def set_state(self, m, f):
+        a = np.ascontiguousarray(f, dtype=self.dtype).reshape(-1)
+        assert a.size == int(np.prod(self.shapes[m]))
+        _check(lib().btx_batch_set_state(self.h, m, C.c_void_p(a.ctypes.data), 0))
+
+    def get_state(self, m):
+        a = np.empty(self.shapes[m], dtype=self.dtype)
+        _check(lib().btx_batch_get_state(self.h, m, C.c_void_p(a.ctypes.data), 0))
+        return a
+
+    def step(self, dts, n=1):
+        d = np.ascontiguousarray(dts, dtype=np.float64)
+        assert d.size == len(self.ws)
+        _check(lib().btx_batch_step(self.h, _p(d), int(n)))
+
+    def use_graph(self, enable):
+        _check(lib().btx_batch_use_graph(self.h, int(enable)))
+
+    def shape(self, m):
+        a, b = C.c_int32(), C.c_int32()
+        _check(lib().btx_batch_shape(self.h, m, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def moments(self, m):
+        w = self.ws[m]
+        zm = np.zeros((w.n_zones, w.n_species, 5))
+        tot = np.zeros((w.n_species, 3))
+        _check(lib().btx_batch_moments(self.h, m, _p(zm), _p(tot)))
+        return zm, tot

@@ -24,6 +24,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -75,6 +77,22 @@ struct FaceAux {
   double v[5][3];
   double alpha[5], psi[5], gam[5], p6[5];
   double M[2][9];
+};
+
+// Everything the kernels need about one model (a grid with its background,
+// state and per-face data), in device memory.  A batch holds one per model; a
+// single context holds one.  Work items name (model, face) or (model, zone).
+struct ModelDev {
+  DevGrid g;
+  const FaceDesc *faces;
+  const btx::ZoneFaces *zf;
+  char *tabs;                  // remap tables of every face
+  FaceAux *aux;                // frame data of every face
+  void *f[2];                  // state double buffer (storage precision)
+  const void *ka, *ks, *feq;   // [zone][species][group] (storage precision)
+  void *dN;                    // [face][side][species][group][direction]
+  double *tally;               // [face][species] cumulative content through ghost faces
+  double dt;                   // step of the current launch
 };
 
 __device__ inline double dsq(double x) { return x * x; }
@@ -419,13 +437,17 @@ __device__ inline double frame_weight(const DevGrid &g, const FaceAux &A, int k,
 // table t: 0 Lm->L, 1 R->L, 2 L->R, 3 Rp->R, 4 L->s, 5 R->s, 6 s->L, 7 s->R
 template <typename T>
 __global__ void __launch_bounds__(256)
-table_kernel(DevGrid g, const FaceDesc *__restrict__ faces, char *__restrict__ tabs_g,
-             FaceAux *__restrict__ aux, int face0)
+table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items)
 {
   extern __shared__ __align__(16) char lds[];
   __shared__ int flg[kTables];
-  const int fid = face0 + blockIdx.x;
-  const FaceDesc &F = faces[fid];
+  const int2 it = items[blockIdx.x];
+  const ModelDev &M = models[it.x];
+  const DevGrid &g = M.g;
+  char *__restrict__ tabs_g = M.tabs;
+  FaceAux *__restrict__ aux = M.aux;
+  const int fid = it.y;
+  const FaceDesc &F = M.faces[fid];
   const int nd = g.ndir, tid = threadIdx.x, nthr = blockDim.x;
   const size_t tstride = tab_stride(nd, sizeof(T));
   char *p = lds;
@@ -617,14 +639,23 @@ __device__ __forceinline__ void store_side(const T v[CE], const T gl[CE], T a, i
 //   phase 3 remapped content change of both sides (Eq. fullstep)
 template <typename T, int NCH, int CE, int MAXT, bool SPLIT>
 __global__ void __launch_bounds__(MAXT)
-face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restrict__ tabs_g,
-            const FaceAux *__restrict__ aux, const T *__restrict__ f, const T *__restrict__ ka,
-            const T *__restrict__ ks, const T *__restrict__ feq, T *__restrict__ dN,
-            double *__restrict__ tally, double dt, int face0)
+face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity)
 {
   extern __shared__ __align__(16) char lds[];
-  const int fid = face0 + blockIdx.x;
-  const FaceDesc &F = faces[fid];
+  const int2 it = items[blockIdx.x];
+  const ModelDev &M = models[it.x];
+  const DevGrid &g = M.g;
+  const char *__restrict__ tabs_g = M.tabs;
+  const FaceAux *__restrict__ aux = M.aux;
+  const T *__restrict__ f = (const T *)M.f[parity];
+  const T *__restrict__ ka = (const T *)M.ka;
+  const T *__restrict__ ks = (const T *)M.ks;
+  const T *__restrict__ feq = (const T *)M.feq;
+  T *__restrict__ dN = (T *)M.dN;
+  double *__restrict__ tally = M.tally;
+  const double dt = M.dt;
+  const int fid = it.y;
+  const FaceDesc &F = M.faces[fid];
   const int nd = g.ndir, ne = g.ne, tid = threadIdx.x, nthr = blockDim.x;
   T *outL = dN + (size_t)fid * 2 * g.blk, *outR = outL + g.blk;
   if (!F.active) {
@@ -902,11 +933,20 @@ face_kernel(DevGrid g, const FaceDesc *__restrict__ faces, const char *__restric
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-zone_kernel(DevGrid g, const btx::ZoneFaces *__restrict__ zf, const T *__restrict__ f,
-            const T *__restrict__ dN, const T *__restrict__ ka, const T *__restrict__ ks,
-            const T *__restrict__ feq, T *__restrict__ fout, double dt)
+zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity)
 {
-  const int z = blockIdx.x;
+  const int2 it = items[blockIdx.x];
+  const ModelDev &M = models[it.x];
+  const DevGrid &g = M.g;
+  const btx::ZoneFaces *__restrict__ zf = M.zf;
+  const T *__restrict__ f = (const T *)M.f[parity];
+  T *__restrict__ fout = (T *)M.f[parity ^ 1];
+  const T *__restrict__ dN = (const T *)M.dN;
+  const T *__restrict__ ka = (const T *)M.ka;
+  const T *__restrict__ ks = (const T *)M.ks;
+  const T *__restrict__ feq = (const T *)M.feq;
+  const double dt = M.dt;
+  const int z = it.y;
   const int nd = g.ndir, ne = g.ne, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
   const btx::ZoneFaces L = zf[z];
@@ -956,8 +996,12 @@ zone_kernel(DevGrid g, const btx::ZoneFaces *__restrict__ zf, const T *__restric
 // zm[z][s][0..4] = N, J, H, K, number flux; ze[z][s] = energy content
 template <typename T>
 __global__ void __launch_bounds__(256)
-moments_kernel(DevGrid g, const T *__restrict__ f, double *__restrict__ zm, double *__restrict__ ze)
+moments_kernel(const ModelDev *__restrict__ models, int m, int parity, double *__restrict__ zm,
+               double *__restrict__ ze)
 {
+  const ModelDev &M = models[m];
+  const DevGrid &g = M.g;
+  const T *__restrict__ f = (const T *)M.f[parity];
   const int z = blockIdx.x;
   __shared__ double red[6][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
@@ -1008,64 +1052,45 @@ __global__ void cast_kernel(const double *__restrict__ src, T *__restrict__ dst,
 
 }  // namespace
 
-// ---------------------------------------------------------------- the ABI
-
-struct btx_ctx {
-  btx::Grid g;
-  int device = 0;
-  hipStream_t stream = nullptr;
-  size_t tsize = 8;                 // bytes per stored value
-  // device buffers
-  double *d_mu = nullptr, *d_Phi = nullptr, *d_dOm = nullptr, *d_nvec = nullptr, *d_G = nullptr,
-         *d_eps = nullptr, *d_vol = nullptr;
-  double *d_vr = nullptr, *d_vth = nullptr, *d_alp = nullptr, *d_psi = nullptr;
-  void *d_ka = nullptr, *d_ks = nullptr, *d_feq = nullptr;
-  void *d_f = nullptr, *d_fn = nullptr, *d_dN = nullptr;
-  char *d_tabs = nullptr;            // remap tables of every face (per background)
-  FaceAux *d_aux = nullptr;          // frame data of every face (per background)
-  size_t tab_lds = 0;
-  double *d_tally = nullptr, *d_zm = nullptr, *d_ze = nullptr, *d_stage = nullptr;
-  FaceDesc *d_faces = nullptr;
-  btx::ZoneFaces *d_zf = nullptr;
-  bool have_bg = false, have_state = false;
-  double dt_max1 = 0.0;
-  size_t lds_bytes = 0;
-  int face_threads = 0;
-  // timing: three events per step recorded on the stream, resolved on query
-  bool timing = false;
-  double t_ms[2] = { 0, 0 };
-  int64_t t_n[2] = { 0, 0 };
-  std::vector<hipEvent_t> ev;      // pool, 3 per recorded step
-  size_t ev_used = 0;              // events recorded and not yet resolved
-};
+// ---------------------------------------------------------------- host side
 
 namespace {
 
-// Face work-item shape.  FP32: 8 items per direction (up to 96 directions in
-// workgroups of up to 768 threads, up to 128 in 1024); FP64: 4 items per
-// direction (up to 128 directions, 512 threads), which keeps its larger LDS
-// buffers within one CU.  CE is the smallest instantiated value with
-// nch CE >= ne + 3; 0 if there is none (more than 61 groups).
+// Face work-item shape: nch items per direction (a power of two), CE groups
+// per item, the workgroup size bound and whether group -1 ends an item.
+// FP32 takes 8 items per direction by default (up to 96 directions in
+// workgroups of up to 768 threads, up to 128 in 1024) or 4; FP64 takes 4 (up
+// to 128 directions, 512 threads), which keeps its larger LDS buffers within
+// one CU.  CE is the smallest instantiated value with nch CE >= ne + 3.
 struct FaceShape {
   int nch = 0, ce = 0, maxt = 0;
+  bool split = false;
+  bool operator==(const FaceShape &o) const
+  {
+    return nch == o.nch && ce == o.ce && maxt == o.maxt && split == o.split;
+  }
 };
 
 constexpr int kCE8[] = { 3, 4, 5, 6, 8 };
 constexpr int kCE4[] = { 4, 5, 6, 7, 8, 12, 16 };
 
-FaceShape face_shape(const btx::Grid &g)
+FaceShape make_shape(int prec, int nd, int ne, int nch)
 {
   FaceShape f;
-  if (g.ndir > 128) return f;
-  f.nch = g.prec == BTX_PREC_FP64 ? 4 : 8;
-  f.maxt = f.nch == 4 ? 512 : (g.ndir <= 96 ? 768 : 1024);
-  auto pick = [&](const int *c, int n) {
-    for (int k = 0; k < n; ++k)
-      if (f.nch * c[k] >= g.ne + 3) return c[k];
-    return 0;
-  };
-  f.ce = f.nch == 8 ? pick(kCE8, 5) : pick(kCE4, 7);
+  if (nd > 128 || (nch != 4 && nch != 8) || (prec == BTX_PREC_FP64 && nch != 4)) return f;
+  f.nch = nch;
+  f.maxt = nch == 4 ? 512 : (nd <= 96 ? 768 : 1024);
+  const int *c = nch == 8 ? kCE8 : kCE4;
+  const int n = nch == 8 ? 5 : 7;
+  for (int k = 0; k < n && !f.ce; ++k)
+    if (nch * c[k] >= ne + 3) f.ce = c[k];
+  f.split = f.ce && (ne + 2) % f.ce == 0;
   return f;
+}
+
+FaceShape default_shape(const btx::Grid &g)
+{
+  return make_shape(g.prec, g.ndir, g.ne, g.prec == BTX_PREC_FP64 ? 4 : 8);
 }
 
 template <typename T, int NCH, int MAXT, bool SPLIT>
@@ -1094,37 +1119,22 @@ const void *face_fn_t(int ce)
   }
 }
 
-// the instance for this grid; SPLIT when group -1 ends a work item
-// ((ne + 2) a multiple of CE)
+// the face-kernel instance of a shape
 template <typename T>
-const void *face_fn(const btx::Grid &g)
+const void *face_fn(const FaceShape &f)
 {
-  const FaceShape f = face_shape(g);
   if (f.ce == 0) return nullptr;
-  const bool split = (g.ne + 2) % f.ce == 0;
-  if constexpr (sizeof(T) == 8) {
-    return split ? face_fn_t<T, 4, 512, true>(f.ce) : face_fn_t<T, 4, 512, false>(f.ce);
-  } else {
-    if (f.maxt == 768) return split ? face_fn_t<T, 8, 768, true>(f.ce) : face_fn_t<T, 8, 768, false>(f.ce);
-    return split ? face_fn_t<T, 8, 1024, true>(f.ce) : face_fn_t<T, 8, 1024, false>(f.ce);
+  if (f.nch == 4) return f.split ? face_fn_t<T, 4, 512, true>(f.ce) : face_fn_t<T, 4, 512, false>(f.ce);
+  if constexpr (sizeof(T) == 4) {
+    if (f.maxt == 768) return f.split ? face_fn_t<T, 8, 768, true>(f.ce) : face_fn_t<T, 8, 768, false>(f.ce);
+    return f.split ? face_fn_t<T, 8, 1024, true>(f.ce) : face_fn_t<T, 8, 1024, false>(f.ce);
   }
+  return nullptr;
 }
 
-DevGrid dev_grid(const btx_ctx *c)
+const void *face_fn(size_t tsize, const FaceShape &f)
 {
-  const btx::Grid &g = c->g;
-  DevGrid d;
-  d.nr = g.nr; d.nth = g.nth; d.ne = g.ne; d.nmu = g.nmu; d.nphi = g.nphi; d.ns = g.ns;
-  d.ndir = g.ndir; d.nz = g.nz; d.geom = g.geom; d.phi_rule = g.phi_rule;
-  d.eblk = g.ne * g.ndir; d.blk = g.ns * d.eblk;
-  d.nfaces = (int)g.faces.size();
-  d.lnq = g.lnq; d.q = g.q; d.fp64_thr = g.fp64_thr;
-  d.nch = face_shape(g).nch;
-  d.ce = face_shape(g).ce;
-  d.mu = c->d_mu; d.Phi = c->d_Phi; d.dOm = c->d_dOm; d.nvec = c->d_nvec; d.G = c->d_G;
-  d.eps = c->d_eps; d.vol = c->d_vol;
-  d.vr = c->d_vr; d.vth = c->d_vth; d.alp = c->d_alp; d.psi = c->d_psi;
-  return d;
+  return tsize == 8 ? face_fn<double>(f) : face_fn<float>(f);
 }
 
 template <typename X>
@@ -1135,68 +1145,59 @@ btx_status upload(X **dst, const X *src, size_t n)
   return BTX_OK;
 }
 
-size_t face_lds(const btx::Grid &g, size_t szT)
+btx_status device_lds_cap(int device, size_t *cap)
 {
-  const FaceShape f = face_shape(g);
-  return face_lds_bytes(g.ndir, f.nch, f.ce, szT);
-}
-
-void free_ctx(btx_ctx *c)
-{
-  void *ptrs[] = { c->d_mu, c->d_Phi, c->d_dOm, c->d_nvec, c->d_G, c->d_eps, c->d_vol, c->d_vr,
-                   c->d_vth, c->d_alp, c->d_psi, c->d_ka, c->d_ks, c->d_feq, c->d_f, c->d_fn,
-                   c->d_dN, c->d_tally, c->d_zm, c->d_ze, c->d_stage, c->d_faces, c->d_zf, c->d_tabs, c->d_aux };
-  for (void *p : ptrs) if (p) (void)hipFree(p);
-  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
-  delete c;
-}
-
-template <typename T>
-btx_status launch_step(btx_ctx *c, double dt)
-{
-  DevGrid dg = dev_grid(c);
-  int nf = dg.nfaces;
-  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-  bool rec = c->timing && c->ev_used + 3 <= c->ev.size();
-  if (rec) {
-    e0 = c->ev[c->ev_used]; e1 = c->ev[c->ev_used + 1]; e2 = c->ev[c->ev_used + 2];
-    c->ev_used += 3;
-    HIP_TRY(hipEventRecord(e0, c->stream));
-  }
-  const void *fn = face_fn<T>(c->g);
-  const FaceDesc *faces = c->d_faces;
-  const char *tabs = c->d_tabs;
-  const FaceAux *aux = c->d_aux;
-  const T *f = (const T *)c->d_f, *ka = (const T *)c->d_ka, *ks = (const T *)c->d_ks, *feq = (const T *)c->d_feq;
-  T *dN = (T *)c->d_dN;
-  double *tally = c->d_tally;
-  const int maxgrid = 1 << 30;
-  for (int f0 = 0; f0 < nf; f0 += maxgrid) {
-    int nb = std::min(nf - f0, maxgrid);
-    void *args[] = { &dg, &faces, &tabs, &aux, &f, &ka, &ks, &feq, &dN, &tally, &dt, &f0 };
-    HIP_TRY(hipLaunchKernel(fn, dim3(nb), dim3(c->face_threads), args, c->lds_bytes, c->stream));
-  }
-  HIP_TRY(hipGetLastError());
-  if (rec) HIP_TRY(hipEventRecord(e1, c->stream));
-  hipLaunchKernelGGL((zone_kernel<T>), dim3(dg.nz), dim3(256), 0, c->stream, dg, c->d_zf,
-                     (const T *)c->d_f, (const T *)c->d_dN, (const T *)c->d_ka, (const T *)c->d_ks,
-                     (const T *)c->d_feq, (T *)c->d_fn, dt);
-  HIP_TRY(hipGetLastError());
-  if (rec) HIP_TRY(hipEventRecord(e2, c->stream));
-  std::swap(c->d_f, c->d_fn);
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  *cap = std::max<size_t>((size_t)prop.sharedMemPerBlock, (size_t)prop.maxSharedMemoryPerMultiProcessor);
   return BTX_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *btx_last_error(void) { return g_err.c_str(); }
-
-btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, btx_ctx **out)
+// Raises the dynamic-LDS limit of a kernel to at least lds bytes.  The
+// attribute belongs to the function and is shared by every context and batch
+// of the process, so it is only ever raised (each launch still allocates just
+// what it asks for).
+btx_status raise_lds_limit(const void *fn, size_t lds)
 {
-  if (!d || !out) return fail(BTX_E_INVAL, "null argument");
-  *out = nullptr;
+  static std::mutex mu;
+  static std::map<const void *, size_t> limit;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t &cur = limit[fn];
+  if (lds <= cur) return BTX_OK;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess)
+    return fail(BTX_E_UNSUPPORTED, "a workgroup needs " + std::to_string(lds) + " B of LDS: " + hipGetErrorString(e));
+  cur = lds;
+  return BTX_OK;
+}
+
+// ------------------------------------------------------------ one model
+
+// Host-side owner of one model's device memory.
+struct Model {
+  btx::Grid g;
+  int index = 0;                     // position in the device descriptor array
+  size_t tsize = 8;                  // bytes per stored value
+  FaceShape shape;
+  double *d_mu = nullptr, *d_Phi = nullptr, *d_dOm = nullptr, *d_nvec = nullptr, *d_G = nullptr,
+         *d_eps = nullptr, *d_vol = nullptr;
+  double *d_vr = nullptr, *d_vth = nullptr, *d_alp = nullptr, *d_psi = nullptr;
+  void *d_ka = nullptr, *d_ks = nullptr, *d_feq = nullptr, *d_f[2] = { nullptr, nullptr }, *d_dN = nullptr;
+  char *d_tabs = nullptr;
+  FaceAux *d_aux = nullptr;
+  double *d_tally = nullptr, *d_zm = nullptr, *d_ze = nullptr, *d_stage = nullptr;
+  FaceDesc *d_faces = nullptr;
+  btx::ZoneFaces *d_zf = nullptr;
+  int2 *d_fitems = nullptr, *d_zitems = nullptr;   // (index, face), (index, zone)
+  bool have_bg = false, have_state = false;
+  double dt_max1 = 0.0;
+  size_t tab_lds = 0;
+};
+
+// Checks a grid description; the message names the first problem.
+btx_status validate_desc(const btx_grid_desc *d)
+{
+  if (!d) return fail(BTX_E_INVAL, "null grid description");
   if (d->n_r < 1 || d->n_eps < 1 || d->n_mu < 2 || d->n_phi < 1 || d->n_species < 1)
     return fail(BTX_E_INVAL, "sizes must be positive (n_mu >= 2)");
   if (d->geometry < 0 || d->geometry > 2) return fail(BTX_E_INVAL, "unknown geometry");
@@ -1209,10 +1210,10 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
   if (d->precision != BTX_PREC_FP64 && d->precision != BTX_PREC_MIXED)
     return fail(BTX_E_INVAL, "unknown precision");
   if (!d->r_edges || !d->eps_edges) return fail(BTX_E_INVAL, "null edge array");
-  int nth = d->geometry == BTX_GEOM_AXISYM2D ? d->n_theta : 1;
+  const int nth = d->geometry == BTX_GEOM_AXISYM2D ? d->n_theta : 1;
   if (nth < 1) return fail(BTX_E_INVAL, "n_theta must be positive");
   if (d->n_mu * d->n_phi > 128) return fail(BTX_E_UNSUPPORTED, "at most 128 directions");
-  if (d->n_mu * d->n_phi * 4 > 65535) return fail(BTX_E_UNSUPPORTED, "too many directions");
+  if (d->n_eps > 61) return fail(BTX_E_UNSUPPORTED, "at most 61 energy groups");
   for (int a = 0; a < d->n_r; ++a)
     if (!(d->r_edges[a + 1] > d->r_edges[a])) return fail(BTX_E_INVAL, "r edges must ascend");
   if (d->geometry != BTX_GEOM_PLANAR && !(d->r_edges[0] >= 0.0)) return fail(BTX_E_INVAL, "r edges must be >= 0");
@@ -1227,8 +1228,27 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
       if (!(d->theta_edges[b + 1] > d->theta_edges[b])) return fail(BTX_E_INVAL, "theta edges must ascend");
     if (!(d->dphi > 0.0) || d->dphi > kPi) return fail(BTX_E_INVAL, "dphi must be in (0, pi]");
   }
-  btx_ctx *c = new btx_ctx();
-  btx::Grid &g = c->g;
+  return BTX_OK;
+}
+
+void model_free(Model &m)
+{
+  void *ptrs[] = { m.d_mu, m.d_Phi, m.d_dOm, m.d_nvec, m.d_G, m.d_eps, m.d_vol, m.d_vr, m.d_vth,
+                   m.d_alp, m.d_psi, m.d_ka, m.d_ks, m.d_feq, m.d_f[0], m.d_f[1], m.d_dN, m.d_tally,
+                   m.d_zm, m.d_ze, m.d_stage, m.d_faces, m.d_zf, m.d_tabs, m.d_aux, m.d_fitems, m.d_zitems };
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  m = Model();
+}
+
+// Grid, quadrature and faces (paper Sec. 3.1) on the host, device buffers.
+// The current device must be set.  On failure nothing stays allocated.
+btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_cap)
+{
+  btx_status st = validate_desc(d);
+  if (st != BTX_OK) return st;
+  btx::Grid &g = m.g;
+  const int nth = d->geometry == BTX_GEOM_AXISYM2D ? d->n_theta : 1;
   g.nr = d->n_r; g.nth = nth; g.ne = d->n_eps; g.nmu = d->n_mu; g.nphi = d->n_phi; g.ns = d->n_species;
   g.geom = d->geometry; g.mu_rule = d->mu_rule; g.phi_rule = d->phi_rule;
   g.inner_bc = d->inner_bc; g.outer_bc = d->outer_bc; g.prec = d->precision;
@@ -1239,86 +1259,93 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
   if (g.geom == BTX_GEOM_AXISYM2D) g.th_e.assign(d->theta_edges, d->theta_edges + nth + 1);
   else g.th_e = { 0.0, kPi };
   std::string why = btx::build_grid(g);
-  if (!why.empty()) { delete c; return fail(BTX_E_UNSUPPORTED, why); }
-  c->device = hip_device;
-  c->stream = (hipStream_t)hip_stream;
-  c->tsize = g.prec == BTX_PREC_FP64 ? 8 : 4;
-  c->dt_max1 = btx::max_dt(g, 1.0);
-  c->lds_bytes = face_lds(g, c->tsize);
-  c->tab_lds = kTables * tab_stride(g.ndir, c->tsize) + align16(5 * sizeof(Frame)) +
-               align16(scratch_bytes(g.ndir, c->tsize));
-  if (face_shape(g).ce == 0) {
-    delete c;
-    return fail(BTX_E_UNSUPPORTED, "no face work-item shape for n_eps = " + std::to_string(d->n_eps));
-  }
-  c->face_threads = ((face_shape(g).nch * g.ndir + 63) / 64) * 64;
-  btx_status st = BTX_OK;
-  hipError_t he = hipSetDevice(hip_device);
-  if (he != hipSuccess) { delete c; return fail(BTX_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(he)); }
-  hipDeviceProp_t prop;
-  he = hipGetDeviceProperties(&prop, hip_device);
-  if (he != hipSuccess) { delete c; return fail(BTX_E_DEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(he)); }
-  {
-    const void *fk = c->tsize == 8 ? face_fn<double>(g) : face_fn<float>(g);
-    he = hipFuncSetAttribute(fk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes);
-    (void)he;
-    const void *tk = c->tsize == 8 ? (const void *)table_kernel<double> : (const void *)table_kernel<float>;
-    he = hipFuncSetAttribute(tk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->tab_lds);
-    (void)he;
-  }
-  size_t lds_cap = std::max<size_t>((size_t)prop.sharedMemPerBlock, (size_t)prop.maxSharedMemoryPerMultiProcessor);
-  if (c->lds_bytes > lds_cap) {
-    size_t need = c->lds_bytes;
-    delete c;
-    return fail(BTX_E_UNSUPPORTED, "face workgroup needs " + std::to_string(need) + " B of LDS");
-  }
-  size_t nz = g.nz, blk = (size_t)g.ns * g.ne * g.ndir, nk = nz * g.ns * g.ne;
-  size_t nf = g.faces.size();
-#define TRY(x) do { st = (x); if (st != BTX_OK) { free_ctx(c); return st; } } while (0)
-  TRY(upload(&c->d_mu, g.mu.data(), g.mu.size()));
-  TRY(upload(&c->d_Phi, g.Phi.data(), g.Phi.size()));
-  TRY(upload(&c->d_dOm, g.dOm.data(), g.dOm.size()));
-  TRY(upload(&c->d_nvec, g.nvec.data(), g.nvec.size()));
-  TRY(upload(&c->d_G, g.G.data(), g.G.size()));
-  TRY(upload(&c->d_eps, g.eps.data(), g.eps.size()));
-  TRY(upload(&c->d_vol, g.vol.data(), g.vol.size()));
-  TRY(upload(&c->d_faces, g.faces.data(), nf));
-  TRY(upload(&c->d_zf, g.zfaces.data(), g.zfaces.size()));
+  if (!why.empty()) return fail(BTX_E_UNSUPPORTED, why);
+  m.index = index;
+  m.tsize = g.prec == BTX_PREC_FP64 ? 8 : 4;
+  m.dt_max1 = btx::max_dt(g, 1.0);
+  m.shape = default_shape(g);
+  if (m.shape.ce == 0) return fail(BTX_E_UNSUPPORTED, "no face work-item shape for this grid");
+  if (face_lds_bytes(g.ndir, m.shape.nch, m.shape.ce, m.tsize) > lds_cap)
+    return fail(BTX_E_UNSUPPORTED, "face workgroup needs " +
+                                       std::to_string(face_lds_bytes(g.ndir, m.shape.nch, m.shape.ce, m.tsize)) +
+                                       " B of LDS");
+  m.tab_lds = kTables * tab_stride(g.ndir, m.tsize) + align16(5 * sizeof(Frame)) +
+              align16(scratch_bytes(g.ndir, m.tsize));
+  const size_t nz = g.nz, blk = (size_t)g.ns * g.ne * g.ndir, nk = nz * g.ns * g.ne, nf = g.faces.size();
+  std::vector<int2> fit(nf), zit(nz);
+  for (size_t k = 0; k < nf; ++k) fit[k] = make_int2(index, (int)k);
+  for (size_t k = 0; k < nz; ++k) zit[k] = make_int2(index, (int)k);
   std::vector<double> zero(nz, 0.0), one(nz, 1.0);
-  TRY(upload(&c->d_vr, zero.data(), nz));
-  TRY(upload(&c->d_vth, zero.data(), nz));
-  TRY(upload(&c->d_alp, one.data(), nz));
-  TRY(upload(&c->d_psi, one.data(), nz));
+#define TRY(x) do { st = (x); if (st != BTX_OK) { model_free(m); return st; } } while (0)
+  TRY(upload(&m.d_mu, g.mu.data(), g.mu.size()));
+  TRY(upload(&m.d_Phi, g.Phi.data(), g.Phi.size()));
+  TRY(upload(&m.d_dOm, g.dOm.data(), g.dOm.size()));
+  TRY(upload(&m.d_nvec, g.nvec.data(), g.nvec.size()));
+  TRY(upload(&m.d_G, g.G.data(), g.G.size()));
+  TRY(upload(&m.d_eps, g.eps.data(), g.eps.size()));
+  TRY(upload(&m.d_vol, g.vol.data(), g.vol.size()));
+  TRY(upload(&m.d_faces, g.faces.data(), nf));
+  TRY(upload(&m.d_zf, g.zfaces.data(), g.zfaces.size()));
+  TRY(upload(&m.d_fitems, fit.data(), nf));
+  TRY(upload(&m.d_zitems, zit.data(), nz));
+  TRY(upload(&m.d_vr, zero.data(), nz));
+  TRY(upload(&m.d_vth, zero.data(), nz));
+  TRY(upload(&m.d_alp, one.data(), nz));
+  TRY(upload(&m.d_psi, one.data(), nz));
 #undef TRY
   auto dmalloc = [&](void **p, size_t bytes) -> bool {
     if (hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) return false;
     return hipMemset(*p, 0, std::max<size_t>(bytes, 16)) == hipSuccess;
   };
-  if (!dmalloc(&c->d_ka, nk * c->tsize) || !dmalloc(&c->d_ks, nk * c->tsize) ||
-      !dmalloc(&c->d_feq, nk * c->tsize) || !dmalloc(&c->d_f, nz * blk * c->tsize) ||
-      !dmalloc(&c->d_fn, nz * blk * c->tsize) || !dmalloc(&c->d_dN, nf * 2 * blk * c->tsize) ||
-      !dmalloc((void **)&c->d_tally, nf * g.ns * 8) || !dmalloc((void **)&c->d_zm, nz * g.ns * 5 * 8) ||
-      !dmalloc((void **)&c->d_ze, nz * g.ns * 8) ||
-      !dmalloc((void **)&c->d_stage, nk * 8) ||
-      !dmalloc((void **)&c->d_tabs, nf * kTables * tab_stride(g.ndir, c->tsize)) ||
-      !dmalloc((void **)&c->d_aux, nf * sizeof(FaceAux))) {
-    free_ctx(c);
+  if (!dmalloc(&m.d_ka, nk * m.tsize) || !dmalloc(&m.d_ks, nk * m.tsize) || !dmalloc(&m.d_feq, nk * m.tsize) ||
+      !dmalloc(&m.d_f[0], nz * blk * m.tsize) || !dmalloc(&m.d_f[1], nz * blk * m.tsize) ||
+      !dmalloc(&m.d_dN, nf * 2 * blk * m.tsize) || !dmalloc((void **)&m.d_tally, nf * g.ns * 8) ||
+      !dmalloc((void **)&m.d_zm, nz * g.ns * 5 * 8) || !dmalloc((void **)&m.d_ze, nz * g.ns * 8) ||
+      !dmalloc((void **)&m.d_stage, nk * 8) ||
+      !dmalloc((void **)&m.d_tabs, nf * kTables * tab_stride(g.ndir, m.tsize)) ||
+      !dmalloc((void **)&m.d_aux, nf * sizeof(FaceAux))) {
+    model_free(m);
     return fail(BTX_E_NOMEM, "device allocation failed");
   }
-  c->ev.resize(3 * 256);
-  for (auto &e : c->ev)
-    if (hipEventCreate(&e) != hipSuccess) { free_ctx(c); return fail(BTX_E_DEVICE, "hipEventCreate failed"); }
-  *out = c;
   return BTX_OK;
 }
 
-btx_status btx_set_background(btx_ctx *c, const btx_background *bg)
+// the device descriptor of a model (its current face shape and step)
+ModelDev model_dev(const Model &m, double dt)
 {
-  if (!c || !bg) return fail(BTX_E_INVAL, "null argument");
+  const btx::Grid &g = m.g;
+  ModelDev M;
+  DevGrid &d = M.g;
+  d.nr = g.nr; d.nth = g.nth; d.ne = g.ne; d.nmu = g.nmu; d.nphi = g.nphi; d.ns = g.ns;
+  d.ndir = g.ndir; d.nz = g.nz; d.geom = g.geom; d.phi_rule = g.phi_rule;
+  d.eblk = g.ne * g.ndir; d.blk = g.ns * d.eblk;
+  d.nfaces = (int)g.faces.size();
+  d.nch = m.shape.nch;
+  d.ce = m.shape.ce;
+  d.lnq = g.lnq; d.q = g.q; d.fp64_thr = g.fp64_thr;
+  d.mu = m.d_mu; d.Phi = m.d_Phi; d.dOm = m.d_dOm; d.nvec = m.d_nvec; d.G = m.d_G;
+  d.eps = m.d_eps; d.vol = m.d_vol;
+  d.vr = m.d_vr; d.vth = m.d_vth; d.alp = m.d_alp; d.psi = m.d_psi;
+  M.faces = m.d_faces;
+  M.zf = m.d_zf;
+  M.tabs = m.d_tabs;
+  M.aux = m.d_aux;
+  M.f[0] = m.d_f[0];
+  M.f[1] = m.d_f[1];
+  M.ka = m.d_ka; M.ks = m.d_ks; M.feq = m.d_feq;
+  M.dN = m.d_dN;
+  M.tally = m.d_tally;
+  M.dt = dt;
+  return M;
+}
+
+btx_status check_background(const Model &m, const btx_background *bg)
+{
+  if (!bg) return fail(BTX_E_INVAL, "null argument");
   if (!bg->v_r || !bg->v_theta || !bg->alpha || !bg->psi || !bg->kappa_a || !bg->kappa_s || !bg->f_eq)
     return fail(BTX_E_INVAL, "null background array");
-  const btx::Grid &g = c->g;
-  size_t nz = g.nz, nk = nz * g.ns * g.ne;
+  const btx::Grid &g = m.g;
+  const size_t nz = g.nz, nk = nz * g.ns * g.ne;
   for (size_t z = 0; z < nz; ++z) {
     double v2 = bg->v_r[z] * bg->v_r[z] + bg->v_theta[z] * bg->v_theta[z];
     if (!(v2 < 1.0) || !(bg->alpha[z] > 0.0) || !(bg->psi[z] > 0.0) || !std::isfinite(bg->alpha[z]) ||
@@ -1329,42 +1356,488 @@ btx_status btx_set_background(btx_ctx *c, const btx_background *bg)
     if (!(bg->kappa_a[k] >= 0.0) || !(bg->kappa_s[k] >= 0.0) || !std::isfinite(bg->kappa_a[k]) ||
         !std::isfinite(bg->kappa_s[k]) || !std::isfinite(bg->f_eq[k]))
       return fail(BTX_E_INVAL, "opacities must be finite and >= 0 (entry " + std::to_string(k) + ")");
-  HIP_TRY(hipSetDevice(c->device));
-  HIP_TRY(hipMemcpy(c->d_vr, bg->v_r, nz * 8, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(c->d_vth, bg->v_theta, nz * 8, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(c->d_alp, bg->alpha, nz * 8, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(c->d_psi, bg->psi, nz * 8, hipMemcpyHostToDevice));
+  return BTX_OK;
+}
+
+// copies the background into the model's buffers (storage precision)
+btx_status upload_background(Model &m, const btx_background *bg, hipStream_t s)
+{
+  const btx::Grid &g = m.g;
+  const size_t nz = g.nz, nk = nz * g.ns * g.ne;
+  HIP_TRY(hipMemcpy(m.d_vr, bg->v_r, nz * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(m.d_vth, bg->v_theta, nz * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(m.d_alp, bg->alpha, nz * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(m.d_psi, bg->psi, nz * 8, hipMemcpyHostToDevice));
   const double *src[3] = { bg->kappa_a, bg->kappa_s, bg->f_eq };
-  void *dst[3] = { c->d_ka, c->d_ks, c->d_feq };
+  void *dst[3] = { m.d_ka, m.d_ks, m.d_feq };
   for (int k = 0; k < 3; ++k) {
-    if (c->tsize == 8) {
+    if (m.tsize == 8) {
       HIP_TRY(hipMemcpy(dst[k], src[k], nk * 8, hipMemcpyHostToDevice));
     } else {
-      HIP_TRY(hipMemcpy(c->d_stage, src[k], nk * 8, hipMemcpyHostToDevice));
-      hipLaunchKernelGGL((cast_kernel<float>), dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, 0,
-                         c->d_stage, (float *)dst[k], nk);
+      HIP_TRY(hipMemcpy(m.d_stage, src[k], nk * 8, hipMemcpyHostToDevice));
+      hipLaunchKernelGGL((cast_kernel<float>), dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s,
+                         m.d_stage, (float *)dst[k], nk);
       HIP_TRY(hipGetLastError());
-      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipStreamSynchronize(s));
     }
   }
-  // remap tables of every face for this background
-  {
-    DevGrid dg = dev_grid(c);
-    int nf = dg.nfaces;
-    const int maxgrid = 1 << 30;
-    for (int f0 = 0; f0 < nf; f0 += maxgrid) {
-      int nb = std::min(nf - f0, maxgrid);
-      if (c->tsize == 8)
-        hipLaunchKernelGGL((table_kernel<double>), dim3(nb), dim3(256), c->tab_lds, c->stream, dg, c->d_faces,
-                           c->d_tabs, c->d_aux, f0);
-      else
-        hipLaunchKernelGGL((table_kernel<float>), dim3(nb), dim3(256), c->tab_lds, c->stream, dg, c->d_faces,
-                           c->d_tabs, c->d_aux, f0);
+  return BTX_OK;
+}
+
+// remap tables and frame data of every face of a model (its descriptor must
+// be current on the device: the window offsets depend on the face shape)
+btx_status build_tables(const Model &m, const ModelDev *d_models, hipStream_t s)
+{
+  const int nf = (int)m.g.faces.size();
+  if (nf == 0) return BTX_OK;
+  const void *tk = m.tsize == 8 ? (const void *)table_kernel<double> : (const void *)table_kernel<float>;
+  btx_status st = raise_lds_limit(tk, m.tab_lds);
+  if (st != BTX_OK) return st;
+  const int2 *items = m.d_fitems;
+  void *args[] = { &d_models, &items };
+  HIP_TRY(hipLaunchKernel(tk, dim3(nf), dim3(256), args, m.tab_lds, s));
+  return BTX_OK;
+}
+
+btx_status launch_faces(const FaceShape &shape, size_t tsize, const ModelDev *d_models, const int2 *items,
+                        int n, int threads, size_t lds, int parity, hipStream_t s)
+{
+  if (n == 0) return BTX_OK;
+  const void *fn = face_fn(tsize, shape);
+  if (!fn) return fail(BTX_E_UNSUPPORTED, "no face kernel for this shape");
+  void *args[] = { &d_models, &items, &parity };
+  HIP_TRY(hipLaunchKernel(fn, dim3(n), dim3(threads), args, lds, s));
+  return BTX_OK;
+}
+
+btx_status launch_zones(size_t tsize, const ModelDev *d_models, const int2 *items, int n, int parity,
+                        hipStream_t s)
+{
+  if (n == 0) return BTX_OK;
+  const void *zk = tsize == 8 ? (const void *)zone_kernel<double> : (const void *)zone_kernel<float>;
+  void *args[] = { &d_models, &items, &parity };
+  HIP_TRY(hipLaunchKernel(zk, dim3(n), dim3(256), args, 0, s));
+  return BTX_OK;
+}
+
+int face_threads(const Model &m) { return ((m.shape.nch * m.g.ndir + 63) / 64) * 64; }
+
+size_t face_lds(const Model &m) { return face_lds_bytes(m.g.ndir, m.shape.nch, m.shape.ce, m.tsize); }
+
+btx_status set_face_lds(size_t tsize, const FaceShape &f, size_t lds)
+{
+  const void *fn = face_fn(tsize, f);
+  if (!fn) return fail(BTX_E_UNSUPPORTED, "no face kernel for this shape");
+  return raise_lds_limit(fn, lds);
+}
+
+btx_status model_set_state(Model &m, int parity, const void *f, int is_device_ptr, hipStream_t s)
+{
+  if (!f) return fail(BTX_E_INVAL, "null state");
+  const btx::Grid &g = m.g;
+  const size_t bytes = (size_t)g.nz * g.ns * g.ne * g.ndir * m.tsize;
+  HIP_TRY(hipMemcpyAsync(m.d_f[parity], f, bytes, is_device_ptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(m.d_tally, 0, std::max<size_t>(g.faces.size(), 1) * g.ns * 8, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  m.have_state = true;
+  return BTX_OK;
+}
+
+btx_status model_get_state(const Model &m, int parity, void *f, int is_device_ptr, hipStream_t s)
+{
+  if (!f) return fail(BTX_E_INVAL, "null state");
+  if (!m.have_state) return fail(BTX_E_STATE, "no state set");
+  const btx::Grid &g = m.g;
+  const size_t bytes = (size_t)g.nz * g.ns * g.ne * g.ndir * m.tsize;
+  HIP_TRY(hipMemcpyAsync(f, m.d_f[parity], bytes, is_device_ptr ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return BTX_OK;
+}
+
+btx_status model_moments(const Model &m, const ModelDev *d_models, int parity, double *zone_moments,
+                         double *totals, hipStream_t s)
+{
+  if (!m.have_bg || !m.have_state) return fail(BTX_E_STATE, "background and state must be set");
+  const btx::Grid &g = m.g;
+  int idx = m.index;
+  double *zm = m.d_zm, *ze = m.d_ze;
+  void *args[] = { &d_models, &idx, &parity, &zm, &ze };
+  const void *mk = m.tsize == 8 ? (const void *)moments_kernel<double> : (const void *)moments_kernel<float>;
+  HIP_TRY(hipLaunchKernel(mk, dim3(g.nz), dim3(256), args, 0, s));
+  std::vector<double> hzm((size_t)g.nz * g.ns * 5), hze((size_t)g.nz * g.ns), tally(g.faces.size() * g.ns);
+  HIP_TRY(hipMemcpyAsync(hzm.data(), m.d_zm, hzm.size() * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hze.data(), m.d_ze, hze.size() * 8, hipMemcpyDeviceToHost, s));
+  if (!tally.empty()) HIP_TRY(hipMemcpyAsync(tally.data(), m.d_tally, tally.size() * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (zone_moments) std::memcpy(zone_moments, hzm.data(), hzm.size() * 8);
+  if (totals) {
+    for (int sp = 0; sp < g.ns; ++sp) {
+      double N = 0.0, E = 0.0, out = 0.0;
+      for (int z = 0; z < g.nz; ++z) {
+        N += hzm[((size_t)z * g.ns + sp) * 5];
+        E += hze[(size_t)z * g.ns + sp];
+      }
+      for (int f : g.bface) out += tally[(size_t)f * g.ns + sp];
+      totals[3 * sp] = N;
+      totals[3 * sp + 1] = out;
+      totals[3 * sp + 2] = E;
     }
-    HIP_TRY(hipGetLastError());
+  }
+  return BTX_OK;
+}
+
+btx_status check_dt(const Model &m, double dt)
+{
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(BTX_E_INVAL, "dt must be positive and finite");
+  if (dt > m.dt_max1 * (1.0 + 1e-12)) return fail(BTX_E_CFL, "dt exceeds the Courant limit");
+  return BTX_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ single context
+
+struct btx_ctx {
+  Model m;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  ModelDev *d_model = nullptr;       // descriptor of m on the device
+  ModelDev h_model;                  // its host copy (dt of the last launch)
+  int parity = 0;                    // buffer holding the current state
+  // timing: three events per step recorded on the stream, resolved on query
+  bool timing = false;
+  double t_ms[2] = { 0, 0 };
+  int64_t t_n[2] = { 0, 0 };
+  std::vector<hipEvent_t> ev;      // pool, 3 per recorded step
+  size_t ev_used = 0;              // events recorded and not yet resolved
+};
+
+namespace {
+
+void free_ctx(btx_ctx *c)
+{
+  model_free(c->m);
+  if (c->d_model) (void)hipFree(c->d_model);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+btx_status ctx_step(btx_ctx *c, double dt)
+{
+  Model &m = c->m;
+  if (c->h_model.dt != dt) {                // kernels in flight read the descriptor
     HIP_TRY(hipStreamSynchronize(c->stream));
+    c->h_model.dt = dt;
+    HIP_TRY(hipMemcpy(c->d_model, &c->h_model, sizeof(ModelDev), hipMemcpyHostToDevice));
   }
-  c->have_bg = true;
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+  const bool rec = c->timing && c->ev_used + 3 <= c->ev.size();
+  if (rec) {
+    e0 = c->ev[c->ev_used]; e1 = c->ev[c->ev_used + 1]; e2 = c->ev[c->ev_used + 2];
+    c->ev_used += 3;
+    HIP_TRY(hipEventRecord(e0, c->stream));
+  }
+  btx_status st = launch_faces(m.shape, m.tsize, c->d_model, m.d_fitems, (int)m.g.faces.size(), face_threads(m),
+                               face_lds(m), c->parity, c->stream);
+  if (st != BTX_OK) return st;
+  if (rec) HIP_TRY(hipEventRecord(e1, c->stream));
+  st = launch_zones(m.tsize, c->d_model, m.d_zitems, m.g.nz, c->parity, c->stream);
+  if (st != BTX_OK) return st;
+  if (rec) HIP_TRY(hipEventRecord(e2, c->stream));
+  c->parity ^= 1;
+  return BTX_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ batch
+
+namespace {
+
+// Face work items of the models that share one face shape: one launch each.
+struct BatchGroup {
+  FaceShape shape;
+  int first = 0, count = 0;          // range in the group item array
+  int threads = 64;
+  size_t lds = 0;
+};
+
+}  // namespace
+
+struct btx_batch {
+  std::vector<Model> models;
+  int device = 0;
+  size_t tsize = 8;
+  hipStream_t stream = nullptr;      // caller's stream: all work is ordered on it
+  hipStream_t cap = nullptr;         // library stream used only to capture graphs
+  ModelDev *d_models = nullptr;
+  std::vector<ModelDev> h_models;
+  std::vector<BatchGroup> groups;
+  int2 *d_gitems = nullptr;          // face items of all groups, group after group
+  int2 *d_zitems = nullptr;          // zone items of every model
+  int nz_all = 0;
+  double *d_tscratch = nullptr;      // tally target while shapes are timed
+  int parity = 0;
+  bool tuned = false, use_graph = true;
+  hipGraphExec_t exec[2] = { nullptr, nullptr };
+  std::string tune_path;
+};
+
+namespace {
+
+void drop_graphs(btx_batch *b)
+{
+  for (auto &e : b->exec)
+    if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
+}
+
+void free_batch(btx_batch *b)
+{
+  drop_graphs(b);
+  for (Model &m : b->models) model_free(m);
+  void *ptrs[] = { b->d_models, b->d_gitems, b->d_zitems, b->d_tscratch };
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+}
+
+btx_status upload_descriptors(btx_batch *b)
+{
+  HIP_TRY(hipStreamSynchronize(b->stream));            // kernels in flight read them
+  HIP_TRY(hipMemcpy(b->d_models, b->h_models.data(), b->h_models.size() * sizeof(ModelDev),
+                    hipMemcpyHostToDevice));
+  return BTX_OK;
+}
+
+std::string tune_key(const Model &m)
+{
+  return std::string(m.tsize == 8 ? "f64" : "f32") + ":nd" + std::to_string(m.g.ndir) + ":ne" +
+         std::to_string(m.g.ne);
+}
+
+// tuning cache: a flat JSON object {"f32:nd16:ne12": 8, ...} (work items per
+// direction of each model class)
+std::vector<std::pair<std::string, int>> read_cache(const std::string &path)
+{
+  std::vector<std::pair<std::string, int>> out;
+  if (path.empty()) return out;
+  FILE *fp = std::fopen(path.c_str(), "r");
+  if (!fp) return out;
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof(buf), fp)) > 0) text.append(buf, n);
+  std::fclose(fp);
+  size_t p = 0;
+  while ((p = text.find('"', p)) != std::string::npos) {
+    size_t q = text.find('"', p + 1);
+    if (q == std::string::npos) break;
+    std::string key = text.substr(p + 1, q - p - 1);
+    size_t c = text.find(':', q);
+    if (c == std::string::npos) break;
+    int v = std::atoi(text.c_str() + c + 1);
+    if (v == 4 || v == 8) out.emplace_back(key, v);
+    p = c + 1;
+  }
+  return out;
+}
+
+void write_cache(const std::string &path, const std::vector<std::pair<std::string, int>> &kv)
+{
+  if (path.empty()) return;
+  FILE *fp = std::fopen(path.c_str(), "w");
+  if (!fp) return;
+  std::fprintf(fp, "{\n");
+  for (size_t k = 0; k < kv.size(); ++k)
+    std::fprintf(fp, "  \"%s\": %d%s\n", kv[k].first.c_str(), kv[k].second, k + 1 < kv.size() ? "," : "");
+  std::fprintf(fp, "}\n");
+  std::fclose(fp);
+}
+
+btx_status set_shape(btx_batch *b, Model &m, const FaceShape &f)
+{
+  m.shape = f;
+  b->h_models[m.index].g.nch = f.nch;
+  b->h_models[m.index].g.ce = f.ce;
+  return BTX_OK;
+}
+
+// Groups models by face shape and uploads the grouped face items.
+btx_status build_groups(btx_batch *b)
+{
+  drop_graphs(b);
+  b->groups.clear();
+  std::vector<int2> items;
+  std::vector<bool> done(b->models.size(), false);
+  for (size_t i = 0; i < b->models.size(); ++i) {
+    if (done[i]) continue;
+    BatchGroup gr;
+    gr.shape = b->models[i].shape;
+    gr.first = (int)items.size();
+    for (size_t j = i; j < b->models.size(); ++j) {
+      Model &m = b->models[j];
+      if (done[j] || !(m.shape == gr.shape)) continue;
+      done[j] = true;
+      for (size_t k = 0; k < m.g.faces.size(); ++k) items.push_back(make_int2(m.index, (int)k));
+      gr.threads = std::max(gr.threads, face_threads(m));
+      gr.lds = std::max(gr.lds, face_lds(m));
+    }
+    gr.count = (int)items.size() - gr.first;
+    btx_status st = set_face_lds(b->tsize, gr.shape, gr.lds);
+    if (st != BTX_OK) return st;
+    b->groups.push_back(gr);
+  }
+  if (b->d_gitems) { (void)hipFree(b->d_gitems); b->d_gitems = nullptr; }
+  return upload(&b->d_gitems, items.data(), items.size());
+}
+
+// Autotuner: FP32 models may run their faces with 8 or 4 work items per
+// direction (groups per item follow); each model class (precision,
+// directions, groups) takes the faster, timed on its own faces with the
+// current state.  Choices persist in the tuning cache file.
+btx_status tune(btx_batch *b)
+{
+  auto cache = read_cache(b->tune_path);
+  auto lookup = [&](const std::string &k) {
+    for (auto &kv : cache)
+      if (kv.first == k) return kv.second;
+    return 0;
+  };
+  // timing launches must not add to the boundary tallies
+  size_t tmax = 1;
+  for (Model &m : b->models) tmax = std::max(tmax, m.g.faces.size() * (size_t)m.g.ns);
+  if (!b->d_tscratch) HIP_TRY(hipMalloc((void **)&b->d_tscratch, tmax * 8));
+  std::vector<double *> tsave(b->models.size());
+  for (Model &m : b->models) {
+    tsave[m.index] = b->h_models[m.index].tally;
+    b->h_models[m.index].tally = b->d_tscratch;
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  btx_status st = BTX_OK;
+  for (size_t i = 0; i < b->models.size() && st == BTX_OK; ++i) {
+    const std::string key = tune_key(b->models[i]);
+    if (b->tsize == 8 || lookup(key)) continue;
+    std::vector<Model *> cls;
+    for (Model &m : b->models)
+      if (tune_key(m) == key) cls.push_back(&m);
+    float best = 1e30f;
+    int best_nch = 8;
+    for (int nch : { 8, 4 }) {
+      const FaceShape f = make_shape(cls[0]->g.prec, cls[0]->g.ndir, cls[0]->g.ne, nch);
+      if (f.ce == 0 || face_lds_bytes(cls[0]->g.ndir, f.nch, f.ce, b->tsize) > 160 * 1024) continue;
+      for (Model *m : cls) set_shape(b, *m, f);
+      if ((st = upload_descriptors(b)) != BTX_OK) break;
+      for (Model *m : cls)
+        if ((st = build_tables(*m, b->d_models, b->stream)) != BTX_OK) break;
+      if (st != BTX_OK || (st = set_face_lds(b->tsize, f, face_lds(*cls[0]))) != BTX_OK) break;
+      float ms = 0.f;
+      for (int rep = 0; rep < 4 && st == BTX_OK; ++rep) {
+        if (rep == 1) HIP_TRY(hipEventRecord(e0, b->stream));
+        for (Model *m : cls) {
+          st = launch_faces(f, b->tsize, b->d_models, m->d_fitems, (int)m->g.faces.size(), face_threads(*m),
+                            face_lds(*m), b->parity, b->stream);
+          if (st != BTX_OK) break;
+        }
+      }
+      if (st != BTX_OK) break;
+      HIP_TRY(hipEventRecord(e1, b->stream));
+      HIP_TRY(hipEventSynchronize(e1));
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) { best = ms; best_nch = nch; }
+    }
+    cache.emplace_back(key, best_nch);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (Model &m : b->models) b->h_models[m.index].tally = tsave[m.index];
+  if (st != BTX_OK) return st;
+  for (Model &m : b->models) {
+    const int nch = b->tsize == 8 ? 4 : (lookup(tune_key(m)) ? lookup(tune_key(m)) : 8);
+    set_shape(b, m, make_shape(m.g.prec, m.g.ndir, m.g.ne, nch));
+  }
+  if ((st = upload_descriptors(b)) != BTX_OK) return st;
+  for (Model &m : b->models)
+    if ((st = build_tables(m, b->d_models, b->stream)) != BTX_OK) return st;
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  write_cache(b->tune_path, cache);
+  if ((st = build_groups(b)) != BTX_OK) return st;
+  b->tuned = true;
+  return BTX_OK;
+}
+
+// one step of every model: one face launch per shape group, one zone launch
+btx_status batch_launch(btx_batch *b, int parity, hipStream_t s)
+{
+  for (const BatchGroup &gr : b->groups) {
+    btx_status st = launch_faces(gr.shape, b->tsize, b->d_models, b->d_gitems + gr.first, gr.count, gr.threads,
+                                 gr.lds, parity, s);
+    if (st != BTX_OK) return st;
+  }
+  return launch_zones(b->tsize, b->d_models, b->d_zitems, b->nz_all, parity, s);
+}
+
+// the step of each parity captured once as a graph on the library's stream
+btx_status capture_graphs(btx_batch *b)
+{
+  for (int p = 0; p < 2; ++p) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    btx_status st = batch_launch(b, p, b->cap);
+    hipError_t he = hipStreamEndCapture(b->cap, &g);
+    if (st != BTX_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (he != hipSuccess) return fail(BTX_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(he));
+    he = hipGraphInstantiate(&b->exec[p], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (he != hipSuccess) return fail(BTX_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(he));
+  }
+  return BTX_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- the ABI
+
+extern "C" {
+
+const char *btx_last_error(void) { return g_err.c_str(); }
+
+btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, btx_ctx **out)
+{
+  if (!d || !out) return fail(BTX_E_INVAL, "null argument");
+  *out = nullptr;
+  btx_status st = validate_desc(d);
+  if (st != BTX_OK) return st;
+  HIP_TRY(hipSetDevice(hip_device));
+  size_t cap = 0;
+  if ((st = device_lds_cap(hip_device, &cap)) != BTX_OK) return st;
+  btx_ctx *c = new btx_ctx();
+  c->device = hip_device;
+  c->stream = (hipStream_t)hip_stream;
+  if ((st = model_init(c->m, d, 0, cap)) != BTX_OK) { delete c; return st; }
+  c->h_model = model_dev(c->m, 0.0);
+  if ((st = upload(&c->d_model, &c->h_model, 1)) != BTX_OK) { free_ctx(c); return st; }
+  if ((st = set_face_lds(c->m.tsize, c->m.shape, face_lds(c->m))) != BTX_OK) { free_ctx(c); return st; }
+  c->ev.resize(3 * 256);
+  for (auto &e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) { free_ctx(c); return fail(BTX_E_DEVICE, "hipEventCreate failed"); }
+  *out = c;
+  return BTX_OK;
+}
+
+btx_status btx_set_background(btx_ctx *c, const btx_background *bg)
+{
+  if (!c) return fail(BTX_E_INVAL, "null argument");
+  btx_status st = check_background(c->m, bg);
+  if (st != BTX_OK) return st;
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if ((st = upload_background(c->m, bg, c->stream)) != BTX_OK) return st;
+  if ((st = build_tables(c->m, c->d_model, c->stream)) != BTX_OK) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->m.have_bg = true;
   return BTX_OK;
 }
 
@@ -1372,86 +1845,42 @@ btx_status btx_max_dt(const btx_ctx *c, double cfl, double *dt_out)
 {
   if (!c || !dt_out) return fail(BTX_E_INVAL, "null argument");
   if (!(cfl > 0.0)) return fail(BTX_E_INVAL, "cfl must be positive");
-  *dt_out = c->dt_max1 * cfl;
+  *dt_out = c->m.dt_max1 * cfl;
   return BTX_OK;
 }
 
 btx_status btx_set_state(btx_ctx *c, const void *f, int is_device_ptr)
 {
   if (!c || !f) return fail(BTX_E_INVAL, "null argument");
-  const btx::Grid &g = c->g;
-  size_t bytes = (size_t)g.nz * g.ns * g.ne * g.ndir * c->tsize;
   HIP_TRY(hipSetDevice(c->device));
-  HIP_TRY(hipMemcpyAsync(c->d_f, f, bytes, is_device_ptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                         c->stream));
-  HIP_TRY(hipMemsetAsync(c->d_tally, 0, g.faces.size() * g.ns * 8, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  c->have_state = true;
-  return BTX_OK;
+  return model_set_state(c->m, c->parity, f, is_device_ptr, c->stream);
 }
 
 btx_status btx_get_state(btx_ctx *c, void *f, int is_device_ptr)
 {
   if (!c || !f) return fail(BTX_E_INVAL, "null argument");
-  if (!c->have_state) return fail(BTX_E_STATE, "no state set");
-  const btx::Grid &g = c->g;
-  size_t bytes = (size_t)g.nz * g.ns * g.ne * g.ndir * c->tsize;
   HIP_TRY(hipSetDevice(c->device));
-  HIP_TRY(hipMemcpyAsync(f, c->d_f, bytes, is_device_ptr ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                         c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  return BTX_OK;
+  return model_get_state(c->m, c->parity, f, is_device_ptr, c->stream);
 }
 
 btx_status btx_step(btx_ctx *c, double dt, int32_t n_steps)
 {
   if (!c) return fail(BTX_E_INVAL, "null context");
-  if (!c->have_bg || !c->have_state) return fail(BTX_E_STATE, "background and state must be set");
+  if (!c->m.have_bg || !c->m.have_state) return fail(BTX_E_STATE, "background and state must be set");
   if (n_steps < 0) return fail(BTX_E_INVAL, "n_steps must be >= 0");
-  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(BTX_E_INVAL, "dt must be positive and finite");
-  if (dt > c->dt_max1 * (1.0 + 1e-12)) return fail(BTX_E_CFL, "dt exceeds the Courant limit");
+  btx_status st = check_dt(c->m, dt);
+  if (st != BTX_OK) return st;
   HIP_TRY(hipSetDevice(c->device));
-  for (int t = 0; t < n_steps; ++t) {
-    btx_status s = c->tsize == 8 ? launch_step<double>(c, dt) : launch_step<float>(c, dt);
-    if (s != BTX_OK) return s;
-  }
+  for (int t = 0; t < n_steps; ++t)
+    if ((st = ctx_step(c, dt)) != BTX_OK) return st;
   return BTX_OK;
 }
 
 btx_status btx_moments(btx_ctx *c, double *zone_moments, double *totals)
 {
   if (!c) return fail(BTX_E_INVAL, "null context");
-  if (!c->have_bg || !c->have_state) return fail(BTX_E_STATE, "background and state must be set");
-  const btx::Grid &g = c->g;
   HIP_TRY(hipSetDevice(c->device));
-  DevGrid dg = dev_grid(c);
-  if (c->tsize == 8)
-    hipLaunchKernelGGL((moments_kernel<double>), dim3(g.nz), dim3(256), 0, c->stream, dg,
-                       (const double *)c->d_f, c->d_zm, c->d_ze);
-  else
-    hipLaunchKernelGGL((moments_kernel<float>), dim3(g.nz), dim3(256), 0, c->stream, dg,
-                       (const float *)c->d_f, c->d_zm, c->d_ze);
-  HIP_TRY(hipGetLastError());
-  std::vector<double> zm((size_t)g.nz * g.ns * 5), ze((size_t)g.nz * g.ns), tally(g.faces.size() * g.ns);
-  HIP_TRY(hipMemcpyAsync(zm.data(), c->d_zm, zm.size() * 8, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipMemcpyAsync(ze.data(), c->d_ze, ze.size() * 8, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipMemcpyAsync(tally.data(), c->d_tally, tally.size() * 8, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  if (zone_moments) std::memcpy(zone_moments, zm.data(), zm.size() * 8);
-  if (totals) {
-    for (int s = 0; s < g.ns; ++s) {
-      double N = 0.0, E = 0.0, out = 0.0;
-      for (int z = 0; z < g.nz; ++z) {
-        N += zm[((size_t)z * g.ns + s) * 5];
-        E += ze[(size_t)z * g.ns + s];
-      }
-      for (int f : g.bface) out += tally[(size_t)f * g.ns + s];
-      totals[3 * s] = N;
-      totals[3 * s + 1] = out;
-      totals[3 * s + 2] = E;
-    }
-  }
-  return BTX_OK;
+  return model_moments(c->m, c->d_model, c->parity, zone_moments, totals, c->stream);
 }
 
 btx_status btx_timing(btx_ctx *c, int enable, double *ms, int64_t *launches, int reset)
@@ -1481,6 +1910,149 @@ btx_status btx_destroy(btx_ctx *c)
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   free_ctx(c);
+  return BTX_OK;
+}
+
+btx_status btx_batch_create(const btx_grid_desc *descs, int32_t n_models, int hip_device, void *hip_stream,
+                            const char *tune_cache_path, btx_batch **out)
+{
+  if (!descs || !out || n_models < 1) return fail(BTX_E_INVAL, "null argument or no models");
+  *out = nullptr;
+  for (int i = 0; i < n_models; ++i) {
+    btx_status st = validate_desc(&descs[i]);
+    if (st != BTX_OK) return fail(st, "model " + std::to_string(i) + ": " + g_err);
+    if (descs[i].precision != descs[0].precision)
+      return fail(BTX_E_INVAL, "all models of a batch share one precision");
+  }
+  HIP_TRY(hipSetDevice(hip_device));
+  size_t cap = 0;
+  btx_status st = device_lds_cap(hip_device, &cap);
+  if (st != BTX_OK) return st;
+  btx_batch *b = new btx_batch();
+  b->device = hip_device;
+  b->stream = (hipStream_t)hip_stream;
+  b->tsize = descs[0].precision == BTX_PREC_FP64 ? 8 : 4;
+  b->tune_path = tune_cache_path ? tune_cache_path : "";
+  b->models.resize(n_models);
+  std::vector<int2> zit;
+  for (int i = 0; i < n_models; ++i) {
+    if ((st = model_init(b->models[i], &descs[i], i, cap)) != BTX_OK) {
+      std::string why = g_err;
+      free_batch(b);
+      return fail(st, "model " + std::to_string(i) + ": " + why);
+    }
+    b->h_models.push_back(model_dev(b->models[i], 0.0));
+    for (int z = 0; z < b->models[i].g.nz; ++z) zit.push_back(make_int2(i, z));
+  }
+  b->nz_all = (int)zit.size();
+  if ((st = upload(&b->d_models, b->h_models.data(), b->h_models.size())) != BTX_OK ||
+      (st = upload(&b->d_zitems, zit.data(), zit.size())) != BTX_OK) {
+    free_batch(b);
+    return st;
+  }
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    free_batch(b);
+    return fail(BTX_E_DEVICE, "hipStreamCreateWithFlags failed");
+  }
+  *out = b;
+  return BTX_OK;
+}
+
+btx_status btx_batch_set_background(btx_batch *b, int32_t model, const btx_background *bg)
+{
+  if (!b || model < 0 || model >= (int)b->models.size()) return fail(BTX_E_INVAL, "bad batch or model index");
+  Model &m = b->models[model];
+  btx_status st = check_background(m, bg);
+  if (st != BTX_OK) return st;
+  HIP_TRY(hipSetDevice(b->device));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if ((st = upload_background(m, bg, b->stream)) != BTX_OK) return st;
+  if ((st = build_tables(m, b->d_models, b->stream)) != BTX_OK) return st;
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  m.have_bg = true;
+  return BTX_OK;
+}
+
+btx_status btx_batch_max_dt(const btx_batch *b, int32_t model, double cfl, double *dt_out)
+{
+  if (!b || !dt_out || model < 0 || model >= (int)b->models.size()) return fail(BTX_E_INVAL, "bad argument");
+  if (!(cfl > 0.0)) return fail(BTX_E_INVAL, "cfl must be positive");
+  *dt_out = b->models[model].dt_max1 * cfl;
+  return BTX_OK;
+}
+
+btx_status btx_batch_set_state(btx_batch *b, int32_t model, const void *f, int is_device_ptr)
+{
+  if (!b || model < 0 || model >= (int)b->models.size()) return fail(BTX_E_INVAL, "bad batch or model index");
+  HIP_TRY(hipSetDevice(b->device));
+  return model_set_state(b->models[model], b->parity, f, is_device_ptr, b->stream);
+}
+
+btx_status btx_batch_get_state(btx_batch *b, int32_t model, void *f, int is_device_ptr)
+{
+  if (!b || model < 0 || model >= (int)b->models.size()) return fail(BTX_E_INVAL, "bad batch or model index");
+  HIP_TRY(hipSetDevice(b->device));
+  return model_get_state(b->models[model], b->parity, f, is_device_ptr, b->stream);
+}
+
+btx_status btx_batch_step(btx_batch *b, const double *dt_per_model, int32_t n_steps)
+{
+  if (!b || !dt_per_model) return fail(BTX_E_INVAL, "null argument");
+  if (n_steps < 0) return fail(BTX_E_INVAL, "n_steps must be >= 0");
+  bool changed = false;
+  for (Model &m : b->models) {
+    if (!m.have_bg || !m.have_state)
+      return fail(BTX_E_STATE, "model " + std::to_string(m.index) + ": background and state must be set");
+    btx_status st = check_dt(m, dt_per_model[m.index]);
+    if (st != BTX_OK) return fail(st, "model " + std::to_string(m.index) + ": " + g_err);
+    changed |= b->h_models[m.index].dt != dt_per_model[m.index];
+  }
+  HIP_TRY(hipSetDevice(b->device));
+  btx_status st = BTX_OK;
+  if (changed) {
+    for (Model &m : b->models) b->h_models[m.index].dt = dt_per_model[m.index];
+    if ((st = upload_descriptors(b)) != BTX_OK) return st;
+  }
+  if (!b->tuned && (st = tune(b)) != BTX_OK) return st;
+  if (b->use_graph && !b->exec[0] && (st = capture_graphs(b)) != BTX_OK) return st;
+  for (int t = 0; t < n_steps; ++t) {
+    if (b->use_graph) HIP_TRY(hipGraphLaunch(b->exec[b->parity], b->stream));
+    else if ((st = batch_launch(b, b->parity, b->stream)) != BTX_OK) return st;
+    b->parity ^= 1;
+  }
+  return BTX_OK;
+}
+
+btx_status btx_batch_use_graph(btx_batch *b, int enable)
+{
+  if (!b) return fail(BTX_E_INVAL, "null batch");
+  b->use_graph = enable != 0;
+  return BTX_OK;
+}
+
+btx_status btx_batch_shape(const btx_batch *b, int32_t model, int32_t *items_per_direction,
+                           int32_t *groups_per_item)
+{
+  if (!b || model < 0 || model >= (int)b->models.size()) return fail(BTX_E_INVAL, "bad batch or model index");
+  if (items_per_direction) *items_per_direction = b->models[model].shape.nch;
+  if (groups_per_item) *groups_per_item = b->models[model].shape.ce;
+  return BTX_OK;
+}
+
+btx_status btx_batch_moments(btx_batch *b, int32_t model, double *zone_moments, double *totals)
+{
+  if (!b || model < 0 || model >= (int)b->models.size()) return fail(BTX_E_INVAL, "bad batch or model index");
+  HIP_TRY(hipSetDevice(b->device));
+  return model_moments(b->models[model], b->d_models, b->parity, zone_moments, totals, b->stream);
+}
+
+btx_status btx_batch_destroy(btx_batch *b)
+{
+  if (!b) return BTX_OK;
+  (void)hipSetDevice(b->device);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  else (void)hipDeviceSynchronize();
+  free_batch(b);
   return BTX_OK;
 }
 

@@ -1,0 +1,158 @@
+"""Batches of independent spherically symmetric models (btx_batch_*).
+
+Each model of a batch is checked against the FP64 reference (FP64 batches to
+1e-12; mixed batches to 1e-5 in the per-zone number and energy moments) and
+against the same model stepped alone with btx_step.  Graph replay is checked
+against direct launches of the same steps, with host work and
+synchronisations between the replays.  The full 64-model batch of uneven
+sizes (100-600 radial zones, 12-24 groups, 16-48 directions) runs with the
+autotuner and its cache file.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2003_02845_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _btx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2003_02845_amd import btx
+    return btx
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _models(n, scale, precision, seed):
+    rng = np.random.default_rng(seed)
+    ws = W.batch_models(n_models=n, size_scale=scale)
+    for w in ws:
+        w.precision = precision
+        w.f0 = w.f0 * (1.0 + 0.3 * rng.random(w.f0.shape)) + 1e-3 * rng.random(w.f0.shape)
+    return ws
+
+
+def _batch(btx, ws, precision, **kw):
+    import torch
+    b = btx.Batch(ws, precision=precision, stream=torch.cuda.current_stream().cuda_stream, **kw)
+    for m, w in enumerate(ws):
+        b.set_background(m)
+        b.set_state(m, w.f0)
+    return b
+
+
+def _moments_close(zg, zr, tol):
+    for k in (0, 1):
+        mask = np.abs(zr[..., 1]) > 1e-8 * np.abs(zr[..., 1]).max()
+        rel = np.max(np.abs(zg[..., k] - zr[..., k])[mask] / np.abs(zr[..., k][mask]))
+        assert rel <= tol, (k, rel)
+
+
+def test_batch_fp64_matches_reference(oracle_mod):
+    btx = _btx()
+    ws = _models(5, 0.03, W.PREC_FP64, 21)
+    _say(f"[gpu] fp64 batch of {len(ws)} models: " + ", ".join(f"{w.n_zones}x{w.block}" for w in ws))
+    b = _batch(btx, ws, W.PREC_FP64)
+    dts = [b.max_dt(m, 0.4) for m in range(len(ws))]
+    b.step(dts, 3)
+    for m, w in enumerate(ws):
+        o = oracle_mod.Oracle(w)
+        assert abs(o.max_dt(0.4) - dts[m]) <= 1e-13 * dts[m]
+        o.step(dts[m], 3)
+        ref, got = o.state(), b.get_state(m)
+        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        _say(f"[gpu]   model {m}: rel err {err:.3e}")
+        assert err <= 1e-12
+        zg, tg = b.moments(m)
+        zr, tr = o.moments()
+        assert np.allclose(tg, tr, rtol=1e-12, atol=1e-12 * np.abs(tr).max())
+    b.close()
+
+
+def test_batch_mixed_matches_single_contexts(oracle_mod):
+    btx = _btx()
+    import torch
+    ws = _models(6, 0.05, W.PREC_MIXED, 22)
+    _say(f"[gpu] mixed batch of {len(ws)} models vs single contexts")
+    b = _batch(btx, ws, W.PREC_MIXED)
+    dts = [b.max_dt(m, 0.4) for m in range(len(ws))]
+    b.step(dts, 5)
+    for m, w in enumerate(ws):
+        c = btx.Context(w, precision=W.PREC_MIXED, stream=torch.cuda.current_stream().cuda_stream)
+        c.set_background()
+        c.set_state(w.f0)
+        c.step(dts[m], 5)
+        single, batched = c.get_state(), b.get_state(m)
+        nch, ce = b.shape(m)
+        err = float(np.max(np.abs(batched - single)) / np.max(np.abs(single)))
+        _say(f"[gpu]   model {m}: shape {nch}x{ce}, batch vs single {err:.3e}")
+        if nch == 8:                       # the single context's own shape: same arithmetic
+            assert err == 0.0
+        else:
+            assert err <= 1e-5
+        o = oracle_mod.Oracle(w)
+        o.step(dts[m], 5)
+        zr, _ = o.moments()
+        zg, _ = b.moments(m)
+        _moments_close(zg, zr, 1e-5)
+        c.close()
+    b.close()
+
+
+def test_batch_graph_replays_match_direct_launches():
+    btx = _btx()
+    ws = _models(4, 0.04, W.PREC_MIXED, 23)
+    _say("[gpu] batch graph replays vs direct launches")
+    a = _batch(btx, ws, W.PREC_MIXED)
+    d = _batch(btx, ws, W.PREC_MIXED)
+    d.use_graph(False)
+    dts = [a.max_dt(m, 0.4) for m in range(len(ws))]
+    for rep in range(4):                    # one step per call, host reads in between
+        a.step(dts, 1)
+        d.step(dts, 1)
+        for m in range(len(ws)):
+            assert a.shape(m) == d.shape(m)
+            assert np.array_equal(a.get_state(m), d.get_state(m)), (rep, m)
+    a.step(dts, 3)
+    d.step(dts, 3)
+    for m in range(len(ws)):
+        assert np.array_equal(a.get_state(m), d.get_state(m))
+        _, ta = a.moments(m)
+        _, td = d.moments(m)
+        assert np.array_equal(ta, td)
+    a.close()
+    d.close()
+
+
+def test_full_batch_tuned_with_cache(oracle_mod, tmp_path):
+    btx = _btx()
+    ws = _models(64, 1.0, W.PREC_MIXED, 24)
+    total = sum(w.n_values for w in ws)
+    _say(f"[gpu] 64-model batch, {total:.3g} values")
+    cache = tmp_path / "tune.json"
+    b = _batch(btx, ws, W.PREC_MIXED, tune_cache=cache)
+    dts = [b.max_dt(m, 0.4) for m in range(len(ws))]
+    b.step(dts, 10)
+    assert cache.exists()
+    shapes = [b.shape(m) for m in range(len(ws))]
+    _say(f"[gpu]   shapes {sorted(set(shapes))}")
+    for m in (0, 17, 40, 63):
+        o = oracle_mod.Oracle(ws[m])
+        o.step(dts[m], 10)
+        zr, tr = o.moments()
+        zg, tg = b.moments(m)
+        _moments_close(zg, zr, 1e-5)
+        assert abs(tg[0, 0] + tg[0, 1] - tr[0, 0] - tr[0, 1]) <= 1e-5 * tr[0, 0]
+    b.close()
+    again = _batch(btx, ws, W.PREC_MIXED, tune_cache=cache)
+    again.step(dts, 1)
+    assert [again.shape(m) for m in range(len(ws))] == shapes
+    again.close()

@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n-r", type=int, default=600)
     ap.add_argument("--n-theta", type=int, default=256)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -90,6 +92,51 @@ def cpu_baseline(steps_note):
             "kind": "oracle",
             "sample": f"one FP64 step of the same profile and momentum grid on 600 r x 96 theta "
                       f"zones ({w.n_values:.3g} values, {el:.1f} s)"}
+
+
+def run_batch(torch, btx, W, steps):
+    """the 64-model batch of spherically symmetric models (mixed precision): one batched,
+    graph-replayed step against 64 sequential single-model steps, same models and dt"""
+    ws = W.batch_models()
+    stream = torch.cuda.current_stream()
+    b = btx.Batch(ws, precision=W.PREC_MIXED, stream=stream.cuda_stream)
+    for m, w in enumerate(ws):
+        b.set_background(m)
+        b.set_state(m, w.f0)
+    dts = [b.max_dt(m, 0.4) for m in range(len(ws))]
+    b.step(dts, 2)                                  # tuning, graph capture, warm-up
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    b.step(dts, steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_b = t0.elapsed_time(t1) / steps
+    shapes = sorted({f"{a}x{c}" for a, c in (b.shape(m) for m in range(len(ws)))})
+    b.close()
+    ctxs = []
+    for m, w in enumerate(ws):
+        c = btx.Context(w, precision=W.PREC_MIXED, stream=stream.cuda_stream)
+        c.set_background()
+        c.set_state(w.f0)
+        c.step(dts[m], 1)
+        ctxs.append(c)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(steps):
+        for m, c in enumerate(ctxs):
+            c.step(dts[m], 1)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_s = t0.elapsed_time(t1) / steps
+    for c in ctxs:
+        c.close()
+    nv = sum(w.n_values for w in ws)
+    return {"workload": "64 spherically symmetric models, 100-600 radial zones, 12-24 groups, "
+                        "16-48 directions, mixed precision",
+            "values": nv, "steps": steps, "ms_per_step": ms_b, "value": nv / (ms_b * 1e-3),
+            "sequential_ms_per_step": ms_s, "sequential_value": nv / (ms_s * 1e-3),
+            "speedup_vs_sequential": ms_s / ms_b, "face_shapes": shapes}
 
 
 def face_traffic():
@@ -188,6 +235,10 @@ def main():
         if k64 == a.steps:
                 out["number_drift_mixed"] = float(np.max(np.abs(tot[:, 0] + tot[:, 1] - res64["tot"][:, 0]
                                                             - res64["tot"][:, 1]) / res64["tot"][:, 0]))
+    if not a.no_batch:
+        out["batch"] = run_batch(torch, btx, W, a.batch_steps)
+        print(f"[bench] batch: {out['batch']['ms_per_step']:.3f} ms/step batched, "
+              f"{out['batch']['sequential_ms_per_step']:.3f} ms/step sequential", file=sys.stderr, flush=True)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.steps)
     print(json.dumps(out), flush=True)

@@ -97,6 +97,26 @@ struct ModelDev {
 
 __device__ inline double dsq(double x) { return x * x; }
 
+// Pointers read from a descriptor in memory are generic; these all point to
+// device global memory, and saying so lets the compiler use global (not flat)
+// loads and stores, which do not hold up the LDS wait counter.
+template <typename P>
+__device__ __forceinline__ P *as_global(P *p)
+{
+  return (P *)((__attribute__((address_space(1))) P *)(uintptr_t)p);
+}
+
+// a descriptor's grid with its pointers marked global
+__device__ __forceinline__ DevGrid global_grid(const DevGrid &src)
+{
+  DevGrid g = src;
+  g.mu = as_global(g.mu); g.Phi = as_global(g.Phi); g.dOm = as_global(g.dOm);
+  g.nvec = as_global(g.nvec); g.G = as_global(g.G); g.eps = as_global(g.eps);
+  g.vol = as_global(g.vol); g.vr = as_global(g.vr); g.vth = as_global(g.vth);
+  g.alp = as_global(g.alp); g.psi = as_global(g.psi);
+  return g;
+}
+
 __device__ Frame side_frame(const DevGrid &g, const SideDesc &s)
 {
   Frame f;
@@ -443,11 +463,11 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
   __shared__ int flg[kTables];
   const int2 it = items[blockIdx.x];
   const ModelDev &M = models[it.x];
-  const DevGrid &g = M.g;
-  char *__restrict__ tabs_g = M.tabs;
-  FaceAux *__restrict__ aux = M.aux;
+  const DevGrid g = global_grid(M.g);
+  char *__restrict__ tabs_g = as_global(M.tabs);
+  FaceAux *__restrict__ aux = as_global(M.aux);
   const int fid = it.y;
-  const FaceDesc &F = M.faces[fid];
+  const FaceDesc &F = as_global(M.faces)[fid];
   const int nd = g.ndir, tid = threadIdx.x, nthr = blockDim.x;
   const size_t tstride = tab_stride(nd, sizeof(T));
   char *p = lds;
@@ -644,18 +664,18 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   extern __shared__ __align__(16) char lds[];
   const int2 it = items[blockIdx.x];
   const ModelDev &M = models[it.x];
-  const DevGrid &g = M.g;
-  const char *__restrict__ tabs_g = M.tabs;
-  const FaceAux *__restrict__ aux = M.aux;
-  const T *__restrict__ f = (const T *)M.f[parity];
-  const T *__restrict__ ka = (const T *)M.ka;
-  const T *__restrict__ ks = (const T *)M.ks;
-  const T *__restrict__ feq = (const T *)M.feq;
-  T *__restrict__ dN = (T *)M.dN;
-  double *__restrict__ tally = M.tally;
+  const DevGrid g = global_grid(M.g);
+  const char *__restrict__ tabs_g = as_global((const char *)M.tabs);
+  const FaceAux *__restrict__ aux = as_global((const FaceAux *)M.aux);
+  const T *__restrict__ f = as_global((const T *)M.f[parity]);
+  const T *__restrict__ ka = as_global((const T *)M.ka);
+  const T *__restrict__ ks = as_global((const T *)M.ks);
+  const T *__restrict__ feq = as_global((const T *)M.feq);
+  T *__restrict__ dN = as_global((T *)M.dN);
+  double *__restrict__ tally = as_global(M.tally);
   const double dt = M.dt;
   const int fid = it.y;
-  const FaceDesc &F = M.faces[fid];
+  const FaceDesc &F = as_global(M.faces)[fid];
   const int nd = g.ndir, ne = g.ne, tid = threadIdx.x, nthr = blockDim.x;
   T *outL = dN + (size_t)fid * 2 * g.blk, *outR = outL + g.blk;
   if (!F.active) {
@@ -937,14 +957,14 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
 {
   const int2 it = items[blockIdx.x];
   const ModelDev &M = models[it.x];
-  const DevGrid &g = M.g;
-  const btx::ZoneFaces *__restrict__ zf = M.zf;
-  const T *__restrict__ f = (const T *)M.f[parity];
-  T *__restrict__ fout = (T *)M.f[parity ^ 1];
-  const T *__restrict__ dN = (const T *)M.dN;
-  const T *__restrict__ ka = (const T *)M.ka;
-  const T *__restrict__ ks = (const T *)M.ks;
-  const T *__restrict__ feq = (const T *)M.feq;
+  const DevGrid g = global_grid(M.g);
+  const btx::ZoneFaces *__restrict__ zf = as_global(M.zf);
+  const T *__restrict__ f = as_global((const T *)M.f[parity]);
+  T *__restrict__ fout = as_global((T *)M.f[parity ^ 1]);
+  const T *__restrict__ dN = as_global((const T *)M.dN);
+  const T *__restrict__ ka = as_global((const T *)M.ka);
+  const T *__restrict__ ks = as_global((const T *)M.ks);
+  const T *__restrict__ feq = as_global((const T *)M.feq);
   const double dt = M.dt;
   const int z = it.y;
   const int nd = g.ndir, ne = g.ne, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1000,8 +1020,8 @@ moments_kernel(const ModelDev *__restrict__ models, int m, int parity, double *_
                double *__restrict__ ze)
 {
   const ModelDev &M = models[m];
-  const DevGrid &g = M.g;
-  const T *__restrict__ f = (const T *)M.f[parity];
+  const DevGrid g = global_grid(M.g);
+  const T *__restrict__ f = as_global((const T *)M.f[parity]);
   const int z = blockIdx.x;
   __shared__ double red[6][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;

@@ -273,13 +273,15 @@ __host__ __device__ inline size_t scratch_bytes(int nd, size_t szT)
 }
 
 // LDS of one face workgroup: 8 tables, 4 data buffers (Lm, L, R, Rp), per-row
-// constants (G, 1/G, source, blend weight as T; two collision coefficients as
-// FP64; a precision flag) and the wave partials of the angle sums and tally
-__host__ __device__ inline size_t face_lds_bytes(int nd, int nch, int ce, size_t szT)
+// constants (G, 1/G as T; per species: source and blend weight as T, two
+// collision coefficients as FP64, a precision flag), the wave partials and
+// totals of the angle sums, and the tally partials
+__host__ __device__ inline size_t face_lds_bytes(int nd, int ns, int nch, int ce, size_t szT)
 {
-  const size_t nrow = col_rows(nch, ce);
-  return kTables * tab_stride(nd, szT) + 4 * buf_bytes(nd, nch, ce, szT) + 4 * align16(nrow * szT) +
-         2 * align16(nrow * 8) + align16(nrow * 4) + align16(16 * nrow * 8) + align16(16 * 8);
+  const size_t nrow = col_rows(nch, ce), nsr = (size_t)ns * nrow;
+  return kTables * tab_stride(nd, szT) + 4 * buf_bytes(nd, nch, ce, szT) + 2 * align16(nrow * szT) +
+         2 * align16(nsr * szT) + 2 * align16(nsr * 8) + align16(nsr * 4) + align16(16 * nrow * 8) +
+         align16(nrow * 8) + align16(16 * 8);
 }
 
 // ascending node bracket with edge clamping (all weight to the edge node)
@@ -426,13 +428,14 @@ __device__ __forceinline__ void gather(const Tab<T> &tb, int nd, const T *__rest
   }
 }
 
+// MC limiter minmod(2 dm, 2 dp, (dm + dp)/2): the argument closest to zero
+// when all three have the same strict sign, else zero (branch-free form)
 template <typename T>
 __device__ inline T mc_limiter(T dm, T dp)
 {
-  T a = (T)2 * dm, b = (T)2 * dp, m = (T)0.5 * (dm + dp);
-  if (a > (T)0 && b > (T)0 && m > (T)0) return fmin(a, fmin(b, m));
-  if (a < (T)0 && b < (T)0 && m < (T)0) return fmax(a, fmax(b, m));
-  return (T)0;
+  const T a = (T)2 * dm, b = (T)2 * dp, m = (T)0.5 * (dm + dp);
+  const T lo = fmin(a, fmin(b, m)), hi = fmax(a, fmax(b, m));
+  return lo > (T)0 ? lo : (hi < (T)0 ? hi : (T)0);
 }
 
 __device__ inline double wave_sum(double v)
@@ -691,14 +694,16 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   char *bufs = p;               p += 4 * bb;
   T *XLm = (T *)(bufs) + gb, *XL = (T *)(bufs + bb) + gb, *XR = (T *)(bufs + 2 * bb) + gb,
     *XRp = (T *)(bufs + 3 * bb) + gb;
+  const int nsr = g.ns * nrow;
   T *rG = (T *)p + gb;          p += align16(nrow * sizeof(T));
   T *riG = (T *)p + gb;         p += align16(nrow * sizeof(T));
-  T *rsrc = (T *)p + gb;        p += align16(nrow * sizeof(T));
-  T *rw = (T *)p + gb;          p += align16(nrow * sizeof(T));
-  double *rc0 = (double *)p + gb;  p += align16(nrow * 8);
-  double *rc1 = (double *)p + gb;  p += align16(nrow * 8);
-  int *rthick = (int *)p + gb;  p += align16(nrow * 4);
+  T *rsrc0 = (T *)p + gb;       p += align16(nsr * sizeof(T));
+  T *rw0 = (T *)p + gb;         p += align16(nsr * sizeof(T));
+  double *rc00 = (double *)p + gb;  p += align16(nsr * 8);
+  double *rc10 = (double *)p + gb;  p += align16(nsr * 8);
+  int *rthick0 = (int *)p + gb; p += align16(nsr * 4);
   double *spart = (double *)p;  p += align16(16 * nrow * 8);
+  double *savr = (double *)p + gb;  p += align16(nrow * 8);
   double *tpart = (double *)p;
 
 #define TB(t) tab_at<T>(tabs + (t) * tstride, nd)
@@ -722,7 +727,6 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
       const bool in = r >= 0 && r < ne;
       rG[r] = in ? (T)g.G[r] : (T)0;
       riG[r] = in ? (T)(1.0 / g.G[r]) : (T)0;
-      if (!in) { rsrc[r] = (T)0; rw[r] = (T)0; rc0[r] = 0.0; rc1[r] = 0.0; rthick[r] = 0; }
     }
   }
   const FaceAux &A = aux[fid];
@@ -734,6 +738,25 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   const double vn = A.v[4][ax];
   const double Uadv = ap4 * gs * vn;
   const double tau = 0.5 * A.alpha[4] * dt / gs;
+  // ---- per (species, group) interface opacities and collision coefficients
+  for (int q = tid; q < nsr; q += nthr) {
+    const int sp = q / nrow, i = q - sp * nrow - gb;
+    double a_ = 0.0, b_ = 0.0, e_ = 0.0;
+    const bool in = i >= 0 && i < ne;
+    if (in && !F.zero_opacity) {
+      size_t l = ((size_t)F.L.z * g.ns + sp) * ne + i, r = ((size_t)F.R.z * g.ns + sp) * ne + i;
+      a_ = 0.5 * ((double)ka[l] + (double)ka[r]);
+      b_ = 0.5 * ((double)ks[l] + (double)ks[r]);
+      e_ = 0.5 * ((double)feq[l] + (double)feq[r]);
+    }
+    const double den = 1.0 + tau * (a_ + b_);
+    const int o = sp * nrow + i;
+    rc00[o] = in ? 1.0 / den : 0.0;
+    rc10[o] = in ? tau * b_ / (1.0 + tau * a_) / den : 0.0;
+    rsrc0[o] = (T)(tau * a_ * e_);
+    rw0[o] = in ? (T)exp(-(a_ + b_) * F.h) : (T)0;
+    rthick0[o] = sizeof(T) == 8 || tau * (a_ + b_) > g.fp64_thr;
+  }
 
   // ---- load mapping: direction ld, rows li, li + NCH, ...
   const bool ldown = tid < NCH * nd;
@@ -818,22 +841,9 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
       store_side<T, NCH, CE>(v2, gl, aS_[2], colS[2], li, ne, cs, XR);
       if (slopeR) store_side<T, NCH, CE>(v3, gl, aS_[3], colS[3], li, ne, cs, XRp);
     }
-    // ---- per-group interface opacities and collision coefficients
-    for (int i = tid; i < ne; i += nthr) {
-      double a_ = 0.0, b_ = 0.0, e_ = 0.0;
-      if (!F.zero_opacity) {
-        size_t l = ((size_t)F.L.z * g.ns + s) * ne + i, r = ((size_t)F.R.z * g.ns + s) * ne + i;
-        a_ = 0.5 * ((double)ka[l] + (double)ka[r]);
-        b_ = 0.5 * ((double)ks[l] + (double)ks[r]);
-        e_ = 0.5 * ((double)feq[l] + (double)feq[r]);
-      }
-      const double den = 1.0 + tau * (a_ + b_);
-      rc0[i] = 1.0 / den;
-      rc1[i] = tau * b_ / (1.0 + tau * a_) / den;
-      rsrc[i] = (T)(tau * a_ * e_);
-      rw[i] = (T)exp(-(a_ + b_) * F.h);
-      rthick[i] = sizeof(T) == 8 || tau * (a_ + b_) > g.fp64_thr;
-    }
+    const T *rsrc = rsrc0 + s * nrow, *rw = rw0 + s * nrow;
+    const double *rc0 = rc00 + s * nrow, *rc1 = rc10 + s * nrow;
+    const int *rthick = rthick0 + s * nrow;
     __syncthreads();
     // ---- five remap stages, each the sum of two gathers a = Ta . Xa, b = Tb . Xb
     //   0 slopes of L      T0 . Lm,  T1 . R
@@ -899,15 +909,19 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
           if (lane < NCH) spart[wave * nrow + r0 + k + gb] = v;
         }
         __syncthreads();                               // partial sums visible, buffers free
+        if (tid < nrow) {                              // totals over the waves, fixed order
+          double t = 0.0;
+          for (int w = 0; w < nw; ++w) t += spart[w * nrow + tid];
+          savr[tid - gb] = t * (1.0 / (4.0 * kPi));
+        }
+        __syncthreads();
         // implicit interface collision, blend weights and content fluxes
         if (own) {
 #pragma unroll
           for (int k = 0; k < CE; ++k) {
             const int r = r0 + k;
             if (r < 0 || r >= ne) continue;
-            double sav = 0.0;
-            for (int w = 0; w < nw; ++w) sav += spart[w * nrow + r + gb];
-            sav *= 1.0 / (4.0 * kPi);
+            const double sav = savr[r];
             T flw;
             if (rthick[r]) flw = (T)((double)Sv[k] * rc0[r] + rc1[r] * sav);
             else flw = (T)((float)Sv[k] * (float)rc0[r] + (float)rc1[r] * (float)sav);
@@ -1285,9 +1299,9 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
   m.dt_max1 = btx::max_dt(g, 1.0);
   m.shape = default_shape(g);
   if (m.shape.ce == 0) return fail(BTX_E_UNSUPPORTED, "no face work-item shape for this grid");
-  if (face_lds_bytes(g.ndir, m.shape.nch, m.shape.ce, m.tsize) > lds_cap)
+  if (face_lds_bytes(g.ndir, g.ns, m.shape.nch, m.shape.ce, m.tsize) > lds_cap)
     return fail(BTX_E_UNSUPPORTED, "face workgroup needs " +
-                                       std::to_string(face_lds_bytes(g.ndir, m.shape.nch, m.shape.ce, m.tsize)) +
+                                       std::to_string(face_lds_bytes(g.ndir, g.ns, m.shape.nch, m.shape.ce, m.tsize)) +
                                        " B of LDS");
   m.tab_lds = kTables * tab_stride(g.ndir, m.tsize) + align16(5 * sizeof(Frame)) +
               align16(scratch_bytes(g.ndir, m.tsize));
@@ -1442,7 +1456,7 @@ btx_status launch_zones(size_t tsize, const ModelDev *d_models, const int2 *item
 
 int face_threads(const Model &m) { return ((m.shape.nch * m.g.ndir + 63) / 64) * 64; }
 
-size_t face_lds(const Model &m) { return face_lds_bytes(m.g.ndir, m.shape.nch, m.shape.ce, m.tsize); }
+size_t face_lds(const Model &m) { return face_lds_bytes(m.g.ndir, m.g.ns, m.shape.nch, m.shape.ce, m.tsize); }
 
 btx_status set_face_lds(size_t tsize, const FaceShape &f, size_t lds)
 {
@@ -1747,7 +1761,7 @@ btx_status tune(btx_batch *b)
     int best_nch = 8;
     for (int nch : { 8, 4 }) {
       const FaceShape f = make_shape(cls[0]->g.prec, cls[0]->g.ndir, cls[0]->g.ne, nch);
-      if (f.ce == 0 || face_lds_bytes(cls[0]->g.ndir, f.nch, f.ce, b->tsize) > 160 * 1024) continue;
+      if (f.ce == 0 || face_lds_bytes(cls[0]->g.ndir, cls[0]->g.ns, f.nch, f.ce, b->tsize) > 160 * 1024) continue;
       for (Model *m : cls) set_shape(b, *m, f);
       if ((st = upload_descriptors(b)) != BTX_OK) break;
       for (Model *m : cls)

@@ -52,7 +52,15 @@ CASES = {
     # groups between neighbouring frames
     "large_shift": lambda: _steep(W.planar(n_z=6, n_eps=12, n_mu=6, kappa_a=0.5, kappa_s=1.0,
                                            f_eq=0.3, inner_bc=W.BC_EQUIL, outer_bc=W.BC_OUTFLOW)),
+    # an outgoing packet in the Lobatto mu = 1 bins of a static vacuum column
+    "beam": lambda: _beam_case(),
 }
+
+
+def _beam_case():
+    sys.path.insert(0, __import__("os").path.dirname(__file__))
+    from test_oracle_pins import _beam
+    return _beam()[0]
 
 
 def _steep(w):

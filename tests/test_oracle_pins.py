@@ -412,3 +412,45 @@ def test_radiating_sphere(oracle_mod):
         hj, kj = np.mean(fe * mu) / np.mean(fe), np.mean(fe * mu * mu) / np.mean(fe)
         assert abs(H[a] / J[a] - hj) < 0.03, (x, H[a] / J[a], hj)
         assert abs(K[a] / J[a] - kj) < 0.03, (x, K[a] / J[a], kj)
+
+
+def _beam(n_r=60, n_mu=6, r_in=1.0, r_out=3.0):
+    """a static flat vacuum column with an outgoing packet in the Lobatto mu = 1 bins"""
+    w = W.radiating_sphere(n_r=n_r, n_eps=1, n_mu=n_mu, n_phi=4, r_max=r_out, kappa=0.0,
+                           mu_rule="lobatto")
+    w.r_edges = np.linspace(r_in, r_out, n_r + 1)
+    w.kappa_a = np.zeros((n_r, 1, 1))
+    w.f_eq = np.zeros((n_r, 1, 1))
+    rc = 0.5 * (w.r_edges[1:] + w.r_edges[:-1])
+    f0 = np.zeros((n_r, 1, 1, w.n_dir))
+    packet = (rc > 1.2) & (rc < 1.4)
+    f0[packet, 0, 0, (n_mu - 1) * 4:] = 1.0           # mu = +1 node, all Phi
+    w.f0 = f0
+    return w, rc
+
+
+def test_free_streaming_beam(oracle_mod):
+    """P-16: an outgoing packet in the Lobatto mu = 1 bins of a static, flat
+    vacuum column.  Lateral faces carry nothing in that direction (its normal
+    component is zero) and radial faces remap between identical frames, so all
+    content stays in the mu = 1 bins, the number is conserved exactly while the
+    packet is inside, and the number-weighted mean radius advances at the
+    speed of light (the donor cell moves the first moment exactly at unit
+    speed up to the r^2 weighting of the shell volumes)."""
+    w, rc = _beam()
+    o = oracle_mod.Oracle(w)
+    dt = o.max_dt(0.4)
+    zm0, t0 = o.moments()
+    N0 = zm0[:, 0, 0]
+    rbar0 = np.sum(N0 * rc) / np.sum(N0)
+    steps = int(round(0.8 / dt))
+    o.step(dt, steps)
+    f = o.state()[:, 0, 0, :]
+    assert np.max(np.abs(f[:, :(w.n_mu - 1) * 4])) == 0.0          # other directions untouched
+    zm, t1 = o.moments()
+    N = zm[:, 0, 0]
+    assert t1[0, 1] == 0.0                                          # nothing reached r_max yet
+    assert abs(t1[0, 0] - t0[0, 0]) < 1e-13 * t0[0, 0]
+    rbar = np.sum(N * rc) / np.sum(N)
+    dr = rc[1] - rc[0]
+    assert abs((rbar - rbar0) - steps * dt) < 0.5 * dr

@@ -102,6 +102,14 @@ btx_status btx_create(const btx_grid_desc *desc, int hip_device, void *hip_strea
 /* Fluid velocity, metric (conformally flat, zero shift, Sec. 2.4) and
  * opacities (Eq. sourceterms).  Static until the next call. */
 btx_status btx_set_background(btx_ctx *ctx, const btx_background *bg);
+/* Evolving background (Sec. 3.2, the remap applied as time advances; the
+ * closing T_{n->n+1} of a step, Sec. 3.3): the current state of every zone is
+ * remapped from its comoving frame under the current background to its
+ * comoving frame under bg (same place, no rotation; the covariant spatial
+ * momentum is kept and the energy follows from the new metric), then bg
+ * replaces the background.  Without a state or background it acts as
+ * btx_set_background.  Synchronises the stream. */
+btx_status btx_update_background(btx_ctx *ctx, const btx_background *bg);
 /* Largest stable global step (Sec. 3.3): cfl times the smallest Courant
  * length (zone volume over its largest face on an axis) of the grid. */
 btx_status btx_max_dt(const btx_ctx *ctx, double cfl, double *dt_out);
@@ -140,6 +148,7 @@ typedef struct btx_batch btx_batch;
 btx_status btx_batch_create(const btx_grid_desc *descs, int32_t n_models, int hip_device, void *hip_stream,
                             const char *tune_cache_path, btx_batch **out);
 btx_status btx_batch_set_background(btx_batch *b, int32_t model, const btx_background *bg);
+btx_status btx_batch_update_background(btx_batch *b, int32_t model, const btx_background *bg);
 btx_status btx_batch_max_dt(const btx_batch *b, int32_t model, double cfl, double *dt_out);
 btx_status btx_batch_set_state(btx_batch *b, int32_t model, const void *f, int is_device_ptr);
 btx_status btx_batch_get_state(btx_batch *b, int32_t model, void *f, int is_device_ptr);

@@ -131,7 +131,11 @@ static double gamma_of(const double v[3])
  * destination metric; the root keeps the sign of the source component
  * (Reading: sign(0) = +); without a real root the component is set to zero and
  * the others are scaled to keep the four-velocity null.  The kick is skipped
- * when the two metrics are identical (it is then the identity). */
+ * when the two metrics are identical (it is then the identity).
+ * axis < 0 is the remap forward in time at a fixed place (Sec. 3.2, the same
+ * procedure applied as time advances).  Reading: with no motion across the
+ * grid the covariant spatial momentum is kept and the covariant energy is set
+ * by the null condition of the new metric. */
 static void chain_frames(const frame_t *S, const frame_t *D, int axis, int rotate,
                          const double uS[4], double uD[4])
 {
@@ -140,7 +144,11 @@ static void chain_frames(const frame_t *S, const frame_t *D, int axis, int rotat
   double low0 = -S->alpha * uh[0];              /* u_0 = -alpha^2 u^0, u^0 = uh^0/alpha */
   double low[3];
   for (int i = 0; i < 3; ++i) low[i] = S->psi * S->psi * uh[i + 1]; /* psi^4 * uh^i/psi^2 */
-  if (S->alpha != D->alpha || S->psi != D->psi) {
+  if (axis < 0 && (S->alpha != D->alpha || S->psi != D->psi)) {
+    double p2 = 0.0;
+    for (int i = 0; i < 3; ++i) p2 += low[i] * low[i];
+    low0 = -D->alpha * sqrt(p2) / (D->psi * D->psi);
+  } else if (S->alpha != D->alpha || S->psi != D->psi) {
     double perp2 = 0.0;
     for (int i = 0; i < 3; ++i) if (i != axis) perp2 += low[i] * low[i];
     double p4 = sq(D->psi * D->psi);
@@ -1083,4 +1091,32 @@ int orc_remap_block(const orc_ctx *c, const double *S, const double *D, int axis
   unpack_frame(D, &b);
   remap(c, &a, &b, axis, rotate, density, general, X, Y);
   return 0;
+}
+
+/* Time-dependent background (Sec. 3.2, the remap applied as particles travel
+ * forward in time; the closing T_{n->n+1} of a step, Sec. 3.3): every zone's
+ * distribution is remapped from its comoving frame under the current
+ * background to its comoving frame under the new one (same place and basis,
+ * no rotation, time kick of chain_frames), then the new background is
+ * adopted.  The outflow tally is kept. */
+int orc_update_background(orc_ctx *c, const double *v_r, const double *v_theta,
+                          const double *alpha, const double *psi, const double *ka,
+                          const double *ks, const double *feq)
+{
+  if (!c) return 1;
+  if (!c->have_bg || !c->have_state) return 5;
+  int n = c->eblk;
+  double *tmp = (double *)malloc(sizeof(double) * n);
+  for (int z = 0; z < c->nz; ++z) {
+    frame_t S = zone_frame(c, z, zone_th(c, z), 0.0), D = S;
+    D.v[0] = v_r[z]; D.v[1] = v_theta[z]; D.v[2] = 0.0;
+    D.alpha = alpha[z]; D.psi = psi[z];
+    for (int s = 0; s < c->ns; ++s) {
+      double *blk = c->f + (size_t)z * c->blk + (size_t)s * n;
+      remap(c, &S, &D, -1, 0, 1, 0, blk, tmp);
+      memcpy(blk, tmp, sizeof(double) * n);
+    }
+  }
+  free(tmp);
+  return orc_set_background(c, v_r, v_theta, alpha, psi, ka, ks, feq);
 }

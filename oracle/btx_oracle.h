@@ -42,6 +42,11 @@ int orc_set_background(orc_ctx *c, const double *v_r, const double *v_theta,
                        const double *alpha, const double *psi,
                        const double *kappa_a, const double *kappa_s,
                        const double *f_eq);
+/* new background: remaps the state from the old to the new comoving frames
+ * (forward in time, no rotation), then adopts it; 5 if no background/state */
+int orc_update_background(orc_ctx *c, const double *v_r, const double *v_theta,
+                          const double *alpha, const double *psi, const double *ka,
+                          const double *ks, const double *feq);
 int orc_set_state(orc_ctx *c, const double *f);
 int orc_get_state(const orc_ctx *c, double *f);
 double orc_max_dt(const orc_ctx *c, double cfl);

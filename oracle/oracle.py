@@ -53,6 +53,7 @@ def lib():
         L.orc_create.argtypes = [C.POINTER(_Desc)]
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_set_background.argtypes = [C.c_void_p] + [_dp] * 7
+        L.orc_update_background.argtypes = [C.c_void_p] + [_dp] * 7
         L.orc_set_state.argtypes = [C.c_void_p, _dp]
         L.orc_get_state.argtypes = [C.c_void_p, _dp]
         L.orc_max_dt.restype = C.c_double
@@ -145,6 +146,13 @@ class Oracle:
         arrs = [_c(w.v_r), _c(w.v_theta), _c(w.alpha), _c(w.psi), _c(w.kappa_a),
                 _c(w.kappa_s), _c(w.f_eq)]
         rc = lib().orc_set_background(self.ctx, *[_p(a) for a in arrs])
+        assert rc == 0
+
+    def update_background(self, w):
+        """new background: the state is remapped to the new comoving frames (forward in time)"""
+        arrs = [_c(w.v_r), _c(w.v_theta), _c(w.alpha), _c(w.psi), _c(w.kappa_a),
+                _c(w.kappa_s), _c(w.f_eq)]
+        rc = lib().orc_update_background(self.ctx, *[_p(a) for a in arrs])
         assert rc == 0
 
     def set_state(self, f):

@@ -24,7 +24,8 @@ PREC_FP64, PREC_MIXED = 0, 1
 MU_LEGENDRE, MU_LOBATTO = 0, 1
 ABI_SYMBOLS = ["btx_create", "btx_set_background", "btx_max_dt", "btx_set_state",
                "btx_get_state", "btx_step", "btx_moments", "btx_timing", "btx_destroy",
-               "btx_last_error", "btx_batch_create", "btx_batch_set_background",
+               "btx_last_error", "btx_update_background", "btx_batch_create",
+               "btx_batch_set_background", "btx_batch_update_background",
                "btx_batch_max_dt", "btx_batch_set_state", "btx_batch_get_state", "btx_batch_step",
                "btx_batch_use_graph", "btx_batch_shape", "btx_batch_moments", "btx_batch_destroy"]
 
@@ -63,6 +64,8 @@ def lib():
         vp = C.c_void_p
         L.btx_create.argtypes = [C.POINTER(GridDesc), C.c_int, vp, C.POINTER(vp)]
         L.btx_set_background.argtypes = [vp, C.POINTER(Background)]
+        L.btx_update_background.argtypes = [vp, C.POINTER(Background)]
+        L.btx_batch_update_background.argtypes = [vp, C.c_int32, C.POINTER(Background)]
         L.btx_max_dt.argtypes = [vp, C.c_double, _dp]
         L.btx_set_state.argtypes = [vp, vp, C.c_int]
         L.btx_get_state.argtypes = [vp, vp, C.c_int]
@@ -150,6 +153,11 @@ class Context:
         bg = Background(*[_p(a) for a in arrs])
         _check(lib().btx_set_background(self.h, C.byref(bg)))
 
+    def update_background(self, w):
+        """evolve the background: the state is remapped into the new comoving frames"""
+        bg, keep = _background(w)
+        _check(lib().btx_update_background(self.h, C.byref(bg)))
+
     def max_dt(self, cfl=None):
         out = C.c_double()
         _check(lib().btx_max_dt(self.h, self.w.cfl if cfl is None else cfl, C.byref(out)))
@@ -226,6 +234,10 @@ class Batch:
     def set_background(self, m, w=None):
         bg, keep = _background(w or self.ws[m])
         _check(lib().btx_batch_set_background(self.h, m, C.byref(bg)))
+
+    def update_background(self, m, w):
+        bg, keep = _background(w)
+        _check(lib().btx_batch_update_background(self.h, m, C.byref(bg)))
 
     def max_dt(self, m, cfl=None):
         out = C.c_double()

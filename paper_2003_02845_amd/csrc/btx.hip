@@ -176,7 +176,10 @@ __device__ void lorentz(const double v[3], const double u[4], double o[4])
 
 // comoving(S) -> comoving(D) through Eulerian and coordinate frames, the
 // Hamiltonian kick on the axis of motion and the geometric rotation
-// (Eq. transformchain, Sec. 3.2.1-3.2.4; conformally flat, zero shift)
+// (Eq. transformchain, Sec. 3.2.1-3.2.4; conformally flat, zero shift).
+// axis < 0: the remap forward in time at a fixed place, where the covariant
+// spatial momentum is kept and the covariant energy follows from the null
+// condition of the new metric.
 __device__ void frame_chain(const Frame &S, const Frame &D, int axis, bool rot, const double u[4], double o[4])
 {
   double e[4];
@@ -184,7 +187,9 @@ __device__ void frame_chain(const Frame &S, const Frame &D, int axis, bool rot, 
   double u0 = -S.alpha * e[0];                       // covariant time component
   double p2 = S.psi * S.psi;
   double uc[3] = { p2 * e[1], p2 * e[2], p2 * e[3] };  // covariant spatial components
-  if (S.alpha != D.alpha || S.psi != D.psi) {
+  if (axis < 0 && (S.alpha != D.alpha || S.psi != D.psi)) {
+    u0 = -D.alpha * sqrt(uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]) / (D.psi * D.psi);
+  } else if (S.alpha != D.alpha || S.psi != D.psi) {
     double tr = 0.0;
     for (int i = 0; i < 3; ++i) if (i != axis) tr += uc[i] * uc[i];
     double dp2 = D.psi * D.psi;
@@ -616,6 +621,143 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
   const uint4 *src = (const uint4 *)tabs;
   const int n16 = (int)(kTables * tstride / 16);
   for (int q = tid; q < n16; q += nthr) dst[q] = src[q];
+}
+
+// ------------------------------------------------------------ time remap
+
+// LDS of the time-remap workgroup: one remap table under construction and in
+// gather form, the frame weights of both frames and one species block
+__host__ __device__ inline size_t time_lds_bytes(int nd, int ne, size_t szT)
+{
+  return align16((size_t)nd * 4) * 2 + align16((size_t)16 * nd) + align16((size_t)8 * nd * szT) * 2 +
+         align16((size_t)4 * nd * 2) + align16((size_t)(nd + 1) * 2) + align16((size_t)nd * 8) * 2 +
+         align16((size_t)nd * ne * szT);
+}
+
+// Remaps every species block of one zone from its comoving frame under the
+// current background to its comoving frame under a new one: the remap forward
+// in time of Sec. 3.2 (the closing T_{n->n+1} of a step, Sec. 3.3), at a fixed
+// place, so without rotation and with the time kick of frame_chain.  The
+// zone's gather table is built in LDS and applied in place to the number
+// content (W = psi^6 u0 G dOmega; the cell volume is unchanged).
+// nvr, nvth, nalp, npsi: the new background of the model.
+template <typename T>
+__global__ void __launch_bounds__(256)
+time_remap_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity,
+                  const double *__restrict__ nvr, const double *__restrict__ nvth,
+                  const double *__restrict__ nalp, const double *__restrict__ npsi)
+{
+  extern __shared__ __align__(16) char lds[];
+  const int2 it = items[blockIdx.x];
+  const ModelDev &M = models[it.x];
+  const DevGrid g = global_grid(M.g);
+  T *__restrict__ f = as_global((T *)M.f[parity]);
+  const int z = it.y, nd = g.ndir, ne = g.ne, tid = threadIdx.x, nthr = blockDim.x;
+  Frame S;
+  S.v[0] = g.vr[z]; S.v[1] = g.vth[z]; S.v[2] = 0.0;
+  S.alpha = g.alp[z]; S.psi = g.psi[z];
+  S.th = 0.0; S.ph = 0.0;
+  Frame D = S;
+  D.v[0] = as_global(nvr)[z]; D.v[1] = as_global(nvth)[z];
+  D.alpha = as_global(nalp)[z]; D.psi = as_global(npsi)[z];
+  if (same_frame(S, D)) return;                          // the whole workgroup leaves
+  char *p = lds;
+  int *cnt = (int *)p;                 p += align16((size_t)nd * 4);
+  int *cur = (int *)p;                 p += align16((size_t)nd * 4);
+  int *rtg = (int *)p;                 p += align16((size_t)16 * nd);
+  T *rcf = (T *)p;                     p += align16((size_t)8 * nd * sizeof(T));
+  T *cw = (T *)p;                      p += align16((size_t)8 * nd * sizeof(T));
+  unsigned short *key = (unsigned short *)p;  p += align16((size_t)4 * nd * 2);
+  unsigned short *start = (unsigned short *)p; p += align16((size_t)(nd + 1) * 2);
+  double *aS = (double *)p;            p += align16((size_t)nd * 8);
+  double *aD = (double *)p;            p += align16((size_t)nd * 8);
+  T *cont = (T *)p;
+  const double gS = 1.0 / sqrt(1.0 - (S.v[0] * S.v[0] + S.v[1] * S.v[1]));
+  const double gD = 1.0 / sqrt(1.0 - (D.v[0] * D.v[0] + D.v[1] * D.v[1]));
+  const double p6S = pow(S.psi, 6.0), p6D = pow(D.psi, 6.0);
+  for (int q = tid; q < nd; q += nthr) {
+    cnt[q] = 0;
+    const double *nv = g.nvec + 3 * q;
+    aS[q] = p6S * gS * (1.0 + S.v[0] * nv[0] + S.v[1] * nv[1]) * g.dOm[q];
+    aD[q] = p6D * gD * (1.0 + D.v[0] * nv[0] + D.v[1] * nv[1]) * g.dOm[q];
+  }
+  __syncthreads();
+  for (int q = tid; q < nd; q += nthr) {               // each source direction
+    int rt[4], di;
+    double rl[4], rr[4];
+    remap_source(g, S, D, -1, false, false, q, rt, rl, rr, di);
+    for (int r = 0; r < 4; ++r) {
+      rtg[q * 4 + r] = rt[r] >= 0 ? (rt[r] | ((di + 128) << 16)) : -1;
+      rcf[(q * 4 + r) * 2] = (T)rl[r];
+      rcf[(q * 4 + r) * 2 + 1] = (T)rr[r];
+      if (rt[r] >= 0) atomicAdd(&cnt[rt[r]], 1);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {                                       // list starts per target
+    int acc = 0;
+    for (int d = 0; d < nd; ++d) { start[d] = (unsigned short)acc; cur[d] = acc; acc += cnt[d]; }
+    start[nd] = (unsigned short)acc;
+  }
+  __syncthreads();
+  for (int q = tid; q < nd; q += nthr)
+    for (int r = 0; r < 4; ++r) {
+      const int v = rtg[q * 4 + r];
+      if (v < 0) continue;
+      const int slot = atomicAdd(&cur[v & 0xffff], 1);
+      key[slot] = (unsigned short)(q | ((v >> 16) << 8));
+      cw[2 * slot] = rcf[(q * 4 + r) * 2];
+      cw[2 * slot + 1] = rcf[(q * 4 + r) * 2 + 1];
+    }
+  __syncthreads();
+  for (int q = tid; q < nd; q += nthr) {               // fixed summation order: sort by key
+    const int a = start[q], b = start[q + 1];
+    for (int x = a + 1; x < b; ++x) {
+      const unsigned short kx = key[x];
+      const T c0 = cw[2 * x], c1 = cw[2 * x + 1];
+      int y = x - 1;
+      while (y >= a && key[y] > kx) {
+        key[y + 1] = key[y];
+        cw[2 * y + 2] = cw[2 * y];
+        cw[2 * y + 3] = cw[2 * y + 1];
+        --y;
+      }
+      key[y + 1] = kx;
+      cw[2 * y + 2] = c0;
+      cw[2 * y + 3] = c1;
+    }
+  }
+  __syncthreads();
+  for (int s = 0; s < g.ns; ++s) {
+    T *blk = f + (size_t)z * g.blk + (size_t)s * g.eblk;
+    for (int q = tid; q < ne * nd; q += nthr) {          // content, direction-major
+      const int i = q / nd, d = q - i * nd;
+      cont[d * ne + i] = (T)((double)blk[q] * g.G[i] * aS[d]);
+    }
+    __syncthreads();
+    for (int q = tid; q < ne * nd; q += nthr) {
+      const int i = q / nd, dp = q - i * nd;
+      T acc = (T)0;
+      for (int e = start[dp]; e < start[dp + 1]; ++e) {
+        const int src = key[e] & 0xff, di = (int)(key[e] >> 8) - 128;
+        const T cl = cw[2 * e], cr = cw[2 * e + 1];
+        const T *col = cont + src * ne;
+        const int iL = i - di, iR = iL - 1;
+        if (iL >= 0 && iL < ne) acc += cl * col[iL];
+        if (iR >= 0 && iR < ne) acc += cr * col[iR];
+        if (i == 0) {                                     // sent below group 0
+          for (int j = 0; j < ne && j + di < 0; ++j) acc += cl * col[j];
+          for (int j = 0; j < ne && j + di + 1 < 0; ++j) acc += cr * col[j];
+        }
+        if (i == ne - 1) {                                // sent above group ne-1
+          for (int j = max(0, ne - di); j < ne; ++j) acc += cl * col[j];
+          for (int j = max(0, ne - 1 - di); j < ne; ++j) acc += cr * col[j];
+        }
+      }
+      blk[q] = (T)((double)acc / (g.G[i] * aD[dp]));
+    }
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------ face kernel
@@ -1220,6 +1362,7 @@ struct Model {
   char *d_tabs = nullptr;
   FaceAux *d_aux = nullptr;
   double *d_tally = nullptr, *d_zm = nullptr, *d_ze = nullptr, *d_stage = nullptr;
+  double *d_nbg = nullptr;           // new v_r, v_theta, alpha, psi of a background update
   FaceDesc *d_faces = nullptr;
   btx::ZoneFaces *d_zf = nullptr;
   int2 *d_fitems = nullptr, *d_zitems = nullptr;   // (index, face), (index, zone)
@@ -1269,7 +1412,8 @@ void model_free(Model &m)
 {
   void *ptrs[] = { m.d_mu, m.d_Phi, m.d_dOm, m.d_nvec, m.d_G, m.d_eps, m.d_vol, m.d_vr, m.d_vth,
                    m.d_alp, m.d_psi, m.d_ka, m.d_ks, m.d_feq, m.d_f[0], m.d_f[1], m.d_dN, m.d_tally,
-                   m.d_zm, m.d_ze, m.d_stage, m.d_faces, m.d_zf, m.d_tabs, m.d_aux, m.d_fitems, m.d_zitems };
+                   m.d_zm, m.d_ze, m.d_stage, m.d_faces, m.d_zf, m.d_tabs, m.d_aux, m.d_fitems, m.d_zitems,
+                   m.d_nbg };
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   m = Model();
@@ -1335,7 +1479,7 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
       !dmalloc(&m.d_f[0], nz * blk * m.tsize) || !dmalloc(&m.d_f[1], nz * blk * m.tsize) ||
       !dmalloc(&m.d_dN, nf * 2 * blk * m.tsize) || !dmalloc((void **)&m.d_tally, nf * g.ns * 8) ||
       !dmalloc((void **)&m.d_zm, nz * g.ns * 5 * 8) || !dmalloc((void **)&m.d_ze, nz * g.ns * 8) ||
-      !dmalloc((void **)&m.d_stage, nk * 8) ||
+      !dmalloc((void **)&m.d_stage, nk * 8) || !dmalloc((void **)&m.d_nbg, nz * 4 * 8) ||
       !dmalloc((void **)&m.d_tabs, nf * kTables * tab_stride(g.ndir, m.tsize)) ||
       !dmalloc((void **)&m.d_aux, nf * sizeof(FaceAux))) {
     model_free(m);
@@ -1463,6 +1607,38 @@ btx_status set_face_lds(size_t tsize, const FaceShape &f, size_t lds)
   const void *fn = face_fn(tsize, f);
   if (!fn) return fail(BTX_E_UNSUPPORTED, "no face kernel for this shape");
   return raise_lds_limit(fn, lds);
+}
+
+// A new background for a model (set_background), or, once a state exists, a
+// background that evolves: the state is first remapped from the comoving
+// frames of the current background to those of the new one (forward in time,
+// time_remap_kernel), then the new background and its face tables are adopted.
+btx_status model_update_background(Model &m, const btx_background *bg, const ModelDev *d_models, int parity,
+                                   hipStream_t s)
+{
+  btx_status st = check_background(m, bg);
+  if (st != BTX_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s));
+  if (m.have_bg && m.have_state) {
+    const size_t nz = m.g.nz;
+    HIP_TRY(hipMemcpy(m.d_nbg, bg->v_r, nz * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m.d_nbg + nz, bg->v_theta, nz * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m.d_nbg + 2 * nz, bg->alpha, nz * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m.d_nbg + 3 * nz, bg->psi, nz * 8, hipMemcpyHostToDevice));
+    const void *tk = m.tsize == 8 ? (const void *)time_remap_kernel<double> : (const void *)time_remap_kernel<float>;
+    const size_t lds = time_lds_bytes(m.g.ndir, m.g.ne, m.tsize);
+    if ((st = raise_lds_limit(tk, lds)) != BTX_OK) return st;
+    const int2 *items = m.d_zitems;
+    const double *nvr = m.d_nbg, *nvth = m.d_nbg + nz, *nalp = m.d_nbg + 2 * nz, *npsi = m.d_nbg + 3 * nz;
+    void *args[] = { &d_models, &items, &parity, &nvr, &nvth, &nalp, &npsi };
+    HIP_TRY(hipLaunchKernel(tk, dim3((unsigned)nz), dim3(256), args, lds, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  if ((st = upload_background(m, bg, s)) != BTX_OK) return st;
+  if ((st = build_tables(m, d_models, s)) != BTX_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s));
+  m.have_bg = true;
+  return BTX_OK;
 }
 
 btx_status model_set_state(Model &m, int parity, const void *f, int is_device_ptr, hipStream_t s)
@@ -1875,6 +2051,13 @@ btx_status btx_set_background(btx_ctx *c, const btx_background *bg)
   return BTX_OK;
 }
 
+btx_status btx_update_background(btx_ctx *c, const btx_background *bg)
+{
+  if (!c) return fail(BTX_E_INVAL, "null argument");
+  HIP_TRY(hipSetDevice(c->device));
+  return model_update_background(c->m, bg, c->d_model, c->parity, c->stream);
+}
+
 btx_status btx_max_dt(const btx_ctx *c, double cfl, double *dt_out)
 {
   if (!c || !dt_out) return fail(BTX_E_INVAL, "null argument");
@@ -2005,6 +2188,13 @@ btx_status btx_batch_set_background(btx_batch *b, int32_t model, const btx_backg
   HIP_TRY(hipStreamSynchronize(b->stream));
   m.have_bg = true;
   return BTX_OK;
+}
+
+btx_status btx_batch_update_background(btx_batch *b, int32_t model, const btx_background *bg)
+{
+  if (!b || model < 0 || model >= (int)b->models.size()) return fail(BTX_E_INVAL, "bad batch or model index");
+  HIP_TRY(hipSetDevice(b->device));
+  return model_update_background(b->models[model], bg, b->d_models, b->parity, b->stream);
 }
 
 btx_status btx_batch_max_dt(const btx_batch *b, int32_t model, double cfl, double *dt_out)

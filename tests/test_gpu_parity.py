@@ -4,6 +4,7 @@ FP64 mode: ||f_gpu - f_ref||_inf / ||f_ref||_inf <= 1e-12 after several steps;
 moments to 1e-12 where they are not negligible.  Mixed mode: per-zone number
 and J within 1e-5 relative where J > 1e-8 max J.
 """
+import copy
 import math
 import sys
 
@@ -154,3 +155,78 @@ def test_errors_gpu():
         ctx.set_background(w)
     assert e.value.status == btx.BTX_E_INVAL
     ctx.close()
+
+
+def _evolved(w):
+    w2 = copy.copy(w)
+    w2.v_r = w.v_r * 1.3 + 0.02
+    w2.alpha = w.alpha * 0.97
+    w2.psi = w2.alpha ** -0.5
+    w2.kappa_a = w.kappa_a * 1.1
+    return w2
+
+
+@pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
+def test_evolving_background_gpu(precision, oracle_mod):
+    """steps, a background update (state remapped forward in time into the new
+    comoving frames), more steps: against the reference"""
+    btx = _btx()
+    w = _perturb(W.shock_2d(n_r=10, n_theta=4, n_eps=8, n_mu=4, n_phi=4, precision=W.PREC_FP64))
+    w2 = _evolved(w)
+    _say(f"[gpu] evolving background, precision {precision}")
+    o = oracle_mod.Oracle(w)
+    dt = min(o.max_dt(0.4), 0.9 * o.max_dt(0.4))
+    ctx = btx.Context(w, precision=precision)
+    ctx.set_background()
+    ctx.set_state(w.f0)
+    o.step(dt, 2)
+    ctx.step(dt, 2)
+    o.update_background(w2)
+    ctx.update_background(w2)
+    if precision == W.PREC_FP64:
+        ref, got = o.state(), ctx.get_state()
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    o.step(dt, 2)
+    ctx.step(dt, 2)
+    zr, tr = o.moments()
+    zg, tg = ctx.moments()
+    if precision == W.PREC_FP64:
+        ref, got = o.state(), ctx.get_state()
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        _say(f"[gpu]   rel err {err:.3e}")
+        assert err <= 1e-12
+        assert np.allclose(tg, tr, rtol=1e-12, atol=1e-12 * np.abs(tr).max())
+    else:
+        for k in (0, 1):
+            mask = np.abs(zr[..., 1]) > 1e-8 * np.abs(zr[..., 1]).max()
+            rel = np.max(np.abs(zg[..., k] - zr[..., k])[mask] / np.abs(zr[..., k][mask]))
+            _say(f"[gpu]   moment {k} rel err {rel:.3e}")
+            assert rel <= 1e-5
+    ctx.close()
+
+
+def test_batch_evolving_background_gpu(oracle_mod):
+    btx = _btx()
+    import torch
+    ws = W.batch_models(n_models=3, size_scale=0.04)
+    for w in ws:
+        w.precision = W.PREC_FP64
+        w.f0 = w.f0 * (1.0 + 0.3 * RNG.random(w.f0.shape))
+    _say("[gpu] batch with an evolving background")
+    b = btx.Batch(ws, precision=W.PREC_FP64, stream=torch.cuda.current_stream().cuda_stream)
+    for m, w in enumerate(ws):
+        b.set_background(m)
+        b.set_state(m, w.f0)
+    dts = [0.9 * b.max_dt(m, 0.4) for m in range(len(ws))]
+    b.step(dts, 2)
+    for m, w in enumerate(ws):
+        b.update_background(m, _evolved(w))
+    b.step(dts, 2)
+    for m, w in enumerate(ws):
+        o = oracle_mod.Oracle(w)
+        o.step(dts[m], 2)
+        o.update_background(_evolved(w))
+        o.step(dts[m], 2)
+        ref, got = o.state(), b.get_state(m)
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    b.close()

@@ -3,6 +3,7 @@ mathematics (closed forms, textbook special cases, invariants, brute force).
 
 Each test names the passage of Chan & Mueller (arXiv:2003.02845) it pins.
 """
+import copy
 import math
 
 import numpy as np
@@ -454,3 +455,63 @@ def test_free_streaming_beam(oracle_mod):
     rbar = np.sum(N * rc) / np.sum(N)
     dr = rc[1] - rc[0]
     assert abs((rbar - rbar0) - steps * dt) < 0.5 * dr
+
+
+# ------------------------------------------------- evolving background
+def _static_column(n_eps=10):
+    w = W.batch_models(n_models=1, size_scale=0.03)[0]
+    w.v_r = np.zeros(w.n_zones)
+    w.alpha = np.ones(w.n_zones)
+    w.psi = np.ones(w.n_zones)
+    f0 = np.zeros_like(w.f0)
+    f0[:, :, 3:w.n_eps - 3, :] = 0.5 + RNG.random(f0[:, :, 3:w.n_eps - 3, :].shape)
+    w.f0 = f0
+    return w
+
+
+def test_time_remap_identity_and_lapse(oracle_mod):
+    """Sec. 3.2 forward in time: an unchanged background leaves the state
+    untouched; a change of the lapse alone (static fluid, same conformal
+    factor) keeps the covariant spatial momentum and so every energy and
+    direction: the state is unchanged to rounding."""
+    w = _static_column()
+    o = oracle_mod.Oracle(w)
+    before = o.state()
+    o.update_background(w)
+    assert np.array_equal(o.state(), before)
+    w2 = copy.copy(w)
+    w2.alpha = np.linspace(0.6, 0.9, w.n_zones)
+    o.update_background(w2)
+    assert np.max(np.abs(o.state() - before)) < 1e-13 * np.max(np.abs(before))
+
+
+def test_time_remap_conformal_factor_shift(oracle_mod):
+    """A change of the conformal factor alone (static fluid) scales every
+    comoving energy by psi_old^2 / psi_new^2 in every direction: number is
+    conserved, and the energy content scales by exactly that ratio (the
+    trilinear split keeps the first energy moment inside the grid)."""
+    w = _static_column()
+    o = oracle_mod.Oracle(w)
+    _, t0 = o.moments()
+    w2 = copy.copy(w)
+    w2.psi = np.full(w.n_zones, 1.05)
+    o.update_background(w2)
+    _, t1 = o.moments()
+    rho = 1.0 / 1.05 ** 2
+    assert abs(t1[0, 0] - t0[0, 0]) < 1e-13 * t0[0, 0]
+    assert abs(t1[0, 2] / t0[0, 2] - rho) < 1e-13
+
+
+def test_time_remap_boost_conserves_number(oracle_mod):
+    """a change of fluid velocity, lapse and conformal factor together moves
+    number content between bins and conserves it"""
+    w = _static_column()
+    o = oracle_mod.Oracle(w)
+    _, t0 = o.moments()
+    w2 = copy.copy(w)
+    w2.v_r = np.linspace(-0.15, 0.1, w.n_zones)
+    w2.alpha = np.linspace(0.7, 0.95, w.n_zones)
+    w2.psi = w2.alpha ** -0.5
+    o.update_background(w2)
+    _, t1 = o.moments()
+    assert abs(t1[0, 0] - t0[0, 0]) < 1e-13 * t0[0, 0]

@@ -282,6 +282,47 @@ def planar(n_z=100, z_min=-1.0, z_max=1.0, n_eps=1, n_mu=8, n_phi=1, kappa_a=0.0
                      phi_rule=PHI_LINEAR if n_phi < 3 else PHI_SIN)
 
 
+# --------------------------------------------------------------------------
+# relativistic radiating spheres (boost, redshift, both), spherical symmetry
+# --------------------------------------------------------------------------
+def relativistic_sphere(test, params, n_inner=8, n_outer=56, r_max=600.0, n_mu=8, n_phi=4,
+                        kappa=100.0, T=10.0):
+    """Column grid: uniform radial zones inside the sphere, logarithmic outside.
+    test 1: shock-like infall profile, flat metric; test 2: static fluid in a
+    lapse well; test 3: both, opaque in the top energy group only.  params: the
+    printed set-up (sphere radius, velocity and lapse laws, energy grid)."""
+    R = params["sphere_radius_km"]
+    eg = params["combined_test_energy_grid"]
+    r_in = np.linspace(0.0, R, n_inner + 1)
+    r_out = R * (r_max / R) ** (np.arange(1, n_outer + 1) / n_outer)
+    r_edges = np.concatenate([r_in, r_out])
+    rc = _centres(r_edges)
+    n_r = len(rc)
+    eps_edges = log_edges(eg["eps_min_MeV"], eg["eps_max_MeV"], eg["n_eps"])
+    e = _group_energies(eps_edges)
+    vp, lp = params["velocity_profile"], params["lapse_profile"]
+    v = np.zeros(n_r)
+    alpha = np.ones(n_r)
+    if test in (1, 3):
+        r0, r1, vmax = vp["r0_km"], vp["r1_km"], vp["vmax"]
+        v = np.where(rc < r0, 0.0, np.where(rc <= r1, -vmax * (rc - r0) / (r1 - r0),
+                                              -vmax * (r1 / rc) ** 2))
+    if test in (2, 3):
+        a0, rk = lp["a0"], lp["rk_km"]
+        alpha = np.where(rc < rk, a0, a0 + (1.0 - a0) * (1.0 - rk / rc))
+    psi = alpha ** -0.5
+    inside = rc < R
+    ka = np.zeros((n_r, 1, len(e)))
+    if test == 3:
+        ka[inside, 0, -1] = params["combined_test_opacity"]["kappa_a"]
+    else:
+        ka[inside, 0, :] = kappa
+    feq = np.where(inside[:, None, None], fermi_dirac(e, T)[None, None, :], 0.0)
+    return _assemble(f"relativistic_sphere_{test}", GEOM_COLUMN, r_edges, np.array([0.0, math.pi]), 0.0,
+                     eps_edges, n_mu, n_phi, "lobatto", v, np.zeros(n_r), alpha, psi, ka,
+                     np.zeros_like(ka), feq, False, 0, PREC_FP64, meta={"R": R, "test": test})
+
+
 CONFIGS = {
     "radiating_sphere": radiating_sphere,
     "axisym_2d": axisym_2d,

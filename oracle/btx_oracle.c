@@ -56,6 +56,7 @@ struct orc_ctx {
   double *vr, *vth, *alp, *psi, *ka, *ks, *feq;
   int have_bg, have_state;
   double *f, *fn, *outflow;
+  double *q;        /* hydro source terms of the last full step, [zone][4] */
   int blend_mode;
 };
 
@@ -336,7 +337,7 @@ static void free_all(orc_ctx *c)
   free(c->r_e); free(c->th_e); free(c->e_e); free(c->eps); free(c->G); free(c->mu);
   free(c->wmu); free(c->Phi); free(c->dOm); free(c->nvec); free(c->rc); free(c->thc);
   free(c->vol); free(c->vr); free(c->vth); free(c->alp); free(c->psi); free(c->ka);
-  free(c->ks); free(c->feq); free(c->f); free(c->fn); free(c->outflow);
+  free(c->ks); free(c->feq); free(c->f); free(c->fn); free(c->outflow); free(c->q);
 }
 
 orc_ctx *orc_create(const orc_desc *d)
@@ -421,6 +422,7 @@ orc_ctx *orc_create(const orc_desc *d)
   c->f = (double *)calloc((size_t)c->nz * c->blk, sizeof(double));
   c->fn = (double *)calloc((size_t)c->nz * c->blk, sizeof(double));
   c->outflow = (double *)calloc(c->ns, sizeof(double));
+  c->q = (double *)calloc((size_t)c->nz * 4, sizeof(double));
   return c;
 }
 
@@ -960,6 +962,7 @@ static int do_step(orc_ctx *c, double dt, int nlist, const int *zones, double *f
     double g = gamma_of(self.v), p6 = pow(self.psi, 6.0);
     double tau = self.alpha * dt / g;             /* Reading: dt_c = alpha dt / gamma */
     double *out = fout + (size_t)l * c->blk;
+    double qz[4] = { 0.0, 0.0, 0.0, 0.0 };
     for (int s = 0; s < c->ns; ++s)
       for (int i = 0; i < ne; ++i) {
         const double *fz0 = c->f + (size_t)z * c->blk + (size_t)s * n + (size_t)i * nd;
@@ -970,7 +973,29 @@ static int do_step(orc_ctx *c, double dt, int nlist, const int *zones, double *f
         size_t kidx = ((size_t)z * c->ns + s) * ne + i;
         orc_collide(nd, fz0, dJ, tau, c->ka[kidx], c->ks[kidx], c->feq[kidx], c->dOm, tmp);
         memcpy(out + (size_t)s * n + (size_t)i * nd, tmp, sizeof(double) * nd);
+        /* hydro source terms (Eq. hydrosource1-3): the collision term of
+         * Eq. sourceterms_discrete at the new distribution f' (backward Euler
+         * puts the whole collision change of the step there), integrated over
+         * each bin's momentum-space cell G_i dOmega_d with weight 1 (lepton
+         * number: + for the first species, - for the second), eps_i (energy)
+         * and eps_i n_d (momentum, r and theta components); the fluid gains
+         * what the radiation loses.  Readings: d^3p = eps^2 deps dOmega, so
+         * the bin integrals are G_i dOmega_d; the 1/h^3 normalisation is
+         * omitted; comoving frame, per unit comoving volume and time. */
+        double ka = c->ka[kidx], ks = c->ks[kidx], fe = c->feq[kidx], avg = 0.0;
+        for (int d = 0; d < nd; ++d) avg += tmp[d] * c->dOm[d];
+        avg /= 4.0 * PI;
+        double lep = s == 0 ? 1.0 : (s == 1 ? -1.0 : 0.0);
+        for (int d = 0; d < nd; ++d) {
+          double C = ka * (fe - tmp[d]) + ks * avg - ks * tmp[d];
+          double wgt = C * c->G[i] * c->dOm[d];
+          qz[0] -= lep * wgt;
+          qz[1] -= wgt * c->eps[i];
+          qz[2] -= wgt * c->eps[i] * c->nvec[3 * d];
+          qz[3] -= wgt * c->eps[i] * c->nvec[3 * d + 1];
+        }
       }
+    if (out_tally) memcpy(c->q + 4 * (size_t)z, qz, sizeof(qz));
     free(dN); free(dJ); free(tmp);
   }
   /* number leaving the domain: what the boundary ghosts would receive */
@@ -1119,4 +1144,13 @@ int orc_update_background(orc_ctx *c, const double *v_r, const double *v_theta,
   }
   free(tmp);
   return orc_set_background(c, v_r, v_theta, alpha, psi, ka, ks, feq);
+}
+
+/* hydro source terms of the last full step: q[zone][4] = Q_Ye, Q_E, Q_M,r,
+ * Q_M,theta (comoving frame, per unit volume and time, without 1/h^3) */
+int orc_source_terms(const orc_ctx *c, double *q)
+{
+  if (!c) return 1;
+  memcpy(q, c->q, sizeof(double) * 4 * (size_t)c->nz);
+  return 0;
 }

@@ -47,6 +47,9 @@ int orc_set_background(orc_ctx *c, const double *v_r, const double *v_theta,
 int orc_update_background(orc_ctx *c, const double *v_r, const double *v_theta,
                           const double *alpha, const double *psi, const double *ka,
                           const double *ks, const double *feq);
+/* hydro source terms of the last full step (Eq. hydrosource1-3):
+ * q[zone][4] = Q_Ye, Q_E, Q_M,r, Q_M,theta */
+int orc_source_terms(const orc_ctx *c, double *q);
 int orc_set_state(orc_ctx *c, const double *f);
 int orc_get_state(const orc_ctx *c, double *f);
 double orc_max_dt(const orc_ctx *c, double cfl);

@@ -54,6 +54,7 @@ def lib():
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_set_background.argtypes = [C.c_void_p] + [_dp] * 7
         L.orc_update_background.argtypes = [C.c_void_p] + [_dp] * 7
+        L.orc_source_terms.argtypes = [C.c_void_p, _dp]
         L.orc_set_state.argtypes = [C.c_void_p, _dp]
         L.orc_get_state.argtypes = [C.c_void_p, _dp]
         L.orc_max_dt.restype = C.c_double
@@ -180,6 +181,12 @@ class Oracle:
         if rc:
             raise RuntimeError(f"orc_step_sample failed ({rc})")
         return out
+
+    def source_terms(self):
+        """[zone][4]: Q_Ye, Q_E, Q_M,r, Q_M,theta of the last full step"""
+        q = np.zeros((self.w.n_zones, 4))
+        assert lib().orc_source_terms(self.ctx, _p(q)) == 0
+        return q
 
     def moments(self):
         zm = np.zeros((self.w.n_zones, self.w.n_species, 5))

@@ -515,3 +515,107 @@ def test_time_remap_boost_conserves_number(oracle_mod):
     o.update_background(w2)
     _, t1 = o.moments()
     assert abs(t1[0, 0] - t0[0, 0]) < 1e-13 * t0[0, 0]
+
+
+# ----------------------------------------------------- hydro source terms
+def _source_case(ka_scale=1.0, ks_scale=1.0):
+    """three species on a small axisymmetric grid, random anisotropic state,
+    nothing in the inner- and outermost three radial zones (so nothing crosses
+    the radial boundaries in one step)"""
+    w = W.shock_2d(n_r=12, n_theta=4, n_eps=5, n_mu=4, n_phi=4)
+    w.v_r = np.zeros(w.n_zones)
+    w.v_theta = np.zeros(w.n_zones)
+    w.alpha = np.ones(w.n_zones)
+    w.psi = np.ones(w.n_zones)
+    w.kappa_a = w.kappa_a * ka_scale
+    w.kappa_s = w.kappa_s * ks_scale
+    f0 = RNG.random(w.f0.shape)
+    ir = np.arange(w.n_zones) % w.n_r
+    f0[(ir < 3) | (ir >= w.n_r - 3)] = 0.0
+    w.f0 = f0
+    return w
+
+
+def _bin_geometry(w):
+    from oracle import oracle
+    mu, wmu = oracle.quadrature(w.mu_rule, w.n_mu)
+    dOm = np.repeat(wmu * 2.0 * np.pi / w.n_phi, w.n_phi)
+    Phi = (np.arange(w.n_phi) + 0.5) * 2.0 * np.pi / w.n_phi
+    n_r = np.repeat(mu, w.n_phi)
+    n_t = (np.sqrt(1.0 - mu * mu)[:, None] * np.cos(Phi)[None, :]).ravel()
+    e = w.eps_edges
+    G = (e[1:] ** 3 - e[:-1] ** 3) / 3.0
+    return dOm, n_r, n_t, np.sqrt(e[1:] * e[:-1]), G
+
+
+def _gross_rate(w, f1):
+    """per zone: sum over bins of |each collision term| eps G dOmega, the scale
+    against which the rounding of the source terms is judged"""
+    dOm, _, _, eps, G = _bin_geometry(w)
+    ka, ks, fe = w.kappa_a[..., None], w.kappa_s[..., None], w.f_eq[..., None]
+    af = np.abs(f1)
+    avg = np.einsum("zsid,d->zsi", af, dOm)[..., None] / (4 * np.pi)
+    g = ka * (np.abs(fe) + af) + ks * (avg + af)
+    return np.einsum("zsid,i,d->z", g, G * np.maximum(eps, 1.0), dOm)
+
+
+def test_source_terms_equilibrium(oracle_mod):
+    """P-18 (Eq. hydrosource1-3): matter and radiation in equilibrium exchange
+    nothing: every source term vanishes."""
+    w = _planar(n_z=20, n_eps=3, kappa_a=5.0, kappa_s=3.0, f_eq=0.37,
+                inner_bc=W.BC_EQUIL, outer_bc=W.BC_EQUIL)
+    o = oracle_mod.Oracle(w)
+    o.step(o.max_dt(0.4), 1)
+    q = o.source_terms()
+    assert np.all(np.abs(q) <= 1e-13 * _gross_rate(w, o.state())[:, None])
+
+
+def test_source_terms_scattering_moments(oracle_mod):
+    """P-19: isotropic elastic scattering moves neither lepton number nor
+    energy between matter and radiation; with any opacities the energy and
+    number terms are kappa_a times (content - equilibrium content) of the new
+    state, and the momentum terms are (kappa_a + kappa_s) times its flux, the
+    isotropic parts dropping out over the symmetric quadrature."""
+    for ka_scale in (0.0, 1.0):
+        w = _source_case(ka_scale=ka_scale)
+        o = oracle_mod.Oracle(w)
+        o.step(o.max_dt(0.4), 1)
+        q, f1 = o.source_terms(), o.state()
+        dOm, n_r, n_t, eps, G = _bin_geometry(w)
+        scale = _gross_rate(w, f1)
+        lep = np.array([1.0, -1.0, 0.0])
+        ka, ks, fe = w.kappa_a, w.kappa_s, w.f_eq
+        J = np.einsum("zsid,d->zsi", f1, dOm)
+        Fr = np.einsum("zsid,d->zsi", f1, dOm * n_r)
+        Ft = np.einsum("zsid,d->zsi", f1, dOm * n_t)
+        exp = np.stack([
+            np.einsum("zsi,s,i->z", ka * (J - 4 * np.pi * fe), lep, G),
+            np.einsum("zsi,i->z", ka * (J - 4 * np.pi * fe), G * eps),
+            np.einsum("zsi,i->z", (ka + ks) * Fr, G * eps),
+            np.einsum("zsi,i->z", (ka + ks) * Ft, G * eps)], axis=1)
+        assert np.all(np.abs(q - exp) <= 1e-12 * scale[:, None])
+        if ka_scale == 0.0:
+            assert np.all(np.abs(q[:, :2]) <= 1e-12 * scale[:, None])
+        assert np.max(np.abs(q[:, 2])) > 1e-3 * np.max(scale)
+
+
+def test_source_terms_balance_the_step(oracle_mod):
+    """P-20: what the radiation gains in a step is what the matter loses.
+    With nothing leaving the grid and a static, flat background (transport
+    then keeps number and energy), the change of the total radiation energy is
+    -dt sum(Q_E dV), and the change of (first species - second species) number
+    is -dt sum(Q_Ye dV)."""
+    w = _source_case()
+    o = oracle_mod.Oracle(w)
+    dt = o.max_dt(0.4)
+    _, t0 = o.moments()
+    o.step(dt, 1)
+    _, t1 = o.moments()
+    q = o.source_terms()
+    vol, _, _ = o.geometry()
+    assert np.all(np.abs(t1[:, 1]) <= 1e-20 * t0[:, 0])       # only the axis faces' rounding
+    dn = (t1[0, 0] - t0[0, 0]) - (t1[1, 0] - t0[1, 0])
+    assert abs(dn + dt * np.sum(vol * q[:, 0])) <= 1e-12 * (t0[0, 0] + t0[1, 0])
+    de = np.sum(t1[:, 2] - t0[:, 2])
+    assert abs(de + dt * np.sum(vol * q[:, 1])) <= 1e-12 * np.sum(t0[:, 2])
+    assert abs(dn) > 1e-4 * (t0[0, 0] + t0[1, 0]) and abs(de) > 1e-4 * np.sum(t0[:, 2])

@@ -14,7 +14,7 @@
  * resulting number content between cells through the momentum-space remap of
  * Sec. 3.2 (Lorentz boost, conformally flat frame change, Hamiltonian kick,
  * geometric rotation), and ends with the zone-local closed-form solve of
- * absorption, emission and isotropic elastic scattering (Sec. 3.4).
+ * absorption, emission and isotropic elastic scattering (Sec. 3.4-3.5).
  *
  * Conventions
  *   Units: c = 1; lengths km; time km/c; energies MeV; opacities 1/km.  The
@@ -117,13 +117,25 @@ btx_status btx_max_dt(const btx_ctx *ctx, double cfl, double *dt_out);
  * resets the cumulative boundary outflow. */
 btx_status btx_set_state(btx_ctx *ctx, const void *f, int is_device_ptr);
 btx_status btx_get_state(btx_ctx *ctx, void *f, int is_device_ptr);
-/* n_steps steps of size dt (Eq. fullstep + Sec. 3.4); BTX_E_CFL if dt exceeds
+/* n_steps steps of size dt (Eq. fullstep + Sec. 3.5); BTX_E_CFL if dt exceeds
  * btx_max_dt(cfl = 1). */
 btx_status btx_step(btx_ctx *ctx, double dt, int32_t n_steps);
 /* zone_moments[zone][species][5] = N (number), J, H, K, number flux (Sec. 4.1,
  * 4.2); totals[species][3] = total number, cumulative boundary outflow, total
  * energy.  Either pointer may be NULL.  Computed on the device in FP64. */
 btx_status btx_moments(btx_ctx *ctx, double *zone_moments, double *totals);
+/* Hydro source terms of the last step (coupling to matter, Sec. 3.4,
+ * Eq. hydrosource1-3): q[zone][4] = Q_Ye, Q_E, Q_M,r, Q_M,theta, what
+ * the fluid gains per unit comoving volume and comoving time.  They integrate
+ * the collision term of Eq. sourceterms_discrete at the new state (backward
+ * Euler puts the step's whole collision change there) over each bin's
+ * momentum cell G_i dOmega_d (group i, direction d): weight +1 for
+ * species 0 (electron neutrinos), -1 for species 1 (antineutrinos), 0
+ * otherwise (Q_Ye); eps (Q_E); eps n in the zone's comoving (r, theta)
+ * directions (Q_M).  No 1/h^3.  Zero before
+ * the first step.  Computed in FP64 by the zone update; synchronises the
+ * stream. */
+btx_status btx_source_terms(btx_ctx *ctx, double *q);
 /* Per-kernel GPU time: enable = 1 records HIP events around the kernels of
  * each btx_step step on the context's stream (no synchronisation; up to 256
  * steps between two queries).  The query synchronises the recorded events and
@@ -163,6 +175,7 @@ btx_status btx_batch_use_graph(btx_batch *b, int enable);
 btx_status btx_batch_shape(const btx_batch *b, int32_t model, int32_t *items_per_direction,
                            int32_t *groups_per_item);
 btx_status btx_batch_moments(btx_batch *b, int32_t model, double *zone_moments, double *totals);
+btx_status btx_batch_source_terms(btx_batch *b, int32_t model, double *q);
 btx_status btx_batch_destroy(btx_batch *b);
 
 #ifdef __cplusplus

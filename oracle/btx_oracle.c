@@ -286,7 +286,7 @@ static void remap(const orc_ctx *c, const frame_t *S, const frame_t *D, int axis
 
 /* Backward-Euler solve of f' = S + tau*[ka (feq - f') + ks (<f'> - f')] with
  * S = f + tau ka feq + dJ and <x> = (1/4pi) sum_d x_d dOmega_d (Eq.
- * sourceterms_discrete).  Reading: the closed form printed in Sec. 3.4 divides
+ * sourceterms_discrete).  Reading: the closed form printed in Sec. 3.5 divides
  * the scattering sum by 1 + (ka+ks) tau; the exact solution of the linear
  * system divides it by 1 + ka tau, which is what is used here. */
 void orc_collide(int nd, const double *f, const double *dJ, double tau, double ka,
@@ -945,7 +945,7 @@ static int do_step(orc_ctx *c, double dt, int nlist, const int *zones, double *f
                  dt, dl, dr, NULL, NULL);
   }
   /* conservative update and zone-local implicit collision (Eq. fullstep,
-   * Sec. 3.4): the zone sums the content changes of its faces, divides by
+   * Sec. 3.5): the zone sums the content changes of its faces, divides by
    * its bin content weights W = psi^6 dV u0 dGamma and solves the collisions. */
 #pragma omp parallel for schedule(dynamic)
   for (int l = 0; l < nlist; ++l) {

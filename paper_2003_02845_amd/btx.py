@@ -27,7 +27,8 @@ ABI_SYMBOLS = ["btx_create", "btx_set_background", "btx_max_dt", "btx_set_state"
                "btx_last_error", "btx_update_background", "btx_batch_create",
                "btx_batch_set_background", "btx_batch_update_background",
                "btx_batch_max_dt", "btx_batch_set_state", "btx_batch_get_state", "btx_batch_step",
-               "btx_batch_use_graph", "btx_batch_shape", "btx_batch_moments", "btx_batch_destroy"]
+               "btx_batch_use_graph", "btx_batch_shape", "btx_batch_moments", "btx_batch_destroy",
+               "btx_source_terms", "btx_batch_source_terms"]
 
 _dp = C.POINTER(C.c_double)
 
@@ -83,6 +84,8 @@ def lib():
         L.btx_batch_use_graph.argtypes = [vp, C.c_int]
         L.btx_batch_shape.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.btx_batch_moments.argtypes = [vp, C.c_int32, _dp, _dp]
+        L.btx_source_terms.argtypes = [vp, _dp]
+        L.btx_batch_source_terms.argtypes = [vp, C.c_int32, _dp]
         L.btx_batch_destroy.argtypes = [vp]
         L.btx_last_error.restype = C.c_char_p
         for name in ABI_SYMBOLS:
@@ -192,6 +195,12 @@ class Context:
         _check(lib().btx_moments(self.h, _p(zm), _p(tot)))
         return zm, tot
 
+    def source_terms(self):
+        """[zone][4]: Q_Ye, Q_E, Q_M,r, Q_M,theta of the last step"""
+        q = np.zeros((self.w.n_zones, 4))
+        _check(lib().btx_source_terms(self.h, _p(q)))
+        return q
+
     def timing(self, enable=True, reset=False):
         ms = np.zeros(2)
         n = (C.c_int64 * 2)()
@@ -273,3 +282,9 @@ class Batch:
         tot = np.zeros((w.n_species, 3))
         _check(lib().btx_batch_moments(self.h, m, _p(zm), _p(tot)))
         return zm, tot
+
+    def source_terms(self, m):
+        """[zone][4]: Q_Ye, Q_E, Q_M,r, Q_M,theta of model m's last step"""
+        q = np.zeros((self.ws[m].n_zones, 4))
+        _check(lib().btx_batch_source_terms(self.h, m, _p(q)))
+        return q

@@ -13,7 +13,7 @@
 //                 remapped number-content change of both sides (Eq. fullstep).
 //   zone_kernel   one workgroup per zone: sums the content changes of its
 //                 faces, converts them to occupation and applies the
-//                 zone-local closed-form implicit collision solve (Sec. 3.4).
+//                 zone-local closed-form implicit collision solve (Sec. 3.5).
 // Precision: T = double (FP64 mode) or float (mixed mode: storage, remap and
 // fluxes in FP32; angle sums in FP64; the collision solve of a (zone, species,
 // group) in FP64 where dt_c (ka + ks) exceeds the threshold).
@@ -92,6 +92,7 @@ struct ModelDev {
   const void *ka, *ks, *feq;   // [zone][species][group] (storage precision)
   void *dN;                    // [face][side][species][group][direction]
   double *tally;               // [face][species] cumulative content through ghost faces
+  double *q;                   // [zone][4] hydro source terms of the last step
   double dt;                   // step of the current launch
 };
 
@@ -1130,6 +1131,7 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   const double gam = 1.0 / sqrt(1.0 - (vr * vr + vt * vt));
   const double p6v = pow(g.psi[z], 6.0) * g.vol[z];
   const double tau = g.alp[z] * dt / gam;
+  double qa[4] = { 0.0, 0.0, 0.0, 0.0 };   // this lane's share of Q_Ye, Q_E, Q_M,r, Q_M,theta
   for (int row = wave; row < g.ns * ne; row += nwaves) {
     int s = row / ne, i = row - s * ne;
     size_t kidx = ((size_t)z * g.ns + s) * ne + i;
@@ -1153,6 +1155,12 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
       part += S * g.dOm[d];
     }
     double avg = wave_sum(part) / (4.0 * kPi);
+    // Collision term at the new state (backward Euler), in FP64 from the
+    // closed form: the new angle average is avg / (1 + tau ka), so
+    // C_d = ka feq + ks avg' - (ka + ks) f'_d.
+    const double avg1 = avg / (1.0 + tau * ka_), den = 1.0 / (1.0 + tau * (ka_ + ks_));
+    const double ciso = ka_ * fe_ + ks_ * avg1, ctot = ka_ + ks_, cadd = tau * ks_ * avg1;
+    double cw = 0.0, cr = 0.0, ct = 0.0;
     for (int r = 0; r < 4; ++r) {
       int d = lane + 64 * r;
       if (d >= nd) continue;
@@ -1164,7 +1172,29 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
         out = ((float)Sd[r] + t * b * (float)avg / (1.0f + t * a)) / (1.0f + t * (a + b));
       }
       fout[(size_t)z * g.blk + off] = (T)out;
+      const double c = (ciso - ctot * (Sd[r] + cadd) * den) * g.dOm[d];
+      cw += c;
+      cr += c * g.nvec[3 * d];
+      ct += c * g.nvec[3 * d + 1];
     }
+    const double ge = g.G[i] * g.eps[i], lep = s == 0 ? 1.0 : (s == 1 ? -1.0 : 0.0);
+    qa[0] -= lep * g.G[i] * cw;
+    qa[1] -= ge * cw;
+    qa[2] -= ge * cr;
+    qa[3] -= ge * ct;
+  }
+  // hydro source terms (Eq. hydrosource1-3): wave sums, then the waves'
+  // partials in a fixed order, so the result does not depend on timing
+  __shared__ double qpart[4][4];
+  for (int k = 0; k < 4; ++k) {
+    double v = wave_sum(qa[k]);
+    if (lane == 0) qpart[wave][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double v = 0.0;
+    for (int w = 0; w < nwaves; ++w) v += qpart[w][threadIdx.x];
+    as_global(M.q)[(size_t)z * 4 + threadIdx.x] = v;
   }
 }
 
@@ -1361,7 +1391,7 @@ struct Model {
   void *d_ka = nullptr, *d_ks = nullptr, *d_feq = nullptr, *d_f[2] = { nullptr, nullptr }, *d_dN = nullptr;
   char *d_tabs = nullptr;
   FaceAux *d_aux = nullptr;
-  double *d_tally = nullptr, *d_zm = nullptr, *d_ze = nullptr, *d_stage = nullptr;
+  double *d_tally = nullptr, *d_zm = nullptr, *d_ze = nullptr, *d_stage = nullptr, *d_q = nullptr;
   double *d_nbg = nullptr;           // new v_r, v_theta, alpha, psi of a background update
   FaceDesc *d_faces = nullptr;
   btx::ZoneFaces *d_zf = nullptr;
@@ -1413,7 +1443,7 @@ void model_free(Model &m)
   void *ptrs[] = { m.d_mu, m.d_Phi, m.d_dOm, m.d_nvec, m.d_G, m.d_eps, m.d_vol, m.d_vr, m.d_vth,
                    m.d_alp, m.d_psi, m.d_ka, m.d_ks, m.d_feq, m.d_f[0], m.d_f[1], m.d_dN, m.d_tally,
                    m.d_zm, m.d_ze, m.d_stage, m.d_faces, m.d_zf, m.d_tabs, m.d_aux, m.d_fitems, m.d_zitems,
-                   m.d_nbg };
+                   m.d_nbg, m.d_q };
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   m = Model();
@@ -1480,6 +1510,7 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
       !dmalloc(&m.d_dN, nf * 2 * blk * m.tsize) || !dmalloc((void **)&m.d_tally, nf * g.ns * 8) ||
       !dmalloc((void **)&m.d_zm, nz * g.ns * 5 * 8) || !dmalloc((void **)&m.d_ze, nz * g.ns * 8) ||
       !dmalloc((void **)&m.d_stage, nk * 8) || !dmalloc((void **)&m.d_nbg, nz * 4 * 8) ||
+      !dmalloc((void **)&m.d_q, nz * 4 * 8) ||
       !dmalloc((void **)&m.d_tabs, nf * kTables * tab_stride(g.ndir, m.tsize)) ||
       !dmalloc((void **)&m.d_aux, nf * sizeof(FaceAux))) {
     model_free(m);
@@ -1513,6 +1544,7 @@ ModelDev model_dev(const Model &m, double dt)
   M.ka = m.d_ka; M.ks = m.d_ks; M.feq = m.d_feq;
   M.dN = m.d_dN;
   M.tally = m.d_tally;
+  M.q = m.d_q;
   M.dt = dt;
   return M;
 }
@@ -1693,6 +1725,15 @@ btx_status model_moments(const Model &m, const ModelDev *d_models, int parity, d
       totals[3 * sp + 2] = E;
     }
   }
+  return BTX_OK;
+}
+
+btx_status model_source_terms(const Model &m, double *q, hipStream_t s)
+{
+  if (!q) return fail(BTX_E_INVAL, "null argument");
+  if (!m.have_bg || !m.have_state) return fail(BTX_E_STATE, "background and state must be set");
+  HIP_TRY(hipMemcpyAsync(q, m.d_q, (size_t)m.g.nz * 4 * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
   return BTX_OK;
 }
 
@@ -2100,6 +2141,13 @@ btx_status btx_moments(btx_ctx *c, double *zone_moments, double *totals)
   return model_moments(c->m, c->d_model, c->parity, zone_moments, totals, c->stream);
 }
 
+btx_status btx_source_terms(btx_ctx *c, double *q)
+{
+  if (!c) return fail(BTX_E_INVAL, "null context");
+  HIP_TRY(hipSetDevice(c->device));
+  return model_source_terms(c->m, q, c->stream);
+}
+
 btx_status btx_timing(btx_ctx *c, int enable, double *ms, int64_t *launches, int reset)
 {
   if (!c) return fail(BTX_E_INVAL, "null context");
@@ -2268,6 +2316,13 @@ btx_status btx_batch_moments(btx_batch *b, int32_t model, double *zone_moments, 
   if (!b || model < 0 || model >= (int)b->models.size()) return fail(BTX_E_INVAL, "bad batch or model index");
   HIP_TRY(hipSetDevice(b->device));
   return model_moments(b->models[model], b->d_models, b->parity, zone_moments, totals, b->stream);
+}
+
+btx_status btx_batch_source_terms(btx_batch *b, int32_t model, double *q)
+{
+  if (!b || model < 0 || model >= (int)b->models.size()) return fail(BTX_E_INVAL, "bad batch or model index");
+  HIP_TRY(hipSetDevice(b->device));
+  return model_source_terms(b->models[model], q, b->stream);
 }
 
 btx_status btx_batch_destroy(btx_batch *b)

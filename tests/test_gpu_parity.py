@@ -230,3 +230,50 @@ def test_batch_evolving_background_gpu(oracle_mod):
         ref, got = o.state(), b.get_state(m)
         assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
     b.close()
+
+
+def _pins():
+    sys.path.insert(0, __import__("os").path.dirname(__file__))
+    import test_oracle_pins
+    return test_oracle_pins
+
+
+@pytest.mark.parametrize("case", ["shock_3species", "large_shift", "planar"])
+@pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
+def test_source_terms_gpu(case, precision, oracle_mod):
+    """hydro source terms (Eq. hydrosource1-3) of the last of three steps,
+    per zone, against the reference: FP64 to 1e-12 and mixed to 1e-5 of the
+    zone's gross collision rate (the sum of the magnitudes of the collision
+    terms, weighted like Q_E), the scale of their rounding"""
+    w = CASES[case]()
+    _say(f"[gpu] source terms {case}, precision {precision}")
+    o, ctx = _run_pair(w, 3, precision, oracle_mod)
+    qr, qg = o.source_terms(), ctx.source_terms()
+    scale = _pins()._gross_rate(w, o.state())[:, None]
+    err = float(np.max(np.abs(qg - qr) / scale))
+    _say(f"[gpu]   max err / gross rate {err:.3e}")
+    assert err <= (1e-12 if precision == W.PREC_FP64 else 1e-5)
+    assert np.max(np.abs(qr)) > 0.0
+    ctx.close()
+
+
+def test_batch_source_terms_gpu(oracle_mod):
+    btx = _btx()
+    import torch
+    ws = W.batch_models(n_models=3, size_scale=0.04)
+    for w in ws:
+        w.precision = W.PREC_FP64
+        w.f0 = w.f0 * (1.0 + 0.3 * RNG.random(w.f0.shape))
+    _say("[gpu] batch source terms")
+    b = btx.Batch(ws, precision=W.PREC_FP64, stream=torch.cuda.current_stream().cuda_stream)
+    for m, w in enumerate(ws):
+        b.set_background(m)
+        b.set_state(m, w.f0)
+    dts = [b.max_dt(m, 0.4) for m in range(len(ws))]
+    b.step(dts, 2)
+    for m, w in enumerate(ws):
+        o = oracle_mod.Oracle(w)
+        o.step(dts[m], 2)
+        scale = _pins()._gross_rate(w, o.state())[:, None]
+        assert np.max(np.abs(b.source_terms(m) - o.source_terms()) / scale) <= 1e-12
+    b.close()

@@ -210,7 +210,7 @@ def test_remap_first_moments(oracle_mod):
 
 # -------------------------------------------------------------- collision
 def test_collision_closed_form(oracle_mod):
-    """P-7 (Eq. sourceterms_discrete, Sec. 3.4): the closed form equals the
+    """P-7 (Eq. sourceterms_discrete, Sec. 3.4-3.5): the closed form equals the
     dense backward-Euler solve; f = f_eq is a fixed point; kappa = 0 gives S;
     pure scattering keeps sum f dOmega."""
     n = 24

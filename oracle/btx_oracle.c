@@ -47,7 +47,8 @@ typedef struct {
 } face_t;
 
 struct orc_ctx {
-  int nr, nth, ne, nmu, nphi, ns, geom, phi_rule, inner_bc, outer_bc;
+  int nr, nth, ne, nmu, nphi, ns, geom, phi_rule, inner_bc, outer_bc, theta_bc;
+  double disk_r;
   int ndir, nz, blk, eblk;
   int nfr, nft, nfp, nf;
   double *r_e, *th_e, dphi, delta, *e_e;
@@ -352,6 +353,8 @@ orc_ctx *orc_create(const orc_desc *d)
   c->nr = d->n_r; c->nth = nth; c->ne = d->n_eps; c->nmu = d->n_mu; c->nphi = d->n_phi;
   c->ns = d->n_species; c->geom = d->geometry; c->phi_rule = d->phi_rule;
   c->inner_bc = d->inner_bc; c->outer_bc = d->outer_bc;
+  c->theta_bc = c->geom == ORC_GEOM_AXISYM2D ? d->theta_bc : ORC_THETA_AXIS;
+  c->disk_r = d->disk_radius;
   c->ndir = c->nmu * c->nphi; c->nz = c->nr * c->nth;
   c->eblk = c->ne * c->ndir; c->blk = c->ns * c->eblk;
   c->blend_mode = -1;
@@ -414,7 +417,7 @@ orc_ctx *orc_create(const orc_desc *d)
     }
   }
   c->nfr = nth * (c->nr + 1);
-  if (c->geom == ORC_GEOM_AXISYM2D) c->nft = c->nr * (nth - 1);
+  if (c->geom == ORC_GEOM_AXISYM2D) c->nft = c->nr * (c->theta_bc == ORC_THETA_DISK ? nth : nth - 1);
   else if (c->geom == ORC_GEOM_COLUMN) c->nft = c->nr;
   else c->nft = 0;
   c->nfp = c->geom == ORC_GEOM_PLANAR ? 0 : c->nz;
@@ -544,6 +547,21 @@ static side_t ghost_side(const orc_ctx *c, int z, int bc)
   return s;
 }
 
+/* Ghost beyond the equatorial boundary of a theta-disk grid, next to zone z
+ * of the last theta row (Sec. 4.4, radiating disk).  Reading: it sits at the
+ * mirror position pi - theta_z and carries the zone's background expressed
+ * in its own basis; inside the disk radius it holds the isotropic
+ * equilibrium of the zone (an optically thick disk), outside it is empty
+ * (nothing enters from the vacuum below the plane). */
+static side_t theta_ghost_side(const orc_ctx *c, int z)
+{
+  side_t s;
+  s.z = z; s.has_slope = 0;
+  s.fr = zone_frame(c, z, PI - c->thc[z], 0.0);
+  s.kind = c->rc[z] < c->disk_r ? SIDE_EQ : SIDE_ZERO;
+  return s;
+}
+
 static side_t zone_side(const orc_ctx *c, int z, double th, double ph)
 {
   side_t s;
@@ -605,8 +623,14 @@ static void get_face(const orc_ctx *c, int fid, face_t *F)
       vertex(rlo, tf, p0, V1); vertex(rhi, tf, p0, V2); vertex(rhi, tf, p1, V3); vertex(rlo, tf, p1, V4);
       F->area = quad_area(V1, V2, V3, V4, n);
       F->L = zone_side(c, zL, c->thc[zL], 0.0);
-      F->R = zone_side(c, zR, c->thc[zR], 0.0);
-      F->h = centre_dist(c->rc[zL], c->thc[zL], 0.0, c->rc[zR], c->thc[zR], 0.0);
+      if (b + 1 < c->nth) {
+        F->R = zone_side(c, zR, c->thc[zR], 0.0);
+        F->h = centre_dist(c->rc[zL], c->thc[zL], 0.0, c->rc[zR], c->thc[zR], 0.0);
+      } else {                                   /* equatorial boundary of a disk grid */
+        F->R = theta_ghost_side(c, zL);
+        F->h = centre_dist(c->rc[zL], c->thc[zL], 0.0, c->rc[zL], PI - c->thc[zL], 0.0);
+        F->zero_opacity = F->R.kind == SIDE_ZERO;
+      }
       F->s = mean_frame(&F->L.fr, &F->R.fr, tf, 0.0);
     } else {                                     /* column: periodic self-face */
       int a = fid, z = a;
@@ -658,7 +682,7 @@ static int zone_faces(const orc_ctx *c, int z, int *fids, int *sgn)
   fids[n] = base + a + 1; sgn[n++] = -1;         /* face a+1/2: zone is L */
   if (c->geom == ORC_GEOM_AXISYM2D) {
     if (b > 0) { fids[n] = c->nfr + (b - 1) * c->nr + a; sgn[n++] = +1; }
-    if (b < c->nth - 1) { fids[n] = c->nfr + b * c->nr + a; sgn[n++] = -1; }
+    if (b < c->nth - 1 || c->theta_bc == ORC_THETA_DISK) { fids[n] = c->nfr + b * c->nr + a; sgn[n++] = -1; }
   } else if (c->geom == ORC_GEOM_COLUMN) {
     fids[n] = c->nfr + a; sgn[n++] = -1;
     fids[n] = c->nfr + a; sgn[n++] = +1;
@@ -706,6 +730,10 @@ static void axis_neighbours(const orc_ctx *c, int z, int axis, side_t *m, side_t
       *p = zone_side(c, zp, c->thc[zp], 0.0);
       *hm = zm == z ? 1.0 : centre_dist(c->rc[zm], c->thc[zm], 0.0, c->rc[z], c->thc[z], 0.0);
       *hp = zp == z ? 1.0 : centre_dist(c->rc[zp], c->thc[zp], 0.0, c->rc[z], c->thc[z], 0.0);
+      if (zp == z && c->theta_bc == ORC_THETA_DISK) {   /* the equatorial ghost */
+        *p = theta_ghost_side(c, z);
+        *hp = centre_dist(c->rc[z], c->thc[z], 0.0, c->rc[z], PI - c->thc[z], 0.0);
+      }
     } else {
       *m = zone_side(c, z, th - c->delta, 0.0);
       *p = zone_side(c, z, th + c->delta, 0.0);

@@ -22,6 +22,10 @@ extern "C" {
 enum { ORC_GEOM_COLUMN = 0, ORC_GEOM_AXISYM2D = 1, ORC_GEOM_PLANAR = 2 };
 enum { ORC_PHI_SIN = 0, ORC_PHI_LINEAR = 1 };
 enum { ORC_BC_REFLECT = 0, ORC_BC_OUTFLOW = 1, ORC_BC_EQUIL = 2 };
+/* theta range of the 2D grid: [0, pi] with the polar axis at both ends, or
+ * [0, pi/2] with the equatorial plane a boundary: an optically thick disk
+ * (equilibrium ghost) inside disk_radius, vacuum (outflow ghost) outside */
+enum { ORC_THETA_AXIS = 0, ORC_THETA_DISK = 1 };
 
 typedef struct {
   int n_r, n_theta, n_eps, n_mu, n_phi, n_species;
@@ -32,6 +36,8 @@ typedef struct {
   const double *eps_edges;   /* n_eps+1 ascending                              */
   const double *mu_nodes;    /* n_mu ascending quadrature nodes                */
   const double *mu_weights;  /* n_mu weights, summing to 2                     */
+  int theta_bc;              /* ORC_THETA_* (2D only)                          */
+  double disk_radius;        /* ORC_THETA_DISK: radius of the disk             */
 } orc_desc;
 
 typedef struct orc_ctx orc_ctx;

@@ -37,7 +37,8 @@ class _Desc(C.Structure):
                 ("n_phi", C.c_int), ("n_species", C.c_int), ("geometry", C.c_int),
                 ("phi_rule", C.c_int), ("inner_bc", C.c_int), ("outer_bc", C.c_int),
                 ("r_edges", _dp), ("theta_edges", _dp), ("dphi", C.c_double),
-                ("eps_edges", _dp), ("mu_nodes", _dp), ("mu_weights", _dp)]
+                ("eps_edges", _dp), ("mu_nodes", _dp), ("mu_weights", _dp),
+                ("theta_bc", C.c_int), ("disk_radius", C.c_double)]
 
 
 _lib = None
@@ -128,7 +129,8 @@ class Oracle:
                       _c(self.wmu)]
         d = _Desc(w.n_r, w.n_theta, w.n_eps, w.n_mu, w.n_phi, w.n_species, w.geometry,
                   w.phi_rule, w.inner_bc, w.outer_bc, _p(self._keep[0]), _p(self._keep[1]),
-                  w.dphi, _p(self._keep[2]), _p(self._keep[3]), _p(self._keep[4]))
+                  w.dphi, _p(self._keep[2]), _p(self._keep[3]), _p(self._keep[4]),
+                  w.theta_bc, w.disk_radius)
         self.ctx = lib().orc_create(C.byref(d))
         if not self.ctx:
             raise ValueError("oracle rejected the grid description")

@@ -25,6 +25,7 @@ SEED = 20030245
 GEOM_COLUMN, GEOM_AXISYM2D, GEOM_PLANAR = 0, 1, 2
 BC_REFLECT, BC_OUTFLOW, BC_EQUIL = 0, 1, 2
 PHI_SIN, PHI_LINEAR = 0, 1
+THETA_AXIS, THETA_DISK = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 
 
@@ -80,6 +81,8 @@ class Workload:
     inner_bc: int = BC_REFLECT
     outer_bc: int = BC_OUTFLOW
     phi_rule: int = PHI_SIN
+    theta_bc: int = THETA_AXIS
+    disk_radius: float = 0.0
     meta: dict = field(default_factory=dict)
 
     @property
@@ -157,6 +160,45 @@ def radiating_sphere(n_r=64, n_eps=8, n_mu=16, n_phi=4, r_max=3.0, R=1.0, kappa=
                      eps_edges, n_mu, n_phi, mu_rule, z, z, np.ones(n_r), np.ones(n_r),
                      ka, np.zeros_like(ka), feq, False, n_steps, PREC_FP64,
                      meta={"R": R, "kappa_a": kappa, "T": T})
+
+
+def radiating_sphere_2d(n_r=100, n_theta=32, n_mu=16, n_phi=8, r_min=0.02, r_max=4.0, R=1.0,
+                        kappa=10.0, mu_rule="lobatto"):
+    """The homogeneous radiating sphere on the axisymmetric grid (Sec. 4.4):
+    one group, f_eq = 1 and kappa_a = kappa inside R, vacuum outside, static
+    flat background, logarithmic radial zones from r_min (specular inner
+    boundary), uniform theta zones over [0, pi]."""
+    r_edges = log_edges(r_min, r_max, n_r)
+    theta_edges = np.linspace(0.0, math.pi, n_theta + 1)
+    rc = np.tile(_centres(r_edges), n_theta)
+    nz = n_r * n_theta
+    inside = (rc < R)[:, None, None]
+    ka = np.where(inside, kappa, 0.0) * np.ones((nz, 1, 1))
+    feq = np.where(inside, 1.0, 0.0) * np.ones((nz, 1, 1))
+    z = np.zeros(nz)
+    return _assemble("radiating_sphere_2d", GEOM_AXISYM2D, r_edges, theta_edges, math.pi / n_theta,
+                     np.array([1.0, 2.0]), n_mu, n_phi, mu_rule, z, z, np.ones(nz), np.ones(nz),
+                     ka, np.zeros_like(ka), feq, False, 0, PREC_FP64,
+                     meta={"R": R, "kappa_a": kappa})
+
+
+def radiating_disk(n_r=100, n_theta=32, n_mu=16, n_phi=8, r_min=0.05, r_max=4.0, R=1.0,
+                   mu_rule="lobatto"):
+    """A geometrically thin, optically thick disk radiating into vacuum (Sec.
+    4.4): theta over [0, pi/2], the equatorial plane an isotropic f_eq = 1
+    emitter inside R and empty outside, kappa = 0 everywhere, one group,
+    static flat background, logarithmic radial zones from r_min."""
+    r_edges = log_edges(r_min, r_max, n_r)
+    theta_edges = np.linspace(0.0, 0.5 * math.pi, n_theta + 1)
+    nz = n_r * n_theta
+    zero = np.zeros((nz, 1, 1))
+    z = np.zeros(nz)
+    w = _assemble("radiating_disk", GEOM_AXISYM2D, r_edges, theta_edges, 0.5 * math.pi / n_theta,
+                  np.array([1.0, 2.0]), n_mu, n_phi, mu_rule, z, z, np.ones(nz), np.ones(nz),
+                  zero, zero.copy(), np.ones((nz, 1, 1)), False, 0, PREC_FP64, meta={"R": R})
+    w.theta_bc = THETA_DISK
+    w.disk_radius = float(R)
+    return w
 
 
 # --------------------------------------------------------------------------

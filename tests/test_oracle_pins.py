@@ -619,3 +619,57 @@ def test_source_terms_balance_the_step(oracle_mod):
     de = np.sum(t1[:, 2] - t0[:, 2])
     assert abs(de + dt * np.sum(vol * q[:, 1])) <= 1e-12 * np.sum(t0[:, 2])
     assert abs(dn) > 1e-4 * (t0[0, 0] + t0[1, 0]) and abs(de) > 1e-4 * np.sum(t0[:, 2])
+
+
+# ------------------------------------------------------- radiating disk
+def _disk_exact(x, z, R=1.0, n_r=400, n_phi=512):
+    """mean intensity above an isotropic f = 1 disk of radius R (Sec. 4.4):
+    (1/4pi) times the solid angle of the disk seen from (x, z), by Gauss
+    quadrature in r and the periodic midpoint rule in phi"""
+    xr, wr = np.polynomial.legendre.leggauss(n_r)
+    r, wr = 0.5 * R * (xr + 1.0), 0.5 * R * wr
+    phi = (np.arange(n_phi) + 0.5) * 2.0 * np.pi / n_phi
+    rr, pp = np.meshgrid(r, phi, indexing="ij")
+    d = ((x - rr * np.cos(pp)) ** 2 + z * z + (rr * np.sin(pp)) ** 2) ** 1.5
+    return float(np.sum(wr[:, None] * rr * z / d) * (2.0 * np.pi / n_phi) / (4.0 * np.pi))
+
+
+def test_disk_exact_closed_forms():
+    """the quadrature of the disk integral against the on-axis closed form
+    (1 - z / sqrt(z^2 + R^2)) / 2 and the half-sky limit 1/2 just above the
+    disk's centre"""
+    for z in (0.1, 0.5, 2.0):
+        assert abs(_disk_exact(0.0, z) - 0.5 * (1 - z / math.sqrt(z * z + 1))) < 1e-10
+    assert abs(_disk_exact(0.2, 1e-3, n_r=4000, n_phi=4096) - 0.5) < 2e-3
+
+
+def _disk_run(oracle_mod, n_phi):
+    w = W.radiating_disk(n_r=24, n_theta=8, n_mu=8, n_phi=n_phi, r_min=0.2, r_max=2.5)
+    o = oracle_mod.Oracle(w)
+    dt = o.max_dt(0.4)
+    o.step(dt, int(3.0 / dt))
+    zm, tot = o.moments()
+    _, rc, thc = o.geometry()
+    J = zm[:, 0, 1] / (math.sqrt(2.0) * 7.0 / 3.0)          # (1/4pi) sum f dOmega
+    x, z = rc * np.sin(thc), rc * np.cos(thc)
+    row = np.arange(w.n_zones) // w.n_r
+    sel = (z > 0.1) & (row >= 2) & (rc < 2.0)
+    exact = np.array([_disk_exact(a, b) for a, b in zip(x[sel], z[sel])])
+    err = np.abs(J[sel] - exact)
+    return err.max(), err.mean(), tot
+
+
+def test_radiating_disk(oracle_mod):
+    """P-21 (Sec. 4.4, radiating disk): the equatorial disk boundary mode.  A
+    thick f = 1 disk of radius 1 radiates into vacuum; in the stationary state
+    the mean intensity approaches the exact solid-angle integral, away from
+    the polar axis rows (the paper's artefact) and the plane itself.  The
+    error is the ray effect of the discrete directions: it falls when the
+    azimuthal resolution doubles (4 -> 8 Phi cells), and at 8 x 8 directions
+    on this 24 x 8 grid it is below 0.09 at worst and 0.035 on average
+    (measured 0.083 and 0.031)."""
+    e4, m4, _ = _disk_run(oracle_mod, 4)
+    e8, m8, tot = _disk_run(oracle_mod, 8)
+    assert e8 < 0.09 and m8 < 0.035
+    assert e8 < 0.6 * e4 and m8 < 0.8 * m4
+    assert tot[0, 1] < 0.0                               # the disk feeds the grid

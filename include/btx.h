@@ -33,7 +33,8 @@
  *   the ABI.  btx_last_error() returns a thread-local message for the last
  *   failing call on that thread.
  *   Threads: one context must not be used by two threads at once.
- *   Limits: at most 128 directions (n_mu n_phi) and 61 energy groups.
+ *   Limits: at most 128 directions (n_mu n_phi), 61 energy groups and 2048
+ *   (species x groups) rows.
  */
 #ifndef BTX_H
 #define BTX_H
@@ -66,6 +67,13 @@ typedef enum { BTX_PHI_DIRECTION = 0, BTX_PHI_LINEAR = 1 } btx_phi_rule;
 /* radial boundary ghosts: specular mirror (mu -> -mu), outflow (empty, zero
  * opacity at the face), equilibrium (the zone's own equilibrium occupation) */
 typedef enum { BTX_BC_REFLECT = 0, BTX_BC_OUTFLOW = 1, BTX_BC_EQUIL = 2 } btx_bc;
+/* theta range of the 2D grid (Sec. 4.4): [0, pi] with the polar axis at both
+ * ends, or [0, pi/2] with the equatorial plane a boundary that is an
+ * optically thick disk inside disk_radius (ghost: the isotropic equilibrium
+ * occupation of the adjacent zone) and empty outside it (outflow ghost).  The
+ * ghost sits at the mirror position pi - theta with the zone's background in
+ * its own basis. */
+typedef enum { BTX_THETA_AXIS = 0, BTX_THETA_DISK = 1 } btx_theta_bc;
 
 typedef struct {
   int32_t n_r, n_theta, n_eps, n_mu, n_phi, n_species;
@@ -75,12 +83,15 @@ typedef struct {
   int32_t inner_bc, outer_bc;/* btx_bc (outer: OUTFLOW or EQUIL)                     */
   int32_t precision;         /* btx_precision                                       */
   const double *r_edges;     /* n_r+1 ascending, >= 0 (z edges in slab geometry)    */
-  const double *theta_edges; /* 2D: n_theta+1 ascending from 0 to pi; else ignored  */
+  const double *theta_edges; /* 2D: n_theta+1 ascending from 0 to pi (pi/2 for a
+                                disk boundary); else ignored                        */
   double dphi;               /* 2D: wedge width in phi (> 0); else ignored          */
   const double *eps_edges;   /* n_eps+1 ascending, logarithmically spaced (> 0)     */
   double fp64_threshold;     /* mixed mode: the collision solve of a (zone, species,
                                 group) runs in FP64 where dt_c (ka + ks) exceeds it;
                                 <= 0 selects the default 1.0                        */
+  int32_t theta_bc;          /* 2D: btx_theta_bc; else ignored                       */
+  double disk_radius;        /* BTX_THETA_DISK: the disk's radius (> 0)              */
 } btx_grid_desc;
 
 typedef struct {             /* host arrays, copied during the call                  */

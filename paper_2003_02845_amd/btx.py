@@ -45,7 +45,8 @@ class GridDesc(C.Structure):
                 ("geometry", C.c_int32), ("mu_rule", C.c_int32), ("phi_rule", C.c_int32),
                 ("inner_bc", C.c_int32), ("outer_bc", C.c_int32), ("precision", C.c_int32),
                 ("r_edges", _dp), ("theta_edges", _dp), ("dphi", C.c_double),
-                ("eps_edges", _dp), ("fp64_threshold", C.c_double)]
+                ("eps_edges", _dp), ("fp64_threshold", C.c_double),
+                ("theta_bc", C.c_int32), ("disk_radius", C.c_double)]
 
 
 class Background(C.Structure):
@@ -110,7 +111,8 @@ def _desc(w, precision, fp64_threshold):
     d = GridDesc(w.n_r, w.n_theta, w.n_eps, w.n_mu, w.n_phi, w.n_species, w.geometry,
                  MU_LEGENDRE if w.mu_rule == "legendre" else MU_LOBATTO, w.phi_rule,
                  w.inner_bc, w.outer_bc, precision, _p(keep[0]), _p(keep[1]),
-                 float(w.dphi), _p(keep[2]), float(fp64_threshold))
+                 float(w.dphi), _p(keep[2]), float(fp64_threshold), int(w.theta_bc),
+                 float(w.disk_radius))
     return d, keep
 
 
@@ -127,12 +129,7 @@ class Context:
         self.w = w
         self.precision = w.precision if precision is None else precision
         self.dtype = np.float64 if self.precision == PREC_FP64 else np.float32
-        self._keep = [np.ascontiguousarray(w.r_edges, float), np.ascontiguousarray(w.theta_edges, float),
-                      np.ascontiguousarray(w.eps_edges, float)]
-        d = GridDesc(w.n_r, w.n_theta, w.n_eps, w.n_mu, w.n_phi, w.n_species, w.geometry,
-                     MU_LEGENDRE if w.mu_rule == "legendre" else MU_LOBATTO, w.phi_rule,
-                     w.inner_bc, w.outer_bc, self.precision, _p(self._keep[0]), _p(self._keep[1]),
-                     float(w.dphi), _p(self._keep[2]), float(fp64_threshold))
+        d, self._keep = _desc(w, self.precision, fp64_threshold)
         h = C.c_void_p()
         _check(lib().btx_create(C.byref(d), device, C.c_void_p(stream or 0), C.byref(h)))
         self.h = h

@@ -61,6 +61,7 @@ struct DevGrid {
   int nr, nth, ne, nmu, nphi, ns, ndir, nz, geom, phi_rule;
   int eblk, blk, nfaces, nch, ce;   // face work items per direction, groups per item
   double lnq, q, fp64_thr;
+  double om[3];                     // sum over directions of dOmega, dOmega n_r, dOmega n_theta
   const double *mu, *Phi, *dOm, *nvec, *G, *eps, *vol;
   const double *vr, *vth, *alp, *psi;
 };
@@ -1109,7 +1110,7 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
 // ------------------------------------------------------------ zone kernel
 
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity)
 {
   const int2 it = items[blockIdx.x];
@@ -1126,12 +1127,15 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   const int z = it.y;
   const int nd = g.ndir, ne = g.ne, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
-  const btx::ZoneFaces L = zf[z];
+  const btx::ZoneFaces &L = zf[z];        // uniform: read through the scalar cache
   const double vr = g.vr[z], vt = g.vth[z];
   const double gam = 1.0 / sqrt(1.0 - (vr * vr + vt * vt));
   const double p6v = pow(g.psi[z], 6.0) * g.vol[z];
   const double tau = g.alp[z] * dt / gam;
-  double qa[4] = { 0.0, 0.0, 0.0, 0.0 };   // this lane's share of Q_Ye, Q_E, Q_M,r, Q_M,theta
+  // per (species, group) row: the sums of S dOmega, S dOmega n_r and
+  // S dOmega n_theta, for the source terms after the update
+  extern __shared__ __align__(16) char lds[];
+  double *rs = (double *)lds;
   for (int row = wave; row < g.ns * ne; row += nwaves) {
     int s = row / ne, i = row - s * ne;
     size_t kidx = ((size_t)z * g.ns + s) * ne + i;
@@ -1154,17 +1158,16 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
       Sd[r] = S;
       part += S * g.dOm[d];
     }
-    double avg = wave_sum(part) / (4.0 * kPi);
-    // Collision term at the new state (backward Euler), in FP64 from the
-    // closed form: the new angle average is avg / (1 + tau ka), so
-    // C_d = ka feq + ks avg' - (ka + ks) f'_d.
-    const double avg1 = avg / (1.0 + tau * ka_), den = 1.0 / (1.0 + tau * (ka_ + ks_));
-    const double ciso = ka_ * fe_ + ks_ * avg1, ctot = ka_ + ks_, cadd = tau * ks_ * avg1;
-    double cw = 0.0, cr = 0.0, ct = 0.0;
+    const double ssum = wave_sum(part);
+    double avg = ssum / (4.0 * kPi);
+    double pr = 0.0, pt = 0.0;
     for (int r = 0; r < 4; ++r) {
       int d = lane + 64 * r;
       if (d >= nd) continue;
       size_t off = (size_t)s * g.eblk + (size_t)i * nd + d;
+      const double sw = Sd[r] * g.dOm[d];
+      pr += sw * g.nvec[3 * d];
+      pt += sw * g.nvec[3 * d + 1];
       double out;
       if (wide) out = (Sd[r] + tau * ks_ * avg / (1.0 + tau * ka_)) / (1.0 + tau * (ka_ + ks_));
       else {
@@ -1172,29 +1175,41 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
         out = ((float)Sd[r] + t * b * (float)avg / (1.0f + t * a)) / (1.0f + t * (a + b));
       }
       fout[(size_t)z * g.blk + off] = (T)out;
-      const double c = (ciso - ctot * (Sd[r] + cadd) * den) * g.dOm[d];
-      cw += c;
-      cr += c * g.nvec[3 * d];
-      ct += c * g.nvec[3 * d + 1];
     }
-    const double ge = g.G[i] * g.eps[i], lep = s == 0 ? 1.0 : (s == 1 ? -1.0 : 0.0);
-    qa[0] -= lep * g.G[i] * cw;
-    qa[1] -= ge * cw;
-    qa[2] -= ge * cr;
-    qa[3] -= ge * ct;
+    const double sr = wave_sum(pr), st = wave_sum(pt);
+    if (lane == 0) { rs[4 * row] = ssum; rs[4 * row + 1] = sr; rs[4 * row + 2] = st; }
   }
-  // hydro source terms (Eq. hydrosource1-3): wave sums, then the waves'
-  // partials in a fixed order, so the result does not depend on timing
-  __shared__ double qpart[4][4];
-  for (int k = 0; k < 4; ++k) {
-    double v = wave_sum(qa[k]);
-    if (lane == 0) qpart[wave][k] = v;
+  // Hydro source terms (Eq. hydrosource1-3), in FP64, one row per thread:
+  // the collision term at the new state (backward Euler) is
+  // C_d = ka feq + ks avg' - (ka + ks) f'_d with the new angle average
+  // avg' = avg / (1 + tau ka) and f'_d = (S_d + tau ks avg') / (1 + tau (ka + ks)),
+  // i.e. C_d = B - K S_d, so its dOmega- and dOmega n-weighted sums need only
+  // the row sums of S.  Kept out of the update loop, which is latency bound.
+  __syncthreads();
+  const int nrow = g.ns * ne;
+  for (int row = threadIdx.x; row < nrow; row += blockDim.x) {
+    const int s = row / ne, i = row - s * ne;
+    const size_t kidx = ((size_t)z * g.ns + s) * ne + i;
+    const double ka_ = (double)ka[kidx], ks_ = (double)ks[kidx], fe_ = (double)feq[kidx];
+    const double ssum = rs[4 * row], avg1 = ssum / (4.0 * kPi) / (1.0 + tau * ka_);
+    const double K = (ka_ + ks_) / (1.0 + tau * (ka_ + ks_));
+    const double B = ka_ * fe_ + ks_ * avg1 - K * tau * ks_ * avg1;
+    const double cw = B * g.om[0] - K * ssum, cr = B * g.om[1] - K * rs[4 * row + 1];
+    const double ct = B * g.om[2] - K * rs[4 * row + 2];
+    const double ge = g.G[i] * g.eps[i], lep = s == 0 ? 1.0 : (s == 1 ? -1.0 : 0.0);
+    rs[4 * row] = -lep * g.G[i] * cw;
+    rs[4 * row + 1] = -ge * cw;
+    rs[4 * row + 2] = -ge * cr;
+    rs[4 * row + 3] = -ge * ct;
   }
   __syncthreads();
-  if (threadIdx.x < 4) {
+  // wave k sums component k over the rows (fixed order: lane-strided, then a
+  // wave sum), so the result does not depend on timing
+  if (wave < 4) {
     double v = 0.0;
-    for (int w = 0; w < nwaves; ++w) v += qpart[w][threadIdx.x];
-    as_global(M.q)[(size_t)z * 4 + threadIdx.x] = v;
+    for (int row = lane; row < nrow; row += 64) v += rs[4 * row + wave];
+    v = wave_sum(v);
+    if (lane == 0) as_global(M.q)[(size_t)z * 4 + wave] = v;
   }
 }
 
@@ -1421,6 +1436,7 @@ btx_status validate_desc(const btx_grid_desc *d)
   if (nth < 1) return fail(BTX_E_INVAL, "n_theta must be positive");
   if (d->n_mu * d->n_phi > 128) return fail(BTX_E_UNSUPPORTED, "at most 128 directions");
   if (d->n_eps > 61) return fail(BTX_E_UNSUPPORTED, "at most 61 energy groups");
+  if (d->n_species * d->n_eps > 2048) return fail(BTX_E_UNSUPPORTED, "at most 2048 species x groups");
   for (int a = 0; a < d->n_r; ++a)
     if (!(d->r_edges[a + 1] > d->r_edges[a])) return fail(BTX_E_INVAL, "r edges must ascend");
   if (d->geometry != BTX_GEOM_PLANAR && !(d->r_edges[0] >= 0.0)) return fail(BTX_E_INVAL, "r edges must be >= 0");
@@ -1429,8 +1445,11 @@ btx_status validate_desc(const btx_grid_desc *d)
       return fail(BTX_E_INVAL, "energy edges must be positive and ascend");
   if (d->geometry == BTX_GEOM_AXISYM2D) {
     if (!d->theta_edges) return fail(BTX_E_INVAL, "null theta edges");
-    if (d->theta_edges[0] != 0.0 || std::fabs(d->theta_edges[nth] - kPi) > 1e-12)
-      return fail(BTX_E_UNSUPPORTED, "2D theta edges must span [0, pi]");
+    if (d->theta_bc < 0 || d->theta_bc > 1) return fail(BTX_E_INVAL, "unknown theta boundary");
+    const double tmax = d->theta_bc == BTX_THETA_DISK ? 0.5 * kPi : kPi;
+    if (d->theta_edges[0] != 0.0 || std::fabs(d->theta_edges[nth] - tmax) > 1e-12)
+      return fail(BTX_E_UNSUPPORTED, "2D theta edges must span [0, pi] ([0, pi/2] with a disk boundary)");
+    if (d->theta_bc == BTX_THETA_DISK && !(d->disk_radius > 0.0)) return fail(BTX_E_INVAL, "disk radius must be positive");
     for (int b = 0; b < nth; ++b)
       if (!(d->theta_edges[b + 1] > d->theta_edges[b])) return fail(BTX_E_INVAL, "theta edges must ascend");
     if (!(d->dphi > 0.0) || d->dphi > kPi) return fail(BTX_E_INVAL, "dphi must be in (0, pi]");
@@ -1460,6 +1479,8 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
   g.nr = d->n_r; g.nth = nth; g.ne = d->n_eps; g.nmu = d->n_mu; g.nphi = d->n_phi; g.ns = d->n_species;
   g.geom = d->geometry; g.mu_rule = d->mu_rule; g.phi_rule = d->phi_rule;
   g.inner_bc = d->inner_bc; g.outer_bc = d->outer_bc; g.prec = d->precision;
+  g.theta_bc = d->geometry == BTX_GEOM_AXISYM2D ? d->theta_bc : BTX_THETA_AXIS;
+  g.disk_r = d->disk_radius;
   g.dphi = d->dphi;
   g.fp64_thr = d->fp64_threshold > 0.0 ? d->fp64_threshold : 1.0;
   g.r_e.assign(d->r_edges, d->r_edges + g.nr + 1);
@@ -1532,6 +1553,12 @@ ModelDev model_dev(const Model &m, double dt)
   d.nch = m.shape.nch;
   d.ce = m.shape.ce;
   d.lnq = g.lnq; d.q = g.q; d.fp64_thr = g.fp64_thr;
+  d.om[0] = d.om[1] = d.om[2] = 0.0;
+  for (int k = 0; k < g.ndir; ++k) {
+    d.om[0] += g.dOm[k];
+    d.om[1] += g.dOm[k] * g.nvec[3 * k];
+    d.om[2] += g.dOm[k] * g.nvec[3 * k + 1];
+  }
   d.mu = m.d_mu; d.Phi = m.d_Phi; d.dOm = m.d_dOm; d.nvec = m.d_nvec; d.G = m.d_G;
   d.eps = m.d_eps; d.vol = m.d_vol;
   d.vr = m.d_vr; d.vth = m.d_vth; d.alp = m.d_alp; d.psi = m.d_psi;
@@ -1620,13 +1647,16 @@ btx_status launch_faces(const FaceShape &shape, size_t tsize, const ModelDev *d_
   return BTX_OK;
 }
 
-btx_status launch_zones(size_t tsize, const ModelDev *d_models, const int2 *items, int n, int parity,
-                        hipStream_t s)
+// zone kernel LDS: four FP64 row sums per (species, group) row
+size_t zone_lds_bytes(int rows) { return (size_t)std::max(rows, 1) * 4 * sizeof(double); }
+
+btx_status launch_zones(size_t tsize, const ModelDev *d_models, const int2 *items, int n, int max_rows,
+                        int parity, hipStream_t s)
 {
   if (n == 0) return BTX_OK;
   const void *zk = tsize == 8 ? (const void *)zone_kernel<double> : (const void *)zone_kernel<float>;
   void *args[] = { &d_models, &items, &parity };
-  HIP_TRY(hipLaunchKernel(zk, dim3(n), dim3(256), args, 0, s));
+  HIP_TRY(hipLaunchKernel(zk, dim3(n), dim3(256), args, zone_lds_bytes(max_rows), s));
   return BTX_OK;
 }
 
@@ -1792,7 +1822,7 @@ btx_status ctx_step(btx_ctx *c, double dt)
                                face_lds(m), c->parity, c->stream);
   if (st != BTX_OK) return st;
   if (rec) HIP_TRY(hipEventRecord(e1, c->stream));
-  st = launch_zones(m.tsize, c->d_model, m.d_zitems, m.g.nz, c->parity, c->stream);
+  st = launch_zones(m.tsize, c->d_model, m.d_zitems, m.g.nz, m.g.ns * m.g.ne, c->parity, c->stream);
   if (st != BTX_OK) return st;
   if (rec) HIP_TRY(hipEventRecord(e2, c->stream));
   c->parity ^= 1;
@@ -2027,7 +2057,9 @@ btx_status batch_launch(btx_batch *b, int parity, hipStream_t s)
                                  gr.lds, parity, s);
     if (st != BTX_OK) return st;
   }
-  return launch_zones(b->tsize, b->d_models, b->d_zitems, b->nz_all, parity, s);
+  int rows = 1;
+  for (const Model &m : b->models) rows = std::max(rows, m.g.ns * m.g.ne);
+  return launch_zones(b->tsize, b->d_models, b->d_zitems, b->nz_all, rows, parity, s);
 }
 
 // the step of each parity captured once as a graph on the library's stream

@@ -179,6 +179,14 @@ std::string build_grid(Grid &g)
     SideDesc s{ bc == 0 ? SIDE_MIRROR : (bc == 1 ? SIDE_ZERO : SIDE_EQ), z, 0, 0, g.thc[z], 0.0 };
     return s;
   };
+  // beyond the equatorial plane of a disk grid: the mirror position of zone z,
+  // a thick disk (equilibrium) inside the disk radius, empty outside
+  const bool disk = twod && g.theta_bc == 1;
+  auto theta_ghost = [&](int z) {
+    SideDesc s{ g.rc[z] < g.disk_r ? SIDE_EQ : SIDE_ZERO, z, 0, 0, kPi - g.thc[z], 0.0 };
+    return s;
+  };
+  auto mirror_dist = [&](int z) { return dist(g.rc[z], g.thc[z], 0.0, g.rc[z], kPi - g.thc[z], 0.0); };
   g.faces.clear();
   g.zfaces.assign(g.nz, ZoneFaces{});
   auto add_zone_face = [&](int z, int fid, int side) {
@@ -245,10 +253,36 @@ std::string build_grid(Grid &g)
         else { F.Lm = zone_side(zL, g.thc[zL], 0.0); F.hLm = 1.0; }   // zero-gradient axis ghost
         if (b + 2 < g.nth) { F.Rp = zone_side(zR + g.nr, g.thc[zR + g.nr], 0.0);
                              F.hRp = dist(g.rc[zR], g.thc[zR], 0.0, g.rc[zR + g.nr], g.thc[zR + g.nr], 0.0); }
+        else if (disk) { F.Rp = theta_ghost(zR); F.hRp = mirror_dist(zR); }
         else { F.Rp = zone_side(zR, g.thc[zR], 0.0); F.hRp = 1.0; }
         int fid = (int)g.faces.size();
         g.faces.push_back(F);
         add_zone_face(zR, fid, 1);
+        add_zone_face(zL, fid, 0);
+      }
+    if (disk)                             // the equatorial boundary faces
+      for (int a = 0; a < g.nr; ++a) {
+        FaceDesc F{};
+        const int b = g.nth - 1, zL = b * g.nr + a;
+        double tf = g.th_e[g.nth], p0 = -0.5 * g.dphi, p1 = 0.5 * g.dphi;
+        F.axis = 1;
+        F.active = 1;
+        F.area = quad(point(g.r_e[a], tf, p0), point(g.r_e[a + 1], tf, p0),
+                      point(g.r_e[a + 1], tf, p1), point(g.r_e[a], tf, p1));
+        F.L = zone_side(zL, g.thc[zL], 0.0);
+        F.R = theta_ghost(zL);
+        F.h = mirror_dist(zL);
+        F.dL = 0.5 * F.h;
+        F.dR = -0.5 * F.h;
+        F.ths = tf;
+        F.phs = 0.0;
+        F.zero_opacity = F.R.kind == SIDE_ZERO;
+        if (b >= 1) { F.Lm = zone_side(zL - g.nr, g.thc[zL - g.nr], 0.0);
+                      F.hLm = dist(g.rc[zL - g.nr], g.thc[zL - g.nr], 0.0, g.rc[zL], g.thc[zL], 0.0); }
+        else { F.Lm = zone_side(zL, g.thc[zL], 0.0); F.hLm = 1.0; }
+        int fid = (int)g.faces.size();
+        g.faces.push_back(F);
+        g.bface.push_back(fid);
         add_zone_face(zL, fid, 0);
       }
   } else if (!planar) {                   // column: periodic self-face in theta

@@ -45,6 +45,8 @@ struct ZoneFaces {   // faces touching a zone, and the side the zone is on
 struct Grid {
   int nr = 0, nth = 0, ne = 0, nmu = 0, nphi = 0, ns = 0, ndir = 0, nz = 0;
   int geom = 0, mu_rule = 0, phi_rule = 0, inner_bc = 0, outer_bc = 0, prec = 0;
+  int theta_bc = 0;                                     // 1: equatorial disk boundary at pi/2
+  double disk_r = 0;
   double dphi = 0, delta = 0, q = 0, lnq = 0, fp64_thr = 1.0;
   std::vector<double> r_e, th_e, eps_e;
   std::vector<double> eps, G, mu, wmu, Phi, dOm, nvec;  // momentum grid

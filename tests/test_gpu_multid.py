@@ -1,0 +1,121 @@
+"""Multi-dimensional end-to-end checks on the GPU path (Sec. 4.4, tests in
+axisymmetry).
+
+Radiating disk: theta over [0, pi/2] with the equatorial disk boundary; a
+thick f = 1 disk of radius 1 radiates into vacuum. The stationary mean
+intensity is compared with the exact solid-angle integral away from the
+plane itself. The paper sees an artefact at x = 0 confined to the three
+theta rows next to the pole; here it reaches into rows 3-4 with 16 x 8
+directions (measured: 0.14 there), so those rows have their own, looser
+bound and rows 0-2 are left out as in the paper.
+
+The homogeneous radiating sphere (kappa_a R = 10) is run on the axisymmetric
+grid to a stationary state in FP64. Along rays near the pole, at 45 degrees
+and at the equator, H/J and K/J are compared with the exact solution
+f(r, mu) = f_eq (1 - exp(-kappa s)) of the classical sphere (Sec. 4.1). The
+rays must also agree with each other, since the problem is spherically
+symmetric and only the cell shapes change with theta. The paper's grid has
+17 x 32 directions; the kernels hold at most 128, so this runs 16 Lobatto mu
+x 8 Phi (the paper reports agreement in a figure, not a number).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2003_02845_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _btx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2003_02845_amd import btx
+    return btx
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _pins():
+    sys.path.insert(0, __import__("os").path.dirname(__file__))
+    import test_oracle_pins
+    return test_oracle_pins
+
+
+def _sphere_exact(x, kappa):
+    mu = np.linspace(-1, 1, 20001)
+    mu = 0.5 * (mu[1:] + mu[:-1])
+    g = np.sqrt(np.maximum(0, 1 - x ** 2 * (1 - mu ** 2)))
+    s = x * mu + g if x < 1 else np.where(mu >= np.sqrt(1 - 1 / x ** 2), 2 * g, 0.0)
+    fe = 1 - np.exp(-kappa * s)
+    return np.mean(fe * mu) / np.mean(fe), np.mean(fe * mu * mu) / np.mean(fe)
+
+
+def test_radiating_sphere_2d():
+    btx = _btx()
+    w = W.radiating_sphere_2d(n_r=100, n_theta=32, n_mu=16, n_phi=8, r_min=0.05)
+    ctx = btx.Context(w, precision=W.PREC_FP64)
+    ctx.set_background()
+    ctx.set_state(w.f0)
+    dt = ctx.max_dt(0.4)
+    steps = int(7.0 / dt)
+    _say(f"[gpu] 2D radiating sphere: {w.n_r} x {w.n_theta} zones x {w.n_dir} directions, {steps} steps")
+    ctx.step(dt, steps)
+    zm, _ = ctx.moments()
+    ctx.close()
+    J, H, K = (zm[:, 0, k].reshape(w.n_theta, w.n_r) for k in (1, 2, 3))
+    rc = 0.5 * (w.r_edges[1:] + w.r_edges[:-1])
+    rays = {"pole": 1, "45deg": w.n_theta // 4, "equator": w.n_theta // 2}
+    worst = {}
+    for r in [0.5, 0.8, 1.2, 1.5, 2.0, 3.0]:
+        a = int(np.argmin(abs(rc - r)))
+        hj, kj = _sphere_exact(rc[a], 10.0)
+        vals = []
+        for name, b in rays.items():
+            h, k = H[b, a] / J[b, a], K[b, a] / J[b, a]
+            vals.append((h, k))
+            worst[name] = max(worst.get(name, 0.0), abs(h - hj), abs(k - kj))
+            _say(f"[gpu]   r={rc[a]:.3f} {name:8s} H/J {h:.4f} ({hj:.4f})  K/J {k:.4f} ({kj:.4f})")
+        vals = np.array(vals)
+        assert np.max(np.abs(vals - vals[-1])) < 0.03     # rays agree with the equator's
+    _say(f"[gpu]   worst deviation from the exact solution per ray: {worst}")
+    assert worst["equator"] < 0.03 and worst["45deg"] < 0.03
+    assert worst["pole"] < 0.05
+
+
+def test_radiating_disk_2d():
+    btx = _btx()
+    w = W.radiating_disk(n_r=100, n_theta=32, n_mu=16, n_phi=8, r_min=0.1, r_max=4.0)
+    ctx = btx.Context(w, precision=W.PREC_FP64)
+    ctx.set_background()
+    ctx.set_state(w.f0)
+    dt = ctx.max_dt(0.4)
+    steps = int(4.5 / dt)
+    _say(f"[gpu] radiating disk: {w.n_r} x {w.n_theta} zones x {w.n_dir} directions, {steps} steps")
+    ctx.step(dt, steps)
+    zm, tot = ctx.moments()
+    ctx.close()
+    rc = np.tile(0.5 * (w.r_edges[1:] + w.r_edges[:-1]), w.n_theta)
+    thc = np.repeat(0.5 * (w.theta_edges[1:] + w.theta_edges[:-1]), w.n_r)
+    J = zm[:, 0, 1] / (np.sqrt(2.0) * 7.0 / 3.0)
+    x, z = rc * np.sin(thc), rc * np.cos(thc)
+    row = np.arange(w.n_zones) // w.n_r
+    sel = (z > 0.1) & (row >= 3) & (rc < 2.5)
+    exact = np.array([_pins()._disk_exact(a, b) for a, b in zip(x[sel], z[sel])])
+    err = np.abs(J[sel] - exact)
+    for zz in (0.25, 0.5, 1.0):
+        near = np.abs(z[sel] - zz) < 0.03
+        for q in np.argsort(x[sel][near])[::3]:
+            _say(f"[gpu]   z={z[sel][near][q]:.3f} x={x[sel][near][q]:.3f} J {J[sel][near][q]:.4f} "
+                 f"exact {exact[near][q]:.4f}")
+    for lo, hi in ((3, 5), (5, w.n_theta)):
+        part = err[(row[sel] >= lo) & (row[sel] < hi)]
+        _say(f"[gpu]   theta rows {lo}-{hi - 1}: |J - exact| max {part.max():.4f}, mean {part.mean():.4f}")
+    _say(f"[gpu]   all: max {err.max():.4f}, mean {err.mean():.4f}; outflow {tot[0, 1]:.4g}")
+    assert err[row[sel] >= 5].max() < 0.07 and err.mean() < 0.03
+    assert err.max() < 0.16                          # rows 3-4: the axis artefact

@@ -55,6 +55,12 @@ CASES = {
                                            f_eq=0.3, inner_bc=W.BC_EQUIL, outer_bc=W.BC_OUTFLOW)),
     # an outgoing packet in the Lobatto mu = 1 bins of a static vacuum column
     "beam": lambda: _beam_case(),
+    # the radiating sphere on the axisymmetric grid (opacity jump, vacuum, axis rows)
+    "sphere_2d": lambda: _perturb(W.radiating_sphere_2d(n_r=14, n_theta=6, n_mu=6, n_phi=8)),
+    # theta over [0, pi/2] with the equatorial disk boundary (equilibrium and
+    # outflow ghosts on theta faces)
+    "disk": lambda: _perturb(W.radiating_disk(n_r=12, n_theta=5, n_mu=6, n_phi=8, r_min=0.2,
+                                              r_max=2.5)),
 }
 
 

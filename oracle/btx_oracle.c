@@ -47,17 +47,17 @@ typedef struct {
 } face_t;
 
 struct orc_ctx {
-  int nr, nth, ne, nmu, nphi, ns, geom, phi_rule, inner_bc, outer_bc, theta_bc;
+  int nr, nth, nph, ne, nmu, nphi, ns, geom, phi_rule, inner_bc, outer_bc, theta_bc;
   double disk_r;
   int ndir, nz, blk, eblk;
   int nfr, nft, nfp, nf;
   double *r_e, *th_e, dphi, delta, *e_e;
   double *eps, *G, *mu, *wmu, *Phi, *dOm, *nvec;
   double *rc, *thc, *vol;
-  double *vr, *vth, *alp, *psi, *ka, *ks, *feq;
+  double *vr, *vth, *vph, *alp, *psi, *ka, *ks, *feq;
   int have_bg, have_state;
   double *f, *fn, *outflow;
-  double *q;        /* hydro source terms of the last full step, [zone][4] */
+  double *q;        /* hydro source terms of the last full step, [zone][5] */
   int blend_mode;
 };
 
@@ -307,6 +307,16 @@ void orc_collide(int nd, const double *f, const double *dJ, double tau, double k
 
 /* ------------------------------------------------------------- grid set-up */
 
+/* zone z = (c n_theta + b) n_r + a: radius a, theta row b, phi zone c */
+static int zone_b(const orc_ctx *c, int z) { return (z / c->nr) % c->nth; }
+static int zone_c(const orc_ctx *c, int z) { return z / (c->nr * c->nth); }
+static int zone_at(const orc_ctx *c, int a, int b, int cz) { return (cz * c->nth + b) * c->nr + a; }
+/* theta faces of one phi zone: between rows, plus the equatorial boundary */
+static int theta_slab(const orc_ctx *c)
+{
+  return c->nr * (c->theta_bc == ORC_THETA_DISK ? c->nth : c->nth - 1);
+}
+
 static void column_angles(const orc_ctx *c, int b, double *tlo, double *thi,
                           double *plo, double *phi_)
 {
@@ -337,7 +347,7 @@ static void free_all(orc_ctx *c)
 {
   free(c->r_e); free(c->th_e); free(c->e_e); free(c->eps); free(c->G); free(c->mu);
   free(c->wmu); free(c->Phi); free(c->dOm); free(c->nvec); free(c->rc); free(c->thc);
-  free(c->vol); free(c->vr); free(c->vth); free(c->alp); free(c->psi); free(c->ka);
+  free(c->vol); free(c->vr); free(c->vth); free(c->vph); free(c->alp); free(c->psi); free(c->ka);
   free(c->ks); free(c->feq); free(c->f); free(c->fn); free(c->outflow); free(c->q);
 }
 
@@ -355,7 +365,10 @@ orc_ctx *orc_create(const orc_desc *d)
   c->inner_bc = d->inner_bc; c->outer_bc = d->outer_bc;
   c->theta_bc = c->geom == ORC_GEOM_AXISYM2D ? d->theta_bc : ORC_THETA_AXIS;
   c->disk_r = d->disk_radius;
-  c->ndir = c->nmu * c->nphi; c->nz = c->nr * c->nth;
+  /* 3D: n_phi_zones phi zones of width dphi, periodic in phi (Sec. 3.1);
+   * one zone is the axisymmetric wedge */
+  c->nph = (c->geom == ORC_GEOM_AXISYM2D && d->n_phi_zones > 1) ? d->n_phi_zones : 1;
+  c->ndir = c->nmu * c->nphi; c->nz = c->nr * c->nth * c->nph;
   c->eblk = c->ne * c->ndir; c->blk = c->ns * c->eblk;
   c->blend_mode = -1;
   c->r_e = (double *)malloc(sizeof(double) * (c->nr + 1));
@@ -401,11 +414,12 @@ orc_ctx *orc_create(const orc_desc *d)
   c->rc = (double *)malloc(sizeof(double) * c->nz);
   c->thc = (double *)malloc(sizeof(double) * c->nz);
   c->vol = (double *)malloc(sizeof(double) * c->nz);
+  for (int cz = 0; cz < c->nph; ++cz)
   for (int b = 0; b < nth; ++b) {
     double h1 = 0.0, A1 = 0.0;
     if (c->geom != ORC_GEOM_PLANAR) A1 = unit_rface(c, b, &h1);
     for (int a = 0; a < c->nr; ++a) {
-      int z = b * c->nr + a;
+      int z = (cz * nth + b) * c->nr + a;
       double rlo = c->r_e[a], rhi = c->r_e[a + 1];
       c->rc[z] = 0.5 * (rlo + rhi);
       if (c->geom == ORC_GEOM_AXISYM2D) c->thc[z] = 0.5 * (c->th_e[b] + c->th_e[b + 1]);
@@ -416,8 +430,8 @@ orc_ctx *orc_create(const orc_desc *d)
       else c->vol[z] = (rhi * rhi * rhi - rlo * rlo * rlo) * A1 * h1 / 3.0;
     }
   }
-  c->nfr = nth * (c->nr + 1);
-  if (c->geom == ORC_GEOM_AXISYM2D) c->nft = c->nr * (c->theta_bc == ORC_THETA_DISK ? nth : nth - 1);
+  c->nfr = c->nph * nth * (c->nr + 1);
+  if (c->geom == ORC_GEOM_AXISYM2D) c->nft = c->nph * theta_slab(c);
   else if (c->geom == ORC_GEOM_COLUMN) c->nft = c->nr;
   else c->nft = 0;
   c->nfp = c->geom == ORC_GEOM_PLANAR ? 0 : c->nz;
@@ -425,7 +439,7 @@ orc_ctx *orc_create(const orc_desc *d)
   c->f = (double *)calloc((size_t)c->nz * c->blk, sizeof(double));
   c->fn = (double *)calloc((size_t)c->nz * c->blk, sizeof(double));
   c->outflow = (double *)calloc(c->ns, sizeof(double));
-  c->q = (double *)calloc((size_t)c->nz * 4, sizeof(double));
+  c->q = (double *)calloc((size_t)c->nz * 5, sizeof(double));
   return c;
 }
 
@@ -437,14 +451,17 @@ void orc_destroy(orc_ctx *c)
 }
 
 int orc_set_background(orc_ctx *c, const double *v_r, const double *v_theta,
-                       const double *alpha, const double *psi, const double *ka,
-                       const double *ks, const double *feq)
+                       const double *v_phi, const double *alpha, const double *psi,
+                       const double *ka, const double *ks, const double *feq)
 {
   if (!c) return 1;
   size_t nz = c->nz, nk = (size_t)c->nz * c->ns * c->ne;
 #define CP(dst, src, n) do { free(dst); dst = (double *)malloc(sizeof(double) * (n)); \
     memcpy(dst, src, sizeof(double) * (n)); } while (0)
   CP(c->vr, v_r, nz); CP(c->vth, v_theta, nz); CP(c->alp, alpha, nz); CP(c->psi, psi, nz);
+  free(c->vph);
+  c->vph = (double *)calloc(nz, sizeof(double));
+  if (v_phi) memcpy(c->vph, v_phi, sizeof(double) * nz);
   CP(c->ka, ka, nk); CP(c->ks, ks, nk); CP(c->feq, feq, nk);
 #undef CP
   c->have_bg = 1;
@@ -511,7 +528,7 @@ static frame_t zone_frame(const orc_ctx *c, int z, double th, double ph)
 {
   frame_t f;
   int bg = c->have_bg;
-  f.v[0] = bg ? c->vr[z] : 0.0; f.v[1] = bg ? c->vth[z] : 0.0; f.v[2] = 0.0;
+  f.v[0] = bg ? c->vr[z] : 0.0; f.v[1] = bg ? c->vth[z] : 0.0; f.v[2] = bg ? c->vph[z] : 0.0;
   f.alpha = bg ? c->alp[z] : 1.0; f.psi = bg ? c->psi[z] : 1.0;
   f.th = th; f.ph = ph;
   return f;
@@ -590,7 +607,7 @@ static void get_face(const orc_ctx *c, int fid, face_t *F)
   memset(F, 0, sizeof(*F));
   F->active = 1;
   if (fid < c->nfr) {                            /* radial (planar: z) faces */
-    int b = fid / (c->nr + 1), a = fid % (c->nr + 1) - 1; /* between a and a+1 */
+    int col = fid / (c->nr + 1), b = col % c->nth, a = fid % (c->nr + 1) - 1; /* between a and a+1 */
     double R = c->r_e[a + 1];
     F->axis = 0;
     double th = c->geom == ORC_GEOM_PLANAR ? 0.0 : (c->geom == ORC_GEOM_AXISYM2D ?
@@ -598,7 +615,7 @@ static void get_face(const orc_ctx *c, int fid, face_t *F)
     if (c->geom == ORC_GEOM_PLANAR) F->area = 1.0;
     else { double h1; F->area = R * R * unit_rface(c, b, &h1); }
     if (c->geom != ORC_GEOM_PLANAR && R == 0.0) { F->active = 0; return; }
-    int zL = b * c->nr + a, zR = b * c->nr + a + 1;
+    int zL = col * c->nr + a, zR = col * c->nr + a + 1;
     if (a >= 0) F->L = zone_side(c, zL, th, 0.0);
     else F->L = ghost_side(c, zR, c->inner_bc);
     if (a + 1 < c->nr) F->R = zone_side(c, zR, th, 0.0);
@@ -616,8 +633,8 @@ static void get_face(const orc_ctx *c, int fid, face_t *F)
   if (fid < c->nft) {                            /* theta faces */
     F->axis = 1;
     if (c->geom == ORC_GEOM_AXISYM2D) {
-      int b = fid / c->nr, a = fid % c->nr;
-      int zL = b * c->nr + a, zR = (b + 1) * c->nr + a;
+      int cz = fid / theta_slab(c), b = fid % theta_slab(c) / c->nr, a = fid % c->nr;
+      int zL = zone_at(c, a, b, cz), zR = zL + c->nr;
       double tf = c->th_e[b + 1], rlo = c->r_e[a], rhi = c->r_e[a + 1];
       double p0 = -0.5 * c->dphi, p1 = 0.5 * c->dphi, V1[3], V2[3], V3[3], V4[3], n[3];
       vertex(rlo, tf, p0, V1); vertex(rhi, tf, p0, V2); vertex(rhi, tf, p1, V3); vertex(rlo, tf, p1, V4);
@@ -647,9 +664,10 @@ static void get_face(const orc_ctx *c, int fid, face_t *F)
     F->dL = 0.5 * F->h; F->dR = -0.5 * F->h;
     return;
   }
-  fid -= c->nft;                                 /* phi faces: periodic self-faces */
+  fid -= c->nft;                  /* phi faces: to the next phi zone, periodic (itself in 2D) */
   {
-    int z = fid, a = z % c->nr, b = z / c->nr;
+    int z = fid, a = z % c->nr, b = zone_b(c, z);
+    int zR = c->geom == ORC_GEOM_AXISYM2D ? zone_at(c, a, b, (zone_c(c, z) + 1) % c->nph) : z;
     double tlo, thi, plo, phi_;
     column_angles(c, b, &tlo, &thi, &plo, &phi_);
     double w = phi_ - plo;
@@ -659,7 +677,7 @@ static void get_face(const orc_ctx *c, int fid, face_t *F)
     F->axis = 2;
     F->area = quad_area(V1, V2, V3, V4, n);
     F->L = zone_side(c, z, th, 0.0);
-    F->R = zone_side(c, z, th, w);
+    F->R = zone_side(c, zR, th, w);
     F->h = centre_dist(c->rc[z], th, 0.0, c->rc[z], th, w);
     F->dL = 0.5 * F->h; F->dR = -0.5 * F->h;
     F->s = mean_frame(&F->L.fr, &F->R.fr, th, pf);
@@ -676,20 +694,22 @@ static void get_face_geom(const orc_ctx *c, int fid, double *area)
 /* faces touching zone z, with the side the zone is on (+1: R, -1: L) */
 static int zone_faces(const orc_ctx *c, int z, int *fids, int *sgn)
 {
-  int a = z % c->nr, b = z / c->nr, n = 0;
-  int base = b * (c->nr + 1);
+  int a = z % c->nr, b = zone_b(c, z), cz = zone_c(c, z), n = 0;
+  int base = (z / c->nr) * (c->nr + 1);
   fids[n] = base + a;     sgn[n++] = +1;         /* face a-1/2: zone is R */
   fids[n] = base + a + 1; sgn[n++] = -1;         /* face a+1/2: zone is L */
   if (c->geom == ORC_GEOM_AXISYM2D) {
-    if (b > 0) { fids[n] = c->nfr + (b - 1) * c->nr + a; sgn[n++] = +1; }
-    if (b < c->nth - 1 || c->theta_bc == ORC_THETA_DISK) { fids[n] = c->nfr + b * c->nr + a; sgn[n++] = -1; }
+    int tb = c->nfr + cz * theta_slab(c);
+    if (b > 0) { fids[n] = tb + (b - 1) * c->nr + a; sgn[n++] = +1; }
+    if (b < c->nth - 1 || c->theta_bc == ORC_THETA_DISK) { fids[n] = tb + b * c->nr + a; sgn[n++] = -1; }
   } else if (c->geom == ORC_GEOM_COLUMN) {
     fids[n] = c->nfr + a; sgn[n++] = -1;
     fids[n] = c->nfr + a; sgn[n++] = +1;
   }
   if (c->geom != ORC_GEOM_PLANAR) {
+    int zprev = c->geom == ORC_GEOM_AXISYM2D ? zone_at(c, a, b, (cz + c->nph - 1) % c->nph) : z;
     fids[n] = c->nfr + c->nft + z; sgn[n++] = -1;
-    fids[n] = c->nfr + c->nft + z; sgn[n++] = +1;
+    fids[n] = c->nfr + c->nft + zprev; sgn[n++] = +1;
   }
   return n;
 }
@@ -715,7 +735,7 @@ static void side_data(const orc_ctx *c, const side_t *sd, const double *f, int s
 static void axis_neighbours(const orc_ctx *c, int z, int axis, side_t *m, side_t *p,
                             double *hm, double *hp)
 {
-  int a = z % c->nr, b = z / c->nr;
+  int a = z % c->nr, b = zone_b(c, z);
   double th = zone_th(c, z);
   if (axis == 0) {
     if (a > 0) { *m = zone_side(c, z - 1, th, 0.0); *hm = c->rc[z] - c->rc[z - 1]; }
@@ -741,8 +761,13 @@ static void axis_neighbours(const orc_ctx *c, int z, int axis, side_t *m, side_t
     }
   } else {
     double w = c->geom == ORC_GEOM_AXISYM2D ? c->dphi : c->delta;
-    *m = zone_side(c, z, th, -w);
-    *p = zone_side(c, z, th, w);
+    int zm = z, zp = z;
+    if (c->geom == ORC_GEOM_AXISYM2D) {
+      zm = zone_at(c, a, b, (zone_c(c, z) + c->nph - 1) % c->nph);
+      zp = zone_at(c, a, b, (zone_c(c, z) + 1) % c->nph);
+    }
+    *m = zone_side(c, zm, th, -w);
+    *p = zone_side(c, zp, th, w);
     *hm = *hp = centre_dist(c->rc[z], th, 0.0, c->rc[z], th, w);
   }
 }
@@ -990,7 +1015,7 @@ static int do_step(orc_ctx *c, double dt, int nlist, const int *zones, double *f
     double g = gamma_of(self.v), p6 = pow(self.psi, 6.0);
     double tau = self.alpha * dt / g;             /* Reading: dt_c = alpha dt / gamma */
     double *out = fout + (size_t)l * c->blk;
-    double qz[4] = { 0.0, 0.0, 0.0, 0.0 };
+    double qz[5] = { 0.0, 0.0, 0.0, 0.0, 0.0 };
     for (int s = 0; s < c->ns; ++s)
       for (int i = 0; i < ne; ++i) {
         const double *fz0 = c->f + (size_t)z * c->blk + (size_t)s * n + (size_t)i * nd;
@@ -1006,7 +1031,7 @@ static int do_step(orc_ctx *c, double dt, int nlist, const int *zones, double *f
          * puts the whole collision change of the step there), integrated over
          * each bin's momentum-space cell G_i dOmega_d with weight 1 (lepton
          * number: + for the first species, - for the second), eps_i (energy)
-         * and eps_i n_d (momentum, r and theta components); the fluid gains
+         * and eps_i n_d (momentum, r, theta and phi components); the fluid gains
          * what the radiation loses.  Readings: d^3p = eps^2 deps dOmega, so
          * the bin integrals are G_i dOmega_d; the 1/h^3 normalisation is
          * omitted; comoving frame, per unit comoving volume and time. */
@@ -1021,9 +1046,10 @@ static int do_step(orc_ctx *c, double dt, int nlist, const int *zones, double *f
           qz[1] -= wgt * c->eps[i];
           qz[2] -= wgt * c->eps[i] * c->nvec[3 * d];
           qz[3] -= wgt * c->eps[i] * c->nvec[3 * d + 1];
+          qz[4] -= wgt * c->eps[i] * c->nvec[3 * d + 2];
         }
       }
-    if (out_tally) memcpy(c->q + 4 * (size_t)z, qz, sizeof(qz));
+    if (out_tally) memcpy(c->q + 5 * (size_t)z, qz, sizeof(qz));
     free(dN); free(dJ); free(tmp);
   }
   /* number leaving the domain: what the boundary ghosts would receive */
@@ -1153,8 +1179,8 @@ int orc_remap_block(const orc_ctx *c, const double *S, const double *D, int axis
  * no rotation, time kick of chain_frames), then the new background is
  * adopted.  The outflow tally is kept. */
 int orc_update_background(orc_ctx *c, const double *v_r, const double *v_theta,
-                          const double *alpha, const double *psi, const double *ka,
-                          const double *ks, const double *feq)
+                          const double *v_phi, const double *alpha, const double *psi,
+                          const double *ka, const double *ks, const double *feq)
 {
   if (!c) return 1;
   if (!c->have_bg || !c->have_state) return 5;
@@ -1162,7 +1188,7 @@ int orc_update_background(orc_ctx *c, const double *v_r, const double *v_theta,
   double *tmp = (double *)malloc(sizeof(double) * n);
   for (int z = 0; z < c->nz; ++z) {
     frame_t S = zone_frame(c, z, zone_th(c, z), 0.0), D = S;
-    D.v[0] = v_r[z]; D.v[1] = v_theta[z]; D.v[2] = 0.0;
+    D.v[0] = v_r[z]; D.v[1] = v_theta[z]; D.v[2] = v_phi ? v_phi[z] : 0.0;
     D.alpha = alpha[z]; D.psi = psi[z];
     for (int s = 0; s < c->ns; ++s) {
       double *blk = c->f + (size_t)z * c->blk + (size_t)s * n;
@@ -1171,14 +1197,14 @@ int orc_update_background(orc_ctx *c, const double *v_r, const double *v_theta,
     }
   }
   free(tmp);
-  return orc_set_background(c, v_r, v_theta, alpha, psi, ka, ks, feq);
+  return orc_set_background(c, v_r, v_theta, v_phi, alpha, psi, ka, ks, feq);
 }
 
-/* hydro source terms of the last full step: q[zone][4] = Q_Ye, Q_E, Q_M,r,
- * Q_M,theta (comoving frame, per unit volume and time, without 1/h^3) */
+/* hydro source terms of the last full step: q[zone][5] = Q_Ye, Q_E, Q_M,r,
+ * Q_M,theta, Q_M,phi (comoving frame, per unit volume and time, without 1/h^3) */
 int orc_source_terms(const orc_ctx *c, double *q)
 {
   if (!c) return 1;
-  memcpy(q, c->q, sizeof(double) * 4 * (size_t)c->nz);
+  memcpy(q, c->q, sizeof(double) * 5 * (size_t)c->nz);
   return 0;
 }

@@ -38,23 +38,26 @@ typedef struct {
   const double *mu_weights;  /* n_mu weights, summing to 2                     */
   int theta_bc;              /* ORC_THETA_* (2D only)                          */
   double disk_radius;        /* ORC_THETA_DISK: radius of the disk             */
+  int n_phi_zones;           /* 2D geometry: phi zones of width dphi, periodic
+                                (<= 1: the axisymmetric wedge; > 1: 3D)        */
 } orc_desc;
 
 typedef struct orc_ctx orc_ctx;
 
 orc_ctx *orc_create(const orc_desc *d);
 void orc_destroy(orc_ctx *c);
+/* v_phi may be NULL (no azimuthal motion) */
 int orc_set_background(orc_ctx *c, const double *v_r, const double *v_theta,
-                       const double *alpha, const double *psi,
+                       const double *v_phi, const double *alpha, const double *psi,
                        const double *kappa_a, const double *kappa_s,
                        const double *f_eq);
 /* new background: remaps the state from the old to the new comoving frames
  * (forward in time, no rotation), then adopts it; 5 if no background/state */
 int orc_update_background(orc_ctx *c, const double *v_r, const double *v_theta,
-                          const double *alpha, const double *psi, const double *ka,
-                          const double *ks, const double *feq);
+                          const double *v_phi, const double *alpha, const double *psi,
+                          const double *ka, const double *ks, const double *feq);
 /* hydro source terms of the last full step (Eq. hydrosource1-3):
- * q[zone][4] = Q_Ye, Q_E, Q_M,r, Q_M,theta */
+ * q[zone][5] = Q_Ye, Q_E, Q_M,r, Q_M,theta, Q_M,phi */
 int orc_source_terms(const orc_ctx *c, double *q);
 int orc_set_state(orc_ctx *c, const double *f);
 int orc_get_state(const orc_ctx *c, double *f);

@@ -38,7 +38,7 @@ class _Desc(C.Structure):
                 ("phi_rule", C.c_int), ("inner_bc", C.c_int), ("outer_bc", C.c_int),
                 ("r_edges", _dp), ("theta_edges", _dp), ("dphi", C.c_double),
                 ("eps_edges", _dp), ("mu_nodes", _dp), ("mu_weights", _dp),
-                ("theta_bc", C.c_int), ("disk_radius", C.c_double)]
+                ("theta_bc", C.c_int), ("disk_radius", C.c_double), ("n_phi_zones", C.c_int)]
 
 
 _lib = None
@@ -53,8 +53,8 @@ def lib():
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.POINTER(_Desc)]
         L.orc_destroy.argtypes = [C.c_void_p]
-        L.orc_set_background.argtypes = [C.c_void_p] + [_dp] * 7
-        L.orc_update_background.argtypes = [C.c_void_p] + [_dp] * 7
+        L.orc_set_background.argtypes = [C.c_void_p] + [_dp] * 8
+        L.orc_update_background.argtypes = [C.c_void_p] + [_dp] * 8
         L.orc_source_terms.argtypes = [C.c_void_p, _dp]
         L.orc_set_state.argtypes = [C.c_void_p, _dp]
         L.orc_get_state.argtypes = [C.c_void_p, _dp]
@@ -130,7 +130,7 @@ class Oracle:
         d = _Desc(w.n_r, w.n_theta, w.n_eps, w.n_mu, w.n_phi, w.n_species, w.geometry,
                   w.phi_rule, w.inner_bc, w.outer_bc, _p(self._keep[0]), _p(self._keep[1]),
                   w.dphi, _p(self._keep[2]), _p(self._keep[3]), _p(self._keep[4]),
-                  w.theta_bc, w.disk_radius)
+                  w.theta_bc, w.disk_radius, w.n_phi_zones)
         self.ctx = lib().orc_create(C.byref(d))
         if not self.ctx:
             raise ValueError("oracle rejected the grid description")
@@ -145,16 +145,20 @@ class Oracle:
             lib().orc_destroy(self.ctx)
             self.ctx = None
 
+    @staticmethod
+    def _bg(w):
+        vph = getattr(w, "v_phi", None)
+        return [_c(w.v_r), _c(w.v_theta), _c(vph if vph is not None else np.zeros_like(w.v_r)),
+                _c(w.alpha), _c(w.psi), _c(w.kappa_a), _c(w.kappa_s), _c(w.f_eq)]
+
     def set_background(self, w):
-        arrs = [_c(w.v_r), _c(w.v_theta), _c(w.alpha), _c(w.psi), _c(w.kappa_a),
-                _c(w.kappa_s), _c(w.f_eq)]
+        arrs = self._bg(w)
         rc = lib().orc_set_background(self.ctx, *[_p(a) for a in arrs])
         assert rc == 0
 
     def update_background(self, w):
         """new background: the state is remapped to the new comoving frames (forward in time)"""
-        arrs = [_c(w.v_r), _c(w.v_theta), _c(w.alpha), _c(w.psi), _c(w.kappa_a),
-                _c(w.kappa_s), _c(w.f_eq)]
+        arrs = self._bg(w)
         rc = lib().orc_update_background(self.ctx, *[_p(a) for a in arrs])
         assert rc == 0
 
@@ -185,8 +189,8 @@ class Oracle:
         return out
 
     def source_terms(self):
-        """[zone][4]: Q_Ye, Q_E, Q_M,r, Q_M,theta of the last full step"""
-        q = np.zeros((self.w.n_zones, 4))
+        """[zone][5]: Q_Ye, Q_E, Q_M,r, Q_M,theta, Q_M,phi of the last full step"""
+        q = np.zeros((self.w.n_zones, 5))
         assert lib().orc_source_terms(self.ctx, _p(q)) == 0
         return q
 

@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
+from typing import Optional
 
 import numpy as np
 
@@ -83,11 +84,13 @@ class Workload:
     phi_rule: int = PHI_SIN
     theta_bc: int = THETA_AXIS
     disk_radius: float = 0.0
+    n_phi_zones: int = 1             # > 1: 3D, phi zones of width dphi, periodic
+    v_phi: Optional[np.ndarray] = None   # [zone] azimuthal fluid velocity (None: 0)
     meta: dict = field(default_factory=dict)
 
     @property
     def n_zones(self) -> int:
-        return self.n_r * self.n_theta
+        return self.n_r * self.n_theta * self.n_phi_zones
 
     @property
     def n_dir(self) -> int:
@@ -199,6 +202,22 @@ def radiating_disk(n_r=100, n_theta=32, n_mu=16, n_phi=8, r_min=0.05, r_max=4.0,
     w.theta_bc = THETA_DISK
     w.disk_radius = float(R)
     return w
+
+
+def extrude_phi(w, n_phi_zones):
+    """The 3D grid of n_phi_zones copies of an axisymmetric workload's wedge
+    around the axis (phi zones of the wedge's width, periodic): every
+    per-zone array repeated for each phi zone, zone index (c n_theta + b) n_r + a."""
+    import copy as _copy
+    assert w.geometry == GEOM_AXISYM2D and w.n_phi_zones == 1
+    v = _copy.copy(w)
+    rep = lambda a: np.ascontiguousarray(np.concatenate([a] * n_phi_zones, axis=0))
+    for name in ("v_r", "v_theta", "alpha", "psi", "kappa_a", "kappa_s", "f_eq", "f0"):
+        setattr(v, name, rep(getattr(w, name)))
+    v.v_phi = rep(w.v_phi) if w.v_phi is not None else np.zeros(w.n_zones * n_phi_zones)
+    v.n_phi_zones = int(n_phi_zones)
+    v.name = w.name + f"_3d{n_phi_zones}"
+    return v
 
 
 # --------------------------------------------------------------------------

@@ -543,15 +543,16 @@ def _bin_geometry(w):
     Phi = (np.arange(w.n_phi) + 0.5) * 2.0 * np.pi / w.n_phi
     n_r = np.repeat(mu, w.n_phi)
     n_t = (np.sqrt(1.0 - mu * mu)[:, None] * np.cos(Phi)[None, :]).ravel()
+    n_p = (np.sqrt(1.0 - mu * mu)[:, None] * np.sin(Phi)[None, :]).ravel()
     e = w.eps_edges
     G = (e[1:] ** 3 - e[:-1] ** 3) / 3.0
-    return dOm, n_r, n_t, np.sqrt(e[1:] * e[:-1]), G
+    return dOm, (n_r, n_t, n_p), np.sqrt(e[1:] * e[:-1]), G
 
 
 def _gross_rate(w, f1):
     """per zone: sum over bins of |each collision term| eps G dOmega, the scale
     against which the rounding of the source terms is judged"""
-    dOm, _, _, eps, G = _bin_geometry(w)
+    dOm, _, eps, G = _bin_geometry(w)
     ka, ks, fe = w.kappa_a[..., None], w.kappa_s[..., None], w.f_eq[..., None]
     af = np.abs(f1)
     avg = np.einsum("zsid,d->zsi", af, dOm)[..., None] / (4 * np.pi)
@@ -581,18 +582,16 @@ def test_source_terms_scattering_moments(oracle_mod):
         o = oracle_mod.Oracle(w)
         o.step(o.max_dt(0.4), 1)
         q, f1 = o.source_terms(), o.state()
-        dOm, n_r, n_t, eps, G = _bin_geometry(w)
+        dOm, nvec, eps, G = _bin_geometry(w)
         scale = _gross_rate(w, f1)
         lep = np.array([1.0, -1.0, 0.0])
         ka, ks, fe = w.kappa_a, w.kappa_s, w.f_eq
         J = np.einsum("zsid,d->zsi", f1, dOm)
-        Fr = np.einsum("zsid,d->zsi", f1, dOm * n_r)
-        Ft = np.einsum("zsid,d->zsi", f1, dOm * n_t)
+        flux = [np.einsum("zsid,d->zsi", f1, dOm * n) for n in nvec]
         exp = np.stack([
             np.einsum("zsi,s,i->z", ka * (J - 4 * np.pi * fe), lep, G),
-            np.einsum("zsi,i->z", ka * (J - 4 * np.pi * fe), G * eps),
-            np.einsum("zsi,i->z", (ka + ks) * Fr, G * eps),
-            np.einsum("zsi,i->z", (ka + ks) * Ft, G * eps)], axis=1)
+            np.einsum("zsi,i->z", ka * (J - 4 * np.pi * fe), G * eps)] +
+            [np.einsum("zsi,i->z", (ka + ks) * F, G * eps) for F in flux], axis=1)
         assert np.all(np.abs(q - exp) <= 1e-12 * scale[:, None])
         if ka_scale == 0.0:
             assert np.all(np.abs(q[:, :2]) <= 1e-12 * scale[:, None])
@@ -673,3 +672,108 @@ def test_radiating_disk(oracle_mod):
     assert e8 < 0.09 and m8 < 0.035
     assert e8 < 0.6 * e4 and m8 < 0.8 * m4
     assert tot[0, 1] < 0.0                               # the disk feeds the grid
+
+
+# ------------------------------------------------------------ 3D grids
+def _shock_small(**kw):
+    w = W.shock_2d(n_r=8, n_theta=4, n_eps=4, n_mu=4, n_phi=4, precision=W.PREC_FP64, **kw)
+    w.f0 = w.f0 * (1.0 + 0.3 * RNG.random(w.f0.shape))
+    return w
+
+
+def _turned(w, n_phi_zones):
+    """a 3D grid with state and background that vary with phi, and rotation"""
+    w3 = W.extrude_phi(w, n_phi_zones)
+    w3.f0 = w3.f0 * (1.0 + 0.3 * RNG.random(w3.f0.shape))
+    w3.v_phi = 0.05 * RNG.standard_normal(w3.n_zones)
+    w3.v_r = w3.v_r * (1.0 + 0.1 * RNG.random(w3.n_zones))
+    w3.kappa_a = w3.kappa_a * (1.0 + RNG.random(w3.kappa_a.shape))
+    return w3
+
+
+def test_3d_symmetric_equals_axisymmetric(oracle_mod):
+    """P-22 (Sec. 4.4: axisymmetric results carry over to 3D with the same
+    dphi): n copies of the wedge around the axis, with data independent of
+    phi, step exactly like the axisymmetric wedge, bit for bit"""
+    w2 = _shock_small()
+    w3 = W.extrude_phi(w2, 3)
+    o2, o3 = oracle_mod.Oracle(w2), oracle_mod.Oracle(w3)
+    dt = o2.max_dt(0.4)
+    assert o3.max_dt(0.4) == dt
+    o2.step(dt, 3)
+    o3.step(dt, 3)
+    s3 = o3.state().reshape((3,) + o2.state().shape)
+    for c in range(3):
+        assert np.array_equal(s3[c], o2.state())
+    assert np.array_equal(o3.source_terms().reshape(3, w2.n_zones, 5)[1], o2.source_terms())
+
+
+def test_3d_number_conservation(oracle_mod):
+    """P-23: without opacity, a 3D grid with phi-dependent state, velocity
+    (v_phi included), lapse and conformal factor keeps N + outflow"""
+    w3 = _turned(_shock_small(), 4)
+    w3.kappa_a[:] = 0.0
+    w3.kappa_s[:] = 0.0
+    o = oracle_mod.Oracle(w3)
+    _, t0 = o.moments()
+    o.step(o.max_dt(0.4), 3)
+    _, t1 = o.moments()
+    for s in range(w3.n_species):
+        assert abs(t1[s, 0] - t0[s, 0] + t1[s, 1]) < 1e-13 * t0[s, 0]
+
+
+def test_3d_phi_mirror(oracle_mod):
+    """P-24: the scheme is symmetric under phi -> -phi: zone c -> -c, momentum
+    Phi bin k -> n_Phi - 1 - k, v_phi -> -v_phi.  Mirrored data step to the
+    mirror of the stepped data (to rounding), and Q_M,phi changes sign."""
+    n = 4
+    w3 = _turned(_shock_small(), n)
+    w2 = W.shock_2d(n_r=8, n_theta=4, n_eps=4, n_mu=4, n_phi=4, precision=W.PREC_FP64)
+    nz2, nphi = w2.n_zones, w3.n_phi
+    zmap = np.array([((-(z // nz2)) % n) * nz2 + z % nz2 for z in range(w3.n_zones)])
+    dmap = np.array([(d // nphi) * nphi + (nphi - 1 - d % nphi) for d in range(w3.n_dir)])
+
+    def mirror(a):
+        return a[zmap]
+
+    wm = copy.copy(w3)
+    for name in ("v_r", "v_theta", "alpha", "psi", "kappa_a", "kappa_s", "f_eq"):
+        setattr(wm, name, mirror(getattr(w3, name)))
+    wm.v_phi = -mirror(w3.v_phi)
+    wm.f0 = mirror(w3.f0)[..., dmap]
+    o, om = oracle_mod.Oracle(w3), oracle_mod.Oracle(wm)
+    dt = o.max_dt(0.4)
+    o.step(dt, 2)
+    om.step(dt, 2)
+    ref = mirror(o.state())[..., dmap]
+    assert np.max(np.abs(om.state() - ref)) <= 1e-12 * np.max(np.abs(ref))
+    q, qm = o.source_terms(), om.source_terms()
+    sgn = np.array([1, 1, 1, 1, -1])
+    scale = _gross_rate(w3, o.state())[:, None]
+    assert np.all(np.abs(qm - mirror(q) * sgn) <= 1e-11 * mirror(scale))
+    assert np.max(np.abs(q[:, 4])) > 1e-6 * np.max(scale)
+
+
+def test_3d_phi_transport_direction(oracle_mod):
+    """P-25: radiation moving in +phi (directions with n_phi > 0) leaves a
+    phi zone through its +phi face into the next phi zone, not the previous
+    one (static flat vacuum, one step)"""
+    n = 6
+    w2 = _shock_small()
+    w3 = W.extrude_phi(w2, n)
+    w3.v_r[:] = 0.0
+    w3.v_theta[:] = 0.0
+    w3.alpha[:] = 1.0
+    w3.psi[:] = 1.0
+    w3.kappa_a[:] = 0.0
+    w3.kappa_s[:] = 0.0
+    Phi = (np.arange(w3.n_phi) + 0.5) * 2.0 * np.pi / w3.n_phi
+    plus = np.tile(np.sin(Phi) > 0, w3.n_mu)
+    f0 = np.zeros_like(w3.f0)
+    f0[:w2.n_zones, :, :, plus] = 1.0
+    w3.f0 = f0
+    o = oracle_mod.Oracle(w3)
+    o.step(o.max_dt(0.4), 1)
+    f = o.state().reshape((n, -1))
+    nxt, prv = np.abs(f[1]).sum(), np.abs(f[n - 1]).sum()
+    assert nxt > 0.01 * np.abs(f[0]).sum() and prv < 0.2 * nxt      # measured: 0.078

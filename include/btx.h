@@ -92,6 +92,10 @@ typedef struct {
                                 <= 0 selects the default 1.0                        */
   int32_t theta_bc;          /* 2D: btx_theta_bc; else ignored                       */
   double disk_radius;        /* BTX_THETA_DISK: the disk's radius (> 0)              */
+  int32_t n_phi_zones;       /* BTX_GEOM_AXISYM2D: phi zones of width dphi, periodic
+                                over n_phi_zones * dphi (<= 2 pi); 0 or 1: the
+                                axisymmetric wedge, > 1: a 3D grid.  Zone index
+                                (c n_theta + b) n_r + a for phi zone c          */
 } btx_grid_desc;
 
 typedef struct {             /* host arrays, copied during the call                  */
@@ -102,6 +106,7 @@ typedef struct {             /* host arrays, copied during the call             
   const double *kappa_a;     /* [zone][species][group] absorption opacity (>= 0)     */
   const double *kappa_s;     /* [zone][species][group] scattering opacity (>= 0)     */
   const double *f_eq;        /* [zone][species][group] equilibrium occupation        */
+  const double *v_phi;       /* [zone] azimuthal fluid velocity, or NULL for none    */
 } btx_background;
 
 typedef struct btx_ctx btx_ctx;
@@ -136,16 +141,15 @@ btx_status btx_step(btx_ctx *ctx, double dt, int32_t n_steps);
  * energy.  Either pointer may be NULL.  Computed on the device in FP64. */
 btx_status btx_moments(btx_ctx *ctx, double *zone_moments, double *totals);
 /* Hydro source terms of the last step (coupling to matter, Sec. 3.4,
- * Eq. hydrosource1-3): q[zone][4] = Q_Ye, Q_E, Q_M,r, Q_M,theta, what
+ * Eq. hydrosource1-3): q[zone][5] = Q_Ye, Q_E, Q_M,r, Q_M,theta, Q_M,phi, what
  * the fluid gains per unit comoving volume and comoving time.  They integrate
  * the collision term of Eq. sourceterms_discrete at the new state (backward
  * Euler puts the step's whole collision change there) over each bin's
  * momentum cell G_i dOmega_d (group i, direction d): weight +1 for
  * species 0 (electron neutrinos), -1 for species 1 (antineutrinos), 0
- * otherwise (Q_Ye); eps (Q_E); eps n in the zone's comoving (r, theta)
- * directions (Q_M).  No 1/h^3.  Zero before
- * the first step.  Computed in FP64 by the zone update; synchronises the
- * stream. */
+ * otherwise (Q_Ye); eps (Q_E); eps n in the zone's comoving (r, theta,
+ * phi) directions (Q_M).  No 1/h^3.  Zero before the first step.  Computed
+ * in FP64 by the zone update; synchronises the stream. */
 btx_status btx_source_terms(btx_ctx *ctx, double *q);
 /* Per-kernel GPU time: enable = 1 records HIP events around the kernels of
  * each btx_step step on the context's stream (no synchronisation; up to 256

@@ -46,11 +46,12 @@ class GridDesc(C.Structure):
                 ("inner_bc", C.c_int32), ("outer_bc", C.c_int32), ("precision", C.c_int32),
                 ("r_edges", _dp), ("theta_edges", _dp), ("dphi", C.c_double),
                 ("eps_edges", _dp), ("fp64_threshold", C.c_double),
-                ("theta_bc", C.c_int32), ("disk_radius", C.c_double)]
+                ("theta_bc", C.c_int32), ("disk_radius", C.c_double), ("n_phi_zones", C.c_int32)]
 
 
 class Background(C.Structure):
-    _fields_ = [(n, _dp) for n in ("v_r", "v_theta", "alpha", "psi", "kappa_a", "kappa_s", "f_eq")]
+    _fields_ = [(n, _dp) for n in ("v_r", "v_theta", "alpha", "psi", "kappa_a", "kappa_s", "f_eq",
+                                   "v_phi")]
 
 
 _lib = None
@@ -112,13 +113,16 @@ def _desc(w, precision, fp64_threshold):
                  MU_LEGENDRE if w.mu_rule == "legendre" else MU_LOBATTO, w.phi_rule,
                  w.inner_bc, w.outer_bc, precision, _p(keep[0]), _p(keep[1]),
                  float(w.dphi), _p(keep[2]), float(fp64_threshold), int(w.theta_bc),
-                 float(w.disk_radius))
+                 float(w.disk_radius), int(w.n_phi_zones))
     return d, keep
 
 
 def _background(w):
     arrs = [np.ascontiguousarray(a, float) for a in
             (w.v_r, w.v_theta, w.alpha, w.psi, w.kappa_a, w.kappa_s, w.f_eq)]
+    vph = getattr(w, "v_phi", None)
+    if vph is not None:
+        arrs.append(np.ascontiguousarray(vph, float))
     return Background(*[_p(a) for a in arrs]), arrs
 
 
@@ -147,10 +151,7 @@ class Context:
             pass
 
     def set_background(self, w=None):
-        w = w or self.w
-        arrs = [np.ascontiguousarray(a, float) for a in
-                (w.v_r, w.v_theta, w.alpha, w.psi, w.kappa_a, w.kappa_s, w.f_eq)]
-        bg = Background(*[_p(a) for a in arrs])
+        bg, keep = _background(w or self.w)
         _check(lib().btx_set_background(self.h, C.byref(bg)))
 
     def update_background(self, w):
@@ -193,8 +194,8 @@ class Context:
         return zm, tot
 
     def source_terms(self):
-        """[zone][4]: Q_Ye, Q_E, Q_M,r, Q_M,theta of the last step"""
-        q = np.zeros((self.w.n_zones, 4))
+        """[zone][5]: Q_Ye, Q_E, Q_M,r, Q_M,theta, Q_M,phi of the last step"""
+        q = np.zeros((self.w.n_zones, 5))
         _check(lib().btx_source_terms(self.h, _p(q)))
         return q
 
@@ -281,7 +282,7 @@ class Batch:
         return zm, tot
 
     def source_terms(self, m):
-        """[zone][4]: Q_Ye, Q_E, Q_M,r, Q_M,theta of model m's last step"""
-        q = np.zeros((self.ws[m].n_zones, 4))
+        """[zone][5]: Q_Ye, Q_E, Q_M,r, Q_M,theta, Q_M,phi of model m's last step"""
+        q = np.zeros((self.ws[m].n_zones, 5))
         _check(lib().btx_batch_source_terms(self.h, m, _p(q)))
         return q

@@ -61,9 +61,9 @@ struct DevGrid {
   int nr, nth, ne, nmu, nphi, ns, ndir, nz, geom, phi_rule;
   int eblk, blk, nfaces, nch, ce;   // face work items per direction, groups per item
   double lnq, q, fp64_thr;
-  double om[3];                     // sum over directions of dOmega, dOmega n_r, dOmega n_theta
+  double om[4];                     // sum over directions of dOmega and dOmega n (r, theta, phi)
   const double *mu, *Phi, *dOm, *nvec, *G, *eps, *vol;
-  const double *vr, *vth, *alp, *psi;
+  const double *vr, *vth, *vph, *alp, *psi;
 };
 
 struct Frame {
@@ -93,7 +93,7 @@ struct ModelDev {
   const void *ka, *ks, *feq;   // [zone][species][group] (storage precision)
   void *dN;                    // [face][side][species][group][direction]
   double *tally;               // [face][species] cumulative content through ghost faces
-  double *q;                   // [zone][4] hydro source terms of the last step
+  double *q;                   // [zone][5] hydro source terms of the last step
   double dt;                   // step of the current launch
 };
 
@@ -115,6 +115,7 @@ __device__ __forceinline__ DevGrid global_grid(const DevGrid &src)
   g.mu = as_global(g.mu); g.Phi = as_global(g.Phi); g.dOm = as_global(g.dOm);
   g.nvec = as_global(g.nvec); g.G = as_global(g.G); g.eps = as_global(g.eps);
   g.vol = as_global(g.vol); g.vr = as_global(g.vr); g.vth = as_global(g.vth);
+  g.vph = as_global(g.vph);
   g.alp = as_global(g.alp); g.psi = as_global(g.psi);
   return g;
 }
@@ -125,7 +126,7 @@ __device__ Frame side_frame(const DevGrid &g, const SideDesc &s)
   int z = s.z;
   f.v[0] = g.vr[z];
   f.v[1] = g.vth[z];
-  f.v[2] = 0.0;
+  f.v[2] = g.vph[z];
   if (s.kind == btx::SIDE_MIRROR) f.v[0] = -f.v[0];
   f.alpha = g.alp[z];
   f.psi = g.psi[z];
@@ -451,6 +452,17 @@ __device__ inline double wave_sum(double v)
   return v;
 }
 
+// three wave sums with their shuffles interleaved
+__device__ inline void wave_sum3(double &a, double &b, double &c)
+{
+  for (int o = 32; o > 0; o >>= 1) {
+    const double x = __shfl_xor(a, o, 64), y = __shfl_xor(b, o, 64), w = __shfl_xor(c, o, 64);
+    a += x;
+    b += y;
+    c += w;
+  }
+}
+
 // frame weight psi^6 u0 dOmega of direction d in frame k of a face
 __device__ inline double frame_weight(const DevGrid &g, const FaceAux &A, int k, int d)
 {
@@ -642,12 +654,11 @@ __host__ __device__ inline size_t time_lds_bytes(int nd, int ne, size_t szT)
 // place, so without rotation and with the time kick of frame_chain.  The
 // zone's gather table is built in LDS and applied in place to the number
 // content (W = psi^6 u0 G dOmega; the cell volume is unchanged).
-// nvr, nvth, nalp, npsi: the new background of the model.
+// nbg: the new background of the model, [5][zone] = v_r, v_theta, v_phi, alpha, psi.
 template <typename T>
 __global__ void __launch_bounds__(256)
 time_remap_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity,
-                  const double *__restrict__ nvr, const double *__restrict__ nvth,
-                  const double *__restrict__ nalp, const double *__restrict__ npsi)
+                  const double *__restrict__ nbg)
 {
   extern __shared__ __align__(16) char lds[];
   const int2 it = items[blockIdx.x];
@@ -656,12 +667,13 @@ time_remap_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ 
   T *__restrict__ f = as_global((T *)M.f[parity]);
   const int z = it.y, nd = g.ndir, ne = g.ne, tid = threadIdx.x, nthr = blockDim.x;
   Frame S;
-  S.v[0] = g.vr[z]; S.v[1] = g.vth[z]; S.v[2] = 0.0;
+  S.v[0] = g.vr[z]; S.v[1] = g.vth[z]; S.v[2] = g.vph[z];
   S.alpha = g.alp[z]; S.psi = g.psi[z];
   S.th = 0.0; S.ph = 0.0;
   Frame D = S;
-  D.v[0] = as_global(nvr)[z]; D.v[1] = as_global(nvth)[z];
-  D.alpha = as_global(nalp)[z]; D.psi = as_global(npsi)[z];
+  const double *nb = as_global(nbg);
+  D.v[0] = nb[z]; D.v[1] = nb[g.nz + z]; D.v[2] = nb[2 * g.nz + z];
+  D.alpha = nb[3 * g.nz + z]; D.psi = nb[4 * g.nz + z];
   if (same_frame(S, D)) return;                          // the whole workgroup leaves
   char *p = lds;
   int *cnt = (int *)p;                 p += align16((size_t)nd * 4);
@@ -674,14 +686,14 @@ time_remap_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ 
   double *aS = (double *)p;            p += align16((size_t)nd * 8);
   double *aD = (double *)p;            p += align16((size_t)nd * 8);
   T *cont = (T *)p;
-  const double gS = 1.0 / sqrt(1.0 - (S.v[0] * S.v[0] + S.v[1] * S.v[1]));
-  const double gD = 1.0 / sqrt(1.0 - (D.v[0] * D.v[0] + D.v[1] * D.v[1]));
+  const double gS = 1.0 / sqrt(1.0 - (S.v[0] * S.v[0] + S.v[1] * S.v[1] + S.v[2] * S.v[2]));
+  const double gD = 1.0 / sqrt(1.0 - (D.v[0] * D.v[0] + D.v[1] * D.v[1] + D.v[2] * D.v[2]));
   const double p6S = pow(S.psi, 6.0), p6D = pow(D.psi, 6.0);
   for (int q = tid; q < nd; q += nthr) {
     cnt[q] = 0;
     const double *nv = g.nvec + 3 * q;
-    aS[q] = p6S * gS * (1.0 + S.v[0] * nv[0] + S.v[1] * nv[1]) * g.dOm[q];
-    aD[q] = p6D * gD * (1.0 + D.v[0] * nv[0] + D.v[1] * nv[1]) * g.dOm[q];
+    aS[q] = p6S * gS * (1.0 + S.v[0] * nv[0] + S.v[1] * nv[1] + S.v[2] * nv[2]) * g.dOm[q];
+    aD[q] = p6D * gD * (1.0 + D.v[0] * nv[0] + D.v[1] * nv[1] + D.v[2] * nv[2]) * g.dOm[q];
   }
   __syncthreads();
   for (int q = tid; q < nd; q += nthr) {               // each source direction
@@ -1128,12 +1140,12 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   const int nd = g.ndir, ne = g.ne, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
   const btx::ZoneFaces &L = zf[z];        // uniform: read through the scalar cache
-  const double vr = g.vr[z], vt = g.vth[z];
-  const double gam = 1.0 / sqrt(1.0 - (vr * vr + vt * vt));
+  const double vr = g.vr[z], vt = g.vth[z], vp = g.vph[z];
+  const double gam = 1.0 / sqrt(1.0 - (vr * vr + vt * vt + vp * vp));
   const double p6v = pow(g.psi[z], 6.0) * g.vol[z];
   const double tau = g.alp[z] * dt / gam;
-  // per (species, group) row: the sums of S dOmega, S dOmega n_r and
-  // S dOmega n_theta, for the source terms after the update
+  // per (species, group) row: the sums of S dOmega and S dOmega n (r, theta,
+  // phi), for the source terms after the update
   extern __shared__ __align__(16) char lds[];
   double *rs = (double *)lds;
   for (int row = wave; row < g.ns * ne; row += nwaves) {
@@ -1152,7 +1164,7 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
       for (int q = 0; q < L.n; ++q)
         acc += (double)dN[((size_t)L.fid[q] * 2 + L.side[q]) * g.blk + off];
       const double *nv = g.nvec + 3 * d;
-      double W = p6v * gam * (1.0 + vr * nv[0] + vt * nv[1]) * g.G[i] * g.dOm[d];
+      double W = p6v * gam * (1.0 + vr * nv[0] + vt * nv[1] + vp * nv[2]) * g.G[i] * g.dOm[d];
       double S = (double)f[(size_t)z * g.blk + off] + tau * ka_ * fe_ + acc / W;
       if (!wide) S = (double)(float)S;
       Sd[r] = S;
@@ -1160,7 +1172,7 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
     }
     const double ssum = wave_sum(part);
     double avg = ssum / (4.0 * kPi);
-    double pr = 0.0, pt = 0.0;
+    double pr = 0.0, pt = 0.0, pp = 0.0;
     for (int r = 0; r < 4; ++r) {
       int d = lane + 64 * r;
       if (d >= nd) continue;
@@ -1168,6 +1180,7 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
       const double sw = Sd[r] * g.dOm[d];
       pr += sw * g.nvec[3 * d];
       pt += sw * g.nvec[3 * d + 1];
+      pp += sw * g.nvec[3 * d + 2];
       double out;
       if (wide) out = (Sd[r] + tau * ks_ * avg / (1.0 + tau * ka_)) / (1.0 + tau * (ka_ + ks_));
       else {
@@ -1176,8 +1189,8 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
       }
       fout[(size_t)z * g.blk + off] = (T)out;
     }
-    const double sr = wave_sum(pr), st = wave_sum(pt);
-    if (lane == 0) { rs[4 * row] = ssum; rs[4 * row + 1] = sr; rs[4 * row + 2] = st; }
+    wave_sum3(pr, pt, pp);
+    if (lane == 0) { rs[5 * row] = ssum; rs[5 * row + 1] = pr; rs[5 * row + 2] = pt; rs[5 * row + 3] = pp; }
   }
   // Hydro source terms (Eq. hydrosource1-3), in FP64, one row per thread:
   // the collision term at the new state (backward Euler) is
@@ -1191,25 +1204,26 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
     const int s = row / ne, i = row - s * ne;
     const size_t kidx = ((size_t)z * g.ns + s) * ne + i;
     const double ka_ = (double)ka[kidx], ks_ = (double)ks[kidx], fe_ = (double)feq[kidx];
-    const double ssum = rs[4 * row], avg1 = ssum / (4.0 * kPi) / (1.0 + tau * ka_);
+    const double ssum = rs[5 * row], avg1 = ssum / (4.0 * kPi) / (1.0 + tau * ka_);
     const double K = (ka_ + ks_) / (1.0 + tau * (ka_ + ks_));
     const double B = ka_ * fe_ + ks_ * avg1 - K * tau * ks_ * avg1;
-    const double cw = B * g.om[0] - K * ssum, cr = B * g.om[1] - K * rs[4 * row + 1];
-    const double ct = B * g.om[2] - K * rs[4 * row + 2];
+    const double cw = B * g.om[0] - K * ssum, cr = B * g.om[1] - K * rs[5 * row + 1];
+    const double ct = B * g.om[2] - K * rs[5 * row + 2], cp = B * g.om[3] - K * rs[5 * row + 3];
     const double ge = g.G[i] * g.eps[i], lep = s == 0 ? 1.0 : (s == 1 ? -1.0 : 0.0);
-    rs[4 * row] = -lep * g.G[i] * cw;
-    rs[4 * row + 1] = -ge * cw;
-    rs[4 * row + 2] = -ge * cr;
-    rs[4 * row + 3] = -ge * ct;
+    rs[5 * row] = -lep * g.G[i] * cw;
+    rs[5 * row + 1] = -ge * cw;
+    rs[5 * row + 2] = -ge * cr;
+    rs[5 * row + 3] = -ge * ct;
+    rs[5 * row + 4] = -ge * cp;
   }
   __syncthreads();
-  // wave k sums component k over the rows (fixed order: lane-strided, then a
-  // wave sum), so the result does not depend on timing
-  if (wave < 4) {
+  // component k is summed over the rows by wave k mod 4 (fixed order:
+  // lane-strided, then a wave sum), so the result does not depend on timing
+  for (int k = wave; k < 5; k += nwaves) {
     double v = 0.0;
-    for (int row = lane; row < nrow; row += 64) v += rs[4 * row + wave];
+    for (int row = lane; row < nrow; row += 64) v += rs[5 * row + k];
     v = wave_sum(v);
-    if (lane == 0) as_global(M.q)[(size_t)z * 4 + wave] = v;
+    if (lane == 0) as_global(M.q)[(size_t)z * 5 + k] = v;
   }
 }
 
@@ -1226,8 +1240,8 @@ moments_kernel(const ModelDev *__restrict__ models, int m, int parity, double *_
   const int z = blockIdx.x;
   __shared__ double red[6][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  const double vr = g.vr[z], vt = g.vth[z];
-  const double gam = 1.0 / sqrt(1.0 - (vr * vr + vt * vt));
+  const double vr = g.vr[z], vt = g.vth[z], vp = g.vph[z];
+  const double gam = 1.0 / sqrt(1.0 - (vr * vr + vt * vt + vp * vp));
   const double p6v = pow(g.psi[z], 6.0) * g.vol[z];
   for (int s = 0; s < g.ns; ++s) {
     double m[6] = { 0, 0, 0, 0, 0, 0 };
@@ -1236,7 +1250,7 @@ moments_kernel(const ModelDev *__restrict__ models, int m, int parity, double *_
       double fv = (double)f[(size_t)z * g.blk + (size_t)s * g.eblk + q];
       const double *nv = g.nvec + 3 * d;
       double dG = g.G[i] * g.dOm[d], mu = nv[0], e = g.eps[i];
-      double nn = p6v * gam * (1.0 + vr * nv[0] + vt * nv[1]) * dG * fv;
+      double nn = p6v * gam * (1.0 + vr * nv[0] + vt * nv[1] + vp * nv[2]) * dG * fv;
       m[0] += nn;
       m[1] += fv * e * dG;
       m[2] += fv * mu * e * dG;
@@ -1402,12 +1416,12 @@ struct Model {
   FaceShape shape;
   double *d_mu = nullptr, *d_Phi = nullptr, *d_dOm = nullptr, *d_nvec = nullptr, *d_G = nullptr,
          *d_eps = nullptr, *d_vol = nullptr;
-  double *d_vr = nullptr, *d_vth = nullptr, *d_alp = nullptr, *d_psi = nullptr;
+  double *d_vr = nullptr, *d_vth = nullptr, *d_vph = nullptr, *d_alp = nullptr, *d_psi = nullptr;
   void *d_ka = nullptr, *d_ks = nullptr, *d_feq = nullptr, *d_f[2] = { nullptr, nullptr }, *d_dN = nullptr;
   char *d_tabs = nullptr;
   FaceAux *d_aux = nullptr;
   double *d_tally = nullptr, *d_zm = nullptr, *d_ze = nullptr, *d_stage = nullptr, *d_q = nullptr;
-  double *d_nbg = nullptr;           // new v_r, v_theta, alpha, psi of a background update
+  double *d_nbg = nullptr;           // new v_r, v_theta, v_phi, alpha, psi of a background update
   FaceDesc *d_faces = nullptr;
   btx::ZoneFaces *d_zf = nullptr;
   int2 *d_fitems = nullptr, *d_zitems = nullptr;   // (index, face), (index, zone)
@@ -1450,6 +1464,9 @@ btx_status validate_desc(const btx_grid_desc *d)
     if (d->theta_edges[0] != 0.0 || std::fabs(d->theta_edges[nth] - tmax) > 1e-12)
       return fail(BTX_E_UNSUPPORTED, "2D theta edges must span [0, pi] ([0, pi/2] with a disk boundary)");
     if (d->theta_bc == BTX_THETA_DISK && !(d->disk_radius > 0.0)) return fail(BTX_E_INVAL, "disk radius must be positive");
+    if (d->n_phi_zones < 0) return fail(BTX_E_INVAL, "n_phi_zones must be >= 0");
+    if (d->n_phi_zones > 1 && d->n_phi_zones * d->dphi > 2.0 * kPi * (1.0 + 1e-12))
+      return fail(BTX_E_INVAL, "the phi zones must fit in 2 pi");
     for (int b = 0; b < nth; ++b)
       if (!(d->theta_edges[b + 1] > d->theta_edges[b])) return fail(BTX_E_INVAL, "theta edges must ascend");
     if (!(d->dphi > 0.0) || d->dphi > kPi) return fail(BTX_E_INVAL, "dphi must be in (0, pi]");
@@ -1459,7 +1476,7 @@ btx_status validate_desc(const btx_grid_desc *d)
 
 void model_free(Model &m)
 {
-  void *ptrs[] = { m.d_mu, m.d_Phi, m.d_dOm, m.d_nvec, m.d_G, m.d_eps, m.d_vol, m.d_vr, m.d_vth,
+  void *ptrs[] = { m.d_mu, m.d_Phi, m.d_dOm, m.d_nvec, m.d_G, m.d_eps, m.d_vol, m.d_vr, m.d_vth, m.d_vph,
                    m.d_alp, m.d_psi, m.d_ka, m.d_ks, m.d_feq, m.d_f[0], m.d_f[1], m.d_dN, m.d_tally,
                    m.d_zm, m.d_ze, m.d_stage, m.d_faces, m.d_zf, m.d_tabs, m.d_aux, m.d_fitems, m.d_zitems,
                    m.d_nbg, m.d_q };
@@ -1480,6 +1497,7 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
   g.geom = d->geometry; g.mu_rule = d->mu_rule; g.phi_rule = d->phi_rule;
   g.inner_bc = d->inner_bc; g.outer_bc = d->outer_bc; g.prec = d->precision;
   g.theta_bc = d->geometry == BTX_GEOM_AXISYM2D ? d->theta_bc : BTX_THETA_AXIS;
+  g.nph = d->geometry == BTX_GEOM_AXISYM2D ? std::max(1, (int)d->n_phi_zones) : 1;
   g.disk_r = d->disk_radius;
   g.dphi = d->dphi;
   g.fp64_thr = d->fp64_threshold > 0.0 ? d->fp64_threshold : 1.0;
@@ -1519,6 +1537,7 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
   TRY(upload(&m.d_zitems, zit.data(), nz));
   TRY(upload(&m.d_vr, zero.data(), nz));
   TRY(upload(&m.d_vth, zero.data(), nz));
+  TRY(upload(&m.d_vph, zero.data(), nz));
   TRY(upload(&m.d_alp, one.data(), nz));
   TRY(upload(&m.d_psi, one.data(), nz));
 #undef TRY
@@ -1530,8 +1549,8 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
       !dmalloc(&m.d_f[0], nz * blk * m.tsize) || !dmalloc(&m.d_f[1], nz * blk * m.tsize) ||
       !dmalloc(&m.d_dN, nf * 2 * blk * m.tsize) || !dmalloc((void **)&m.d_tally, nf * g.ns * 8) ||
       !dmalloc((void **)&m.d_zm, nz * g.ns * 5 * 8) || !dmalloc((void **)&m.d_ze, nz * g.ns * 8) ||
-      !dmalloc((void **)&m.d_stage, nk * 8) || !dmalloc((void **)&m.d_nbg, nz * 4 * 8) ||
-      !dmalloc((void **)&m.d_q, nz * 4 * 8) ||
+      !dmalloc((void **)&m.d_stage, nk * 8) || !dmalloc((void **)&m.d_nbg, nz * 5 * 8) ||
+      !dmalloc((void **)&m.d_q, nz * 5 * 8) ||
       !dmalloc((void **)&m.d_tabs, nf * kTables * tab_stride(g.ndir, m.tsize)) ||
       !dmalloc((void **)&m.d_aux, nf * sizeof(FaceAux))) {
     model_free(m);
@@ -1553,15 +1572,16 @@ ModelDev model_dev(const Model &m, double dt)
   d.nch = m.shape.nch;
   d.ce = m.shape.ce;
   d.lnq = g.lnq; d.q = g.q; d.fp64_thr = g.fp64_thr;
-  d.om[0] = d.om[1] = d.om[2] = 0.0;
+  d.om[0] = d.om[1] = d.om[2] = d.om[3] = 0.0;
   for (int k = 0; k < g.ndir; ++k) {
     d.om[0] += g.dOm[k];
     d.om[1] += g.dOm[k] * g.nvec[3 * k];
     d.om[2] += g.dOm[k] * g.nvec[3 * k + 1];
+    d.om[3] += g.dOm[k] * g.nvec[3 * k + 2];
   }
   d.mu = m.d_mu; d.Phi = m.d_Phi; d.dOm = m.d_dOm; d.nvec = m.d_nvec; d.G = m.d_G;
   d.eps = m.d_eps; d.vol = m.d_vol;
-  d.vr = m.d_vr; d.vth = m.d_vth; d.alp = m.d_alp; d.psi = m.d_psi;
+  d.vr = m.d_vr; d.vth = m.d_vth; d.vph = m.d_vph; d.alp = m.d_alp; d.psi = m.d_psi;
   M.faces = m.d_faces;
   M.zf = m.d_zf;
   M.tabs = m.d_tabs;
@@ -1584,7 +1604,8 @@ btx_status check_background(const Model &m, const btx_background *bg)
   const btx::Grid &g = m.g;
   const size_t nz = g.nz, nk = nz * g.ns * g.ne;
   for (size_t z = 0; z < nz; ++z) {
-    double v2 = bg->v_r[z] * bg->v_r[z] + bg->v_theta[z] * bg->v_theta[z];
+    const double vp = bg->v_phi ? bg->v_phi[z] : 0.0;
+    double v2 = bg->v_r[z] * bg->v_r[z] + bg->v_theta[z] * bg->v_theta[z] + vp * vp;
     if (!(v2 < 1.0) || !(bg->alpha[z] > 0.0) || !(bg->psi[z] > 0.0) || !std::isfinite(bg->alpha[z]) ||
         !std::isfinite(bg->psi[z]))
       return fail(BTX_E_INVAL, "background velocity/metric out of range at zone " + std::to_string(z));
@@ -1603,6 +1624,8 @@ btx_status upload_background(Model &m, const btx_background *bg, hipStream_t s)
   const size_t nz = g.nz, nk = nz * g.ns * g.ne;
   HIP_TRY(hipMemcpy(m.d_vr, bg->v_r, nz * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(m.d_vth, bg->v_theta, nz * 8, hipMemcpyHostToDevice));
+  if (bg->v_phi) HIP_TRY(hipMemcpy(m.d_vph, bg->v_phi, nz * 8, hipMemcpyHostToDevice));
+  else HIP_TRY(hipMemset(m.d_vph, 0, nz * 8));
   HIP_TRY(hipMemcpy(m.d_alp, bg->alpha, nz * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(m.d_psi, bg->psi, nz * 8, hipMemcpyHostToDevice));
   const double *src[3] = { bg->kappa_a, bg->kappa_s, bg->f_eq };
@@ -1647,8 +1670,8 @@ btx_status launch_faces(const FaceShape &shape, size_t tsize, const ModelDev *d_
   return BTX_OK;
 }
 
-// zone kernel LDS: four FP64 row sums per (species, group) row
-size_t zone_lds_bytes(int rows) { return (size_t)std::max(rows, 1) * 4 * sizeof(double); }
+// zone kernel LDS: five FP64 row values per (species, group) row
+size_t zone_lds_bytes(int rows) { return (size_t)std::max(rows, 1) * 5 * sizeof(double); }
 
 btx_status launch_zones(size_t tsize, const ModelDev *d_models, const int2 *items, int n, int max_rows,
                         int parity, hipStream_t s)
@@ -1685,14 +1708,16 @@ btx_status model_update_background(Model &m, const btx_background *bg, const Mod
     const size_t nz = m.g.nz;
     HIP_TRY(hipMemcpy(m.d_nbg, bg->v_r, nz * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(m.d_nbg + nz, bg->v_theta, nz * 8, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(m.d_nbg + 2 * nz, bg->alpha, nz * 8, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(m.d_nbg + 3 * nz, bg->psi, nz * 8, hipMemcpyHostToDevice));
+    if (bg->v_phi) HIP_TRY(hipMemcpy(m.d_nbg + 2 * nz, bg->v_phi, nz * 8, hipMemcpyHostToDevice));
+    else HIP_TRY(hipMemset(m.d_nbg + 2 * nz, 0, nz * 8));
+    HIP_TRY(hipMemcpy(m.d_nbg + 3 * nz, bg->alpha, nz * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m.d_nbg + 4 * nz, bg->psi, nz * 8, hipMemcpyHostToDevice));
     const void *tk = m.tsize == 8 ? (const void *)time_remap_kernel<double> : (const void *)time_remap_kernel<float>;
     const size_t lds = time_lds_bytes(m.g.ndir, m.g.ne, m.tsize);
     if ((st = raise_lds_limit(tk, lds)) != BTX_OK) return st;
     const int2 *items = m.d_zitems;
-    const double *nvr = m.d_nbg, *nvth = m.d_nbg + nz, *nalp = m.d_nbg + 2 * nz, *npsi = m.d_nbg + 3 * nz;
-    void *args[] = { &d_models, &items, &parity, &nvr, &nvth, &nalp, &npsi };
+    const double *nbg = m.d_nbg;
+    void *args[] = { &d_models, &items, &parity, &nbg };
     HIP_TRY(hipLaunchKernel(tk, dim3((unsigned)nz), dim3(256), args, lds, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
@@ -1762,7 +1787,7 @@ btx_status model_source_terms(const Model &m, double *q, hipStream_t s)
 {
   if (!q) return fail(BTX_E_INVAL, "null argument");
   if (!m.have_bg || !m.have_state) return fail(BTX_E_STATE, "background and state must be set");
-  HIP_TRY(hipMemcpyAsync(q, m.d_q, (size_t)m.g.nz * 4 * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(q, m.d_q, (size_t)m.g.nz * 5 * 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return BTX_OK;
 }

@@ -110,7 +110,7 @@ bool gauss_rule(int rule, int n, std::vector<double> &x, std::vector<double> &w)
 std::string build_grid(Grid &g)
 {
   g.ndir = g.nmu * g.nphi;
-  g.nz = g.nr * g.nth;
+  g.nz = g.nr * g.nth * g.nph;        // zone (c n_theta + b) n_r + a
   // momentum grid: geometric group centres, shell volumes per unit solid angle
   g.eps.resize(g.ne);
   g.G.resize(g.ne);
@@ -162,14 +162,15 @@ std::string build_grid(Grid &g)
       A1[b] = 0.5 * norm(n);
       h1 = std::fabs(n.x * a.x + n.y * a.y + n.z * a.z) / norm(n);
     }
-    for (int a = 0; a < g.nr; ++a) {
-      int z = b * g.nr + a;
-      double r0 = g.r_e[a], r1 = g.r_e[a + 1];
-      g.rc[z] = 0.5 * (r0 + r1);
-      g.thc[z] = row_th(b);
-      // flat-faced cell = difference of two pyramids with apex at the origin
-      g.vol[z] = planar ? (r1 - r0) : (r1 * r1 * r1 - r0 * r0 * r0) * A1[b] * h1 / 3.0;
-    }
+    for (int c = 0; c < g.nph; ++c)
+      for (int a = 0; a < g.nr; ++a) {
+        int z = (c * g.nth + b) * g.nr + a;
+        double r0 = g.r_e[a], r1 = g.r_e[a + 1];
+        g.rc[z] = 0.5 * (r0 + r1);
+        g.thc[z] = row_th(b);
+        // flat-faced cell = difference of two pyramids with apex at the origin
+        g.vol[z] = planar ? (r1 - r0) : (r1 * r1 * r1 - r0 * r0 * r0) * A1[b] * h1 / 3.0;
+      }
   }
   auto zone_side = [&](int z, double th, double ph) {
     SideDesc s{ SIDE_ZONE, z, 1, 0, th, ph };
@@ -195,13 +196,14 @@ std::string build_grid(Grid &g)
     zf.side[zf.n] = side;
     ++zf.n;
   };
-  // radial (slab: z) faces
-  for (int b = 0; b < g.nth; ++b) {
+  // radial (slab: z) faces, per (phi zone, theta row) column
+  for (int col = 0; col < g.nph * g.nth; ++col) {
+    const int b = col % g.nth;
     double th = row_th(b);
     for (int a = -1; a < g.nr; ++a) {
       FaceDesc F{};
       double R = g.r_e[a + 1];
-      int zL = b * g.nr + a, zR = zL + 1;
+      int zL = col * g.nr + a, zR = zL + 1;
       F.axis = 0;
       F.active = planar || R > 0.0;
       F.area = planar ? 1.0 : R * R * A1[b];
@@ -232,10 +234,11 @@ std::string build_grid(Grid &g)
   }
   // theta faces
   if (twod) {
+    for (int c = 0; c < g.nph; ++c) {
     for (int b = 0; b + 1 < g.nth; ++b)
       for (int a = 0; a < g.nr; ++a) {
         FaceDesc F{};
-        int zL = b * g.nr + a, zR = zL + g.nr;
+        int zL = (c * g.nth + b) * g.nr + a, zR = zL + g.nr;
         double tf = g.th_e[b + 1], p0 = -0.5 * g.dphi, p1 = 0.5 * g.dphi;
         F.axis = 1;
         F.active = 1;
@@ -263,7 +266,7 @@ std::string build_grid(Grid &g)
     if (disk)                             // the equatorial boundary faces
       for (int a = 0; a < g.nr; ++a) {
         FaceDesc F{};
-        const int b = g.nth - 1, zL = b * g.nr + a;
+        const int b = g.nth - 1, zL = (c * g.nth + b) * g.nr + a;
         double tf = g.th_e[g.nth], p0 = -0.5 * g.dphi, p1 = 0.5 * g.dphi;
         F.axis = 1;
         F.active = 1;
@@ -285,6 +288,7 @@ std::string build_grid(Grid &g)
         g.bface.push_back(fid);
         add_zone_face(zL, fid, 0);
       }
+    }
   } else if (!planar) {                   // column: periodic self-face in theta
     for (int a = 0; a < g.nr; ++a) {
       FaceDesc F{};
@@ -312,23 +316,25 @@ std::string build_grid(Grid &g)
       add_zone_face(z, fid, 1);
     }
   }
-  // phi faces: periodic self-faces (2D wedge and column)
+  // phi faces: between phi zone c and c+1 (periodic); the zone's own image
+  // one wedge over in the axisymmetric wedge and the column
   if (!planar) {
     for (int z = 0; z < g.nz; ++z) {
       FaceDesc F{};
-      int a = z % g.nr, b = z / g.nr;
+      int a = z % g.nr, b = (z / g.nr) % g.nth, c = z / (g.nr * g.nth);
+      auto at = [&](int cc) { return (((cc % g.nph) + g.nph) % g.nph * g.nth + b) * g.nr + a; };
       double t0, t1, p0, p1;
       row_angles(b, t0, t1, p0, p1);
       double w = p1 - p0, pf = 0.5 * w, th = g.thc[z];
       F.axis = 2;
       F.active = 1;
-      F.self = 1;
+      F.self = g.nph == 1;
       F.area = quad(point(g.r_e[a], t0, pf), point(g.r_e[a + 1], t0, pf),
                     point(g.r_e[a + 1], t1, pf), point(g.r_e[a], t1, pf));
       F.L = zone_side(z, th, 0.0);
-      F.R = zone_side(z, th, w);
-      F.Lm = zone_side(z, th, -w);
-      F.Rp = zone_side(z, th, 2.0 * w);
+      F.R = zone_side(at(c + 1), th, w);
+      F.Lm = zone_side(at(c - 1), th, -w);
+      F.Rp = zone_side(at(c + 2), th, 2.0 * w);
       F.h = dist(g.rc[z], th, 0.0, g.rc[z], th, w);
       F.hLm = F.hRp = F.h;
       F.dL = 0.5 * F.h;
@@ -338,7 +344,7 @@ std::string build_grid(Grid &g)
       int fid = (int)g.faces.size();
       g.faces.push_back(F);
       add_zone_face(z, fid, 0);
-      add_zone_face(z, fid, 1);
+      add_zone_face(at(c + 1), fid, 1);
     }
   }
   return "";

@@ -43,7 +43,7 @@ struct ZoneFaces {   // faces touching a zone, and the side the zone is on
 };
 
 struct Grid {
-  int nr = 0, nth = 0, ne = 0, nmu = 0, nphi = 0, ns = 0, ndir = 0, nz = 0;
+  int nr = 0, nth = 0, nph = 1, ne = 0, nmu = 0, nphi = 0, ns = 0, ndir = 0, nz = 0;
   int geom = 0, mu_rule = 0, phi_rule = 0, inner_bc = 0, outer_bc = 0, prec = 0;
   int theta_bc = 0;                                     // 1: equatorial disk boundary at pi/2
   double disk_r = 0;

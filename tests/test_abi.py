@@ -85,3 +85,23 @@ def test_null_arguments_rejected_without_device(lib_path):
     assert L.btx_max_dt(None, C.c_double(0.4), None) == 1
     L.btx_destroy.restype = C.c_int
     assert L.btx_destroy(None) == 0
+
+
+def test_descriptors_carry_every_field():
+    """the marshalled grid and background carry the 3D and disk fields
+    (v_phi is NULL when the workload has none)"""
+    import numpy as np
+    from paper_2003_02845_amd import btx
+    from paper_2003_02845_amd import workloads as W
+    w = W.extrude_phi(W.axisym_2d(n_r=4, n_theta=3, n_eps=2, n_mu=2, n_phi=3), 2)
+    w.v_phi = np.linspace(-0.1, 0.1, w.n_zones)
+    d, _ = btx._desc(w, W.PREC_FP64, 1.0)
+    assert d.n_phi_zones == 2 and d.theta_bc == W.THETA_AXIS
+    bg, _ = btx._background(w)
+    assert bg.v_phi and bg.v_phi[w.n_zones - 1] == 0.1
+    w.v_phi = None
+    bg, _ = btx._background(w)
+    assert not bg.v_phi
+    dk = W.radiating_disk(n_r=4, n_theta=3, n_mu=2, n_phi=3)
+    d, _ = btx._desc(dk, W.PREC_FP64, 1.0)
+    assert d.theta_bc == W.THETA_DISK and d.disk_radius == 1.0

@@ -61,6 +61,9 @@ CASES = {
     # outflow ghosts on theta faces)
     "disk": lambda: _perturb(W.radiating_disk(n_r=12, n_theta=5, n_mu=6, n_phi=8, r_min=0.2,
                                               r_max=2.5)),
+    # 3D: four phi zones, state and background varying with phi, v_phi
+    "shock_3d": lambda: _turned(W.shock_2d(n_r=8, n_theta=4, n_eps=6, n_mu=4, n_phi=4,
+                                           precision=W.PREC_FP64), 4),
 }
 
 
@@ -68,6 +71,15 @@ def _beam_case():
     sys.path.insert(0, __import__("os").path.dirname(__file__))
     from test_oracle_pins import _beam
     return _beam()[0]
+
+
+def _turned(w, n_phi_zones):
+    w3 = W.extrude_phi(w, n_phi_zones)
+    w3.f0 = w3.f0 * (1.0 + 0.3 * RNG.random(w3.f0.shape)) + 1e-3 * RNG.random(w3.f0.shape)
+    w3.v_phi = 0.05 * RNG.standard_normal(w3.n_zones)
+    w3.v_r = w3.v_r * (1.0 + 0.1 * RNG.random(w3.n_zones))
+    w3.kappa_a = w3.kappa_a * (1.0 + RNG.random(w3.kappa_a.shape))
+    return w3
 
 
 def _steep(w):
@@ -110,7 +122,8 @@ def test_fp64_parity(case, oracle_mod):
     ctx.close()
 
 
-@pytest.mark.parametrize("case", ["shock_3species", "column_lobatto_v", "split_groups", "large_shift"])
+@pytest.mark.parametrize("case", ["shock_3species", "column_lobatto_v", "split_groups", "large_shift",
+                                  "shock_3d"])
 def test_mixed_moments(case, oracle_mod):
     w = CASES[case]()
     _say(f"[gpu] mixed moments {case}")
@@ -244,7 +257,7 @@ def _pins():
     return test_oracle_pins
 
 
-@pytest.mark.parametrize("case", ["shock_3species", "large_shift", "planar"])
+@pytest.mark.parametrize("case", ["shock_3species", "large_shift", "planar", "shock_3d"])
 @pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
 def test_source_terms_gpu(case, precision, oracle_mod):
     """hydro source terms (Eq. hydrosource1-3) of the last of three steps,
@@ -283,3 +296,31 @@ def test_batch_source_terms_gpu(oracle_mod):
         scale = _pins()._gross_rate(w, o.state())[:, None]
         assert np.max(np.abs(b.source_terms(m) - o.source_terms()) / scale) <= 1e-12
     b.close()
+
+
+def test_evolving_background_3d_gpu(oracle_mod):
+    """a 3D grid whose background (v_phi included) evolves: FP64 against the
+    reference after the time remap and after more steps"""
+    btx = _btx()
+    w = _turned(W.shock_2d(n_r=8, n_theta=4, n_eps=6, n_mu=4, n_phi=4, precision=W.PREC_FP64), 3)
+    w2 = _evolved(w)
+    w2.v_phi = -0.5 * w.v_phi + 0.02
+    _say("[gpu] evolving background, 3D")
+    o = oracle_mod.Oracle(w)
+    dt = 0.9 * o.max_dt(0.4)
+    ctx = btx.Context(w, precision=W.PREC_FP64)
+    ctx.set_background()
+    ctx.set_state(w.f0)
+    o.step(dt, 2)
+    ctx.step(dt, 2)
+    o.update_background(w2)
+    ctx.update_background(w2)
+    ref, got = o.state(), ctx.get_state()
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    o.step(dt, 2)
+    ctx.step(dt, 2)
+    ref, got = o.state(), ctx.get_state()
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _say(f"[gpu]   rel err {err:.3e}")
+    assert err <= 1e-12
+    ctx.close()

@@ -319,6 +319,7 @@ std::string build_grid(Grid &g)
   // phi faces: between phi zone c and c+1 (periodic); the zone's own image
   // one wedge over in the axisymmetric wedge and the column
   if (!planar) {
+    const int base = (int)g.faces.size();   // the phi face of zone z is base + z
     for (int z = 0; z < g.nz; ++z) {
       FaceDesc F{};
       int a = z % g.nr, b = (z / g.nr) % g.nth, c = z / (g.nr * g.nth);
@@ -341,10 +342,11 @@ std::string build_grid(Grid &g)
       F.dR = -0.5 * F.h;
       F.ths = th;
       F.phs = pf;
-      int fid = (int)g.faces.size();
       g.faces.push_back(F);
-      add_zone_face(z, fid, 0);
-      add_zone_face(at(c + 1), fid, 1);
+      // each zone lists its own phi face (zone is L), then its predecessor's
+      // (zone is R), the order of the axisymmetric wedge's self-face
+      add_zone_face(z, base + z, 0);
+      add_zone_face(z, base + at(c - 1), 1);
     }
   }
   return "";

@@ -123,24 +123,29 @@ def test_radiating_disk_2d():
 
 def test_3d_symmetric_equals_axisymmetric_gpu():
     """a 3D grid of four copies of the wedge around the axis, with data
-    independent of phi, steps exactly like the axisymmetric wedge on the GPU
-    (both precisions, bit for bit), and its phi momentum source term is zero"""
+    independent of phi, steps like the axisymmetric wedge on the GPU.  Not bit
+    for bit: the wedge's periodic self-face reuses the zone's own slope,
+    while a 3D phi face limits each side's slope in its own frame (the same
+    value up to rounding).  FP64 to 1e-13, mixed to 1e-5, relative to the
+    block maximum; the phi momentum source term vanishes to the same level."""
     btx = _btx()
     w2 = W.shock_2d(n_r=16, n_theta=8, n_eps=8, n_mu=6, n_phi=4, precision=W.PREC_FP64)
     w2.f0 = w2.f0 * (1.0 + 0.3 * np.random.default_rng(3).random(w2.f0.shape))
     w3 = W.extrude_phi(w2, 4)
     _say(f"[gpu] 3D (4 phi zones) against the axisymmetric wedge, {w2.n_zones} zones per wedge")
-    for prec in (W.PREC_FP64, W.PREC_MIXED):
+    for prec, tol in ((W.PREC_FP64, 1e-13), (W.PREC_MIXED, 1e-5)):
         out = []
         for w in (w2, w3):
             ctx = btx.Context(w, precision=prec)
             ctx.set_background()
             ctx.set_state(w.f0)
             ctx.step(ctx.max_dt(0.4), 3)
-            out.append((ctx.get_state(), ctx.source_terms()))
+            out.append((ctx.get_state().astype(np.float64), ctx.source_terms()))
             ctx.close()
-        s3 = out[1][0].reshape((4,) + out[0][0].shape)
-        for c in range(4):
-            assert np.array_equal(s3[c], out[0][0]), (prec, c)
-        q3 = out[1][1].reshape(4, w2.n_zones, 5)
-        assert np.array_equal(q3[2], out[0][1])
+        ref = out[0][0]
+        s3 = out[1][0].reshape((4,) + ref.shape)
+        errs = [float(np.max(np.abs(s3[c] - ref)) / np.max(np.abs(ref))) for c in range(4)]
+        q2, q3 = out[0][1], out[1][1].reshape(4, w2.n_zones, 5)
+        qerr = float(np.max(np.abs(q3 - q2[None])) / np.max(np.abs(q2)))
+        _say(f"[gpu]   precision {prec}: state {max(errs):.3e}, source terms {qerr:.3e}")
+        assert max(errs) <= tol and qerr <= 10 * tol

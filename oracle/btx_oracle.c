@@ -58,6 +58,8 @@ struct orc_ctx {
   int have_bg, have_state;
   double *f, *fn, *outflow;
   double *q;        /* hydro source terms of the last full step, [zone][5] */
+  int *lev;         /* time level of every zone (local time stepping), or NULL */
+  int lmax;
   int blend_mode;
 };
 
@@ -348,7 +350,7 @@ static void free_all(orc_ctx *c)
   free(c->r_e); free(c->th_e); free(c->e_e); free(c->eps); free(c->G); free(c->mu);
   free(c->wmu); free(c->Phi); free(c->dOm); free(c->nvec); free(c->rc); free(c->thc);
   free(c->vol); free(c->vr); free(c->vth); free(c->vph); free(c->alp); free(c->psi); free(c->ka);
-  free(c->ks); free(c->feq); free(c->f); free(c->fn); free(c->outflow); free(c->q);
+  free(c->ks); free(c->feq); free(c->f); free(c->fn); free(c->outflow); free(c->q); free(c->lev);
 }
 
 orc_ctx *orc_create(const orc_desc *d)
@@ -954,6 +956,55 @@ static const double *slope_ptr(const orc_ctx *c, const work_t *w, int axis, int 
   return slot < 0 ? NULL : w->sbuf + (size_t)slot * c->blk;
 }
 
+/* Conservative update and zone-local implicit collision of zone z (Eq.
+ * fullstep, Sec. 3.5) over a step dt: the zone's summed face content changes
+ * dN are divided by its bin content weights W = psi^6 dV u0 dGamma and the
+ * collisions are solved; writes f^{n+1} of the zone to out and its hydro
+ * source terms to qz[5]. */
+static void zone_update(const orc_ctx *c, int z, const double *dN, double dt, double *out, double qz[5])
+{
+  int n = c->eblk, ne = c->ne, nd = c->ndir;
+  double *dJ = (double *)malloc(sizeof(double) * nd), *tmp = (double *)malloc(sizeof(double) * nd);
+  frame_t self = zone_frame(c, z, zone_th(c, z), 0.0);
+  double g = gamma_of(self.v), p6 = pow(self.psi, 6.0);
+  double tau = self.alpha * dt / g;             /* Reading: dt_c = alpha dt / gamma */
+  for (int k = 0; k < 5; ++k) qz[k] = 0.0;
+  for (int s = 0; s < c->ns; ++s)
+    for (int i = 0; i < ne; ++i) {
+      const double *fz0 = c->f + (size_t)z * c->blk + (size_t)s * n + (size_t)i * nd;
+      for (int d = 0; d < nd; ++d) {
+        double W = p6 * c->vol[z] * u0_of(c, &self, d) * c->G[i] * c->dOm[d];
+        dJ[d] = dN[(size_t)s * n + i * nd + d] / W;
+      }
+      size_t kidx = ((size_t)z * c->ns + s) * ne + i;
+      orc_collide(nd, fz0, dJ, tau, c->ka[kidx], c->ks[kidx], c->feq[kidx], c->dOm, tmp);
+      memcpy(out + (size_t)s * n + (size_t)i * nd, tmp, sizeof(double) * nd);
+      /* hydro source terms (Eq. hydrosource1-3): the collision term of
+       * Eq. sourceterms_discrete at the new distribution f' (backward Euler
+       * puts the whole collision change of the step there), integrated over
+       * each bin's momentum-space cell G_i dOmega_d with weight 1 (lepton
+       * number: + for the first species, - for the second), eps_i (energy)
+       * and eps_i n_d (momentum, r, theta and phi components); the fluid gains
+       * what the radiation loses.  Readings: d^3p = eps^2 deps dOmega, so
+       * the bin integrals are G_i dOmega_d; the 1/h^3 normalisation is
+       * omitted; comoving frame, per unit comoving volume and time. */
+      double ka = c->ka[kidx], ks = c->ks[kidx], fe = c->feq[kidx], avg = 0.0;
+      for (int d = 0; d < nd; ++d) avg += tmp[d] * c->dOm[d];
+      avg /= 4.0 * PI;
+      double lep = s == 0 ? 1.0 : (s == 1 ? -1.0 : 0.0);
+      for (int d = 0; d < nd; ++d) {
+        double C = ka * (fe - tmp[d]) + ks * avg - ks * tmp[d];
+        double wgt = C * c->G[i] * c->dOm[d];
+        qz[0] -= lep * wgt;
+        qz[1] -= wgt * c->eps[i];
+        qz[2] -= wgt * c->eps[i] * c->nvec[3 * d];
+        qz[3] -= wgt * c->eps[i] * c->nvec[3 * d + 1];
+        qz[4] -= wgt * c->eps[i] * c->nvec[3 * d + 2];
+      }
+    }
+  free(dJ); free(tmp);
+}
+
 /* one step for the listed zones; writes f^{n+1} blocks to fout (list order) */
 static int do_step(orc_ctx *c, double dt, int nlist, const int *zones, double *fout,
                    double *out_tally)
@@ -1002,55 +1053,18 @@ static int do_step(orc_ctx *c, double dt, int nlist, const int *zones, double *f
    * its bin content weights W = psi^6 dV u0 dGamma and solves the collisions. */
 #pragma omp parallel for schedule(dynamic)
   for (int l = 0; l < nlist; ++l) {
-    int z = zones[l], n = c->eblk, ne = c->ne, nd = c->ndir;
+    int z = zones[l];
     int fz[8], sz[8];
     int nfz = zone_faces(c, z, fz, sz);
     double *dN = (double *)calloc((size_t)c->blk, sizeof(double));
-    double *dJ = (double *)malloc(sizeof(double) * nd), *tmp = (double *)malloc(sizeof(double) * nd);
     for (int q = 0; q < nfz; ++q) {
       const double *src = w.fbuf + 2 * (size_t)w.slot_face[fz[q]] * c->blk + (sz[q] > 0 ? c->blk : 0);
       for (int p = 0; p < c->blk; ++p) dN[p] += src[p];
     }
-    frame_t self = zone_frame(c, z, zone_th(c, z), 0.0);
-    double g = gamma_of(self.v), p6 = pow(self.psi, 6.0);
-    double tau = self.alpha * dt / g;             /* Reading: dt_c = alpha dt / gamma */
-    double *out = fout + (size_t)l * c->blk;
-    double qz[5] = { 0.0, 0.0, 0.0, 0.0, 0.0 };
-    for (int s = 0; s < c->ns; ++s)
-      for (int i = 0; i < ne; ++i) {
-        const double *fz0 = c->f + (size_t)z * c->blk + (size_t)s * n + (size_t)i * nd;
-        for (int d = 0; d < nd; ++d) {
-          double W = p6 * c->vol[z] * u0_of(c, &self, d) * c->G[i] * c->dOm[d];
-          dJ[d] = dN[(size_t)s * n + i * nd + d] / W;
-        }
-        size_t kidx = ((size_t)z * c->ns + s) * ne + i;
-        orc_collide(nd, fz0, dJ, tau, c->ka[kidx], c->ks[kidx], c->feq[kidx], c->dOm, tmp);
-        memcpy(out + (size_t)s * n + (size_t)i * nd, tmp, sizeof(double) * nd);
-        /* hydro source terms (Eq. hydrosource1-3): the collision term of
-         * Eq. sourceterms_discrete at the new distribution f' (backward Euler
-         * puts the whole collision change of the step there), integrated over
-         * each bin's momentum-space cell G_i dOmega_d with weight 1 (lepton
-         * number: + for the first species, - for the second), eps_i (energy)
-         * and eps_i n_d (momentum, r, theta and phi components); the fluid gains
-         * what the radiation loses.  Readings: d^3p = eps^2 deps dOmega, so
-         * the bin integrals are G_i dOmega_d; the 1/h^3 normalisation is
-         * omitted; comoving frame, per unit comoving volume and time. */
-        double ka = c->ka[kidx], ks = c->ks[kidx], fe = c->feq[kidx], avg = 0.0;
-        for (int d = 0; d < nd; ++d) avg += tmp[d] * c->dOm[d];
-        avg /= 4.0 * PI;
-        double lep = s == 0 ? 1.0 : (s == 1 ? -1.0 : 0.0);
-        for (int d = 0; d < nd; ++d) {
-          double C = ka * (fe - tmp[d]) + ks * avg - ks * tmp[d];
-          double wgt = C * c->G[i] * c->dOm[d];
-          qz[0] -= lep * wgt;
-          qz[1] -= wgt * c->eps[i];
-          qz[2] -= wgt * c->eps[i] * c->nvec[3 * d];
-          qz[3] -= wgt * c->eps[i] * c->nvec[3 * d + 1];
-          qz[4] -= wgt * c->eps[i] * c->nvec[3 * d + 2];
-        }
-      }
+    double qz[5];
+    zone_update(c, z, dN, dt, fout + (size_t)l * c->blk, qz);
     if (out_tally) memcpy(c->q + 5 * (size_t)z, qz, sizeof(qz));
-    free(dN); free(dJ); free(tmp);
+    free(dN);
   }
   /* number leaving the domain: what the boundary ghosts would receive */
   if (out_tally) {
@@ -1075,9 +1089,18 @@ static int do_step(orc_ctx *c, double dt, int nlist, const int *zones, double *f
   return 0;
 }
 
+static int lts_step(orc_ctx *c, double dt0);
+
 int orc_step(orc_ctx *c, double dt, int n_steps)
 {
   if (!c || !c->have_bg || !c->have_state) return 5;
+  if (c->lev) {
+    for (int t = 0; t < n_steps; ++t) {
+      int rc = lts_step(c, dt);
+      if (rc) return rc;
+    }
+    return 0;
+  }
   int *all = (int *)malloc(sizeof(int) * c->nz);
   for (int z = 0; z < c->nz; ++z) all[z] = z;
   for (int t = 0; t < n_steps; ++t) {
@@ -1206,5 +1229,147 @@ int orc_source_terms(const orc_ctx *c, double *q)
 {
   if (!c) return 1;
   memcpy(q, c->q, sizeof(double) * 5 * (size_t)c->nz);
+  return 0;
+}
+
+/* ------------------------------------------------- local time stepping */
+
+/* Courant length of zone z: its volume over its largest face on an axis,
+ * the smallest over the axes (the global step is cfl times its minimum) */
+static double courant_length(const orc_ctx *c, int z)
+{
+  int fids[8], sg[8];
+  double amax[3] = { 0.0, 0.0, 0.0 }, m = 1e300;
+  int nfz = zone_faces(c, z, fids, sg);
+  for (int q = 0; q < nfz; ++q) {
+    double A;
+    int ax = fids[q] < c->nfr ? 0 : (fids[q] < c->nfr + c->nft ? 1 : 2);
+    get_face_geom(c, fids[q], &A);
+    if (A > amax[ax]) amax[ax] = A;
+  }
+  for (int ax = 0; ax < 3; ++ax)
+    if (amax[ax] > 0.0 && c->vol[z] / amax[ax] < m) m = c->vol[z] / amax[ax];
+  return m;
+}
+
+/* Time levels for local time stepping (Sec. 6 names it as the way to stop
+ * the small central zones from setting every zone's step; the paper gives no
+ * scheme).  Reading: zone z steps with 2^l dt0, l = floor(log2(L_z / L_min))
+ * of its Courant length L_z, capped at max_level, then lowered until zones
+ * that share a face differ by at most one level. */
+int orc_time_levels(const orc_ctx *c, int max_level, int *lev)
+{
+  if (!c || max_level < 0 || max_level > 16) return 1;
+  double lmin = 1e300;
+  double *L = (double *)malloc(sizeof(double) * c->nz);
+  for (int z = 0; z < c->nz; ++z) { L[z] = courant_length(c, z); if (L[z] < lmin) lmin = L[z]; }
+  for (int z = 0; z < c->nz; ++z) {
+    int l = 0;
+    while (l < max_level && L[z] >= lmin * (double)(2 << l) * (1.0 - 1e-12)) ++l;
+    lev[z] = l;
+  }
+  free(L);
+  for (int changed = 1; changed;) {
+    changed = 0;
+    for (int f = 0; f < c->nf; ++f) {
+      face_t F;
+      get_face(c, f, &F);
+      if (!F.active || F.L.kind != SIDE_ZONE || F.R.kind != SIDE_ZONE) continue;
+      int a = F.L.z, b = F.R.z;
+      if (lev[a] > lev[b] + 1) { lev[a] = lev[b] + 1; changed = 1; }
+      if (lev[b] > lev[a] + 1) { lev[b] = lev[a] + 1; changed = 1; }
+    }
+  }
+  return 0;
+}
+
+/* levels: per zone, 0..16, neighbours at most one apart; NULL: global step */
+int orc_set_levels(orc_ctx *c, const int *levels)
+{
+  if (!c) return 1;
+  free(c->lev);
+  c->lev = NULL;
+  c->lmax = 0;
+  if (!levels) return 0;
+  c->lev = (int *)malloc(sizeof(int) * c->nz);
+  for (int z = 0; z < c->nz; ++z) {
+    if (levels[z] < 0 || levels[z] > 16) { free(c->lev); c->lev = NULL; return 1; }
+    c->lev[z] = levels[z];
+    if (levels[z] > c->lmax) c->lmax = levels[z];
+  }
+  return 0;
+}
+
+/* One step with time levels: 2^L substeps of dt0, L the highest level.  At
+ * substep k every face whose finer zone starts a step (k mod 2^m = 0, m the
+ * smaller level of the zones on its sides) is evaluated from the current
+ * state with dt = 2^m dt0, and its content changes are added to the zones on
+ * both sides; then every zone whose step ends (k + 1 mod 2^l = 0) is updated
+ * with the changes it gathered and dt = 2^l dt0.  A zone at a coarser level
+ * thus receives the fluxes of each of its finer neighbour's steps, and what
+ * leaves one zone enters the other.  With every level 0 this is the global
+ * step. */
+static int lts_step(orc_ctx *c, double dt0)
+{
+  const size_t blk = c->blk;
+  double *acc = (double *)calloc((size_t)c->nz * blk, sizeof(double));
+  double *fbuf = (double *)malloc(sizeof(double) * 2 * blk * (size_t)c->nf);
+  int *on = (int *)malloc(sizeof(int) * c->nf);
+  if (!acc || !fbuf || !on) { free(acc); free(fbuf); free(on); return 2; }
+  const int nsub = 1 << c->lmax;
+  for (int k = 0; k < nsub; ++k) {
+    const double *f = c->f;
+#pragma omp parallel for schedule(dynamic)
+    for (int q = 0; q < c->nf; ++q) {
+      face_t F;
+      get_face(c, q, &F);
+      int m = c->lev[F.L.z] < c->lev[F.R.z] ? c->lev[F.L.z] : c->lev[F.R.z];
+      on[q] = F.active && k % (1 << m) == 0;
+      if (!on[q]) continue;
+      double *sL = (double *)calloc(blk, sizeof(double)), *sR = (double *)calloc(blk, sizeof(double));
+      if (F.L.has_slope) zone_slope(c, f, F.L.z, F.axis, sL);
+      if (F.R.has_slope) zone_slope(c, f, F.R.z, F.axis, sR);
+      double *dl = fbuf + 2 * (size_t)q * blk;
+      face_contrib(c, &F, f, sL, sR, dt0 * (double)(1 << m), dl, dl + blk, NULL, NULL);
+      free(sL); free(sR);
+    }
+#pragma omp parallel for schedule(dynamic)
+    for (int z = 0; z < c->nz; ++z) {
+      int fz[8], sz[8], nfz = zone_faces(c, z, fz, sz);
+      for (int q = 0; q < nfz; ++q) {
+        if (!on[fz[q]]) continue;
+        const double *src = fbuf + 2 * (size_t)fz[q] * blk + (sz[q] > 0 ? blk : 0);
+        double *dst = acc + (size_t)z * blk;
+        for (size_t p = 0; p < blk; ++p) dst[p] += src[p];
+      }
+    }
+    for (int q = 0; q < c->nf; ++q) {             /* number leaving the domain */
+      if (!on[q]) continue;
+      face_t F;
+      get_face(c, q, &F);
+      for (int side = 0; side < 2; ++side) {
+        const side_t *sd = side ? &F.R : &F.L;
+        if (sd->kind == SIDE_ZONE) continue;
+        const double *src = fbuf + 2 * (size_t)q * blk + (side ? blk : 0);
+        for (int s = 0; s < c->ns; ++s) {
+          double t = 0.0;
+          for (int p = 0; p < c->eblk; ++p) t += src[(size_t)s * c->eblk + p];
+          c->outflow[s] += t;
+        }
+      }
+    }
+#pragma omp parallel for schedule(dynamic)
+    for (int z = 0; z < c->nz; ++z) {
+      if ((k + 1) % (1 << c->lev[z])) continue;
+      zone_update(c, z, acc + (size_t)z * blk, dt0 * (double)(1 << c->lev[z]),
+                  c->fn + (size_t)z * blk, c->q + 5 * (size_t)z);
+    }
+    for (int z = 0; z < c->nz; ++z) {            /* the updated zones take their new state */
+      if ((k + 1) % (1 << c->lev[z])) continue;
+      memcpy(c->f + (size_t)z * blk, c->fn + (size_t)z * blk, sizeof(double) * blk);
+      memset(acc + (size_t)z * blk, 0, sizeof(double) * blk);
+    }
+  }
+  free(acc); free(fbuf); free(on);
   return 0;
 }

@@ -59,6 +59,12 @@ int orc_update_background(orc_ctx *c, const double *v_r, const double *v_theta,
 /* hydro source terms of the last full step (Eq. hydrosource1-3):
  * q[zone][5] = Q_Ye, Q_E, Q_M,r, Q_M,theta, Q_M,phi */
 int orc_source_terms(const orc_ctx *c, double *q);
+/* local time stepping: time levels from the zones' Courant lengths (at most
+ * max_level, neighbours at most one apart), and the levels to step with
+ * (NULL: the global step).  With levels, one orc_step step is 2^L substeps of
+ * dt, L the highest level. */
+int orc_time_levels(const orc_ctx *c, int max_level, int *levels);
+int orc_set_levels(orc_ctx *c, const int *levels);
 int orc_set_state(orc_ctx *c, const double *f);
 int orc_get_state(const orc_ctx *c, double *f);
 double orc_max_dt(const orc_ctx *c, double cfl);

@@ -56,6 +56,8 @@ def lib():
         L.orc_set_background.argtypes = [C.c_void_p] + [_dp] * 8
         L.orc_update_background.argtypes = [C.c_void_p] + [_dp] * 8
         L.orc_source_terms.argtypes = [C.c_void_p, _dp]
+        L.orc_time_levels.argtypes = [C.c_void_p, C.c_int, _ip]
+        L.orc_set_levels.argtypes = [C.c_void_p, _ip]
         L.orc_set_state.argtypes = [C.c_void_p, _dp]
         L.orc_get_state.argtypes = [C.c_void_p, _dp]
         L.orc_max_dt.restype = C.c_double
@@ -187,6 +189,19 @@ class Oracle:
         if rc:
             raise RuntimeError(f"orc_step_sample failed ({rc})")
         return out
+
+    def time_levels(self, max_level):
+        lev = np.zeros(self.w.n_zones, dtype=np.int32)
+        assert lib().orc_time_levels(self.ctx, max_level, lev.ctypes.data_as(_ip)) == 0
+        return lev
+
+    def set_levels(self, levels):
+        """per-zone time levels for local time stepping (None: global step)"""
+        if levels is None:
+            assert lib().orc_set_levels(self.ctx, None) == 0
+            return
+        self._lev = np.ascontiguousarray(levels, dtype=np.int32)
+        assert lib().orc_set_levels(self.ctx, self._lev.ctypes.data_as(_ip)) == 0
 
     def source_terms(self):
         """[zone][5]: Q_Ye, Q_E, Q_M,r, Q_M,theta, Q_M,phi of the last full step"""

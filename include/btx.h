@@ -151,6 +151,23 @@ btx_status btx_moments(btx_ctx *ctx, double *zone_moments, double *totals);
  * phi) directions (Q_M).  No 1/h^3.  Zero before the first step.  Computed
  * in FP64 by the zone update; synchronises the stream. */
 btx_status btx_source_terms(btx_ctx *ctx, double *q);
+/* Local time stepping (the saving Sec. 6 proposes over the global step set
+ * by the smallest zones; the paper gives no scheme, this is the library's).
+ * btx_time_levels proposes a level per zone: zone z may take 2^l global
+ * steps at once when 2^l times the smallest Courant length is within its own
+ * (l <= max_level <= 16), and zones sharing a face are at most one level
+ * apart.  btx_set_time_levels adopts levels[zone] (0..16; NULL returns to the
+ * global step).  With levels, one btx_step step of size dt is 2^L substeps of
+ * dt (L the highest level): at substep k every face whose finer zone starts a
+ * step (k mod 2^m = 0) is evaluated with dt 2^m, and every zone whose step
+ * ends (k + 1 mod 2^l = 0) is updated with the content changes it gathered
+ * since its last update and dt 2^l; so every zone advances 2^L dt per step
+ * and the number crossing a face leaves one zone and enters the other.
+ * btx_step rejects dt when a zone's 2^l dt exceeds its own Courant length.
+ * Source terms are those of each zone's last update.  btx_timing records
+ * global steps only.  Synchronises the stream. */
+btx_status btx_time_levels(const btx_ctx *ctx, int32_t max_level, int32_t *levels);
+btx_status btx_set_time_levels(btx_ctx *ctx, const int32_t *levels);
 /* Per-kernel GPU time: enable = 1 records HIP events around the kernels of
  * each btx_step step on the context's stream (no synchronisation; up to 256
  * steps between two queries).  The query synchronises the recorded events and

@@ -28,7 +28,8 @@ ABI_SYMBOLS = ["btx_create", "btx_set_background", "btx_max_dt", "btx_set_state"
                "btx_batch_set_background", "btx_batch_update_background",
                "btx_batch_max_dt", "btx_batch_set_state", "btx_batch_get_state", "btx_batch_step",
                "btx_batch_use_graph", "btx_batch_shape", "btx_batch_moments", "btx_batch_destroy",
-               "btx_source_terms", "btx_batch_source_terms"]
+               "btx_source_terms", "btx_batch_source_terms", "btx_time_levels",
+               "btx_set_time_levels"]
 
 _dp = C.POINTER(C.c_double)
 
@@ -87,6 +88,8 @@ def lib():
         L.btx_batch_shape.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.btx_batch_moments.argtypes = [vp, C.c_int32, _dp, _dp]
         L.btx_source_terms.argtypes = [vp, _dp]
+        L.btx_time_levels.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
+        L.btx_set_time_levels.argtypes = [vp, C.POINTER(C.c_int32)]
         L.btx_batch_source_terms.argtypes = [vp, C.c_int32, _dp]
         L.btx_batch_destroy.argtypes = [vp]
         L.btx_last_error.restype = C.c_char_p
@@ -192,6 +195,21 @@ class Context:
         tot = np.zeros((self.w.n_species, 3))
         _check(lib().btx_moments(self.h, _p(zm), _p(tot)))
         return zm, tot
+
+    def time_levels(self, max_level):
+        """the library's proposal of a time level per zone (local time stepping)"""
+        lev = np.zeros(self.w.n_zones, dtype=np.int32)
+        _check(lib().btx_time_levels(self.h, int(max_level), lev.ctypes.data_as(C.POINTER(C.c_int32))))
+        return lev
+
+    def set_time_levels(self, levels):
+        """adopt per-zone time levels (None: the global step); one step is then
+        2^max(levels) substeps of dt"""
+        if levels is None:
+            _check(lib().btx_set_time_levels(self.h, None))
+            return
+        self._lev = np.ascontiguousarray(levels, dtype=np.int32)
+        _check(lib().btx_set_time_levels(self.h, self._lev.ctypes.data_as(C.POINTER(C.c_int32))))
 
     def source_terms(self):
         """[zone][5]: Q_Ye, Q_E, Q_M,r, Q_M,theta, Q_M,phi of the last step"""

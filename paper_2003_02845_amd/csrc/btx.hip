@@ -94,6 +94,7 @@ struct ModelDev {
   void *dN;                    // [face][side][species][group][direction]
   double *tally;               // [face][species] cumulative content through ghost faces
   double *q;                   // [zone][5] hydro source terms of the last step
+  const unsigned char *zlev;   // [zone] time level (local time stepping), or null
   double dt;                   // step of the current launch
 };
 
@@ -818,7 +819,7 @@ __device__ __forceinline__ void store_side(const T v[CE], const T gl[CE], T a, i
 //   phase 3 remapped content change of both sides (Eq. fullstep)
 template <typename T, int NCH, int CE, int MAXT, bool SPLIT>
 __global__ void __launch_bounds__(MAXT)
-face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity)
+face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity, int sub)
 {
   extern __shared__ __align__(16) char lds[];
   const int2 it = items[blockIdx.x];
@@ -832,13 +833,22 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   const T *__restrict__ feq = as_global((const T *)M.feq);
   T *__restrict__ dN = as_global((T *)M.dN);
   double *__restrict__ tally = as_global(M.tally);
-  const double dt = M.dt;
   const int fid = it.y;
   const FaceDesc &F = as_global(M.faces)[fid];
+  // Time levels: the face steps with its finer zone, dt0 2^m; a side whose
+  // zone is at a coarser level adds this step's changes to those it already
+  // holds, unless its own step starts at this substep.
+  int lvL = 0, lvR = 0;
+  if (M.zlev) { lvL = as_global(M.zlev)[F.L.z]; lvR = as_global(M.zlev)[F.R.z]; }
+  const double dt = M.dt * (double)(1 << min(lvL, lvR));
+  const bool accL = (sub & ((1 << lvL) - 1)) != 0, accR = (sub & ((1 << lvR) - 1)) != 0;
   const int nd = g.ndir, ne = g.ne, tid = threadIdx.x, nthr = blockDim.x;
   T *outL = dN + (size_t)fid * 2 * g.blk, *outR = outL + g.blk;
   if (!F.active) {
-    for (size_t q = tid; q < 2 * (size_t)g.blk; q += nthr) outL[q] = (T)0;
+    for (size_t q = tid; q < (size_t)g.blk; q += nthr) {
+      if (!accL) outL[q] = (T)0;
+      if (!accR) outR[q] = (T)0;
+    }
     return;
   }
   const int nrow = col_rows(NCH, CE), cs = nrow, gb = NCH * CE - ne;
@@ -1092,13 +1102,14 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
         T *o = (st == 3 ? outL : outR) + (size_t)s * g.eblk;
         const T *own_c = st == 3 ? XL : XR;
         const T sg = st == 3 ? (T)-1 : (T)1;
+        const bool acc = st == 3 ? accL : accR;
         double sum = 0.0;
 #pragma unroll
         for (int k = 0; k < CE; ++k) {
           const int r = r0 + k;
           if (!own || r < 0 || r >= ne) continue;
           const T v = sg * a[k] - own_c[dp * cs + r] + b[k];
-          o[r * nd + dp] = v;
+          o[r * nd + dp] = acc ? o[r * nd + dp] + v : v;
           sum += (double)v;
         }
         if (st == 3) sumL = sum;
@@ -1135,8 +1146,8 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   const T *__restrict__ ka = as_global((const T *)M.ka);
   const T *__restrict__ ks = as_global((const T *)M.ks);
   const T *__restrict__ feq = as_global((const T *)M.feq);
-  const double dt = M.dt;
   const int z = it.y;
+  const double dt = M.zlev ? M.dt * (double)(1 << as_global(M.zlev)[z]) : M.dt;   // dt0 2^level
   const int nd = g.ndir, ne = g.ne, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
   const btx::ZoneFaces &L = zf[z];        // uniform: read through the scalar cache
@@ -1425,6 +1436,13 @@ struct Model {
   FaceDesc *d_faces = nullptr;
   btx::ZoneFaces *d_zf = nullptr;
   int2 *d_fitems = nullptr, *d_zitems = nullptr;   // (index, face), (index, zone)
+  // local time stepping: zone levels, and the face (zone) items sorted by
+  // level so that the work of a substep is a prefix of each list
+  std::vector<int> lev;              // empty: the global step
+  int lmax = 0;
+  std::vector<int> nf_lev, nz_lev;   // items with level <= l
+  unsigned char *d_zlev = nullptr;
+  int2 *d_fitems_lts = nullptr, *d_zitems_lts = nullptr;
   bool have_bg = false, have_state = false;
   double dt_max1 = 0.0;
   size_t tab_lds = 0;
@@ -1479,7 +1497,7 @@ void model_free(Model &m)
   void *ptrs[] = { m.d_mu, m.d_Phi, m.d_dOm, m.d_nvec, m.d_G, m.d_eps, m.d_vol, m.d_vr, m.d_vth, m.d_vph,
                    m.d_alp, m.d_psi, m.d_ka, m.d_ks, m.d_feq, m.d_f[0], m.d_f[1], m.d_dN, m.d_tally,
                    m.d_zm, m.d_ze, m.d_stage, m.d_faces, m.d_zf, m.d_tabs, m.d_aux, m.d_fitems, m.d_zitems,
-                   m.d_nbg, m.d_q };
+                   m.d_nbg, m.d_q, m.d_zlev, m.d_fitems_lts, m.d_zitems_lts };
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   m = Model();
@@ -1587,7 +1605,8 @@ ModelDev model_dev(const Model &m, double dt)
   M.tabs = m.d_tabs;
   M.aux = m.d_aux;
   M.f[0] = m.d_f[0];
-  M.f[1] = m.d_f[1];
+  M.f[1] = m.lev.empty() ? m.d_f[1] : m.d_f[0];    // time levels: updated in place
+  M.zlev = m.lev.empty() ? nullptr : m.d_zlev;
   M.ka = m.d_ka; M.ks = m.d_ks; M.feq = m.d_feq;
   M.dN = m.d_dN;
   M.tally = m.d_tally;
@@ -1660,12 +1679,12 @@ btx_status build_tables(const Model &m, const ModelDev *d_models, hipStream_t s)
 }
 
 btx_status launch_faces(const FaceShape &shape, size_t tsize, const ModelDev *d_models, const int2 *items,
-                        int n, int threads, size_t lds, int parity, hipStream_t s)
+                        int n, int threads, size_t lds, int parity, hipStream_t s, int sub = 0)
 {
   if (n == 0) return BTX_OK;
   const void *fn = face_fn(tsize, shape);
   if (!fn) return fail(BTX_E_UNSUPPORTED, "no face kernel for this shape");
-  void *args[] = { &d_models, &items, &parity };
+  void *args[] = { &d_models, &items, &parity, &sub };
   HIP_TRY(hipLaunchKernel(fn, dim3(n), dim3(threads), args, lds, s));
   return BTX_OK;
 }
@@ -1792,10 +1811,103 @@ btx_status model_source_terms(const Model &m, double *q, hipStream_t s)
   return BTX_OK;
 }
 
+// Courant length of every zone: its volume over its largest face on an
+// axis, the smallest over the axes (btx::max_dt is cfl times the minimum)
+std::vector<double> courant_lengths(const btx::Grid &g)
+{
+  std::vector<double> len(g.nz);
+  for (int z = 0; z < g.nz; ++z) {
+    double amax[3] = { 0.0, 0.0, 0.0 }, m = 1e300;
+    const btx::ZoneFaces &zf = g.zfaces[z];
+    for (int q = 0; q < zf.n; ++q) {
+      const FaceDesc &F = g.faces[zf.fid[q]];
+      if (F.active && F.area > amax[F.axis]) amax[F.axis] = F.area;
+    }
+    for (int ax = 0; ax < 3; ++ax)
+      if (amax[ax] > 0.0) m = std::min(m, g.vol[z] / amax[ax]);
+    len[z] = m;
+  }
+  return len;
+}
+
+// Time levels (local time stepping, Sec. 6): zone z takes 2^l global steps
+// at once, l the largest with 2^l times the smallest Courant length within
+// its own (at most max_level); then zones that share a face are brought to
+// at most one level apart by lowering the coarser.
+void assign_levels(const btx::Grid &g, int max_level, std::vector<int> &lev)
+{
+  const std::vector<double> len = courant_lengths(g);
+  const double lmin = *std::min_element(len.begin(), len.end());
+  lev.assign(g.nz, 0);
+  for (int z = 0; z < g.nz; ++z) {
+    int l = 0;
+    while (l < max_level && len[z] >= lmin * (double)(2 << l) * (1.0 - 1e-12)) ++l;
+    lev[z] = l;
+  }
+  bool changed = true;
+  while (changed) {
+    changed = false;
+    for (const FaceDesc &F : g.faces) {
+      if (!F.active || F.L.kind != btx::SIDE_ZONE || F.R.kind != btx::SIDE_ZONE) continue;
+      int &a = lev[F.L.z], &b = lev[F.R.z];
+      if (a > b + 1) { a = b + 1; changed = true; }
+      if (b > a + 1) { b = a + 1; changed = true; }
+    }
+  }
+}
+
+// Adopts per-zone time levels (null: back to the global step).  The state is
+// then updated in place (the descriptor points both buffers at the current
+// one); face and zone items are sorted by level for the substep prefixes.
+btx_status model_set_levels(Model &m, const int32_t *levels, int &parity, hipStream_t s)
+{
+  HIP_TRY(hipStreamSynchronize(s));
+  if (m.d_zlev) { (void)hipFree(m.d_zlev); m.d_zlev = nullptr; }
+  if (m.d_fitems_lts) { (void)hipFree(m.d_fitems_lts); m.d_fitems_lts = nullptr; }
+  if (m.d_zitems_lts) { (void)hipFree(m.d_zitems_lts); m.d_zitems_lts = nullptr; }
+  if (parity == 1)
+    HIP_TRY(hipMemcpy(m.d_f[0], m.d_f[1], (size_t)m.g.nz * m.g.ns * m.g.ne * m.g.ndir * m.tsize,
+                      hipMemcpyDeviceToDevice));
+  parity = 0;
+  m.lev.clear();
+  m.lmax = 0;
+  if (!levels) return BTX_OK;
+  const btx::Grid &g = m.g;
+  std::vector<int> lev(levels, levels + g.nz);
+  for (int l : lev)
+    if (l < 0 || l > 16) return fail(BTX_E_INVAL, "time levels must be in 0..16");
+  const int lmax = *std::max_element(lev.begin(), lev.end());
+  std::vector<unsigned char> l8(lev.begin(), lev.end());
+  std::vector<std::pair<int, int>> fs, zs;
+  for (int f = 0; f < (int)g.faces.size(); ++f)
+    fs.emplace_back(std::min(lev[g.faces[f].L.z], lev[g.faces[f].R.z]), f);
+  for (int z = 0; z < g.nz; ++z) zs.emplace_back(lev[z], z);
+  std::stable_sort(fs.begin(), fs.end());
+  std::stable_sort(zs.begin(), zs.end());
+  std::vector<int2> fit, zit;
+  m.nf_lev.assign(lmax + 1, 0);
+  m.nz_lev.assign(lmax + 1, 0);
+  for (auto &p : fs) { fit.push_back(make_int2(m.index, p.second)); for (int l = p.first; l <= lmax; ++l) ++m.nf_lev[l]; }
+  for (auto &p : zs) { zit.push_back(make_int2(m.index, p.second)); for (int l = p.first; l <= lmax; ++l) ++m.nz_lev[l]; }
+  btx_status st;
+  if ((st = upload(&m.d_zlev, l8.data(), l8.size())) != BTX_OK) return st;
+  if ((st = upload(&m.d_fitems_lts, fit.data(), fit.size())) != BTX_OK) return st;
+  if ((st = upload(&m.d_zitems_lts, zit.data(), zit.size())) != BTX_OK) return st;
+  m.lev = lev;
+  m.lmax = lmax;
+  return BTX_OK;
+}
+
 btx_status check_dt(const Model &m, double dt)
 {
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(BTX_E_INVAL, "dt must be positive and finite");
   if (dt > m.dt_max1 * (1.0 + 1e-12)) return fail(BTX_E_CFL, "dt exceeds the Courant limit");
+  if (!m.lev.empty()) {                  // every zone within its own limit at its level
+    const std::vector<double> len = courant_lengths(m.g);
+    for (int z = 0; z < m.g.nz; ++z)
+      if (dt * (double)(1 << m.lev[z]) > len[z] * (1.0 + 1e-12))
+        return fail(BTX_E_CFL, "a zone's time level takes it beyond its Courant limit");
+  }
   return BTX_OK;
 }
 
@@ -1835,6 +1947,19 @@ btx_status ctx_step(btx_ctx *c, double dt)
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->h_model.dt = dt;
     HIP_TRY(hipMemcpy(c->d_model, &c->h_model, sizeof(ModelDev), hipMemcpyHostToDevice));
+  }
+  if (!m.lev.empty()) {                       // time levels: 2^L substeps
+    const int L = m.lmax;
+    for (int k = 0; k < (1 << L); ++k) {
+      const int lf = k == 0 ? L : std::min(L, __builtin_ctz(k));       // faces whose finer zone starts
+      const int lz = std::min(L, __builtin_ctz(k + 1));                 // zones whose step ends
+      btx_status st = launch_faces(m.shape, m.tsize, c->d_model, m.d_fitems_lts, m.nf_lev[lf], face_threads(m),
+                                   face_lds(m), 0, c->stream, k);
+      if (st != BTX_OK) return st;
+      st = launch_zones(m.tsize, c->d_model, m.d_zitems_lts, m.nz_lev[lz], m.g.ns * m.g.ne, 0, c->stream);
+      if (st != BTX_OK) return st;
+    }
+    return BTX_OK;
   }
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   const bool rec = c->timing && c->ev_used + 3 <= c->ev.size();
@@ -2189,6 +2314,26 @@ btx_status btx_step(btx_ctx *c, double dt, int32_t n_steps)
   for (int t = 0; t < n_steps; ++t)
     if ((st = ctx_step(c, dt)) != BTX_OK) return st;
   return BTX_OK;
+}
+
+btx_status btx_time_levels(const btx_ctx *c, int32_t max_level, int32_t *levels)
+{
+  if (!c || !levels) return fail(BTX_E_INVAL, "null argument");
+  if (max_level < 0 || max_level > 16) return fail(BTX_E_INVAL, "max_level must be in 0..16");
+  std::vector<int> lev;
+  assign_levels(c->m.g, max_level, lev);
+  for (int z = 0; z < c->m.g.nz; ++z) levels[z] = lev[z];
+  return BTX_OK;
+}
+
+btx_status btx_set_time_levels(btx_ctx *c, const int32_t *levels)
+{
+  if (!c) return fail(BTX_E_INVAL, "null context");
+  HIP_TRY(hipSetDevice(c->device));
+  btx_status st = model_set_levels(c->m, levels, c->parity, c->stream);
+  c->h_model = model_dev(c->m, c->h_model.dt);
+  HIP_TRY(hipMemcpy(c->d_model, &c->h_model, sizeof(ModelDev), hipMemcpyHostToDevice));
+  return st;
 }
 
 btx_status btx_moments(btx_ctx *c, double *zone_moments, double *totals)

@@ -324,3 +324,52 @@ def test_evolving_background_3d_gpu(oracle_mod):
     _say(f"[gpu]   rel err {err:.3e}")
     assert err <= 1e-12
     ctx.close()
+
+
+@pytest.mark.parametrize("case", ["shock_3species", "shock_3d", "sphere_2d"])
+@pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
+def test_time_levels_gpu(case, precision, oracle_mod):
+    """local time stepping: the library proposes the reference's levels; two
+    steps of up to three levels (eight substeps each), then a global step
+    after switching the levels off, against the reference.  FP64 to 1e-12
+    (state, source terms, outflow); mixed to 1e-5 in the zone moments."""
+    btx = _btx()
+    w = CASES[case]()
+    _say(f"[gpu] time levels {case}, precision {precision}")
+    o = oracle_mod.Oracle(w)
+    ctx = btx.Context(w, precision=precision)
+    lev = ctx.time_levels(3)
+    assert np.array_equal(lev, o.time_levels(3)) and lev.max() >= 1
+    ctx.set_background()
+    ctx.set_state(w.f0)
+    ctx.set_time_levels(lev)
+    o.set_levels(lev)
+    dt = o.max_dt(0.4)
+    for rep in range(2):
+        ctx.step(dt, 2 - rep)
+        o.step(dt, 2 - rep)
+        zr, tr = o.moments()
+        zg, tg = ctx.moments()
+        if precision == W.PREC_FP64:
+            ref, got = o.state(), ctx.get_state()
+            err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+            scale = _pins()._gross_rate(w, ref)[:, None]
+            scale = np.maximum(scale, 1e-30 * scale.max())        # vacuum zones: no collisions
+            qerr = float(np.max(np.abs(ctx.source_terms() - o.source_terms()) / scale))
+            _say(f"[gpu]   {'levels' if rep == 0 else 'global'}: rel err {err:.3e}, source terms {qerr:.3e}")
+            assert err <= 1e-12 and qerr <= 1e-12
+            assert np.allclose(tg, tr, rtol=1e-12, atol=1e-12 * np.abs(tr).max())
+        else:
+            mask = np.abs(zr[..., 1]) > 1e-8 * np.abs(zr[..., 1]).max()
+            for k in (0, 1):
+                rel = np.max(np.abs(zg[..., k] - zr[..., k])[mask] / np.abs(zr[..., k][mask]))
+                _say(f"[gpu]   moment {k} rel err {rel:.3e}")
+                assert rel <= 1e-5
+        ctx.set_time_levels(None)
+        o.set_levels(None)
+    too_coarse = np.full(w.n_zones, 6, dtype=np.int32)
+    ctx.set_time_levels(too_coarse)
+    with pytest.raises(btx.BtxError) as e:
+        ctx.step(dt, 1)
+    assert e.value.status == btx.BTX_E_CFL
+    ctx.close()

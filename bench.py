@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--n-theta", type=int, default=256)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--lts-level", type=int, default=6,
+                    help="highest time level of the local-time-stepping run (0: skip it)")
+    ap.add_argument("--lts-steps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -75,6 +78,40 @@ def run_gpu(torch, btx, w, precision, steps, warmup):
     ctx.close()
     return {"ms": ms, "wall": wall, "kernel_ms": kms / np.maximum(kn, 1), "zm": zm, "tot": tot,
             "dt": dt}
+
+
+def run_lts(torch, btx, w, max_level, steps, ref_ms_per_step):
+    """the same grid and precision with time levels: each step is 2^L substeps of
+    the global dt; reported as simulated time per second against the global step"""
+    stream = torch.cuda.current_stream()
+    ctx = btx.Context(w, device=0, stream=stream.cuda_stream, precision=1)
+    ctx.set_background()
+    f0 = device_state(torch, w, torch.float32)
+    ctx.set_state(f0)
+    del f0
+    dt = ctx.max_dt(w.cfl)
+    lev = ctx.time_levels(max_level)
+    L = int(lev.max())
+    ctx.set_time_levels(lev)
+    ctx.step(dt, 1)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    ctx.step(dt, steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    _, tot = ctx.moments()
+    ctx.close()
+    zone_updates = float(np.sum(2.0 ** (L - lev)))
+    sim_per_s = (2 ** L) * dt / (ms * 1e-3)
+    sim_global = dt / (ref_ms_per_step * 1e-3)
+    return {"max_level": L, "zones_per_level": np.bincount(lev, minlength=L + 1).tolist(),
+            "ms_per_step": ms, "substeps_per_step": 2 ** L,
+            "simulated_time_per_s": sim_per_s, "speedup_vs_global_step": sim_per_s / sim_global,
+            "zone_update_fraction": zone_updates / (w.n_zones * 2 ** L),
+            "updates_per_s": zone_updates * w.block / (ms * 1e-3)}
 
 
 def cpu_baseline(steps_note):
@@ -235,6 +272,12 @@ def main():
         if k64 == a.steps:
                 out["number_drift_mixed"] = float(np.max(np.abs(tot[:, 0] + tot[:, 1] - res64["tot"][:, 0]
                                                             - res64["tot"][:, 1]) / res64["tot"][:, 0]))
+    if a.lts_level > 0:
+        out["local_time_stepping"] = run_lts(torch, btx, w, a.lts_level, a.lts_steps, mixed["ms"] / a.steps)
+        l = out["local_time_stepping"]
+        print(f"[bench] time levels (max {l['max_level']}): {l['ms_per_step']:.2f} ms per "
+              f"{l['substeps_per_step']} substeps, {l['speedup_vs_global_step']:.2f}x the simulated time "
+              f"per second of the global step", file=sys.stderr, flush=True)
     if not a.no_batch:
         out["batch"] = run_batch(torch, btx, W, a.batch_steps)
         print(f"[bench] batch: {out['batch']['ms_per_step']:.3f} ms/step batched, "

@@ -149,3 +149,35 @@ def test_3d_symmetric_equals_axisymmetric_gpu():
         qerr = float(np.max(np.abs(q3 - q2[None])) / np.max(np.abs(q2)))
         _say(f"[gpu]   precision {prec}: state {max(errs):.3e}, source terms {qerr:.3e}")
         assert max(errs) <= tol and qerr <= 10 * tol
+
+
+def test_radiating_sphere_2d_time_levels():
+    """the 2D radiating sphere with local time stepping (levels up to 5)
+    reaches the same stationary H/J and K/J as the global step: within 0.03
+    of the exact solution on the three rays (the global step: 0.011)"""
+    btx = _btx()
+    w = W.radiating_sphere_2d(n_r=100, n_theta=32, n_mu=16, n_phi=8, r_min=0.05)
+    ctx = btx.Context(w, precision=W.PREC_FP64)
+    ctx.set_background()
+    ctx.set_state(w.f0)
+    dt = ctx.max_dt(0.4)
+    lev = ctx.time_levels(5)
+    L = int(lev.max())
+    ctx.set_time_levels(lev)
+    steps = int(7.0 / (dt * 2 ** L))
+    frac = float(np.sum(2.0 ** (L - lev))) / (w.n_zones * 2 ** L)
+    _say(f"[gpu] 2D radiating sphere with time levels up to {L}: {steps} steps of {2 ** L} substeps, "
+         f"zone updates {frac:.3f} of the global step's")
+    ctx.step(dt, steps)
+    zm, _ = ctx.moments()
+    ctx.close()
+    J, H, K = (zm[:, 0, k].reshape(w.n_theta, w.n_r) for k in (1, 2, 3))
+    rc = 0.5 * (w.r_edges[1:] + w.r_edges[:-1])
+    worst = 0.0
+    for r in [0.5, 0.8, 1.2, 1.5, 2.0, 3.0]:
+        a = int(np.argmin(abs(rc - r)))
+        hj, kj = _sphere_exact(rc[a], 10.0)
+        for b in (1, w.n_theta // 4, w.n_theta // 2):
+            worst = max(worst, abs(H[b, a] / J[b, a] - hj), abs(K[b, a] / J[b, a] - kj))
+    _say(f"[gpu]   worst deviation from the exact solution {worst:.4f}")
+    assert worst < 0.03 and frac < 0.5

@@ -1,4 +1,4 @@
-"""Relativistic radiating spheres (Sec. 4.2) end to end on the GPU path.
+"""P-15: relativistic radiating spheres (Sec. 4.2) end to end on the GPU path.
 
 An opaque sphere of 4 km radiates into vacuum through one of three
 backgrounds, with the set-ups printed in the paper

@@ -34,7 +34,12 @@
  *   failing call on that thread.
  *   Threads: one context must not be used by two threads at once.
  *   Limits: at most 128 directions (n_mu n_phi), 61 energy groups and 2048
- *   (species x groups) rows.
+ *   (species x groups) rows; a face workgroup holds its remap tables and
+ *   four stencil blocks of one species in the 160 KB of LDS of a compute
+ *   unit, which bounds directions x groups: FP64 takes up to 61 groups with
+ *   48 directions, 25 with 96 and 13 with 128; mixed precision takes up to 61
+ *   groups with 96 directions and 45 with 128.  btx_create reports
+ *   BTX_E_UNSUPPORTED beyond.
  */
 #ifndef BTX_H
 #define BTX_H

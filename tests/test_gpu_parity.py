@@ -61,6 +61,16 @@ CASES = {
     # outflow ghosts on theta faces)
     "disk": lambda: _perturb(W.radiating_disk(n_r=12, n_theta=5, n_mu=6, n_phi=8, r_min=0.2,
                                               r_max=2.5)),
+    # the largest momentum grids a face workgroup holds in FP64 (its LDS):
+    # 16 x 8 = 128 directions with 13 groups, and 61 groups with 48 directions
+    "max_dirs": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=13, n_mu=16, n_phi=8)),
+    "max_groups": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=61, n_mu=12, n_phi=4,
+                                               e_min=1.0, e_max=300.0)),
+    # the largest in mixed precision at 128 directions: 45 groups
+    "max_mixed": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=45, n_mu=16, n_phi=8,
+                                              e_min=1.0, e_max=300.0)),
+    # an empty state: stays empty where nothing emits
+    "empty": lambda: _empty(W.axisym_2d(n_r=5, n_theta=3, n_eps=3, n_mu=4, n_phi=4)),
     # 3D: four phi zones, state and background varying with phi, v_phi
     "shock_3d": lambda: _turned(W.shock_2d(n_r=8, n_theta=4, n_eps=6, n_mu=4, n_phi=4,
                                            precision=W.PREC_FP64), 4),
@@ -80,6 +90,12 @@ def _turned(w, n_phi_zones):
     w3.v_r = w3.v_r * (1.0 + 0.1 * RNG.random(w3.n_zones))
     w3.kappa_a = w3.kappa_a * (1.0 + RNG.random(w3.kappa_a.shape))
     return w3
+
+
+def _empty(w):
+    w.f0 = np.zeros_like(w.f0)
+    w.f_eq = np.zeros_like(w.f_eq)
+    return w
 
 
 def _steep(w):
@@ -102,13 +118,14 @@ def _run_pair(w, steps, precision, oracle_mod):
     return o, ctx
 
 
-@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("case", [c for c in CASES if c != "max_mixed"])
 def test_fp64_parity(case, oracle_mod):
     w = CASES[case]()
     _say(f"[gpu] fp64 parity {case}: zones {w.n_zones} block {w.block}")
     o, ctx = _run_pair(w, 3, W.PREC_FP64, oracle_mod)
     ref, got = o.state(), ctx.get_state()
-    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref)) / scale if scale > 0 else np.max(np.abs(got))
     _say(f"[gpu]   rel err {err:.3e}")
     assert err <= 1e-12
     zr, tr = o.moments()
@@ -119,11 +136,13 @@ def test_fp64_parity(case, oracle_mod):
         if mask.any():
             assert np.max(np.abs(zg[..., k] - zr[..., k])[mask]) <= 1e-12 * m
     assert np.allclose(tg, tr, rtol=1e-12, atol=1e-12 * np.abs(tr).max())
+    if scale == 0:
+        assert not np.any(got) and not np.any(tg)
     ctx.close()
 
 
 @pytest.mark.parametrize("case", ["shock_3species", "column_lobatto_v", "split_groups", "large_shift",
-                                  "shock_3d"])
+                                  "shock_3d", "max_dirs", "max_groups", "max_mixed"])
 def test_mixed_moments(case, oracle_mod):
     w = CASES[case]()
     _say(f"[gpu] mixed moments {case}")
@@ -159,6 +178,11 @@ def test_number_conservation_gpu(oracle_mod):
 
 def test_errors_gpu():
     btx = _btx()
+    big = W.axisym_2d(n_r=3, n_theta=2, n_eps=61, n_mu=16, n_phi=8, e_min=1.0, e_max=300.0)
+    for prec in (W.PREC_FP64, W.PREC_MIXED):        # beyond a face workgroup's LDS
+        with pytest.raises(btx.BtxError) as e:
+            btx.Context(big, precision=prec)
+        assert e.value.status == btx.BTX_E_UNSUPPORTED and "LDS" in str(e.value)
     w = W.axisym_2d(n_r=6, n_theta=4, n_eps=4, n_mu=4, n_phi=4)
     ctx = btx.Context(w)
     with pytest.raises(btx.BtxError) as e:

@@ -276,19 +276,40 @@ __host__ __device__ inline size_t buf_bytes(int nd, int nch, int ce, size_t szT)
 }
 
 // table-build scratch for one round of 4 tables
-__host__ __device__ inline size_t scratch_bytes(int nd, size_t szT)
+// table build scratch for tpr tables at a time
+__host__ __device__ inline size_t scratch_bytes(int nd, size_t szT, int tpr = 4)
 {
-  return (size_t)4 * nd * 4 * 2 + (size_t)16 * nd * 4 + (size_t)32 * nd * szT;
+  return (size_t)tpr * nd * 4 * 2 + (size_t)4 * tpr * nd * 4 + (size_t)8 * tpr * nd * szT;
+}
+
+// 16-bit gather keys before their conversion to window offsets: the source
+// direction and the energy shift.  Up to 256 directions they take 8 bits
+// each; up to 1024 directions the source takes 10 bits and the shift 6, which
+// is exact there: such grids have at most 29 groups, and a shift that takes
+// every group past the edge of the grid folds like one just past it.
+__host__ __device__ inline unsigned short pack_key(int src, int di, int nd)
+{
+  if (nd > 256) {
+    di = di < -31 ? -31 : (di > 31 ? 31 : di);
+    return (unsigned short)(src | ((di + 32) << 10));
+  }
+  return (unsigned short)(src | ((di + 128) << 8));
+}
+
+__host__ __device__ inline void unpack_key(unsigned key, int nd, int &src, int &di)
+{
+  if (nd > 256) { src = key & 0x3ff; di = (int)(key >> 10) - 32; }
+  else { src = key & 0xff; di = (int)(key >> 8) - 128; }
 }
 
 // LDS of one face workgroup: 8 tables, 4 data buffers (Lm, L, R, Rp), per-row
 // constants (G, 1/G as T; per species: source and blend weight as T, two
 // collision coefficients as FP64, a precision flag), the wave partials and
 // totals of the angle sums, and the tally partials
-__host__ __device__ inline size_t face_lds_bytes(int nd, int ns, int nch, int ce, size_t szT)
+__host__ __device__ inline size_t face_lds_bytes(int nd, int ns, int nch, int ce, size_t szT, bool gtab = false)
 {
   const size_t nrow = col_rows(nch, ce), nsr = (size_t)ns * nrow;
-  return kTables * tab_stride(nd, szT) + 4 * buf_bytes(nd, nch, ce, szT) + 2 * align16(nrow * szT) +
+  return (gtab ? 0 : kTables * tab_stride(nd, szT)) + 4 * buf_bytes(nd, nch, ce, szT) + 2 * align16(nrow * szT) +
          2 * align16(nsr * szT) + 2 * align16(nsr * 8) + align16(nsr * 4) + align16(16 * nrow * 8) +
          align16(nrow * 8) + align16(16 * 8);
 }
@@ -407,8 +428,8 @@ __device__ __forceinline__ void gather(const Tab<T> &tb, int nd, const T *__rest
     for (int k = 0; k + 1 < CE; ++k) acc[k + 1] += k == kb ? acc[k] : (T)0;
   } else {
     for (int e = e0; e < e1; ++e) {
-      const unsigned key = tb.key[e];
-      const int d = key & 0xff, di = (int)(key >> 8) - 128;
+      int d, di;
+      unpack_key(tb.key[e], nd, d, di);
       const T cl = tb.cw[2 * e], cr = tb.cw[2 * e + 1];
       const T *col = X + d * cs;
 #pragma unroll
@@ -478,10 +499,13 @@ __device__ inline double frame_weight(const DevGrid &g, const FaceAux &A, int k,
 // inverted into sorted per-target gather lists) and stores them in global
 // memory; run once per background.
 // table t: 0 Lm->L, 1 R->L, 2 L->R, 3 Rp->R, 4 L->s, 5 R->s, 6 s->L, 7 s->R
-template <typename T>
+// GTAB: the tables are built in place in global memory (grids whose tables do
+// not fit in LDS), one table at a time.
+template <typename T, bool GTAB>
 __global__ void __launch_bounds__(256)
 table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items)
 {
+  constexpr int TPR = GTAB ? 1 : 4;                 // tables per round
   extern __shared__ __align__(16) char lds[];
   __shared__ int flg[kTables];
   const int2 it = items[blockIdx.x];
@@ -494,13 +518,14 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
   const int nd = g.ndir, tid = threadIdx.x, nthr = blockDim.x;
   const size_t tstride = tab_stride(nd, sizeof(T));
   char *p = lds;
-  char *tabs = p;              p += kTables * tstride;
+  char *tabs = GTAB ? tabs_g + (size_t)fid * kTables * tstride : p;
+  if (!GTAB) p += kTables * tstride;
   Frame *frm = (Frame *)p;     p += align16(5 * sizeof(Frame));
   char *data = p;
-  int *cnt = (int *)data;                      // 4 nd
-  int *cur = cnt + 4 * nd;                     // 4 nd
-  int *rtg = cur + 4 * nd;                     // 16 nd
-  T *rcf = (T *)(rtg + 16 * nd);               // 32 nd
+  int *cnt = (int *)data;                      // TPR nd
+  int *cur = cnt + TPR * nd;                   // TPR nd
+  int *rtg = cur + TPR * nd;                   // 4 TPR nd
+  T *rcf = (T *)(rtg + 4 * TPR * nd);          // 8 TPR nd
   const int cs = col_rows(g.nch, g.ce);
   auto tw = [&](int t, T *&cw, unsigned short *&key, unsigned short *&start) {
     char *b = tabs + t * tstride;
@@ -528,12 +553,12 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
   }
   const bool rot = g.geom != 2;
   const int ax = F.axis;
-  for (int round = 0; round < 2; ++round) {
+  for (int round = 0; round < kTables / TPR; ++round) {
     __syncthreads();
-    for (int q = tid; q < 4 * nd; q += nthr) cnt[q] = 0;
+    for (int q = tid; q < TPR * nd; q += nthr) cnt[q] = 0;
     __syncthreads();
-    for (int q = tid; q < 4 * nd; q += nthr) {
-      int tl = q / nd, d = q - tl * nd, t = 4 * round + tl;
+    for (int q = tid; q < TPR * nd; q += nthr) {
+      int tl = q / nd, d = q - tl * nd, t = TPR * round + tl;
       const int si = t == 0 ? 0 : (t == 1 || t == 5) ? 2 : (t == 2 || t == 4) ? 1 : t == 3 ? 3 : 4;
       const int di_ = (t == 0 || t == 1 || t == 6) ? 1 : (t == 2 || t == 3 || t == 7) ? 2 : 4;
       const Frame S = frm[si], D = frm[di_];
@@ -550,10 +575,10 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
       }
     }
     __syncthreads();
-    if (tid < 4) {                                     // exclusive scan per table
+    if (tid < TPR) {                                   // exclusive scan per table
       T *cw;
       unsigned short *key, *start;
-      tw(4 * round + tid, cw, key, start);
+      tw(TPR * round + tid, cw, key, start);
       int acc = 0;
       for (int d = 0; d < nd; ++d) {
         start[d] = (unsigned short)acc;
@@ -561,30 +586,30 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
         acc += cnt[tid * nd + d];
       }
       start[nd] = (unsigned short)acc;
-      start[nd + 1] = (unsigned short)flg[4 * round + tid];
+      start[nd + 1] = (unsigned short)flg[TPR * round + tid];
     }
     __syncthreads();
-    for (int q = tid; q < 4 * nd; q += nthr) {         // records into their target lists
+    for (int q = tid; q < TPR * nd; q += nthr) {       // records into their target lists
       int tl = q / nd, d = q - tl * nd;
       T *cw;
       unsigned short *key, *start;
-      tw(4 * round + tl, cw, key, start);
+      tw(TPR * round + tl, cw, key, start);
       for (int r = 0; r < 4; ++r) {
         int v = rtg[q * 4 + r];
         if (v < 0) continue;
         int tg = v & 0xffff, dib = v >> 16;
         int slot = atomicAdd(&cur[tl * nd + tg], 1);
-        key[slot] = (unsigned short)(d | (dib << 8));
+        key[slot] = pack_key(d, dib - 128, nd);
         cw[2 * slot] = rcf[(q * 4 + r) * 2];
         cw[2 * slot + 1] = rcf[(q * 4 + r) * 2 + 1];
       }
     }
     __syncthreads();
-    for (int q = tid; q < 4 * nd; q += nthr) {         // fixed summation order: sort by key
+    for (int q = tid; q < TPR * nd; q += nthr) {       // fixed summation order: sort by key
       int tl = q / nd, d = q - tl * nd;
       T *cw;
       unsigned short *key, *start;
-      tw(4 * round + tl, cw, key, start);
+      tw(TPR * round + tl, cw, key, start);
       int a = start[d], b = start[d + 1];
       for (int x = a + 1; x < b; ++x) {
         unsigned short kx = key[x];
@@ -603,7 +628,8 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
       // shifts within one group: keys become source window offsets
       if (!(start[nd + 1] & 1))
         for (int x = a; x < b; ++x) {
-          const int src = key[x] & 0xff, di = (key[x] >> 8) - 128;
+          int src, di;
+          unpack_key(key[x], nd, src, di);
           key[x] = (unsigned short)(src * cs - di + 2);
         }
     }
@@ -632,10 +658,12 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
     aux[fid] = A;
   }
   __syncthreads();
-  uint4 *dst = (uint4 *)(tabs_g + (size_t)fid * kTables * tstride);
-  const uint4 *src = (const uint4 *)tabs;
-  const int n16 = (int)(kTables * tstride / 16);
-  for (int q = tid; q < n16; q += nthr) dst[q] = src[q];
+  if (!GTAB) {
+    uint4 *dst = (uint4 *)(tabs_g + (size_t)fid * kTables * tstride);
+    const uint4 *src = (const uint4 *)tabs;
+    const int n16 = (int)(kTables * tstride / 16);
+    for (int q = tid; q < n16; q += nthr) dst[q] = src[q];
+  }
 }
 
 // ------------------------------------------------------------ time remap
@@ -720,7 +748,7 @@ time_remap_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ 
       const int v = rtg[q * 4 + r];
       if (v < 0) continue;
       const int slot = atomicAdd(&cur[v & 0xffff], 1);
-      key[slot] = (unsigned short)(q | ((v >> 16) << 8));
+      key[slot] = pack_key(q, (v >> 16) - 128, nd);
       cw[2 * slot] = rcf[(q * 4 + r) * 2];
       cw[2 * slot + 1] = rcf[(q * 4 + r) * 2 + 1];
     }
@@ -754,7 +782,8 @@ time_remap_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ 
       const int i = q / nd, dp = q - i * nd;
       T acc = (T)0;
       for (int e = start[dp]; e < start[dp + 1]; ++e) {
-        const int src = key[e] & 0xff, di = (int)(key[e] >> 8) - 128;
+        int src, di;
+        unpack_key(key[e], nd, src, di);
         const T cl = cw[2 * e], cr = cw[2 * e + 1];
         const T *col = cont + src * ne;
         const int iL = i - di, iR = iL - 1;
@@ -817,7 +846,10 @@ __device__ __forceinline__ void store_side(const T v[CE], const T gl[CE], T a, i
 //           by wave shuffles; implicit interface collision (Eq. halfstep);
 //           blend (Sec. 3.3.3) into flux and donor contents
 //   phase 3 remapped content change of both sides (Eq. fullstep)
-template <typename T, int NCH, int CE, int MAXT, bool SPLIT>
+// GTAB: the face's tables are read from global memory (through the caches)
+// instead of LDS, for momentum grids whose tables do not fit beside the
+// stencil blocks.
+template <typename T, int NCH, int CE, int MAXT, bool SPLIT, bool GTAB = false>
 __global__ void __launch_bounds__(MAXT)
 face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity, int sub)
 {
@@ -856,7 +888,8 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   const size_t tstride = tab_stride(nd, sizeof(T));
   const size_t bb = buf_bytes(nd, NCH, CE, sizeof(T));
   char *p = lds;
-  const char *tabs = p;         p += kTables * tstride;
+  const char *tabs = GTAB ? tabs_g + (size_t)fid * kTables * tstride : p;
+  if (!GTAB) p += kTables * tstride;
   char *bufs = p;               p += 4 * bb;
   T *XLm = (T *)(bufs) + gb, *XL = (T *)(bufs + bb) + gb, *XR = (T *)(bufs + 2 * bb) + gb,
     *XRp = (T *)(bufs + 3 * bb) + gb;
@@ -875,7 +908,7 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
 #define TB(t) tab_at<T>(tabs + (t) * tstride, nd)
 
   // ---- remap tables of this face (built once per background by table_kernel)
-  {
+  if (!GTAB) {
     const uint4 *src = (const uint4 *)(tabs_g + (size_t)fid * kTables * tstride);
     uint4 *dst = (uint4 *)lds;
     const int n16 = (int)(kTables * tstride / 16);
@@ -1132,7 +1165,8 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
 
 // ------------------------------------------------------------ zone kernel
 
-template <typename T>
+// R: directions per lane (64 R directions at most)
+template <typename T, int R>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity)
 {
@@ -1164,9 +1198,9 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
     size_t kidx = ((size_t)z * g.ns + s) * ne + i;
     double ka_ = (double)ka[kidx], ks_ = (double)ks[kidx], fe_ = (double)feq[kidx];
     bool wide = (sizeof(T) == 8) || tau * (ka_ + ks_) > g.fp64_thr;
-    double Sd[4];
+    double Sd[R];
     double part = 0.0;
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < R; ++r) {
       int d = lane + 64 * r;
       Sd[r] = 0.0;
       if (d >= nd) continue;
@@ -1184,7 +1218,7 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
     const double ssum = wave_sum(part);
     double avg = ssum / (4.0 * kPi);
     double pr = 0.0, pt = 0.0, pp = 0.0;
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < R; ++r) {
       int d = lane + 64 * r;
       if (d >= nd) continue;
       size_t off = (size_t)s * g.eblk + (size_t)i * nd + d;
@@ -1311,9 +1345,10 @@ namespace {
 struct FaceShape {
   int nch = 0, ce = 0, maxt = 0;
   bool split = false;
+  bool gtab = false;                 // tables read from global memory
   bool operator==(const FaceShape &o) const
   {
-    return nch == o.nch && ce == o.ce && maxt == o.maxt && split == o.split;
+    return nch == o.nch && ce == o.ce && maxt == o.maxt && split == o.split && gtab == o.gtab;
   }
 };
 
@@ -1331,6 +1366,22 @@ FaceShape make_shape(int prec, int nd, int ne, int nch)
   for (int k = 0; k < n && !f.ce; ++k)
     if (nch * c[k] >= ne + 3) f.ce = c[k];
   f.split = f.ce && (ne + 2) % f.ce == 0;
+  return f;
+}
+
+// Shapes for momentum grids whose tables do not fit in LDS beside the stencil
+// blocks (or with more than 128 directions): tables read from global memory,
+// 4, 2 or 1 work items per direction (up to 256, 512 or 1024 directions) and
+// 4, 8 or 16 groups per item, chosen so that group -1 never ends an item.
+FaceShape make_gtab_shape(int nd, int ne)
+{
+  FaceShape f;
+  if (nd > 1024) return f;
+  f.nch = nd <= 256 ? 4 : (nd <= 512 ? 2 : 1);
+  f.maxt = 1024;
+  f.gtab = true;
+  for (int c : { 4, 8, 16 })
+    if (!f.ce && f.nch * c >= ne + 3 && (ne + 2) % c != 0) f.ce = c;
   return f;
 }
 
@@ -1365,11 +1416,27 @@ const void *face_fn_t(int ce)
   }
 }
 
+template <typename T, int NCH>
+const void *face_fn_g(int ce)
+{
+  switch (ce) {
+  case 4: return (const void *)face_kernel<T, NCH, 4, 1024, false, true>;
+  case 8: return (const void *)face_kernel<T, NCH, 8, 1024, false, true>;
+  case 16: return (const void *)face_kernel<T, NCH, 16, 1024, false, true>;
+  default: return nullptr;
+  }
+}
+
 // the face-kernel instance of a shape
 template <typename T>
 const void *face_fn(const FaceShape &f)
 {
   if (f.ce == 0) return nullptr;
+  if (f.gtab) {
+    if (f.split) return nullptr;
+    return f.nch == 4 ? face_fn_g<T, 4>(f.ce) : f.nch == 2 ? face_fn_g<T, 2>(f.ce)
+                      : f.nch == 1 ? face_fn_g<T, 1>(f.ce) : nullptr;
+  }
   if (f.nch == 4) return f.split ? face_fn_t<T, 4, 512, true>(f.ce) : face_fn_t<T, 4, 512, false>(f.ce);
   if constexpr (sizeof(T) == 4) {
     if (f.maxt == 768) return f.split ? face_fn_t<T, 8, 768, true>(f.ce) : face_fn_t<T, 8, 768, false>(f.ce);
@@ -1466,7 +1533,9 @@ btx_status validate_desc(const btx_grid_desc *d)
   if (!d->r_edges || !d->eps_edges) return fail(BTX_E_INVAL, "null edge array");
   const int nth = d->geometry == BTX_GEOM_AXISYM2D ? d->n_theta : 1;
   if (nth < 1) return fail(BTX_E_INVAL, "n_theta must be positive");
-  if (d->n_mu * d->n_phi > 128) return fail(BTX_E_UNSUPPORTED, "at most 128 directions");
+  if (d->n_mu * d->n_phi > 1024) return fail(BTX_E_UNSUPPORTED, "at most 1024 directions");
+  if (d->n_mu * d->n_phi > 256 && d->n_eps > 29)
+    return fail(BTX_E_UNSUPPORTED, "more than 256 directions take at most 29 groups");
   if (d->n_eps > 61) return fail(BTX_E_UNSUPPORTED, "at most 61 energy groups");
   if (d->n_species * d->n_eps > 2048) return fail(BTX_E_UNSUPPORTED, "at most 2048 species x groups");
   for (int a = 0; a < d->n_r; ++a)
@@ -1529,13 +1598,15 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
   m.tsize = g.prec == BTX_PREC_FP64 ? 8 : 4;
   m.dt_max1 = btx::max_dt(g, 1.0);
   m.shape = default_shape(g);
+  if (m.shape.ce == 0 || face_lds_bytes(g.ndir, g.ns, m.shape.nch, m.shape.ce, m.tsize) > lds_cap)
+    m.shape = make_gtab_shape(g.ndir, g.ne);     // tables through the caches instead of LDS
   if (m.shape.ce == 0) return fail(BTX_E_UNSUPPORTED, "no face work-item shape for this grid");
-  if (face_lds_bytes(g.ndir, g.ns, m.shape.nch, m.shape.ce, m.tsize) > lds_cap)
-    return fail(BTX_E_UNSUPPORTED, "face workgroup needs " +
-                                       std::to_string(face_lds_bytes(g.ndir, g.ns, m.shape.nch, m.shape.ce, m.tsize)) +
-                                       " B of LDS");
-  m.tab_lds = kTables * tab_stride(g.ndir, m.tsize) + align16(5 * sizeof(Frame)) +
-              align16(scratch_bytes(g.ndir, m.tsize));
+  const size_t flds = face_lds_bytes(g.ndir, g.ns, m.shape.nch, m.shape.ce, m.tsize, m.shape.gtab);
+  if (flds > lds_cap)
+    return fail(BTX_E_UNSUPPORTED, "face workgroup needs " + std::to_string(flds) + " B of LDS");
+  m.tab_lds = (m.shape.gtab ? 0 : kTables * tab_stride(g.ndir, m.tsize)) + align16(5 * sizeof(Frame)) +
+              align16(scratch_bytes(g.ndir, m.tsize, m.shape.gtab ? 1 : 4));
+  if (m.tab_lds > lds_cap) return fail(BTX_E_UNSUPPORTED, "table build needs too much LDS");
   const size_t nz = g.nz, blk = (size_t)g.ns * g.ne * g.ndir, nk = nz * g.ns * g.ne, nf = g.faces.size();
   std::vector<int2> fit(nf), zit(nz);
   for (size_t k = 0; k < nf; ++k) fit[k] = make_int2(index, (int)k);
@@ -1669,7 +1740,9 @@ btx_status build_tables(const Model &m, const ModelDev *d_models, hipStream_t s)
 {
   const int nf = (int)m.g.faces.size();
   if (nf == 0) return BTX_OK;
-  const void *tk = m.tsize == 8 ? (const void *)table_kernel<double> : (const void *)table_kernel<float>;
+  const void *tk = m.shape.gtab
+                       ? (m.tsize == 8 ? (const void *)table_kernel<double, true> : (const void *)table_kernel<float, true>)
+                       : (m.tsize == 8 ? (const void *)table_kernel<double, false> : (const void *)table_kernel<float, false>);
   btx_status st = raise_lds_limit(tk, m.tab_lds);
   if (st != BTX_OK) return st;
   const int2 *items = m.d_fitems;
@@ -1693,10 +1766,11 @@ btx_status launch_faces(const FaceShape &shape, size_t tsize, const ModelDev *d_
 size_t zone_lds_bytes(int rows) { return (size_t)std::max(rows, 1) * 5 * sizeof(double); }
 
 btx_status launch_zones(size_t tsize, const ModelDev *d_models, const int2 *items, int n, int max_rows,
-                        int parity, hipStream_t s)
+                        int parity, hipStream_t s, int max_dirs = 0)
 {
   if (n == 0) return BTX_OK;
-  const void *zk = tsize == 8 ? (const void *)zone_kernel<double> : (const void *)zone_kernel<float>;
+  const void *zk = max_dirs > 256 ? (tsize == 8 ? (const void *)zone_kernel<double, 16> : (const void *)zone_kernel<float, 16>)
+                                  : (tsize == 8 ? (const void *)zone_kernel<double, 4> : (const void *)zone_kernel<float, 4>);
   void *args[] = { &d_models, &items, &parity };
   HIP_TRY(hipLaunchKernel(zk, dim3(n), dim3(256), args, zone_lds_bytes(max_rows), s));
   return BTX_OK;
@@ -1704,7 +1778,10 @@ btx_status launch_zones(size_t tsize, const ModelDev *d_models, const int2 *item
 
 int face_threads(const Model &m) { return ((m.shape.nch * m.g.ndir + 63) / 64) * 64; }
 
-size_t face_lds(const Model &m) { return face_lds_bytes(m.g.ndir, m.g.ns, m.shape.nch, m.shape.ce, m.tsize); }
+size_t face_lds(const Model &m)
+{
+  return face_lds_bytes(m.g.ndir, m.g.ns, m.shape.nch, m.shape.ce, m.tsize, m.shape.gtab);
+}
 
 btx_status set_face_lds(size_t tsize, const FaceShape &f, size_t lds)
 {
@@ -1956,7 +2033,8 @@ btx_status ctx_step(btx_ctx *c, double dt)
       btx_status st = launch_faces(m.shape, m.tsize, c->d_model, m.d_fitems_lts, m.nf_lev[lf], face_threads(m),
                                    face_lds(m), 0, c->stream, k);
       if (st != BTX_OK) return st;
-      st = launch_zones(m.tsize, c->d_model, m.d_zitems_lts, m.nz_lev[lz], m.g.ns * m.g.ne, 0, c->stream);
+      st = launch_zones(m.tsize, c->d_model, m.d_zitems_lts, m.nz_lev[lz], m.g.ns * m.g.ne, 0, c->stream,
+                        m.g.ndir);
       if (st != BTX_OK) return st;
     }
     return BTX_OK;
@@ -1972,7 +2050,7 @@ btx_status ctx_step(btx_ctx *c, double dt)
                                face_lds(m), c->parity, c->stream);
   if (st != BTX_OK) return st;
   if (rec) HIP_TRY(hipEventRecord(e1, c->stream));
-  st = launch_zones(m.tsize, c->d_model, m.d_zitems, m.g.nz, m.g.ns * m.g.ne, c->parity, c->stream);
+  st = launch_zones(m.tsize, c->d_model, m.d_zitems, m.g.nz, m.g.ns * m.g.ne, c->parity, c->stream, m.g.ndir);
   if (st != BTX_OK) return st;
   if (rec) HIP_TRY(hipEventRecord(e2, c->stream));
   c->parity ^= 1;
@@ -2150,7 +2228,7 @@ btx_status tune(btx_batch *b)
   btx_status st = BTX_OK;
   for (size_t i = 0; i < b->models.size() && st == BTX_OK; ++i) {
     const std::string key = tune_key(b->models[i]);
-    if (b->tsize == 8 || lookup(key)) continue;
+    if (b->tsize == 8 || lookup(key) || b->models[i].shape.gtab) continue;
     std::vector<Model *> cls;
     for (Model &m : b->models)
       if (tune_key(m) == key) cls.push_back(&m);
@@ -2186,6 +2264,7 @@ btx_status tune(btx_batch *b)
   for (Model &m : b->models) b->h_models[m.index].tally = tsave[m.index];
   if (st != BTX_OK) return st;
   for (Model &m : b->models) {
+    if (m.shape.gtab) continue;                      // tables through the caches: one shape
     const int nch = b->tsize == 8 ? 4 : (lookup(tune_key(m)) ? lookup(tune_key(m)) : 8);
     set_shape(b, m, make_shape(m.g.prec, m.g.ndir, m.g.ne, nch));
   }
@@ -2207,9 +2286,12 @@ btx_status batch_launch(btx_batch *b, int parity, hipStream_t s)
                                  gr.lds, parity, s);
     if (st != BTX_OK) return st;
   }
-  int rows = 1;
-  for (const Model &m : b->models) rows = std::max(rows, m.g.ns * m.g.ne);
-  return launch_zones(b->tsize, b->d_models, b->d_zitems, b->nz_all, rows, parity, s);
+  int rows = 1, dirs = 0;
+  for (const Model &m : b->models) {
+    rows = std::max(rows, m.g.ns * m.g.ne);
+    dirs = std::max(dirs, m.g.ndir);
+  }
+  return launch_zones(b->tsize, b->d_models, b->d_zitems, b->nz_all, rows, parity, s, dirs);
 }
 
 // the step of each parity captured once as a graph on the library's stream

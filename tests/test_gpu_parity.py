@@ -66,6 +66,12 @@ CASES = {
     "max_dirs": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=13, n_mu=16, n_phi=8)),
     "max_groups": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=61, n_mu=12, n_phi=4,
                                                e_min=1.0, e_max=300.0)),
+    # beyond LDS: the remap tables are read through the caches
+    "wide_200": lambda: _perturb(W.axisym_2d(n_r=4, n_theta=3, n_eps=3, n_mu=20, n_phi=10)),
+    "wide_544": lambda: _perturb(W.radiating_sphere_2d(n_r=6, n_theta=4, n_mu=17, n_phi=32,
+                                                       mu_rule="legendre")),
+    "mixed_128x61": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=61, n_mu=16, n_phi=8,
+                                                 e_min=1.0, e_max=300.0)),
     # the largest in mixed precision at 128 directions: 45 groups
     "max_mixed": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=45, n_mu=16, n_phi=8,
                                               e_min=1.0, e_max=300.0)),
@@ -118,7 +124,7 @@ def _run_pair(w, steps, precision, oracle_mod):
     return o, ctx
 
 
-@pytest.mark.parametrize("case", [c for c in CASES if c != "max_mixed"])
+@pytest.mark.parametrize("case", [c for c in CASES if c not in ("max_mixed", "mixed_128x61")])
 def test_fp64_parity(case, oracle_mod):
     w = CASES[case]()
     _say(f"[gpu] fp64 parity {case}: zones {w.n_zones} block {w.block}")
@@ -142,7 +148,8 @@ def test_fp64_parity(case, oracle_mod):
 
 
 @pytest.mark.parametrize("case", ["shock_3species", "column_lobatto_v", "split_groups", "large_shift",
-                                  "shock_3d", "max_dirs", "max_groups", "max_mixed"])
+                                  "shock_3d", "max_dirs", "max_groups", "max_mixed", "wide_200",
+                                  "wide_544", "mixed_128x61"])
 def test_mixed_moments(case, oracle_mod):
     w = CASES[case]()
     _say(f"[gpu] mixed moments {case}")
@@ -179,10 +186,13 @@ def test_number_conservation_gpu(oracle_mod):
 def test_errors_gpu():
     btx = _btx()
     big = W.axisym_2d(n_r=3, n_theta=2, n_eps=61, n_mu=16, n_phi=8, e_min=1.0, e_max=300.0)
-    for prec in (W.PREC_FP64, W.PREC_MIXED):        # beyond a face workgroup's LDS
-        with pytest.raises(btx.BtxError) as e:
-            btx.Context(big, precision=prec)
-        assert e.value.status == btx.BTX_E_UNSUPPORTED and "LDS" in str(e.value)
+    with pytest.raises(btx.BtxError) as e:           # FP64 stencil blocks beyond LDS
+        btx.Context(big, precision=W.PREC_FP64)
+    assert e.value.status == btx.BTX_E_UNSUPPORTED and "LDS" in str(e.value)
+    wide = W.axisym_2d(n_r=3, n_theta=2, n_eps=30, n_mu=20, n_phi=16)
+    with pytest.raises(btx.BtxError) as e:           # more than 256 directions, 30 groups
+        btx.Context(wide, precision=W.PREC_MIXED)
+    assert e.value.status == btx.BTX_E_UNSUPPORTED
     w = W.axisym_2d(n_r=6, n_theta=4, n_eps=4, n_mu=4, n_phi=4)
     ctx = btx.Context(w)
     with pytest.raises(btx.BtxError) as e:
@@ -396,4 +406,30 @@ def test_time_levels_gpu(case, precision, oracle_mod):
     with pytest.raises(btx.BtxError) as e:
         ctx.step(dt, 1)
     assert e.value.status == btx.BTX_E_CFL
+    ctx.close()
+
+
+def test_evolving_background_wide_gpu(oracle_mod):
+    """a background update on a grid of 544 directions (wide gather keys in the
+    time remap): FP64 against the reference"""
+    btx = _btx()
+    w = _perturb(W.radiating_sphere_2d(n_r=5, n_theta=3, n_mu=17, n_phi=32, mu_rule="legendre"))
+    w.v_r = np.linspace(-0.1, 0.1, w.n_zones)
+    w2 = _evolved(w)
+    _say("[gpu] evolving background, 544 directions")
+    o = oracle_mod.Oracle(w)
+    dt = 0.9 * o.max_dt(0.4)
+    ctx = btx.Context(w, precision=W.PREC_FP64)
+    ctx.set_background()
+    ctx.set_state(w.f0)
+    o.step(dt, 1)
+    ctx.step(dt, 1)
+    o.update_background(w2)
+    ctx.update_background(w2)
+    o.step(dt, 1)
+    ctx.step(dt, 1)
+    ref, got = o.state(), ctx.get_state()
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _say(f"[gpu]   rel err {err:.3e}")
+    assert err <= 1e-12
     ctx.close()

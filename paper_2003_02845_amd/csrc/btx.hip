@@ -1371,13 +1371,13 @@ FaceShape make_shape(int prec, int nd, int ne, int nch)
 
 // Shapes for momentum grids whose tables do not fit in LDS beside the stencil
 // blocks (or with more than 128 directions): tables read from global memory,
-// 4, 2 or 1 work items per direction (up to 256, 512 or 1024 directions) and
-// 4, 8 or 16 groups per item, chosen so that group -1 never ends an item.
-FaceShape make_gtab_shape(int nd, int ne)
+// nch = 4, 2 or 1 work items per direction (nch nd <= 1024) and 4, 8 or 16
+// groups per item, chosen so that group -1 never ends an item.
+FaceShape make_gtab_shape(int nd, int ne, int nch)
 {
   FaceShape f;
-  if (nd > 1024) return f;
-  f.nch = nd <= 256 ? 4 : (nd <= 512 ? 2 : 1);
+  if (nch * nd > 1024) return f;
+  f.nch = nch;
   f.maxt = 1024;
   f.gtab = true;
   for (int c : { 4, 8, 16 })
@@ -1598,8 +1598,16 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
   m.tsize = g.prec == BTX_PREC_FP64 ? 8 : 4;
   m.dt_max1 = btx::max_dt(g, 1.0);
   m.shape = default_shape(g);
-  if (m.shape.ce == 0 || face_lds_bytes(g.ndir, g.ns, m.shape.nch, m.shape.ce, m.tsize) > lds_cap)
-    m.shape = make_gtab_shape(g.ndir, g.ne);     // tables through the caches instead of LDS
+  if (m.shape.ce == 0 || face_lds_bytes(g.ndir, g.ns, m.shape.nch, m.shape.ce, m.tsize) > lds_cap) {
+    FaceShape fit, first;                          // tables through the caches instead of LDS
+    for (int nch : { 4, 2, 1 }) {
+      const FaceShape f = make_gtab_shape(g.ndir, g.ne, nch);
+      if (!f.ce) continue;
+      if (!first.ce) first = f;
+      if (face_lds_bytes(g.ndir, g.ns, nch, f.ce, m.tsize, true) <= lds_cap) { fit = f; break; }
+    }
+    m.shape = fit.ce ? fit : first;                // the first that fits, else report the LDS
+  }
   if (m.shape.ce == 0) return fail(BTX_E_UNSUPPORTED, "no face work-item shape for this grid");
   const size_t flds = face_lds_bytes(g.ndir, g.ns, m.shape.nch, m.shape.ce, m.tsize, m.shape.gtab);
   if (flds > lds_cap)

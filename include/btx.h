@@ -33,13 +33,14 @@
  *   the ABI.  btx_last_error() returns a thread-local message for the last
  *   failing call on that thread.
  *   Threads: one context must not be used by two threads at once.
- *   Limits: at most 128 directions (n_mu n_phi), 61 energy groups and 2048
- *   (species x groups) rows; a face workgroup holds its remap tables and
- *   four stencil blocks of one species in the 160 KB of LDS of a compute
- *   unit, which bounds directions x groups: FP64 takes up to 61 groups with
- *   48 directions, 25 with 96 and 13 with 128; mixed precision takes up to 61
- *   groups with 96 directions and 45 with 128.  btx_create reports
- *   BTX_E_UNSUPPORTED beyond.
+ *   Limits: at most 1024 directions (n_mu n_phi), 61 energy groups (29
+ *   beyond 256 directions) and 2048 (species x groups) rows.  A face
+ *   workgroup keeps four stencil blocks of one species in the 160 KB of LDS
+ *   of a compute unit, and its remap tables too where they fit (else it reads
+ *   them through the caches), which bounds directions x groups: FP64 takes up
+ *   to 61 groups with 48 directions, 29 with 96 or 128, 13 with 256 and 1
+ *   with 544; mixed precision 61 with 128 directions, 29 with 256, 5 with
+ *   544 and 1 with 1024.  btx_create reports BTX_E_UNSUPPORTED beyond.
  */
 #ifndef BTX_H
 #define BTX_H

@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--lts-level", type=int, default=6,
                     help="highest time level of the local-time-stepping run (0: skip it)")
     ap.add_argument("--lts-steps", type=int, default=2)
+    ap.add_argument("--no-shard", dest="shard", action="store_false",
+                    help="skip the timing of one GPU's share of a radially split grid")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -272,6 +274,19 @@ def main():
         if k64 == a.steps:
                 out["number_drift_mixed"] = float(np.max(np.abs(tot[:, 0] + tot[:, 1] - res64["tot"][:, 0]
                                                             - res64["tot"][:, 1]) / res64["tot"][:, 0]))
+    if a.shard:
+        # one GPU's share of the grid split radially over 8 GPUs: 75 radial
+        # zones (plus the two-zone halos on each side) of every theta row
+        n_own = w.n_r // 8
+        slab = W.radial_slab(w, 3 * n_own - 2, n_own + 4)
+        sh = run_gpu(torch, btx, slab, W.PREC_MIXED, a.steps, a.warmup)
+        out["shard"] = {"workload": f"radial slab of {n_own} + 2 x 2 halo zones x {w.n_theta} theta rows "
+                                    f"(one eighth of the grid), mixed precision",
+                        "ms_per_step": sh["ms"] / a.steps,
+                        "updates_per_s": slab.n_values * a.steps / (sh["ms"] * 1e-3),
+                        "owned_updates_per_s": n_own * w.n_theta * w.block * a.steps / (sh["ms"] * 1e-3)}
+        print(f"[bench] shard: {out['shard']['ms_per_step']:.3f} ms/step for {slab.n_zones} zones",
+              file=sys.stderr, flush=True)
     if a.lts_level > 0:
         out["local_time_stepping"] = run_lts(torch, btx, w, a.lts_level, a.lts_steps, mixed["ms"] / a.steps)
         l = out["local_time_stepping"]

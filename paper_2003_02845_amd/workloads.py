@@ -204,6 +204,24 @@ def radiating_disk(n_r=100, n_theta=32, n_mu=16, n_phi=8, r_min=0.05, r_max=4.0,
     return w
 
 
+def radial_slab(w, a0, n):
+    """radial zones a0 .. a0+n-1 of every theta row (and phi zone) of a
+    workload, as a workload of its own: the share of one GPU of a radially
+    decomposed grid, its two-zone halos included.  Pure data slicing."""
+    import copy as _copy
+    v = _copy.copy(w)
+    nz_row = w.n_r
+    keep = np.array([z for z in range(w.n_zones) if a0 <= z % nz_row < a0 + n])
+    for name in ("v_r", "v_theta", "alpha", "psi", "kappa_a", "kappa_s", "f_eq", "f0"):
+        setattr(v, name, np.ascontiguousarray(getattr(w, name)[keep]))
+    if w.v_phi is not None:
+        v.v_phi = np.ascontiguousarray(w.v_phi[keep])
+    v.r_edges = np.ascontiguousarray(w.r_edges[a0:a0 + n + 1])
+    v.n_r = n
+    v.name = w.name + f"_slab{a0}+{n}"
+    return v
+
+
 def extrude_phi(w, n_phi_zones):
     """The 3D grid of n_phi_zones copies of an axisymmetric workload's wedge
     around the axis (phi zones of the wedge's width, periodic): every

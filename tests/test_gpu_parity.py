@@ -66,6 +66,9 @@ CASES = {
     "max_dirs": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=13, n_mu=16, n_phi=8)),
     "max_groups": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=61, n_mu=12, n_phi=4,
                                                e_min=1.0, e_max=300.0)),
+    # one GPU's radial share of a larger grid (inner boundary inside the profile)
+    "slab": lambda: _perturb(W.radial_slab(W.shock_2d(n_r=40, n_theta=4, n_eps=5, n_mu=4, n_phi=4,
+                                                      precision=W.PREC_FP64), 15, 9)),
     # beyond LDS: the remap tables are read through the caches
     "wide_200": lambda: _perturb(W.axisym_2d(n_r=4, n_theta=3, n_eps=3, n_mu=20, n_phi=10)),
     "wide_544": lambda: _perturb(W.radiating_sphere_2d(n_r=6, n_theta=4, n_mu=17, n_phi=32,

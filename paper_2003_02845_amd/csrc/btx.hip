@@ -1272,7 +1272,18 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   }
 }
 
-// per-zone moments in FP64 (paper Sec. 4.1-4.2, without 1/h^3):
+// Compensated summation (Neumaier's variant of Kahan's): s + c carries the
+// sum of the added values with the rounding error of every addition kept in c.
+__device__ inline void comp_add(double &s, double &c, double x)
+{
+  const double t = s + x;
+  c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+  s = t;
+}
+
+// per-zone moments in FP64 (paper Sec. 4.1-4.2, without 1/h^3), each a
+// compensated sum over the zone's bins (per thread, over the lanes of a wave
+// and over the waves in a fixed order):
 // zm[z][s][0..4] = N, J, H, K, number flux; ze[z][s] = energy content
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -1283,36 +1294,45 @@ moments_kernel(const ModelDev *__restrict__ models, int m, int parity, double *_
   const DevGrid g = global_grid(M.g);
   const T *__restrict__ f = as_global((const T *)M.f[parity]);
   const int z = blockIdx.x;
-  __shared__ double red[6][16];
+  __shared__ double red[6][16], redc[6][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const double vr = g.vr[z], vt = g.vth[z], vp = g.vph[z];
   const double gam = 1.0 / sqrt(1.0 - (vr * vr + vt * vt + vp * vp));
   const double p6v = pow(g.psi[z], 6.0) * g.vol[z];
   for (int s = 0; s < g.ns; ++s) {
-    double m[6] = { 0, 0, 0, 0, 0, 0 };
+    double m[6] = { 0, 0, 0, 0, 0, 0 }, mc[6] = { 0, 0, 0, 0, 0, 0 };
     for (int q = threadIdx.x; q < g.eblk; q += blockDim.x) {
       int i = q / g.ndir, d = q - i * g.ndir;
       double fv = (double)f[(size_t)z * g.blk + (size_t)s * g.eblk + q];
       const double *nv = g.nvec + 3 * d;
       double dG = g.G[i] * g.dOm[d], mu = nv[0], e = g.eps[i];
       double nn = p6v * gam * (1.0 + vr * nv[0] + vt * nv[1] + vp * nv[2]) * dG * fv;
-      m[0] += nn;
-      m[1] += fv * e * dG;
-      m[2] += fv * mu * e * dG;
-      m[3] += fv * mu * mu * e * dG;
-      m[4] += fv * mu * dG;
-      m[5] += nn * e;
+      comp_add(m[0], mc[0], nn);
+      comp_add(m[1], mc[1], fv * e * dG);
+      comp_add(m[2], mc[2], fv * mu * e * dG);
+      comp_add(m[3], mc[3], fv * mu * mu * e * dG);
+      comp_add(m[4], mc[4], fv * mu * dG);
+      comp_add(m[5], mc[5], nn * e);
     }
     for (int k = 0; k < 6; ++k) {
-      double v = wave_sum(m[k]);
-      if (lane == 0) red[k][wave] = v;
+      double v = m[k], c = mc[k];
+      for (int o = 32; o > 0; o >>= 1) {
+        const double vo = __shfl_xor(v, o, 64), co = __shfl_xor(c, o, 64);
+        comp_add(v, c, vo);
+        c += co;
+      }
+      if (lane == 0) { red[k][wave] = v; redc[k][wave] = c; }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       double t[6];
       for (int k = 0; k < 6; ++k) {
-        t[k] = 0.0;
-        for (int w = 0; w < nwaves; ++w) t[k] += red[k][w];
+        double v = 0.0, c = 0.0;
+        for (int w = 0; w < nwaves; ++w) {
+          comp_add(v, c, red[k][w]);
+          c += redc[k][w];
+        }
+        t[k] = v + c;
       }
       double *o = zm + ((size_t)z * g.ns + s) * 5;
       o[0] = t[0];
@@ -1872,16 +1892,22 @@ btx_status model_moments(const Model &m, const ModelDev *d_models, int parity, d
   HIP_TRY(hipStreamSynchronize(s));
   if (zone_moments) std::memcpy(zone_moments, hzm.data(), hzm.size() * 8);
   if (totals) {
+    // compensated sums over the zones and the boundary faces
+    auto add = [](double &s, double &c, double x) {
+      const double t = s + x;
+      c += std::fabs(s) >= std::fabs(x) ? (s - t) + x : (x - t) + s;
+      s = t;
+    };
     for (int sp = 0; sp < g.ns; ++sp) {
-      double N = 0.0, E = 0.0, out = 0.0;
+      double N = 0.0, Nc = 0.0, E = 0.0, Ec = 0.0, out = 0.0, outc = 0.0;
       for (int z = 0; z < g.nz; ++z) {
-        N += hzm[((size_t)z * g.ns + sp) * 5];
-        E += hze[(size_t)z * g.ns + sp];
+        add(N, Nc, hzm[((size_t)z * g.ns + sp) * 5]);
+        add(E, Ec, hze[(size_t)z * g.ns + sp]);
       }
-      for (int f : g.bface) out += tally[(size_t)f * g.ns + sp];
-      totals[3 * sp] = N;
-      totals[3 * sp + 1] = out;
-      totals[3 * sp + 2] = E;
+      for (int f : g.bface) add(out, outc, tally[(size_t)f * g.ns + sp]);
+      totals[3 * sp] = N + Nc;
+      totals[3 * sp + 1] = out + outc;
+      totals[3 * sp + 2] = E + Ec;
     }
   }
   return BTX_OK;

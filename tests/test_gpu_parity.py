@@ -186,6 +186,35 @@ def test_number_conservation_gpu(oracle_mod):
     ctx.close()
 
 
+def test_compensated_totals_gpu(oracle_mod):
+    """The totals over the zones are compensated sums: within two roundings of
+    the correctly rounded sum (math.fsum) of the zone moments the same call
+    returns.  Every zone holds about the same number except zone 0, which holds
+    2^60 times more, so that a running FP64 sum in zone order drops each of
+    the others and is off by several roundings."""
+    btx = _btx()
+    w = W.shock_2d(n_r=48, n_theta=32, n_eps=3, n_mu=4, n_phi=4, precision=W.PREC_FP64)
+    vol, _, _ = oracle_mod.Oracle(w, state=False).geometry()
+    scale = 1.0 / (vol * w.psi ** 6)
+    scale[0] *= 2.0 ** 60
+    w.f0 = np.ones_like(w.f0) * scale[:, None, None, None]
+    _say("[gpu] compensated totals")
+    ctx = btx.Context(w)
+    ctx.set_background()
+    ctx.set_state(w.f0)
+    zm, tot = ctx.moments()
+    for s in range(w.n_species):
+        exact = math.fsum(zm[:, s, 0])
+        running = 0.0
+        for v in zm[:, s, 0]:
+            running += v
+        _say(f"[gpu]   species {s}: total - fsum = {(tot[s, 0] - exact) / math.ulp(exact):.1f} ulp, "
+             f"running sum {(running - exact) / math.ulp(exact):.1f} ulp")
+        assert abs(tot[s, 0] - exact) <= 2 * math.ulp(exact)
+        assert abs(running - exact) > 2 * math.ulp(exact)      # the case is sensitive
+    ctx.close()
+
+
 def test_errors_gpu():
     btx = _btx()
     big = W.axisym_2d(n_r=3, n_theta=2, n_eps=61, n_mu=16, n_phi=8, e_min=1.0, e_max=300.0)

@@ -144,7 +144,9 @@ btx_status btx_get_state(btx_ctx *ctx, void *f, int is_device_ptr);
 btx_status btx_step(btx_ctx *ctx, double dt, int32_t n_steps);
 /* zone_moments[zone][species][5] = N (number), J, H, K, number flux (Sec. 4.1,
  * 4.2); totals[species][3] = total number, cumulative boundary outflow, total
- * energy.  Either pointer may be NULL.  Computed on the device in FP64. */
+ * energy.  Either pointer may be NULL.  Zone moments are computed on the
+ * device as compensated FP64 sums over the bins, the totals on the host as
+ * compensated sums over the zones and boundary faces. */
 btx_status btx_moments(btx_ctx *ctx, double *zone_moments, double *totals);
 /* Hydro source terms of the last step (coupling to matter, Sec. 3.4,
  * Eq. hydrosource1-3): q[zone][5] = Q_Ye, Q_E, Q_M,r, Q_M,theta, Q_M,phi, what

@@ -235,7 +235,7 @@ def main():
     achieved = b_face / t_face / 1e9
     traffic = face_traffic() if (a.n_r, a.n_theta) == (600, 256) else None
     out = {
-        "metric": "zone*group*direction updates/s (mixed FP32/FP64), with FP64 speedup and % HBM peak",
+        "metric": "zone\u00b7group\u00b7direction updates/s, mixed FP32/FP64 vs FP64; % HBM peak",
         "value": value,
         "unit": "updates/s",
         "n_gpus": 1,

@@ -1165,9 +1165,12 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
 
 // ------------------------------------------------------------ zone kernel
 
-// R: directions per lane (64 R directions at most)
+// R: directions per lane (64 R directions at most).  A direction's loads (the
+// state and the changes from every face side of the zone) all go out before
+// the first is used; at 4 waves per SIMD (not 8) the compiler keeps them in
+// registers, and the kernel is faster for it.
 template <typename T, int R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity)
 {
   const int2 it = items[blockIdx.x];
@@ -1185,6 +1188,7 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   const int nd = g.ndir, ne = g.ne, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
   const btx::ZoneFaces &L = zf[z];        // uniform: read through the scalar cache
+  const int nq = L.n;                     // at most 8 face sides
   const double vr = g.vr[z], vt = g.vth[z], vp = g.vph[z];
   const double gam = 1.0 / sqrt(1.0 - (vr * vr + vt * vt + vp * vp));
   const double p6v = pow(g.psi[z], 6.0) * g.vol[z];
@@ -1205,12 +1209,18 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
       Sd[r] = 0.0;
       if (d >= nd) continue;
       size_t off = (size_t)s * g.eblk + (size_t)i * nd + d;
+      const T fz = f[(size_t)z * g.blk + off];
+      T dv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nq) dv[q] = dN[((size_t)L.fid[q] * 2 + L.side[q]) * g.blk + off];
       double acc = 0.0;
-      for (int q = 0; q < L.n; ++q)
-        acc += (double)dN[((size_t)L.fid[q] * 2 + L.side[q]) * g.blk + off];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nq) acc += (double)dv[q];
       const double *nv = g.nvec + 3 * d;
       double W = p6v * gam * (1.0 + vr * nv[0] + vt * nv[1] + vp * nv[2]) * g.G[i] * g.dOm[d];
-      double S = (double)f[(size_t)z * g.blk + off] + tau * ka_ * fe_ + acc / W;
+      double S = (double)fz + tau * ka_ * fe_ + acc / W;
       if (!wide) S = (double)(float)S;
       Sd[r] = S;
       part += S * g.dOm[d];

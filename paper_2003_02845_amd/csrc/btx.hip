@@ -812,16 +812,17 @@ __device__ __forceinline__ void fetch_side(const DevGrid &g, const SideDesc &sd,
                                            const T *__restrict__ feq, int s, int li, int ld, T v[CE])
 {
   const int nd = g.ndir, ne = g.ne;
-  const T *src = f + (size_t)sd.z * g.blk + (size_t)s * g.eblk + ld;
-  const T *eq = feq + ((size_t)sd.z * g.ns + s) * ne;
+  // one load site per row (a zone's block, or the equilibrium of a ghost), so
+  // that the loads of all rows and sides are in flight together
+  const bool data = sd.kind == btx::SIDE_ZONE || sd.kind == btx::SIDE_MIRROR;
+  const bool any = data || sd.kind == btx::SIDE_EQ;
+  const T *base = data ? f + (size_t)sd.z * g.blk + (size_t)s * g.eblk + ld : feq + ((size_t)sd.z * g.ns + s) * ne;
+  const size_t stride = data ? (size_t)nd : 1;
 #pragma unroll
   for (int m = 0; m < CE; ++m) {
     const int i = li + NCH * m;
     T x = (T)0;
-    if (i < ne) {
-      if (sd.kind == btx::SIDE_ZONE || sd.kind == btx::SIDE_MIRROR) x = src[(size_t)i * nd];
-      else if (sd.kind == btx::SIDE_EQ) x = eq[i];
-    }
+    if (any && i < ne) x = base[(size_t)i * stride];
     v[m] = x;
   }
 }
@@ -912,7 +913,15 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
     const uint4 *src = (const uint4 *)(tabs_g + (size_t)fid * kTables * tstride);
     uint4 *dst = (uint4 *)lds;
     const int n16 = (int)(kTables * tstride / 16);
-    for (int q = tid; q < n16; q += nthr) dst[q] = src[q];
+    // four loads in flight per thread: indexes past the end are clamped to
+    // the last entry (loaded and stored again), so that no load is guarded
+    for (int q0 = tid; q0 < n16; q0 += 4 * nthr) {
+      uint4 t[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) t[u] = src[min(q0 + u * nthr, n16 - 1)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) dst[min(q0 + u * nthr, n16 - 1)] = t[u];
+    }
   }
   // ---- zero rows of the data buffers, per-row constants outside 0 .. ne-1
   {
@@ -964,7 +973,8 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
 #pragma unroll
   for (int m = 0; m < CE; ++m) {
     const int i = li + NCH * m;
-    gl[m] = i < ne ? (T)g.G[i] : (T)0;
+    const double Gi = g.G[min(i, ne - 1)];           // unguarded, so the loads overlap
+    gl[m] = i < ne ? (T)Gi : (T)0;
   }
   const SideDesc *sides[4] = { &F.Lm, &F.L, &F.R, &F.Rp };
   int colS[4];

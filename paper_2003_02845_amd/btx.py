@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libbtx.so")
 BTX_OK, BTX_E_INVAL, BTX_E_NOMEM, BTX_E_DEVICE, BTX_E_CFL, BTX_E_STATE, BTX_E_UNSUPPORTED = range(7)
 PREC_FP64, PREC_MIXED = 0, 1
 MU_LEGENDRE, MU_LOBATTO = 0, 1
+GEOM_COLUMN, GEOM_AXISYM2D, GEOM_PLANAR = 0, 1, 2      # btx_geometry
 ABI_SYMBOLS = ["btx_create", "btx_set_background", "btx_max_dt", "btx_set_state",
                "btx_get_state", "btx_step", "btx_moments", "btx_timing", "btx_destroy",
                "btx_last_error", "btx_update_background", "btx_batch_create",
@@ -109,9 +110,20 @@ def _p(a):
     return a.ctypes.data_as(_dp)
 
 
+def _need(ok, msg, exc=ValueError):
+    if not ok:
+        raise exc(msg)
+
+
 def _desc(w, precision, fp64_threshold):
-    keep = [np.ascontiguousarray(w.r_edges, float), np.ascontiguousarray(w.theta_edges, float),
-            np.ascontiguousarray(w.eps_edges, float)]
+    keep = [np.ascontiguousarray(w.r_edges, float).reshape(-1),
+            np.ascontiguousarray(w.theta_edges, float).reshape(-1),
+            np.ascontiguousarray(w.eps_edges, float).reshape(-1)]
+    # the library reads as many edges as the counts say
+    _need(keep[0].size >= w.n_r + 1, f"r_edges needs {w.n_r + 1} values")
+    _need(w.geometry != GEOM_AXISYM2D or keep[1].size >= w.n_theta + 1,
+          f"theta_edges needs {w.n_theta + 1} values")
+    _need(keep[2].size >= w.n_eps + 1, f"eps_edges needs {w.n_eps + 1} values")
     d = GridDesc(w.n_r, w.n_theta, w.n_eps, w.n_mu, w.n_phi, w.n_species, w.geometry,
                  MU_LEGENDRE if w.mu_rule == "legendre" else MU_LOBATTO, w.phi_rule,
                  w.inner_bc, w.outer_bc, precision, _p(keep[0]), _p(keep[1]),
@@ -120,13 +132,28 @@ def _desc(w, precision, fp64_threshold):
     return d, keep
 
 
-def _background(w):
-    arrs = [np.ascontiguousarray(a, float) for a in
+def _background(w, grid):
+    """the background arrays of w, checked against the sizes of grid (the
+    workload the context or model was created from)"""
+    nz, nk = grid.n_zones, grid.n_zones * grid.n_species * grid.n_eps
+    arrs = [np.ascontiguousarray(a, float).reshape(-1) for a in
             (w.v_r, w.v_theta, w.alpha, w.psi, w.kappa_a, w.kappa_s, w.f_eq)]
+    for name, a, n in zip(("v_r", "v_theta", "alpha", "psi", "kappa_a", "kappa_s", "f_eq"), arrs,
+                          (nz, nz, nz, nz, nk, nk, nk)):
+        _need(a.size == n, f"{name} has {a.size} values, the grid needs {n}")
     vph = getattr(w, "v_phi", None)
     if vph is not None:
-        arrs.append(np.ascontiguousarray(vph, float))
+        arrs.append(np.ascontiguousarray(vph, float).reshape(-1))
+        _need(arrs[-1].size == nz, f"v_phi has {arrs[-1].size} values, the grid needs {nz}")
     return Background(*[_p(a) for a in arrs]), arrs
+
+
+def _device_tensor(t, n, dtype, device):
+    """a GPU tensor the library may read or write n values of dtype through"""
+    _need(t.is_cuda and t.is_contiguous(), "the tensor must be a contiguous GPU tensor")
+    _need(t.device.index == device, f"the tensor is on GPU {t.device.index}, the context on {device}")
+    _need(t.numel() == n, f"the tensor has {t.numel()} values, the state {n}")
+    _need(t.dtype == dtype, f"the tensor is {t.dtype}, the state {dtype}", TypeError)
 
 
 class Context:
@@ -140,6 +167,7 @@ class Context:
         h = C.c_void_p()
         _check(lib().btx_create(C.byref(d), device, C.c_void_p(stream or 0), C.byref(h)))
         self.h = h
+        self.device = device
         self.shape = (w.n_zones, w.n_species, w.n_eps, w.n_dir)
 
     def close(self):
@@ -154,12 +182,12 @@ class Context:
             pass
 
     def set_background(self, w=None):
-        bg, keep = _background(w or self.w)
+        bg, keep = _background(w or self.w, self.w)
         _check(lib().btx_set_background(self.h, C.byref(bg)))
 
     def update_background(self, w):
         """evolve the background: the state is remapped into the new comoving frames"""
-        bg, keep = _background(w)
+        bg, keep = _background(w, self.w)
         _check(lib().btx_update_background(self.h, C.byref(bg)))
 
     def max_dt(self, cfl=None):
@@ -169,18 +197,21 @@ class Context:
 
     def set_state(self, f):
         """f: numpy array (host) or torch tensor on the GPU, dtype of the precision"""
+        n = int(np.prod(self.shape))
         if torch is not None and isinstance(f, torch.Tensor):
-            assert f.is_cuda and f.is_contiguous() and f.numel() == int(np.prod(self.shape))
-            want = torch.float64 if self.dtype == np.float64 else torch.float32
-            assert f.dtype == want
+            _device_tensor(f, n, torch.float64 if self.dtype == np.float64 else torch.float32, self.device)
             _check(lib().btx_set_state(self.h, C.c_void_p(f.data_ptr()), 1))
         else:
             a = np.ascontiguousarray(f, dtype=self.dtype).reshape(-1)
-            assert a.size == int(np.prod(self.shape))
+            _need(a.size == n, f"the state has {n} values, not {a.size}")
             _check(lib().btx_set_state(self.h, C.c_void_p(a.ctypes.data), 0))
 
     def get_state(self, out=None):
+        """the state as a numpy array, or into out (a GPU tensor of the state's size and dtype)"""
         if out is not None:
+            _need(torch is not None and isinstance(out, torch.Tensor), "out must be a torch tensor", TypeError)
+            _device_tensor(out, int(np.prod(self.shape)),
+                           torch.float64 if self.dtype == np.float64 else torch.float32, self.device)
             _check(lib().btx_get_state(self.h, C.c_void_p(out.data_ptr()), 1))
             return out
         a = np.empty(self.shape, dtype=self.dtype)
@@ -257,11 +288,11 @@ class Batch:
             pass
 
     def set_background(self, m, w=None):
-        bg, keep = _background(w or self.ws[m])
+        bg, keep = _background(w or self.ws[m], self.ws[m])
         _check(lib().btx_batch_set_background(self.h, m, C.byref(bg)))
 
     def update_background(self, m, w):
-        bg, keep = _background(w)
+        bg, keep = _background(w, self.ws[m])
         _check(lib().btx_batch_update_background(self.h, m, C.byref(bg)))
 
     def max_dt(self, m, cfl=None):
@@ -271,7 +302,7 @@ class Batch:
 
     def set_state(self, m, f):
         a = np.ascontiguousarray(f, dtype=self.dtype).reshape(-1)
-        assert a.size == int(np.prod(self.shapes[m]))
+        _need(a.size == int(np.prod(self.shapes[m])), f"model {m}'s state has {int(np.prod(self.shapes[m]))} values")
         _check(lib().btx_batch_set_state(self.h, m, C.c_void_p(a.ctypes.data), 0))
 
     def get_state(self, m):
@@ -280,8 +311,8 @@ class Batch:
         return a
 
     def step(self, dts, n=1):
-        d = np.ascontiguousarray(dts, dtype=np.float64)
-        assert d.size == len(self.ws)
+        d = np.ascontiguousarray(dts, dtype=np.float64).reshape(-1)
+        _need(d.size == len(self.ws), f"one dt per model ({len(self.ws)})")
         _check(lib().btx_batch_step(self.h, _p(d), int(n)))
 
     def use_graph(self, enable):

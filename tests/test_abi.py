@@ -97,11 +97,39 @@ def test_descriptors_carry_every_field():
     w.v_phi = np.linspace(-0.1, 0.1, w.n_zones)
     d, _ = btx._desc(w, W.PREC_FP64, 1.0)
     assert d.n_phi_zones == 2 and d.theta_bc == W.THETA_AXIS
-    bg, _ = btx._background(w)
+    bg, _ = btx._background(w, w)
     assert bg.v_phi and bg.v_phi[w.n_zones - 1] == 0.1
     w.v_phi = None
-    bg, _ = btx._background(w)
+    bg, _ = btx._background(w, w)
     assert not bg.v_phi
     dk = W.radiating_disk(n_r=4, n_theta=3, n_mu=2, n_phi=3)
     d, _ = btx._desc(dk, W.PREC_FP64, 1.0)
     assert d.theta_bc == W.THETA_DISK and d.disk_radius == 1.0
+
+
+def test_binding_checks_array_sizes():
+    """the library reads as many values as the grid's counts say, so the
+    binding refuses arrays that are too short before any call (a background
+    is checked against the grid the context was made from)"""
+    import copy
+    import numpy as np
+    from paper_2003_02845_amd import btx
+    from paper_2003_02845_amd import workloads as W
+    w = W.axisym_2d(n_r=4, n_theta=3, n_eps=2, n_mu=2, n_phi=3)
+    for field in ("r_edges", "theta_edges", "eps_edges"):
+        bad = copy.deepcopy(w)
+        setattr(bad, field, getattr(w, field)[:-1])
+        with pytest.raises(ValueError, match=field):
+            btx._desc(bad, W.PREC_FP64, 1.0)
+    for field in ("v_r", "alpha", "kappa_a", "f_eq"):
+        bad = copy.deepcopy(w)
+        setattr(bad, field, np.asarray(getattr(w, field)).reshape(-1)[:-1])
+        with pytest.raises(ValueError, match=field):
+            btx._background(bad, w)
+    other = W.axisym_2d(n_r=5, n_theta=3, n_eps=2, n_mu=2, n_phi=3)
+    with pytest.raises(ValueError, match="v_r"):
+        btx._background(other, w)
+    bad = copy.deepcopy(w)
+    bad.v_phi = np.zeros(w.n_zones + 1)
+    with pytest.raises(ValueError, match="v_phi"):
+        btx._background(bad, w)

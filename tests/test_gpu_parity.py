@@ -239,6 +239,17 @@ def test_errors_gpu():
     with pytest.raises(btx.BtxError) as e:
         ctx.set_background(w)
     assert e.value.status == btx.BTX_E_INVAL
+    # device tensors the library would read or write past: refused by the binding
+    import torch
+    n = int(np.prod(ctx.shape))
+    with pytest.raises(ValueError):
+        ctx.get_state(out=torch.empty(n - 1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(TypeError):
+        ctx.set_state(torch.zeros(n, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        ctx.set_state(torch.zeros(2 * n, dtype=torch.float64, device="cuda")[::2])
+    out = ctx.get_state(out=torch.empty(n, dtype=torch.float64, device="cuda"))
+    assert np.array_equal(out.cpu().numpy().reshape(ctx.shape), ctx.get_state())
     ctx.close()
 
 

@@ -35,12 +35,12 @@
  *   Threads: one context must not be used by two threads at once.
  *   Limits: at most 1024 directions (n_mu n_phi), 61 energy groups (29
  *   beyond 256 directions) and 2048 (species x groups) rows.  A face
- *   workgroup keeps four stencil blocks of one species in the 160 KB of LDS
+ *   workgroup keeps three stencil blocks of one species in the 160 KB of LDS
  *   of a compute unit, and its remap tables too where they fit (else it reads
  *   them through the caches), which bounds directions x groups: FP64 takes up
- *   to 61 groups with 48 directions, 29 with 96 or 128, 13 with 256 and 1
- *   with 544; mixed precision 61 with 128 directions, 29 with 256, 5 with
- *   544 and 1 with 1024.  btx_create reports BTX_E_UNSUPPORTED beyond.
+ *   to 61 groups with 80 directions, 29 with 160, 13 with 256, 5 with 544 and
+ *   1 with 768; mixed precision 61 with 160 directions, 29 with 256, 13 with
+ *   544 and 5 with 1024.  btx_create reports BTX_E_UNSUPPORTED beyond.
  */
 #ifndef BTX_H
 #define BTX_H

@@ -302,14 +302,14 @@ __host__ __device__ inline void unpack_key(unsigned key, int nd, int &src, int &
   else { src = key & 0xff; di = (int)(key >> 8) - 128; }
 }
 
-// LDS of one face workgroup: 8 tables, 4 data buffers (Lm, L, R, Rp), per-row
+// LDS of one face workgroup: 8 tables, 3 data buffers (Lm, then Rp; L; R), per-row
 // constants (G, 1/G as T; per species: source and blend weight as T, two
 // collision coefficients as FP64, a precision flag), the wave partials and
 // totals of the angle sums, and the tally partials
 __host__ __device__ inline size_t face_lds_bytes(int nd, int ns, int nch, int ce, size_t szT, bool gtab = false)
 {
   const size_t nrow = col_rows(nch, ce), nsr = (size_t)ns * nrow;
-  return (gtab ? 0 : kTables * tab_stride(nd, szT)) + 4 * buf_bytes(nd, nch, ce, szT) + 2 * align16(nrow * szT) +
+  return (gtab ? 0 : kTables * tab_stride(nd, szT)) + 3 * buf_bytes(nd, nch, ce, szT) + 2 * align16(nrow * szT) +
          2 * align16(nsr * szT) + 2 * align16(nsr * 8) + align16(nsr * 4) + align16(16 * nrow * 8) +
          align16(nrow * 8) + align16(16 * 8);
 }
@@ -840,7 +840,8 @@ __device__ __forceinline__ void store_side(const T v[CE], const T gl[CE], T a, i
 
 // One workgroup per face, NCH work items per direction.  Per species:
 //   load    the four stencil zones' blocks (coalesced rows, transposed into
-//           direction-major LDS columns as number content)
+//           direction-major LDS columns as number content; three buffers,
+//           Rp taking Lm's after the slopes of L)
 //   phase 1 MC-limited slopes of both sides in their own frames (Sec. 3.3.2)
 //           and the reconstructed donor values
 //   phase 2 Lax-Wendroff half-step source in the interface frame; angle sums
@@ -891,9 +892,9 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   char *p = lds;
   const char *tabs = GTAB ? tabs_g + (size_t)fid * kTables * tstride : p;
   if (!GTAB) p += kTables * tstride;
-  char *bufs = p;               p += 4 * bb;
+  char *bufs = p;               p += 3 * bb;
   T *XLm = (T *)(bufs) + gb, *XL = (T *)(bufs + bb) + gb, *XR = (T *)(bufs + 2 * bb) + gb,
-    *XRp = (T *)(bufs + 3 * bb) + gb;
+    *XRp = XLm;                   // Rp takes Lm's buffer once the slopes of L are done
   const int nsr = g.ns * nrow;
   T *rG = (T *)p + gb;          p += align16(nrow * sizeof(T));
   T *riG = (T *)p + gb;         p += align16(nrow * sizeof(T));
@@ -926,7 +927,7 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   // ---- zero rows of the data buffers, per-row constants outside 0 .. ne-1
   {
     const int ng = nrow - ne;
-    for (int q = tid; q < 4 * nd * ng; q += nthr) {
+    for (int q = tid; q < 3 * nd * ng; q += nthr) {
       int b = q / (nd * ng), rem = q - b * nd * ng, d = rem / ng, r = rem - d * ng;
       ((T *)(bufs + b * bb))[d * cs + (r < gb ? r : r + ne)] = (T)0;
     }
@@ -1039,16 +1040,19 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
 #pragma unroll 1
   for (int s = 0; s < g.ns; ++s) {
     // ---- load the stencil blocks as content densities
+    // Rp goes into Lm's buffer after stage 0.  FP32 loads it with the other
+    // sides and holds it in registers; FP64, short of registers, loads it then.
+    constexpr bool kHoldRp = sizeof(T) == 4;
+    T v3[CE];
     {
-      T v0[CE], v1[CE], v2[CE], v3[CE];
+      T v0[CE], v1[CE], v2[CE];
       if (slopeL) fetch_side<T, NCH, CE>(g, F.Lm, f, feq, s, li, ld, v0);
       fetch_side<T, NCH, CE>(g, F.L, f, feq, s, li, ld, v1);
       fetch_side<T, NCH, CE>(g, F.R, f, feq, s, li, ld, v2);
-      if (slopeR) fetch_side<T, NCH, CE>(g, F.Rp, f, feq, s, li, ld, v3);
+      if (kHoldRp && slopeR) fetch_side<T, NCH, CE>(g, F.Rp, f, feq, s, li, ld, v3);
       if (slopeL) store_side<T, NCH, CE>(v0, gl, aS_[0], colS[0], li, ne, cs, XLm);
       store_side<T, NCH, CE>(v1, gl, aS_[1], colS[1], li, ne, cs, XL);
       store_side<T, NCH, CE>(v2, gl, aS_[2], colS[2], li, ne, cs, XR);
-      if (slopeR) store_side<T, NCH, CE>(v3, gl, aS_[3], colS[3], li, ne, cs, XRp);
     }
     const T *rsrc = rsrc0 + s * nrow, *rw = rw0 + s * nrow;
     const double *rc0 = rc00 + s * nrow, *rc1 = rc10 + s * nrow;
@@ -1060,7 +1064,8 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
     //   2 interface        T4 . L,   T5 . R    -> S, <S>, collision, blend
     //   3 content to L     T6 . FL,  T1 . ER
     //   4 content to R     T7 . FL,  T2 . EL
-    // (buffers: 0 Lm (FL after stage 2), 1 L (EL content), 2 R (ER content), 3 Rp)
+    // (buffers: 0 Lm, Rp after stage 0, FL after stage 2; 1 L (EL content
+    // after stage 2); 2 R (ER content after stage 2))
     T EL[CE], ER[CE];
     double sumL = 0.0, sumR = 0.0;
 #pragma unroll 1
@@ -1072,7 +1077,7 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
 #pragma unroll 1
       for (int j = 0; j < nj; ++j) {
         const int t = (int)((0x2716543210ull >> (4 * (2 * st + j))) & 0xf);
-        const int x = (int)((0x1020213120ull >> (4 * (2 * st + j))) & 0xf);
+        const int x = (int)((0x1020210120ull >> (4 * (2 * st + j))) & 0xf);
         T c[CE];
         gather<T, CE, SPLIT>(TB(t), nd, (const T *)(bufs + x * bb) + gb, cs, ne, dp, r0, top, kb, c);
 #pragma unroll
@@ -1089,6 +1094,12 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
           const T sl = slopeL ? mc_limiter<T>((fl - a[k] * sc) * ihLm, (b[k] * sc - fl) * ih) : (T)0;
           EL[k] = fl + dL * sl;
           if (F.self) ER[k] = XR[dp * cs + r] * riG[r] * iaR + dR * sl;
+        }
+        if (slopeR) {                                  // Rp into Lm's buffer
+          if (!kHoldRp) fetch_side<T, NCH, CE>(g, F.Rp, f, feq, s, li, ld, v3);
+          __syncthreads();
+          store_side<T, NCH, CE>(v3, gl, aS_[3], colS[3], li, ne, cs, XRp);
+          __syncthreads();
         }
       } else if (st == 1) {                            // MC-limited slope of R
         if (!F.self) {
@@ -1379,9 +1390,10 @@ namespace {
 // Face work-item shape: nch items per direction (a power of two), CE groups
 // per item, the workgroup size bound and whether group -1 ends an item.
 // FP32 takes 8 items per direction by default (up to 96 directions in
-// workgroups of up to 768 threads, up to 128 in 1024) or 4; FP64 takes 4 (up
-// to 128 directions, 512 threads), which keeps its larger LDS buffers within
-// one CU.  CE is the smallest instantiated value with nch CE >= ne + 3.
+// workgroups of up to 768 threads, up to 128 in 1024) or 4.  FP64 takes 8 up
+// to 96 directions where its buffers fit in LDS, else 4 (up to 128
+// directions, 512 threads).  CE is the smallest instantiated value with
+// nch CE >= ne + 3.
 struct FaceShape {
   int nch = 0, ce = 0, maxt = 0;
   bool split = false;
@@ -1398,7 +1410,7 @@ constexpr int kCE4[] = { 4, 5, 6, 7, 8, 12, 16 };
 FaceShape make_shape(int prec, int nd, int ne, int nch)
 {
   FaceShape f;
-  if (nd > 128 || (nch != 4 && nch != 8) || (prec == BTX_PREC_FP64 && nch != 4)) return f;
+  if (nd > 128 || (nch != 4 && nch != 8) || (prec == BTX_PREC_FP64 && nch == 8 && nd > 96)) return f;
   f.nch = nch;
   f.maxt = nch == 4 ? 512 : (nd <= 96 ? 768 : 1024);
   const int *c = nch == 8 ? kCE8 : kCE4;
@@ -1425,9 +1437,14 @@ FaceShape make_gtab_shape(int nd, int ne, int nch)
   return f;
 }
 
-FaceShape default_shape(const btx::Grid &g)
+FaceShape default_shape(const btx::Grid &g, size_t lds_cap)
 {
-  return make_shape(g.prec, g.ndir, g.ne, g.prec == BTX_PREC_FP64 ? 4 : 8);
+  if (g.prec == BTX_PREC_FP64) {
+    const FaceShape f8 = make_shape(g.prec, g.ndir, g.ne, 8);
+    if (f8.ce && face_lds_bytes(g.ndir, g.ns, 8, f8.ce, 8) <= lds_cap) return f8;
+    return make_shape(g.prec, g.ndir, g.ne, 4);
+  }
+  return make_shape(g.prec, g.ndir, g.ne, 8);
 }
 
 template <typename T, int NCH, int MAXT, bool SPLIT>
@@ -1478,10 +1495,9 @@ const void *face_fn(const FaceShape &f)
                       : f.nch == 1 ? face_fn_g<T, 1>(f.ce) : nullptr;
   }
   if (f.nch == 4) return f.split ? face_fn_t<T, 4, 512, true>(f.ce) : face_fn_t<T, 4, 512, false>(f.ce);
-  if constexpr (sizeof(T) == 4) {
-    if (f.maxt == 768) return f.split ? face_fn_t<T, 8, 768, true>(f.ce) : face_fn_t<T, 8, 768, false>(f.ce);
+  if (f.maxt == 768) return f.split ? face_fn_t<T, 8, 768, true>(f.ce) : face_fn_t<T, 8, 768, false>(f.ce);
+  if constexpr (sizeof(T) == 4)
     return f.split ? face_fn_t<T, 8, 1024, true>(f.ce) : face_fn_t<T, 8, 1024, false>(f.ce);
-  }
   return nullptr;
 }
 
@@ -1637,7 +1653,7 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
   m.index = index;
   m.tsize = g.prec == BTX_PREC_FP64 ? 8 : 4;
   m.dt_max1 = btx::max_dt(g, 1.0);
-  m.shape = default_shape(g);
+  m.shape = default_shape(g, lds_cap);
   if (m.shape.ce == 0 || face_lds_bytes(g.ndir, g.ns, m.shape.nch, m.shape.ce, m.tsize) > lds_cap) {
     FaceShape fit, first;                          // tables through the caches instead of LDS
     for (int nch : { 4, 2, 1 }) {
@@ -2318,8 +2334,8 @@ btx_status tune(btx_batch *b)
   for (Model &m : b->models) b->h_models[m.index].tally = tsave[m.index];
   if (st != BTX_OK) return st;
   for (Model &m : b->models) {
-    if (m.shape.gtab) continue;                      // tables through the caches: one shape
-    const int nch = b->tsize == 8 ? 4 : (lookup(tune_key(m)) ? lookup(tune_key(m)) : 8);
+    if (m.shape.gtab || b->tsize == 8) continue;     // tables through the caches, or FP64: as created
+    const int nch = lookup(tune_key(m)) ? lookup(tune_key(m)) : 8;
     set_shape(b, m, make_shape(m.g.prec, m.g.ndir, m.g.ne, nch));
   }
   if ((st = upload_descriptors(b)) != BTX_OK) return st;

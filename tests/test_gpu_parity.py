@@ -61,10 +61,11 @@ CASES = {
     # outflow ghosts on theta faces)
     "disk": lambda: _perturb(W.radiating_disk(n_r=12, n_theta=5, n_mu=6, n_phi=8, r_min=0.2,
                                               r_max=2.5)),
-    # the largest momentum grids a face workgroup holds in FP64 (its LDS):
-    # 16 x 8 = 128 directions with 13 groups, and 61 groups with 48 directions
-    "max_dirs": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=13, n_mu=16, n_phi=8)),
-    "max_groups": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=61, n_mu=12, n_phi=4,
+    # the largest momentum grids a face workgroup holds in FP64 with its
+    # tables in LDS: 16 x 8 = 128 directions with 29 groups, and 61 groups
+    # with 10 x 8 = 80 directions
+    "max_dirs": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=29, n_mu=16, n_phi=8)),
+    "max_groups": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=61, n_mu=10, n_phi=8,
                                                e_min=1.0, e_max=300.0)),
     # one GPU's radial share of a larger grid (inner boundary inside the profile)
     "slab": lambda: _perturb(W.radial_slab(W.shock_2d(n_r=40, n_theta=4, n_eps=5, n_mu=4, n_phi=4,
@@ -75,8 +76,9 @@ CASES = {
                                                        mu_rule="legendre")),
     "mixed_128x61": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=61, n_mu=16, n_phi=8,
                                                  e_min=1.0, e_max=300.0)),
-    # the largest in mixed precision at 128 directions: 45 groups
-    "max_mixed": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=45, n_mu=16, n_phi=8,
+    # the largest in mixed precision below 200 directions: 61 groups with
+    # 20 x 8 = 160 directions (tables through the caches)
+    "max_mixed": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=61, n_mu=20, n_phi=8,
                                               e_min=1.0, e_max=300.0)),
     # an empty state: stays empty where nothing emits
     "empty": lambda: _empty(W.axisym_2d(n_r=5, n_theta=3, n_eps=3, n_mu=4, n_phi=4)),

@@ -1131,6 +1131,7 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
         __syncthreads();                               // partial sums visible, buffers free
         if (tid < nrow) {                              // totals over the waves, fixed order
           double t = 0.0;
+#pragma unroll 4
           for (int w = 0; w < nw; ++w) t += spart[w * nrow + tid];
           savr[tid - gb] = t * (1.0 / (4.0 * kPi));
         }
@@ -1218,10 +1219,20 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   // phi), for the source terms after the update
   extern __shared__ __align__(16) char lds[];
   double *rs = (double *)lds;
-  for (int row = wave; row < g.ns * ne; row += nwaves) {
+  // a row's opacities are loaded one row ahead, with the previous row's data
+  const int nrows = g.ns * ne;
+  const size_t kz = (size_t)z * nrows;
+  T kan = (T)0, ksn = (T)0, fen = (T)0;
+  if (wave < nrows) { kan = ka[kz + wave]; ksn = ks[kz + wave]; fen = feq[kz + wave]; }
+  for (int row = wave; row < nrows; row += nwaves) {
     int s = row / ne, i = row - s * ne;
-    size_t kidx = ((size_t)z * g.ns + s) * ne + i;
-    double ka_ = (double)ka[kidx], ks_ = (double)ks[kidx], fe_ = (double)feq[kidx];
+    const double ka_ = (double)kan, ks_ = (double)ksn, fe_ = (double)fen;
+    {
+      const int nx = min(row + nwaves, nrows - 1);
+      kan = ka[kz + nx];
+      ksn = ks[kz + nx];
+      fen = feq[kz + nx];
+    }
     bool wide = (sizeof(T) == 8) || tau * (ka_ + ks_) > g.fp64_thr;
     double Sd[R];
     double part = 0.0;

@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--lts-steps", type=int, default=2)
     ap.add_argument("--no-shard", dest="shard", action="store_false",
                     help="skip the timing of one GPU's share of a radially split grid")
+    ap.add_argument("--evolve-steps", type=int, default=3,
+                    help="steps of the run whose background changes every step (0: skip it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -114,6 +116,45 @@ def run_lts(torch, btx, w, max_level, steps, ref_ms_per_step):
             "simulated_time_per_s": sim_per_s, "speedup_vs_global_step": sim_per_s / sim_global,
             "zone_update_fraction": zone_updates / (w.n_zones * 2 ** L),
             "updates_per_s": zone_updates * w.block / (ms * 1e-3)}
+
+
+def run_evolving(torch, btx, w, steps):
+    """a background that changes every step (velocity, lapse, conformal factor,
+    absorption): each step is btx_update_background (the state remapped into the
+    new comoving frames and the remap tables rebuilt, from host arrays, so
+    PCIe-inclusive) followed by one step; wall clock, mixed precision"""
+    import copy
+    stream = torch.cuda.current_stream()
+    ctx = btx.Context(w, device=0, stream=stream.cuda_stream, precision=1)
+    ctx.set_background()
+    f0 = device_state(torch, w, torch.float32)
+    ctx.set_state(f0)
+    del f0
+    dt = ctx.max_dt(w.cfl)
+    bgs = []
+    for k in range(2):
+        b = copy.copy(w)
+        b.v_r = w.v_r * (1.0 + 0.01 * (k + 1))
+        b.alpha = w.alpha * (1.0 - 0.001 * (k + 1))
+        b.psi = b.alpha ** -0.5
+        b.kappa_a = w.kappa_a * (1.0 + 0.01 * (k + 1))
+        bgs.append(b)
+    ctx.update_background(bgs[1])
+    ctx.step(dt, 1)
+    torch.cuda.synchronize()
+    t_upd = 0.0
+    wall = time.perf_counter()
+    for k in range(steps):
+        torch.cuda.synchronize()                    # the update alone: the previous step done
+        t = time.perf_counter()
+        ctx.update_background(bgs[k % 2])          # synchronises the stream
+        t_upd += time.perf_counter() - t
+        ctx.step(dt, 1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall
+    ctx.close()
+    return {"ms_per_step": wall / steps * 1e3, "update_ms": t_upd / steps * 1e3,
+            "updates_per_s": w.n_values * steps / wall}
 
 
 def cpu_baseline(steps_note):
@@ -293,6 +334,11 @@ def main():
         print(f"[bench] time levels (max {l['max_level']}): {l['ms_per_step']:.2f} ms per "
               f"{l['substeps_per_step']} substeps, {l['speedup_vs_global_step']:.2f}x the simulated time "
               f"per second of the global step", file=sys.stderr, flush=True)
+    if a.evolve_steps > 0:
+        out["evolving_background"] = run_evolving(torch, btx, w, a.evolve_steps)
+        e = out["evolving_background"]
+        print(f"[bench] evolving background: {e['ms_per_step']:.1f} ms per step, of which "
+              f"{e['update_ms']:.1f} ms background update", file=sys.stderr, flush=True)
     if not a.no_batch:
         out["batch"] = run_batch(torch, btx, W, a.batch_steps)
         print(f"[bench] batch: {out['batch']['ms_per_step']:.3f} ms/step batched, "

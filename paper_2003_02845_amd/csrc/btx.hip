@@ -329,8 +329,9 @@ __device__ inline void node_bracket(const double *x, int n, double v, int &L, in
 // One source direction of one remap: frame chain, energy shift and taps,
 // (mu, Phi) corners.  rt[4] receive the targets (-1 unused), rl/rr the tap
 // weights times the corner weight.
-__device__ void remap_source(const DevGrid &g, const Frame &S, const Frame &D, int axis, bool rot,
-                             bool ident, int d, int rt[4], double rl[4], double rr[4], int &di_out)
+// mu: the mu nodes (the grid's, or a copy of them in LDS)
+__device__ void remap_source(const DevGrid &g, const double *mu, const Frame &S, const Frame &D, int axis,
+                             bool rot, bool ident, int d, int rt[4], double rl[4], double rr[4], int &di_out)
 {
   const double *n = g.nvec + 3 * d;
   rt[1] = rt[2] = rt[3] = -1;
@@ -353,7 +354,7 @@ __device__ void remap_source(const DevGrid &g, const Frame &S, const Frame &D, i
   double mus = fmin(1.0, fmax(-1.0, o[1] / o[0]));
   int jL, jR;
   double wj;
-  node_bracket(g.mu, g.nmu, mus, jL, jR, wj);
+  node_bracket(mu, g.nmu, mus, jL, jR, wj);
   int k0 = d % g.nphi;
   double P;
   if (o[2] * o[2] + o[3] * o[3] <= 1e-12 * o[0] * o[0]) {
@@ -495,6 +496,11 @@ __device__ inline double frame_weight(const DevGrid &g, const FaceAux &A, int k,
 
 // ------------------------------------------------------------ table kernel
 
+// frames of table t (0 Lm->L, 1 R->L, 2 L->R, 3 Rp->R, 4 L->s, 5 R->s, 6 s->L,
+// 7 s->R) among 0 Lm, 1 L, 2 R, 3 Rp, 4 the interface s
+__device__ inline int tab_src(int t) { return t == 0 ? 0 : (t == 1 || t == 5) ? 2 : (t == 2 || t == 4) ? 1 : t == 3 ? 3 : 4; }
+__device__ inline int tab_dst(int t) { return (t == 0 || t == 1 || t == 6) ? 1 : (t == 2 || t == 3 || t == 7) ? 2 : 4; }
+
 // Builds the eight remap tables of one face (frame chain once per direction,
 // inverted into sorted per-target gather lists) and stores them in global
 // memory; run once per background.
@@ -526,6 +532,9 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
   int *cur = cnt + TPR * nd;                   // TPR nd
   int *rtg = cur + TPR * nd;                   // 4 TPR nd
   T *rcf = (T *)(rtg + 4 * TPR * nd);          // 8 TPR nd
+  // the mu nodes, searched for every direction of every table
+  double *smu = (double *)(data + align16(scratch_bytes(nd, sizeof(T), TPR)));
+  for (int q = tid; q < g.nmu; q += nthr) smu[q] = g.mu[q];
   const int cs = col_rows(g.nch, g.ce);
   auto tw = [&](int t, T *&cw, unsigned short *&key, unsigned short *&start) {
     char *b = tabs + t * tstride;
@@ -559,12 +568,10 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
     __syncthreads();
     for (int q = tid; q < TPR * nd; q += nthr) {
       int tl = q / nd, d = q - tl * nd, t = TPR * round + tl;
-      const int si = t == 0 ? 0 : (t == 1 || t == 5) ? 2 : (t == 2 || t == 4) ? 1 : t == 3 ? 3 : 4;
-      const int di_ = (t == 0 || t == 1 || t == 6) ? 1 : (t == 2 || t == 3 || t == 7) ? 2 : 4;
-      const Frame S = frm[si], D = frm[di_];
+      const Frame S = frm[tab_src(t)], D = frm[tab_dst(t)];
       int rt[4], di;
       double rl[4], rr[4];
-      remap_source(g, S, D, ax, rot, same_frame(S, D), d, rt, rl, rr, di);
+      remap_source(g, smu, S, D, ax, rot, same_frame(S, D), d, rt, rl, rr, di);
       if (di < -1 || di > 1) atomicOr(&flg[t], 1);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -575,18 +582,31 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
       }
     }
     __syncthreads();
-    if (tid < TPR) {                                   // exclusive scan per table
+    if ((tid >> 6) < TPR) {                            // exclusive scan per table, one wave each
+      const int tl = tid >> 6, ln = tid & 63;
       T *cw;
       unsigned short *key, *start;
-      tw(TPR * round + tid, cw, key, start);
-      int acc = 0;
-      for (int d = 0; d < nd; ++d) {
-        start[d] = (unsigned short)acc;
-        cur[tid * nd + d] = acc;
-        acc += cnt[tid * nd + d];
+      tw(TPR * round + tl, cw, key, start);
+      int base = 0;
+      for (int d0 = 0; d0 < nd; d0 += 64) {
+        const int d = d0 + ln;
+        const int c = d < nd ? cnt[tl * nd + d] : 0;
+        int incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(incl, o, 64);
+          if (ln >= o) incl += y;
+        }
+        if (d < nd) {
+          start[d] = (unsigned short)(base + incl - c);
+          cur[tl * nd + d] = base + incl - c;
+        }
+        base += __shfl(incl, 63, 64);
       }
-      start[nd] = (unsigned short)acc;
-      start[nd + 1] = (unsigned short)flg[TPR * round + tid];
+      if (ln == 0) {
+        start[nd] = (unsigned short)base;
+        start[nd + 1] = (unsigned short)flg[TPR * round + tl];
+      }
     }
     __syncthreads();
     for (int q = tid; q < TPR * nd; q += nthr) {       // records into their target lists
@@ -728,7 +748,7 @@ time_remap_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ 
   for (int q = tid; q < nd; q += nthr) {               // each source direction
     int rt[4], di;
     double rl[4], rr[4];
-    remap_source(g, S, D, -1, false, false, q, rt, rl, rr, di);
+    remap_source(g, g.mu, S, D, -1, false, false, q, rt, rl, rr, di);
     for (int r = 0; r < 4; ++r) {
       rtg[q * 4 + r] = rt[r] >= 0 ? (rt[r] | ((di + 128) << 16)) : -1;
       rcf[(q * 4 + r) * 2] = (T)rl[r];
@@ -1680,7 +1700,7 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
   if (flds > lds_cap)
     return fail(BTX_E_UNSUPPORTED, "face workgroup needs " + std::to_string(flds) + " B of LDS");
   m.tab_lds = (m.shape.gtab ? 0 : kTables * tab_stride(g.ndir, m.tsize)) + align16(5 * sizeof(Frame)) +
-              align16(scratch_bytes(g.ndir, m.tsize, m.shape.gtab ? 1 : 4));
+              align16(scratch_bytes(g.ndir, m.tsize, m.shape.gtab ? 1 : 4)) + align16((size_t)g.nmu * 8);
   if (m.tab_lds > lds_cap) return fail(BTX_E_UNSUPPORTED, "table build needs too much LDS");
   const size_t nz = g.nz, blk = (size_t)g.ns * g.ne * g.ndir, nk = nz * g.ns * g.ne, nf = g.faces.size();
   std::vector<int2> fit(nf), zit(nz);

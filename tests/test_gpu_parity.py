@@ -76,6 +76,12 @@ CASES = {
                                                        mu_rule="legendre")),
     "mixed_128x61": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=61, n_mu=16, n_phi=8,
                                                  e_min=1.0, e_max=300.0)),
+    # 37 and 45 groups: five and six groups per work item at 8 items per
+    # direction (FP64 too, where these shapes run short of registers)
+    "groups_37": lambda: _perturb(W.axisym_2d(n_r=4, n_theta=2, n_eps=37, n_mu=8, n_phi=8,
+                                              e_min=1.0, e_max=300.0)),
+    "groups_45": lambda: _perturb(W.axisym_2d(n_r=4, n_theta=2, n_eps=45, n_mu=8, n_phi=8,
+                                              e_min=1.0, e_max=300.0)),
     # the largest in mixed precision below 200 directions: 61 groups with
     # 20 x 8 = 160 directions (tables through the caches)
     "max_mixed": lambda: _perturb(W.axisym_2d(n_r=3, n_theta=2, n_eps=61, n_mu=20, n_phi=8,
@@ -154,7 +160,7 @@ def test_fp64_parity(case, oracle_mod):
 
 @pytest.mark.parametrize("case", ["shock_3species", "column_lobatto_v", "split_groups", "large_shift",
                                   "shock_3d", "max_dirs", "max_groups", "max_mixed", "wide_200",
-                                  "wide_544", "mixed_128x61"])
+                                  "wide_544", "mixed_128x61", "groups_37", "groups_45"])
 def test_mixed_moments(case, oracle_mod):
     w = CASES[case]()
     _say(f"[gpu] mixed moments {case}")

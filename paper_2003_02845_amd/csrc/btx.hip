@@ -1056,9 +1056,12 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   const T dL = (T)F.dL, dR = (T)F.dR, ih = (T)(1.0 / F.h);
   const T ihLm = (T)(1.0 / F.hLm), ihRp = (T)(1.0 / F.hRp);
   const int lane = tid & 63, wave = tid >> 6, nw = (nthr + 63) >> 6;
+  // a launch with one workgroup row per species (gridDim.y = ns, for launches
+  // with few faces) takes the species of its row; else every species in turn
+  const int s_lo = gridDim.y > 1 ? (int)blockIdx.y : 0, s_hi = gridDim.y > 1 ? s_lo + 1 : g.ns;
 
 #pragma unroll 1
-  for (int s = 0; s < g.ns; ++s) {
+  for (int s = s_lo; s < s_hi; ++s) {
     // ---- load the stencil blocks as content densities
     // Rp goes into Lm's buffer after stage 0.  FP32 loads it with the other
     // sides and holds it in registers; FP64, short of registers, loads it then.
@@ -1417,6 +1420,9 @@ __global__ void cast_kernel(const double *__restrict__ src, T *__restrict__ dst,
 // ---------------------------------------------------------------- host side
 
 namespace {
+
+// face workgroups that fill the device, one per CU (256 compute units)
+constexpr int kFillFaces = 256;
 
 // Face work-item shape: nch items per direction (a power of two), CE groups
 // per item, the workgroup size bound and whether group -1 ends an item.
@@ -1846,14 +1852,17 @@ btx_status build_tables(const Model &m, const ModelDev *d_models, hipStream_t s)
   return BTX_OK;
 }
 
+// species_rows: one workgroup per (face, species) instead of per face (all
+// models of the launch must then have that many species)
 btx_status launch_faces(const FaceShape &shape, size_t tsize, const ModelDev *d_models, const int2 *items,
-                        int n, int threads, size_t lds, int parity, hipStream_t s, int sub = 0)
+                        int n, int threads, size_t lds, int parity, hipStream_t s, int sub = 0,
+                        int species_rows = 1)
 {
   if (n == 0) return BTX_OK;
   const void *fn = face_fn(tsize, shape);
   if (!fn) return fail(BTX_E_UNSUPPORTED, "no face kernel for this shape");
   void *args[] = { &d_models, &items, &parity, &sub };
-  HIP_TRY(hipLaunchKernel(fn, dim3(n), dim3(threads), args, lds, s));
+  HIP_TRY(hipLaunchKernel(fn, dim3(n, std::max(species_rows, 1)), dim3(threads), args, lds, s));
   return BTX_OK;
 }
 
@@ -2131,8 +2140,11 @@ btx_status ctx_step(btx_ctx *c, double dt)
     for (int k = 0; k < (1 << L); ++k) {
       const int lf = k == 0 ? L : std::min(L, __builtin_ctz(k));       // faces whose finer zone starts
       const int lz = std::min(L, __builtin_ctz(k + 1));                 // zones whose step ends
+      // a substep with too few faces to fill the device takes one workgroup
+      // per (face, species)
+      const int rows = m.nf_lev[lf] < 2 * kFillFaces ? m.g.ns : 1;
       btx_status st = launch_faces(m.shape, m.tsize, c->d_model, m.d_fitems_lts, m.nf_lev[lf], face_threads(m),
-                                   face_lds(m), 0, c->stream, k);
+                                   face_lds(m), 0, c->stream, k, rows);
       if (st != BTX_OK) return st;
       st = launch_zones(m.tsize, c->d_model, m.d_zitems_lts, m.nz_lev[lz], m.g.ns * m.g.ne, 0, c->stream,
                         m.g.ndir);

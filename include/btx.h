@@ -216,6 +216,16 @@ btx_status btx_batch_shape(const btx_batch *b, int32_t model, int32_t *items_per
                            int32_t *groups_per_item);
 btx_status btx_batch_moments(btx_batch *b, int32_t model, double *zone_moments, double *totals);
 btx_status btx_batch_source_terms(btx_batch *b, int32_t model, double *q);
+/* Local time stepping in a batch (as btx_time_levels and btx_set_time_levels
+ * for one model).  Once any model has been given levels (NULL: all zones at
+ * level 0), every model updates its state in place and one btx_batch_step
+ * step is 2^L substeps of each model's dt, L the highest level of any model;
+ * a model whose highest level is below L thus takes several of its own
+ * level-stepped steps.  The faces of every model at a substep share one
+ * launch per face-shape class and the zones one launch; no graph is used.
+ * Synchronises the stream. */
+btx_status btx_batch_time_levels(const btx_batch *b, int32_t model, int32_t max_level, int32_t *levels);
+btx_status btx_batch_set_time_levels(btx_batch *b, int32_t model, const int32_t *levels);
 btx_status btx_batch_destroy(btx_batch *b);
 
 #ifdef __cplusplus

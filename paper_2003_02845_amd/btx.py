@@ -29,6 +29,7 @@ ABI_SYMBOLS = ["btx_create", "btx_set_background", "btx_max_dt", "btx_set_state"
                "btx_batch_set_background", "btx_batch_update_background",
                "btx_batch_max_dt", "btx_batch_set_state", "btx_batch_get_state", "btx_batch_step",
                "btx_batch_use_graph", "btx_batch_shape", "btx_batch_moments", "btx_batch_destroy",
+               "btx_batch_time_levels", "btx_batch_set_time_levels",
                "btx_source_terms", "btx_batch_source_terms", "btx_time_levels",
                "btx_set_time_levels"]
 
@@ -92,6 +93,8 @@ def lib():
         L.btx_time_levels.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
         L.btx_set_time_levels.argtypes = [vp, C.POINTER(C.c_int32)]
         L.btx_batch_source_terms.argtypes = [vp, C.c_int32, _dp]
+        L.btx_batch_time_levels.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+        L.btx_batch_set_time_levels.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
         L.btx_batch_destroy.argtypes = [vp]
         L.btx_last_error.restype = C.c_char_p
         for name in ABI_SYMBOLS:
@@ -329,6 +332,21 @@ class Batch:
         tot = np.zeros((w.n_species, 3))
         _check(lib().btx_batch_moments(self.h, m, _p(zm), _p(tot)))
         return zm, tot
+
+    def time_levels(self, m, max_level):
+        """the library's proposal of a time level per zone of model m"""
+        lev = np.zeros(self.ws[m].n_zones, dtype=np.int32)
+        _check(lib().btx_batch_time_levels(self.h, m, int(max_level), lev.ctypes.data_as(C.POINTER(C.c_int32))))
+        return lev
+
+    def set_time_levels(self, m, levels):
+        """levels of model m (None: all zones at level 0); the batch then steps in place"""
+        if levels is None:
+            _check(lib().btx_batch_set_time_levels(self.h, m, None))
+            return
+        lev = np.ascontiguousarray(levels, dtype=np.int32).reshape(-1)
+        _need(lev.size == self.ws[m].n_zones, f"model {m} has {self.ws[m].n_zones} zones")
+        _check(lib().btx_batch_set_time_levels(self.h, m, lev.ctypes.data_as(C.POINTER(C.c_int32))))
 
     def source_terms(self, m):
         """[zone][5]: Q_Ye, Q_E, Q_M,r, Q_M,theta, Q_M,phi of model m's last step"""

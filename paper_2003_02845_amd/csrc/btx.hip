@@ -2180,6 +2180,7 @@ namespace {
 struct BatchGroup {
   FaceShape shape;
   int first = 0, count = 0;          // range in the group item array
+  int first_lts = 0;                 // start in the level-sorted item array
   int threads = 64;
   size_t lds = 0;
 };
@@ -2203,6 +2204,14 @@ struct btx_batch {
   bool tuned = false, use_graph = true;
   hipGraphExec_t exec[2] = { nullptr, nullptr };
   std::string tune_path;
+  // local time stepping: once a model is given time levels, every model
+  // updates in place and a step is 2^L substeps (L the largest level);
+  // face items sorted by level within each group, zone items by level
+  bool lts = false, lts_dirty = true;
+  int lts_L = 0;
+  int2 *d_gitems_lts = nullptr, *d_zitems_lts = nullptr;
+  std::vector<std::vector<int>> gf_lev;  // per group: items of level <= l
+  std::vector<int> z_lev;                // zone items of level <= l
 };
 
 namespace {
@@ -2217,7 +2226,7 @@ void free_batch(btx_batch *b)
 {
   drop_graphs(b);
   for (Model &m : b->models) model_free(m);
-  void *ptrs[] = { b->d_models, b->d_gitems, b->d_zitems, b->d_tscratch };
+  void *ptrs[] = { b->d_models, b->d_gitems, b->d_zitems, b->d_tscratch, b->d_gitems_lts, b->d_zitems_lts };
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -2310,6 +2319,7 @@ btx_status build_groups(btx_batch *b)
     if (st != BTX_OK) return st;
     b->groups.push_back(gr);
   }
+  b->lts_dirty = true;
   if (b->d_gitems) { (void)hipFree(b->d_gitems); b->d_gitems = nullptr; }
   return upload(&b->d_gitems, items.data(), items.size());
 }
@@ -2405,6 +2415,82 @@ btx_status batch_launch(btx_batch *b, int parity, hipStream_t s)
     dirs = std::max(dirs, m.g.ndir);
   }
   return launch_zones(b->tsize, b->d_models, b->d_zitems, b->nz_all, rows, parity, s, dirs);
+}
+
+// Level-sorted work lists of a batch with time levels: per face-shape group
+// the (model, face) items by the level of the face's finer zone, and every
+// (model, zone) item by its zone's level, with the counts up to each level.
+btx_status build_lts_lists(btx_batch *b)
+{
+  int L = 0;
+  for (const Model &m : b->models) L = std::max(L, m.lmax);
+  std::vector<int2> fit, zit;
+  b->gf_lev.assign(b->groups.size(), std::vector<int>(L + 1, 0));
+  std::vector<int> first(b->groups.size());
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    const BatchGroup &gr = b->groups[gi];
+    std::vector<std::pair<int, int2>> v;
+    for (const Model &m : b->models) {
+      if (!(m.shape == gr.shape)) continue;
+      for (size_t f = 0; f < m.g.faces.size(); ++f) {
+        const int lv = std::min(m.lev[m.g.faces[f].L.z], m.lev[m.g.faces[f].R.z]);
+        v.emplace_back(lv, make_int2(m.index, (int)f));
+      }
+    }
+    std::stable_sort(v.begin(), v.end(), [](const std::pair<int, int2> &x, const std::pair<int, int2> &y) {
+      return x.first < y.first;
+    });
+    first[gi] = (int)fit.size();
+    for (auto &e : v) {
+      fit.push_back(e.second);
+      for (int l = e.first; l <= L; ++l) ++b->gf_lev[gi][l];
+    }
+  }
+  std::vector<std::pair<int, int2>> zv;
+  for (const Model &m : b->models)
+    for (int z = 0; z < m.g.nz; ++z) zv.emplace_back(m.lev[z], make_int2(m.index, z));
+  std::stable_sort(zv.begin(), zv.end(), [](const std::pair<int, int2> &x, const std::pair<int, int2> &y) {
+    return x.first < y.first;
+  });
+  b->z_lev.assign(L + 1, 0);
+  for (auto &e : zv) {
+    zit.push_back(e.second);
+    for (int l = e.first; l <= L; ++l) ++b->z_lev[l];
+  }
+  if (b->d_gitems_lts) { (void)hipFree(b->d_gitems_lts); b->d_gitems_lts = nullptr; }
+  if (b->d_zitems_lts) { (void)hipFree(b->d_zitems_lts); b->d_zitems_lts = nullptr; }
+  btx_status st = upload(&b->d_gitems_lts, fit.data(), fit.size());
+  if (st != BTX_OK) return st;
+  if ((st = upload(&b->d_zitems_lts, zit.data(), zit.size())) != BTX_OK) return st;
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) b->groups[gi].first_lts = first[gi];
+  b->lts_L = L;
+  b->lts_dirty = false;
+  return BTX_OK;
+}
+
+// One step of a batch with time levels: 2^L substeps; at substep k the faces
+// whose finer zone starts a step and then the zones whose step ends
+btx_status batch_launch_lts(btx_batch *b, hipStream_t s)
+{
+  const int L = b->lts_L;
+  int rows = 1, dirs = 0;
+  for (const Model &m : b->models) {
+    rows = std::max(rows, m.g.ns * m.g.ne);
+    dirs = std::max(dirs, m.g.ndir);
+  }
+  for (int k = 0; k < (1 << L); ++k) {
+    const int lf = k == 0 ? L : std::min(L, __builtin_ctz(k));
+    const int lz = std::min(L, __builtin_ctz(k + 1));
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      const BatchGroup &gr = b->groups[gi];
+      btx_status st = launch_faces(gr.shape, b->tsize, b->d_models, b->d_gitems_lts + gr.first_lts,
+                                   b->gf_lev[gi][lf], gr.threads, gr.lds, 0, s, k);
+      if (st != BTX_OK) return st;
+    }
+    btx_status st = launch_zones(b->tsize, b->d_models, b->d_zitems_lts, b->z_lev[lz], rows, 0, s, dirs);
+    if (st != BTX_OK) return st;
+  }
+  return BTX_OK;
 }
 
 // the step of each parity captured once as a graph on the library's stream
@@ -2683,6 +2769,12 @@ btx_status btx_batch_step(btx_batch *b, const double *dt_per_model, int32_t n_st
     if ((st = upload_descriptors(b)) != BTX_OK) return st;
   }
   if (!b->tuned && (st = tune(b)) != BTX_OK) return st;
+  if (b->lts) {                                      // time levels: in place, no graphs
+    if (b->lts_dirty && (st = build_lts_lists(b)) != BTX_OK) return st;
+    for (int t = 0; t < n_steps; ++t)
+      if ((st = batch_launch_lts(b, b->stream)) != BTX_OK) return st;
+    return BTX_OK;
+  }
   if (b->use_graph && !b->exec[0] && (st = capture_graphs(b)) != BTX_OK) return st;
   for (int t = 0; t < n_steps; ++t) {
     if (b->use_graph) HIP_TRY(hipGraphLaunch(b->exec[b->parity], b->stream));
@@ -2720,6 +2812,54 @@ btx_status btx_batch_source_terms(btx_batch *b, int32_t model, double *q)
   if (!b || model < 0 || model >= (int)b->models.size()) return fail(BTX_E_INVAL, "bad batch or model index");
   HIP_TRY(hipSetDevice(b->device));
   return model_source_terms(b->models[model], q, b->stream);
+}
+
+btx_status btx_batch_time_levels(const btx_batch *b, int32_t model, int32_t max_level, int32_t *levels)
+{
+  if (!b || !levels) return fail(BTX_E_INVAL, "null argument");
+  if (model < 0 || model >= (int32_t)b->models.size()) return fail(BTX_E_INVAL, "model index out of range");
+  if (max_level < 0 || max_level > 16) return fail(BTX_E_INVAL, "max_level must be in 0..16");
+  std::vector<int> lev;
+  assign_levels(b->models[model].g, max_level, lev);
+  for (int z = 0; z < b->models[model].g.nz; ++z) levels[z] = lev[z];
+  return BTX_OK;
+}
+
+btx_status btx_batch_set_time_levels(btx_batch *b, int32_t model, const int32_t *levels)
+{
+  if (!b) return fail(BTX_E_INVAL, "null batch");
+  if (model < 0 || model >= (int32_t)b->models.size()) return fail(BTX_E_INVAL, "model index out of range");
+  if (levels)
+    for (int z = 0; z < b->models[model].g.nz; ++z)
+      if (levels[z] < 0 || levels[z] > 16) return fail(BTX_E_INVAL, "time levels must be in 0..16");
+  HIP_TRY(hipSetDevice(b->device));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  drop_graphs(b);
+  // every model steps in place from now on: its current state into buffer 0
+  btx_status st = BTX_OK;
+  for (Model &m : b->models) {
+    int p = b->parity;
+    const std::vector<int32_t> zeros(m.g.nz, 0);
+    const int32_t *lv = m.index == model ? (levels ? levels : zeros.data())
+                                         : (m.lev.empty() ? zeros.data() : nullptr);
+    if (lv) st = model_set_levels(m, lv, p, b->stream);
+    else if (p == 1)
+      HIP_TRY(hipMemcpy(m.d_f[0], m.d_f[1], (size_t)m.g.nz * m.g.ns * m.g.ne * m.g.ndir * m.tsize,
+                        hipMemcpyDeviceToDevice));
+    if (st != BTX_OK) return st;
+  }
+  b->parity = 0;
+  for (Model &m : b->models) {
+    const FaceShape sh = m.shape;
+    const double dt = b->h_models[m.index].dt;
+    b->h_models[m.index] = model_dev(m, dt);
+    b->h_models[m.index].g.nch = sh.nch;
+    b->h_models[m.index].g.ce = sh.ce;
+  }
+  if ((st = upload_descriptors(b)) != BTX_OK) return st;
+  b->lts = true;
+  b->lts_dirty = true;
+  return BTX_OK;
 }
 
 btx_status btx_batch_destroy(btx_batch *b)

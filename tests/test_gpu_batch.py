@@ -156,3 +156,40 @@ def test_full_batch_tuned_with_cache(oracle_mod, tmp_path):
     again.step(dts, 1)
     assert [again.shape(m) for m in range(len(ws))] == shapes
     again.close()
+
+
+def test_batch_time_levels(oracle_mod):
+    """Time levels in a batch: models with different highest levels (2, 1 and
+    none) step 2^L substeps of their own dt per batch step; each model's state
+    equals, bit for bit, a single context stepping the same levels as many
+    level-stepped steps, and the first matches the reference (1e-12)."""
+    import torch
+    btx = _btx()
+    ws = _models(3, 0.03, W.PREC_FP64, 31)
+    b = _batch(btx, ws, W.PREC_FP64)
+    dts = [b.max_dt(m, 0.4) for m in range(len(ws))]
+    levs = [b.time_levels(0, 2), b.time_levels(1, 1), None]
+    _say(f"[gpu] batch time levels: highest {[int(l.max()) if l is not None else 0 for l in levs]}")
+    b.set_time_levels(0, levs[0])
+    b.set_time_levels(1, levs[1])
+    L = max(int(l.max()) for l in levs if l is not None)
+    b.step(dts, 2)
+    torch.cuda.synchronize()
+    for m, w in enumerate(ws):
+        c = btx.Context(w, precision=W.PREC_FP64, stream=torch.cuda.current_stream().cuda_stream)
+        c.set_background()
+        c.set_state(w.f0)
+        lm = 0 if levs[m] is None else int(levs[m].max())
+        if levs[m] is not None:
+            c.set_time_levels(levs[m])
+        c.step(dts[m], 2 * 2 ** (L - lm))
+        assert np.array_equal(b.get_state(m), c.get_state()), m
+        c.close()
+    o = oracle_mod.Oracle(ws[0])
+    o.set_levels(levs[0])
+    o.step(dts[0], 2 * 2 ** (L - int(levs[0].max())))
+    ref = o.state()
+    err = np.max(np.abs(b.get_state(0) - ref)) / np.max(np.abs(ref))
+    _say(f"[gpu]   model 0 against the reference: {err:.3e}")
+    assert err <= 1e-12
+    b.close()

@@ -193,6 +193,19 @@ def run_batch(torch, btx, W, steps):
     torch.cuda.synchronize()
     ms_b = t0.elapsed_time(t1) / steps
     shapes = sorted({f"{a}x{c}" for a, c in (b.shape(m) for m in range(len(ws)))})
+    # the same batch with time levels (up to 4 per model): 2^L substeps a step
+    levs = [b.time_levels(m, 4) for m in range(len(ws))]
+    for m in range(len(ws)):
+        b.set_time_levels(m, levs[m])
+    L = max(int(l.max()) for l in levs)
+    b.step(dts, 1)
+    torch.cuda.synchronize()
+    lts_steps = max(1, steps // (2 ** L))
+    t0.record(stream)
+    b.step(dts, lts_steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_l = t0.elapsed_time(t1) / lts_steps
     b.close()
     ctxs = []
     for m, w in enumerate(ws):
@@ -216,7 +229,9 @@ def run_batch(torch, btx, W, steps):
                         "16-48 directions, mixed precision",
             "values": nv, "steps": steps, "ms_per_step": ms_b, "value": nv / (ms_b * 1e-3),
             "sequential_ms_per_step": ms_s, "sequential_value": nv / (ms_s * 1e-3),
-            "speedup_vs_sequential": ms_s / ms_b, "face_shapes": shapes}
+            "speedup_vs_sequential": ms_s / ms_b, "face_shapes": shapes,
+            "time_levels": {"max_level": L, "ms_per_step": ms_l, "substeps_per_step": 2 ** L,
+                            "speedup_vs_global_step": (2 ** L) * ms_b / ms_l}}
 
 
 def face_traffic():
@@ -341,8 +356,11 @@ def main():
               f"{e['update_ms']:.1f} ms background update", file=sys.stderr, flush=True)
     if not a.no_batch:
         out["batch"] = run_batch(torch, btx, W, a.batch_steps)
+        bt = out["batch"]["time_levels"]
         print(f"[bench] batch: {out['batch']['ms_per_step']:.3f} ms/step batched, "
-              f"{out['batch']['sequential_ms_per_step']:.3f} ms/step sequential", file=sys.stderr, flush=True)
+              f"{out['batch']['sequential_ms_per_step']:.3f} ms/step sequential; with time levels "
+              f"(max {bt['max_level']}) {bt['ms_per_step']:.3f} ms per {bt['substeps_per_step']} substeps, "
+              f"{bt['speedup_vs_global_step']:.2f}x the simulated time per second", file=sys.stderr, flush=True)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.steps)
     print(json.dumps(out), flush=True)

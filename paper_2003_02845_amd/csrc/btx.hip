@@ -1213,9 +1213,11 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
 // R: directions per lane (64 R directions at most).  A direction's loads (the
 // state and the changes from every face side of the zone) all go out before
 // the first is used; at 4 waves per SIMD (not 8) the compiler keeps them in
-// registers, and the kernel is faster for it.
+// registers, and the kernel is faster for it.  With 16 directions per lane
+// (above 256 directions) the register bound is that of 2 waves per SIMD: at
+// 4 the kernel spilled; it takes about 120 registers.
 template <typename T, int R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R > 4 ? 2 : 4)))
 zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity)
 {
   const int2 it = items[blockIdx.x];

@@ -484,3 +484,24 @@ def test_evolving_background_wide_gpu(oracle_mod):
     _say(f"[gpu]   rel err {err:.3e}")
     assert err <= 1e-12
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
+def test_repeatable_gpu(precision):
+    """The same step from the same state gives the same bits: every sum (the
+    interface angle sums over waves, the zone sums over faces, the source
+    terms and the moments) is taken in a fixed order, with no atomics."""
+    btx = _btx()
+    w = W.shock_2d(n_r=40, n_theta=16, n_eps=12, n_mu=6, n_phi=8, precision=precision)
+    _say(f"[gpu] repeatable, precision {precision}")
+    out = []
+    for rep in range(2):
+        ctx = btx.Context(w, precision=precision)
+        ctx.set_background()
+        ctx.set_state(w.f0)
+        ctx.step(ctx.max_dt(0.4), 3)
+        zm, tot = ctx.moments()
+        out.append((ctx.get_state(), zm, tot, ctx.source_terms()))
+        ctx.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)

@@ -250,6 +250,20 @@ def face_traffic():
         return None
 
 
+def zone_traffic():
+    """HBM bytes per zone-kernel launch from the same counter summary, or None"""
+    prof = os.path.join(ROOT, "profiles", "face_kernel_hires_2d_mixed_hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_2003_02845_amd", "csrc", "btx.hip")
+    try:
+        text = open(prof).read()
+        want = re.search(r"btx\.hip: ([0-9a-f]{16})", text).group(1)
+        if want != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
+            return None
+        return float(re.search(r"^zone_kernel<float>\s+\d+\s+\d+\s+([0-9.]+)", text, re.M).group(1)) * 1e9
+    except (OSError, AttributeError, ValueError):
+        return None
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -290,6 +304,10 @@ def main():
     t_face = mixed["kernel_ms"][0] * 1e-3
     achieved = b_face / t_face / 1e9
     traffic = face_traffic() if (a.n_r, a.n_theta) == (600, 256) else None
+    # the zone kernel: f read and written, the opacities and the zone background
+    b_zone = w.n_values * 8 + nsg * 3 * 4 + nz * 4 * 8
+    t_zone = mixed["kernel_ms"][1] * 1e-3
+    ztraffic = zone_traffic() if (a.n_r, a.n_theta) == (600, 256) else None
     out = {
         "metric": "zone\u00b7group\u00b7direction updates/s, mixed FP32/FP64 vs FP64; % HBM peak",
         "value": value,
@@ -312,6 +330,12 @@ def main():
                      "traffic": None if traffic is None else traffic / 1e9,
                      "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic": b_face / 1e9, "algorithmic_unit": "GB per launch"},
+        "zone_roofline": {"bound": "hbm", "kernel": "zone_kernel<float>", "achieved": b_zone / t_zone / 1e9,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": b_zone / t_zone / 1e9 / HBM_PEAK_GBS,
+                          "traffic": None if ztraffic is None else ztraffic / 1e9,
+                          "traffic_rate": None if ztraffic is None else ztraffic / t_zone / 1e9,
+                          "traffic_unit": "GB per launch; GB/s",
+                          "algorithmic": b_zone / 1e9, "algorithmic_unit": "GB per launch"},
     }
     if res64 is not None:
         k64 = a.fp64_steps if a.fp64_steps is not None else a.steps

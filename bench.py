@@ -34,6 +34,10 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", choices=["hires_2d", "shock_2d", "axisym_2d"], default="hires_2d",
+                    help="hires_2d: the high-resolution grid (sizes from --n-r, --n-theta); shock_2d: "
+                         "550 x 128 zones, 3 species, 21 groups, 10 x 8 directions; axisym_2d: 256 x 64 "
+                         "zones, 1 species, 16 groups, 8 x 8 directions")
     ap.add_argument("--n-r", type=int, default=600)
     ap.add_argument("--n-theta", type=int, default=256)
     ap.add_argument("--no-batch", action="store_true")
@@ -275,7 +279,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    w = W.hires_2d(n_r=a.n_r, n_theta=a.n_theta)
+    w = W.hires_2d(n_r=a.n_r, n_theta=a.n_theta) if a.workload == "hires_2d" else getattr(W, a.workload)()
+    full = a.workload == "hires_2d" and (a.n_r, a.n_theta) == (600, 256)
     print(f"[bench] workload {w.name}: {w.n_zones} zones x {w.block} = {w.n_values:.4g} values",
           file=sys.stderr, flush=True)
     mixed = run_gpu(torch, btx, w, W.PREC_MIXED, a.steps, a.warmup)
@@ -303,11 +308,11 @@ def main():
     b_face = w.n_values * 4 + nsg * 3 * 4 + nz * 4 * 8
     t_face = mixed["kernel_ms"][0] * 1e-3
     achieved = b_face / t_face / 1e9
-    traffic = face_traffic() if (a.n_r, a.n_theta) == (600, 256) else None
+    traffic = face_traffic() if full else None
     # the zone kernel: f read and written, the opacities and the zone background
     b_zone = w.n_values * 8 + nsg * 3 * 4 + nz * 4 * 8
     t_zone = mixed["kernel_ms"][1] * 1e-3
-    ztraffic = zone_traffic() if (a.n_r, a.n_theta) == (600, 256) else None
+    ztraffic = zone_traffic() if full else None
     out = {
         "metric": "zone\u00b7group\u00b7direction updates/s, mixed FP32/FP64 vs FP64; % HBM peak",
         "value": value,
@@ -321,8 +326,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "hires_2d: 600 r x 256 theta zones, 3 species, 24 groups, "
-                               "12 mu x 8 Phi directions, mixed precision",
+        "config": {"workload": f"{w.name}: {w.n_r} r x {w.n_theta} theta zones, {w.n_species} species, "
+                               f"{w.n_eps} groups, {w.n_mu} mu x {w.n_phi} Phi directions, mixed precision",
                    "zones": nz, "values": w.n_values, "dt": mixed["dt"]},
         "step_hbm_frac": b_step / (mixed["ms"] / a.steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": "face_kernel<float>", "achieved": achieved,

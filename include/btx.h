@@ -148,6 +148,20 @@ btx_status btx_step(btx_ctx *ctx, double dt, int32_t n_steps);
  * device as compensated FP64 sums over the bins, the totals on the host as
  * compensated sums over the zones and boundary faces. */
 btx_status btx_moments(btx_ctx *ctx, double *zone_moments, double *totals);
+/* For callers that cannot allocate device or host memory during the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): btx_moments with DEVICE outputs on the context's device,
+ * enqueued on the context's stream without synchronising.  zone_moments
+ * [zone][species][5] and totals [species][3] are as for btx_moments (either
+ * may be NULL) and must stay valid until the stream reaches the call's work.
+ * The per-zone partial results live in a library array of 24 MiB per GPU
+ * (allocated with the library's code on each GPU it runs on, kept until the
+ * process ends), so the grid may have at most 524288 (zone, species) pairs
+ * (BTX_E_UNSUPPORTED beyond).  Calls on one GPU share that array: calls that
+ * overlap in time on one GPU (different streams, or threads) race.  The zone
+ * moments equal btx_moments's; the totals are compensated sums in another
+ * fixed order. */
+btx_status btx_moments_device(btx_ctx *ctx, double *zone_moments, double *totals);
 /* Hydro source terms of the last step (coupling to matter, Sec. 3.4,
  * Eq. hydrosource1-3): q[zone][5] = Q_Ye, Q_E, Q_M,r, Q_M,theta, Q_M,phi, what
  * the fluid gains per unit comoving volume and comoving time.  They integrate

@@ -31,7 +31,7 @@ ABI_SYMBOLS = ["btx_create", "btx_set_background", "btx_max_dt", "btx_set_state"
                "btx_batch_use_graph", "btx_batch_shape", "btx_batch_moments", "btx_batch_destroy",
                "btx_batch_time_levels", "btx_batch_set_time_levels",
                "btx_source_terms", "btx_batch_source_terms", "btx_time_levels",
-               "btx_set_time_levels"]
+               "btx_set_time_levels", "btx_moments_device"]
 
 _dp = C.POINTER(C.c_double)
 
@@ -90,6 +90,7 @@ def lib():
         L.btx_batch_shape.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.btx_batch_moments.argtypes = [vp, C.c_int32, _dp, _dp]
         L.btx_source_terms.argtypes = [vp, _dp]
+        L.btx_moments_device.argtypes = [vp, vp, vp]
         L.btx_time_levels.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
         L.btx_set_time_levels.argtypes = [vp, C.POINTER(C.c_int32)]
         L.btx_batch_source_terms.argtypes = [vp, C.c_int32, _dp]
@@ -229,6 +230,20 @@ class Context:
         tot = np.zeros((self.w.n_species, 3))
         _check(lib().btx_moments(self.h, _p(zm), _p(tot)))
         return zm, tot
+
+    def moments_device(self, zone_moments=None, totals=None):
+        """btx_moments_device: moments into float64 GPU tensors ([zone][species][5],
+        [species][3]; either may be None), enqueued on the context's stream"""
+        ptrs = []
+        for t, n in ((zone_moments, self.w.n_zones * self.w.n_species * 5), (totals, self.w.n_species * 3)):
+            if t is None:
+                ptrs.append(None)
+                continue
+            _need(torch is not None and isinstance(t, torch.Tensor), "outputs must be torch tensors", TypeError)
+            _device_tensor(t, n, torch.float64, self.device)
+            ptrs.append(C.c_void_p(t.data_ptr()))
+        _check(lib().btx_moments_device(self.h, ptrs[0], ptrs[1]))
+        return zone_moments, totals
 
     def time_levels(self, max_level):
         """the library's proposal of a time level per zone (local time stepping)"""

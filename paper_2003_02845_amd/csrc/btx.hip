@@ -1410,6 +1410,52 @@ moments_kernel(const ModelDev *__restrict__ models, int m, int parity, double *_
   }
 }
 
+// Totals of btx_moments_device: block (s, k) sums, for species s, the zone
+// numbers (k = 0), the boundary tallies (k = 1) or the zone energies (k = 2)
+// as compensated sums in a fixed order (per thread over a stride, over the
+// lanes of a wave, over the waves), and writes totals[3 s + k].
+__global__ void __launch_bounds__(256)
+totals_kernel(const double *__restrict__ zm, const double *__restrict__ ze, const double *__restrict__ tally,
+              const int32_t *__restrict__ bface, int nz, int ns, int nb, double *__restrict__ totals)
+{
+  const int s = blockIdx.x / 3, k = blockIdx.x % 3;
+  const int n = k == 1 ? nb : nz;
+  __shared__ double red[2][4];
+  double v = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double x = k == 0 ? zm[((size_t)i * ns + s) * 5]
+                            : (k == 1 ? tally[(size_t)bface[i] * ns + s] : ze[(size_t)i * ns + s]);
+    comp_add(v, c, x);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double vo = __shfl_xor(v, o, 64), co = __shfl_xor(c, o, 64);
+    comp_add(v, c, vo);
+    c += co;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { red[0][wave] = v; red[1][wave] = c; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0, tc = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      comp_add(t, tc, red[0][w]);
+      tc += red[1][w];
+    }
+    totals[3 * s + k] = t + tc;
+  }
+}
+
+// Scratch of btx_moments_device (the entry point for callers that cannot
+// allocate): the energy content of every (zone, species) pair, followed by
+// room for the zone moments when the caller passes no buffer for them.  It is
+// one array per GPU, alive until the process ends, and shared by every call on
+// that GPU; every value a call reads is written earlier in the same call, so
+// nothing needs clearing, and calls that overlap on one GPU race.  Host code
+// never passes the array's name to a kernel: it passes the device address
+// that scratch_base() resolves once per device.
+constexpr size_t kScratchPairs = (size_t)1 << 19;   // (zone, species) pairs
+static __device__ __align__(256) double scratch[kScratchPairs * 6];   // 24 MiB
+
 template <typename T>
 __global__ void cast_kernel(const double *__restrict__ src, T *__restrict__ dst, size_t n)
 {
@@ -1579,6 +1625,26 @@ btx_status raise_lds_limit(const void *fn, size_t lds)
   return BTX_OK;
 }
 
+// Device address of the scratch array on the current device (its name in
+// host code is only a stand-in).  Resolved once per device, at context or
+// batch creation with that device current, and kept for later calls.
+btx_status scratch_base(int device, double **out)
+{
+  static std::mutex mu;
+  static std::map<int, double *> base;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = base.find(device);
+  if (it == base.end()) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(BTX_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    it = base.emplace(device, (double *)p).first;
+  }
+  *out = it->second;
+  return BTX_OK;
+}
+
 // ------------------------------------------------------------ one model
 
 // Host-side owner of one model's device memory.
@@ -1596,6 +1662,7 @@ struct Model {
   double *d_tally = nullptr, *d_zm = nullptr, *d_ze = nullptr, *d_stage = nullptr, *d_q = nullptr;
   double *d_nbg = nullptr;           // new v_r, v_theta, v_phi, alpha, psi of a background update
   FaceDesc *d_faces = nullptr;
+  int32_t *d_bface = nullptr;        // faces with a ghost side (boundary tallies)
   btx::ZoneFaces *d_zf = nullptr;
   int2 *d_fitems = nullptr, *d_zitems = nullptr;   // (index, face), (index, zone)
   // local time stepping: zone levels, and the face (zone) items sorted by
@@ -1661,7 +1728,7 @@ void model_free(Model &m)
   void *ptrs[] = { m.d_mu, m.d_Phi, m.d_dOm, m.d_nvec, m.d_G, m.d_eps, m.d_vol, m.d_vr, m.d_vth, m.d_vph,
                    m.d_alp, m.d_psi, m.d_ka, m.d_ks, m.d_feq, m.d_f[0], m.d_f[1], m.d_dN, m.d_tally,
                    m.d_zm, m.d_ze, m.d_stage, m.d_faces, m.d_zf, m.d_tabs, m.d_aux, m.d_fitems, m.d_zitems,
-                   m.d_nbg, m.d_q, m.d_zlev, m.d_fitems_lts, m.d_zitems_lts };
+                   m.d_nbg, m.d_q, m.d_zlev, m.d_fitems_lts, m.d_zitems_lts, m.d_bface };
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   m = Model();
@@ -1727,6 +1794,7 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
   TRY(upload(&m.d_zf, g.zfaces.data(), g.zfaces.size()));
   TRY(upload(&m.d_fitems, fit.data(), nf));
   TRY(upload(&m.d_zitems, zit.data(), nz));
+  if (!g.bface.empty()) TRY(upload(&m.d_bface, g.bface.data(), g.bface.size()));
   TRY(upload(&m.d_vr, zero.data(), nz));
   TRY(upload(&m.d_vth, zero.data(), nz));
   TRY(upload(&m.d_vph, zero.data(), nz));
@@ -1987,6 +2055,35 @@ btx_status model_moments(const Model &m, const ModelDev *d_models, int parity, d
       totals[3 * sp + 1] = out + outc;
       totals[3 * sp + 2] = E + Ec;
     }
+  }
+  return BTX_OK;
+}
+
+// btx_moments with device outputs and the scratch array for its partial
+// results: no allocation, no synchronisation.  zm (may be null) and totals
+// (may be null) are device pointers.
+btx_status model_moments_device(const Model &m, const ModelDev *d_models, int parity, double *zm,
+                                double *totals, double *scr, hipStream_t s)
+{
+  const btx::Grid &g = m.g;
+  const size_t pairs = (size_t)g.nz * g.ns;
+  if (pairs > kScratchPairs)
+    return fail(BTX_E_UNSUPPORTED, "btx_moments_device takes at most " + std::to_string(kScratchPairs) +
+                                       " (zone, species) pairs; this grid has " + std::to_string(pairs));
+  if (!m.have_bg || !m.have_state) return fail(BTX_E_STATE, "background and state must be set");
+  if (!zm && !totals) return BTX_OK;
+  int idx = m.index;
+  double *ze = scr, *zmo = zm ? zm : scr + kScratchPairs;
+  void *args[] = { &d_models, &idx, &parity, &zmo, &ze };
+  const void *mk = m.tsize == 8 ? (const void *)moments_kernel<double> : (const void *)moments_kernel<float>;
+  HIP_TRY(hipLaunchKernel(mk, dim3(g.nz), dim3(256), args, 0, s));
+  if (totals) {
+    const double *tally = m.d_tally;
+    const int32_t *bface = m.d_bface;
+    int nz = g.nz, ns = g.ns, nb = (int)g.bface.size();
+    const double *zmc = zmo, *zec = ze;
+    void *targs[] = { &zmc, &zec, &tally, &bface, &nz, &ns, &nb, &totals };
+    HIP_TRY(hipLaunchKernel((const void *)totals_kernel, dim3(3 * g.ns), dim3(256), targs, 0, s));
   }
   return BTX_OK;
 }
@@ -2532,6 +2629,8 @@ btx_status btx_create(const btx_grid_desc *d, int hip_device, void *hip_stream, 
   btx_ctx *c = new btx_ctx();
   c->device = hip_device;
   c->stream = (hipStream_t)hip_stream;
+  double *scr = nullptr;
+  if ((st = scratch_base(hip_device, &scr)) != BTX_OK) return st;
   if ((st = model_init(c->m, d, 0, cap)) != BTX_OK) { delete c; return st; }
   c->h_model = model_dev(c->m, 0.0);
   if ((st = upload(&c->d_model, &c->h_model, 1)) != BTX_OK) { free_ctx(c); return st; }
@@ -2624,6 +2723,16 @@ btx_status btx_moments(btx_ctx *c, double *zone_moments, double *totals)
   if (!c) return fail(BTX_E_INVAL, "null context");
   HIP_TRY(hipSetDevice(c->device));
   return model_moments(c->m, c->d_model, c->parity, zone_moments, totals, c->stream);
+}
+
+btx_status btx_moments_device(btx_ctx *c, double *zone_moments, double *totals)
+{
+  if (!c) return fail(BTX_E_INVAL, "null context");
+  HIP_TRY(hipSetDevice(c->device));
+  double *scr = nullptr;
+  btx_status st = scratch_base(c->device, &scr);
+  if (st != BTX_OK) return st;
+  return model_moments_device(c->m, c->d_model, c->parity, zone_moments, totals, scr, c->stream);
 }
 
 btx_status btx_source_terms(btx_ctx *c, double *q)

@@ -1,15 +1,22 @@
-"""Build libbtx.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libbtx.so (HIP, gfx950) in-tree with hipcc.
+
+The device code is split over several translation units (the face-kernel
+instances of each precision apart from the rest), compiled in parallel and
+linked into one shared library.
+"""
 from __future__ import annotations
 
 import os
 import shutil
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbtx.so")
-SOURCES = [os.path.join(CSRC, "btx.hip"), os.path.join(CSRC, "btx_grid.cpp")]
-FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC", "-shared",
+UNITS = ["btx.hip", "btx_face32.hip", "btx_face64.hip", "btx_grid.cpp"]
+SOURCES = [os.path.join(CSRC, u) for u in UNITS]
+FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC",
          # packed FP32 VALU forms are kept out of the generated code on purpose
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -21,14 +28,27 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: libbtx cannot be built")
 
 
-def build(verbose: bool = False) -> str:
+def _compile(src: str, obj: str) -> subprocess.CompletedProcess:
+    return subprocess.run([hipcc()] + FLAGS + ["-c", src, "-o", obj], capture_output=True, text=True)
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    objs = [os.path.join(objdir, os.path.basename(s) + ".o") for s in SOURCES]
+    jobs = jobs or min(len(SOURCES), max(1, int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(_compile, SOURCES, objs))
+    for src, res in zip(SOURCES, results):
+        if res.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {os.path.basename(src)}:\n" + res.stdout + res.stderr)
+        if verbose and res.stderr:
+            print(res.stderr)
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + ["-o", tmp] + SOURCES
-    res = subprocess.run(cmd, capture_output=True, text=True)
+    res = subprocess.run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs,
+                         capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-    if verbose:
-        print(res.stderr)
+        raise RuntimeError("link failed:\n" + res.stdout + res.stderr)
     os.replace(tmp, LIB)
     return LIB
 

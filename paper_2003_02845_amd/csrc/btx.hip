@@ -29,16 +29,24 @@
 #include <string>
 #include <vector>
 
-#include "../../include/btx.h"
-#include "btx_grid.h"
+#include "btx_dev.h"
 
 using btx::FaceDesc;
+using btx::FaceShape;
 using btx::SideDesc;
 
 namespace {
 
-constexpr int kTables = 8;    // remap tables per face
-constexpr double kPi = 3.14159265358979323846;
+// Scratch of btx_moments_device (the entry point for callers that cannot
+// allocate): the energy content of every (zone, species) pair, followed by
+// room for the zone moments when the caller passes no buffer for them.  It is
+// one array per GPU, alive until the process ends, and shared by every call on
+// that GPU; every value a call reads is written earlier in the same call, so
+// nothing needs clearing, and calls that overlap on one GPU race.  Host code
+// never passes the array's name to a kernel: it passes the device address
+// that scratch_base() resolves once per device.
+constexpr size_t kScratchPairs = (size_t)1 << 19;   // (zone, species) pairs
+static __device__ __align__(256) double scratch[kScratchPairs * 6];   // 24 MiB
 
 thread_local std::string g_err;
 
@@ -55,1415 +63,9 @@ btx_status fail(btx_status s, const std::string &msg)
       return fail(BTX_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
   } while (0)
 
-// ------------------------------------------------------------ device data
-
-struct DevGrid {
-  int nr, nth, ne, nmu, nphi, ns, ndir, nz, geom, phi_rule;
-  int eblk, blk, nfaces, nch, ce;   // face work items per direction, groups per item
-  double lnq, q, fp64_thr;
-  double om[4];                     // sum over directions of dOmega and dOmega n (r, theta, phi)
-  const double *mu, *Phi, *dOm, *nvec, *G, *eps, *vol;
-  const double *vr, *vth, *vph, *alp, *psi;
-};
-
-struct Frame {
-  double v[3];
-  double alpha, psi, th, ph;
-};
-
-// Per-face frame data computed once per background by table_kernel: the five
-// frames (0 Lm, 1 L, 2 R, 3 Rp, 4 interface) with their Lorentz factor and
-// psi^6, and the basis changes L -> interface and R -> interface.
-struct FaceAux {
-  double v[5][3];
-  double alpha[5], psi[5], gam[5], p6[5];
-  double M[2][9];
-};
-
-// Everything the kernels need about one model (a grid with its background,
-// state and per-face data), in device memory.  A batch holds one per model; a
-// single context holds one.  Work items name (model, face) or (model, zone).
-struct ModelDev {
-  DevGrid g;
-  const FaceDesc *faces;
-  const btx::ZoneFaces *zf;
-  char *tabs;                  // remap tables of every face
-  FaceAux *aux;                // frame data of every face
-  void *f[2];                  // state double buffer (storage precision)
-  const void *ka, *ks, *feq;   // [zone][species][group] (storage precision)
-  void *dN;                    // [face][side][species][group][direction]
-  double *tally;               // [face][species] cumulative content through ghost faces
-  double *q;                   // [zone][5] hydro source terms of the last step
-  const unsigned char *zlev;   // [zone] time level (local time stepping), or null
-  double dt;                   // step of the current launch
-};
-
-__device__ inline double dsq(double x) { return x * x; }
-
-// Pointers read from a descriptor in memory are generic; these all point to
-// device global memory, and saying so lets the compiler use global (not flat)
-// loads and stores, which do not hold up the LDS wait counter.
-template <typename P>
-__device__ __forceinline__ P *as_global(P *p)
-{
-  return (P *)((__attribute__((address_space(1))) P *)(uintptr_t)p);
-}
-
-// a descriptor's grid with its pointers marked global
-__device__ __forceinline__ DevGrid global_grid(const DevGrid &src)
-{
-  DevGrid g = src;
-  g.mu = as_global(g.mu); g.Phi = as_global(g.Phi); g.dOm = as_global(g.dOm);
-  g.nvec = as_global(g.nvec); g.G = as_global(g.G); g.eps = as_global(g.eps);
-  g.vol = as_global(g.vol); g.vr = as_global(g.vr); g.vth = as_global(g.vth);
-  g.vph = as_global(g.vph);
-  g.alp = as_global(g.alp); g.psi = as_global(g.psi);
-  return g;
-}
-
-__device__ Frame side_frame(const DevGrid &g, const SideDesc &s)
-{
-  Frame f;
-  int z = s.z;
-  f.v[0] = g.vr[z];
-  f.v[1] = g.vth[z];
-  f.v[2] = g.vph[z];
-  if (s.kind == btx::SIDE_MIRROR) f.v[0] = -f.v[0];
-  f.alpha = g.alp[z];
-  f.psi = g.psi[z];
-  f.th = s.th;
-  f.ph = s.ph;
-  return f;
-}
-
-__device__ inline bool same_frame(const Frame &a, const Frame &b)
-{
-  return a.v[0] == b.v[0] && a.v[1] == b.v[1] && a.v[2] == b.v[2] && a.alpha == b.alpha &&
-         a.psi == b.psi && a.th == b.th && a.ph == b.ph;
-}
-
-// orthonormal basis (e_r, e_theta, e_phi) as columns
-__device__ void basis_cols(double th, double ph, double B[3][3])
-{
-  double st, ct, sp, cp;
-  sincos(th, &st, &ct);
-  sincos(ph, &sp, &cp);
-  B[0][0] = st * cp; B[1][0] = st * sp; B[2][0] = ct;
-  B[0][1] = ct * cp; B[1][1] = ct * sp; B[2][1] = -st;
-  B[0][2] = -sp;     B[1][2] = cp;      B[2][2] = 0.0;
-}
-
-// x given in the basis at (ta, pa) -> components in the basis at (tb, pb)
-__device__ void change_basis(double ta, double pa, double tb, double pb, const double x[3], double y[3])
-{
-  if (ta == tb && pa == pb) { y[0] = x[0]; y[1] = x[1]; y[2] = x[2]; return; }
-  double A[3][3], B[3][3], c[3];
-  basis_cols(ta, pa, A);
-  basis_cols(tb, pb, B);
-  for (int r = 0; r < 3; ++r) c[r] = A[r][0] * x[0] + A[r][1] * x[1] + A[r][2] * x[2];
-  for (int r = 0; r < 3; ++r) y[r] = B[0][r] * c[0] + B[1][r] * c[1] + B[2][r] * c[2];
-}
-
-// Lorentz boost by fluid velocity v (paper Sec. 3.2.2)
-__device__ void lorentz(const double v[3], const double u[4], double o[4])
-{
-  double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-  double gam = 1.0 / sqrt(1.0 - v2);
-  double kv = gam * gam / (gam + 1.0);
-  double vu = v[0] * u[1] + v[1] * u[2] + v[2] * u[3];
-  double a = kv * vu + gam * u[0];
-  o[0] = gam * (u[0] + vu);
-  o[1] = u[1] + a * v[0];
-  o[2] = u[2] + a * v[1];
-  o[3] = u[3] + a * v[2];
-}
-
-// comoving(S) -> comoving(D) through Eulerian and coordinate frames, the
-// Hamiltonian kick on the axis of motion and the geometric rotation
-// (Eq. transformchain, Sec. 3.2.1-3.2.4; conformally flat, zero shift).
-// axis < 0: the remap forward in time at a fixed place, where the covariant
-// spatial momentum is kept and the covariant energy follows from the null
-// condition of the new metric.
-__device__ void frame_chain(const Frame &S, const Frame &D, int axis, bool rot, const double u[4], double o[4])
-{
-  double e[4];
-  lorentz(S.v, u, e);
-  double u0 = -S.alpha * e[0];                       // covariant time component
-  double p2 = S.psi * S.psi;
-  double uc[3] = { p2 * e[1], p2 * e[2], p2 * e[3] };  // covariant spatial components
-  if (axis < 0 && (S.alpha != D.alpha || S.psi != D.psi)) {
-    u0 = -D.alpha * sqrt(uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]) / (D.psi * D.psi);
-  } else if (S.alpha != D.alpha || S.psi != D.psi) {
-    double tr = 0.0;
-    for (int i = 0; i < 3; ++i) if (i != axis) tr += uc[i] * uc[i];
-    double dp2 = D.psi * D.psi;
-    double rad = dp2 * dp2 * u0 * u0 / (D.alpha * D.alpha) - tr;
-    if (rad >= 0.0) {
-      uc[axis] = copysign(sqrt(rad), uc[axis] >= 0.0 ? 1.0 : -1.0);
-    } else {                                          // no real root: reflect along the axis
-      double sc = dp2 * fabs(u0) / D.alpha / sqrt(tr);
-      uc[axis] = 0.0;
-      for (int i = 0; i < 3; ++i) if (i != axis) uc[i] *= sc;
-    }
-  }
-  double ud[3];
-  if (rot) change_basis(S.th, S.ph, D.th, D.ph, uc, ud);
-  else { ud[0] = uc[0]; ud[1] = uc[1]; ud[2] = uc[2]; }
-  double dp2 = D.psi * D.psi;
-  double eD[4] = { -u0 / D.alpha, ud[0] / dp2, ud[1] / dp2, ud[2] / dp2 };
-  double mv[3] = { -D.v[0], -D.v[1], -D.v[2] };
-  lorentz(mv, eD, o);
-}
-
-__device__ inline double u0_dir(const Frame &f, const double *n)
-{
-  double v2 = f.v[0] * f.v[0] + f.v[1] * f.v[1] + f.v[2] * f.v[2];
-  double gam = 1.0 / sqrt(1.0 - v2);
-  return gam * (1.0 + f.v[0] * n[0] + f.v[1] * n[1] + f.v[2] * n[2]);
-}
-
-// ------------------------------------------------------------ LDS tables
-
-// A remap T_{S->D} of one face in gather form.  For every target direction d'
-// the entries [start[d'], start[d'+1]) hold the two energy-tap weights
-// (cl, cr) and a 16-bit key: on a logarithmic energy grid one shift di serves
-// every group, and source group i of direction src sends cl to group i + di and
-// cr to group i + di + 1.  Keys are first built as src | (di + 128) << 8 and
-// sorted; when every shift of the table is within one group (flag bit 0 of
-// start[nd + 1] clear) they are then replaced by the source window offset
-// src * cs - di + 2 in the direction-major data buffers.  Tables act on number
-// content; occupations are turned into content before (x G_i a(d)) and back
-// after (/ (G_i a(d'))) by the caller.
-template <typename T>
-struct Tab {
-  const T *cw;                   // 2 x 4 nd tap weights (cl, cr)
-  const unsigned short *key;     // 4 nd
-  const unsigned short *start;   // nd + 2
-};
-
-__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
-
-__host__ __device__ inline size_t tab_stride(int nd, size_t szT)
-{
-  return align16(8 * (size_t)nd * szT + (5 * (size_t)nd + 2) * 2);
-}
-
-template <typename T>
-__device__ inline Tab<T> tab_at(const char *base, int nd)
-{
-  Tab<T> t;
-  t.cw = (const T *)base;
-  t.key = (const unsigned short *)(t.cw + 8 * nd);
-  t.start = t.key + 4 * nd;
-  return t;
-}
-
-// Work items of the face kernel: nch (a power of two) per target direction,
-// each owning CE consecutive rows (energy groups).  The nch * CE rows of a
-// direction end at group ne + 1, so that the rows ne and ne + 1, which collect
-// the content an upward shift pushes past the top group, share a work item
-// with group ne - 1, and they start at or below group -1.
-
-// Data buffers in LDS are direction-major: column d holds the rows
-// ne - nch CE .. ne + 2 contiguously; rows outside 0 .. ne-1 are zero.  The
-// stride nch CE + 3 is odd, so neighbouring lanes reading different columns
-// hit distinct banks.
-__host__ __device__ inline int col_rows(int nch, int ce) { return nch * ce + 3; }
-
-__host__ __device__ inline size_t buf_bytes(int nd, int nch, int ce, size_t szT)
-{
-  return align16((size_t)nd * col_rows(nch, ce) * szT);
-}
-
-// table-build scratch for one round of 4 tables
-// table build scratch for tpr tables at a time
-__host__ __device__ inline size_t scratch_bytes(int nd, size_t szT, int tpr = 4)
-{
-  return (size_t)tpr * nd * 4 * 2 + (size_t)4 * tpr * nd * 4 + (size_t)8 * tpr * nd * szT;
-}
-
-// 16-bit gather keys before their conversion to window offsets: the source
-// direction and the energy shift.  Up to 256 directions they take 8 bits
-// each; up to 1024 directions the source takes 10 bits and the shift 6, which
-// is exact there: such grids have at most 29 groups, and a shift that takes
-// every group past the edge of the grid folds like one just past it.
-__host__ __device__ inline unsigned short pack_key(int src, int di, int nd)
-{
-  if (nd > 256) {
-    di = di < -31 ? -31 : (di > 31 ? 31 : di);
-    return (unsigned short)(src | ((di + 32) << 10));
-  }
-  return (unsigned short)(src | ((di + 128) << 8));
-}
-
-__host__ __device__ inline void unpack_key(unsigned key, int nd, int &src, int &di)
-{
-  if (nd > 256) { src = key & 0x3ff; di = (int)(key >> 10) - 32; }
-  else { src = key & 0xff; di = (int)(key >> 8) - 128; }
-}
-
-// LDS of one face workgroup: 8 tables, 3 data buffers (Lm, then Rp; L; R), per-row
-// constants (G, 1/G as T; per species: source and blend weight as T, two
-// collision coefficients as FP64, a precision flag), the wave partials and
-// totals of the angle sums, and the tally partials
-__host__ __device__ inline size_t face_lds_bytes(int nd, int ns, int nch, int ce, size_t szT, bool gtab = false)
-{
-  const size_t nrow = col_rows(nch, ce), nsr = (size_t)ns * nrow;
-  return (gtab ? 0 : kTables * tab_stride(nd, szT)) + 3 * buf_bytes(nd, nch, ce, szT) + 2 * align16(nrow * szT) +
-         2 * align16(nsr * szT) + 2 * align16(nsr * 8) + align16(nsr * 4) + align16(16 * nrow * 8) +
-         align16(nrow * 8) + align16(16 * 8);
-}
-
-// ascending node bracket with edge clamping (all weight to the edge node)
-__device__ inline void node_bracket(const double *x, int n, double v, int &L, int &R, double &wR)
-{
-  if (n == 1 || v <= x[0]) { L = R = 0; wR = 0.0; return; }
-  if (v >= x[n - 1]) { L = R = n - 1; wR = 0.0; return; }
-  int l = 0;
-  while (x[l + 1] <= v) ++l;
-  L = l;
-  R = l + 1;
-  wR = (v - x[l]) / (x[l + 1] - x[l]);
-}
-
-// One source direction of one remap: frame chain, energy shift and taps,
-// (mu, Phi) corners.  rt[4] receive the targets (-1 unused), rl/rr the tap
-// weights times the corner weight.
-// mu: the mu nodes (the grid's, or a copy of them in LDS)
-__device__ void remap_source(const DevGrid &g, const double *mu, const Frame &S, const Frame &D, int axis,
-                             bool rot, bool ident, int d, int rt[4], double rl[4], double rr[4], int &di_out)
-{
-  const double *n = g.nvec + 3 * d;
-  rt[1] = rt[2] = rt[3] = -1;
-  rl[1] = rl[2] = rl[3] = rr[1] = rr[2] = rr[3] = 0.0;
-  if (ident) {
-    di_out = 0;
-    rt[0] = d; rl[0] = 1.0; rr[0] = 0.0;
-    return;
-  }
-  double u[4] = { 1.0, n[0], n[1], n[2] }, o[4];
-  frame_chain(S, D, axis, rot, u, o);
-  // energy: eps* = rho eps_i; logarithmic groups -> one shift for every i
-  double rho = o[0];
-  int di = (int)floor(log(rho) / g.lnq);
-  double we = (rho * exp(-di * g.lnq) - 1.0) / (g.q - 1.0);
-  we = fmin(1.0, fmax(0.0, we));
-  di = max(-127, min(127, di));
-  di_out = di;
-  // direction
-  double mus = fmin(1.0, fmax(-1.0, o[1] / o[0]));
-  int jL, jR;
-  double wj;
-  node_bracket(mu, g.nmu, mus, jL, jR, wj);
-  int k0 = d % g.nphi;
-  double P;
-  if (o[2] * o[2] + o[3] * o[3] <= 1e-12 * o[0] * o[0]) {
-    P = g.Phi[k0];                                  // on the mu = +-1 axis: keep the Phi label
-  } else {
-    P = atan2(o[3], o[2]);
-    if (P < 0.0) P += 2.0 * kPi;
-  }
-  int kL, kR;
-  double wk;
-  if (g.nphi == 1) { kL = kR = 0; wk = 0.0; }
-  else {
-    double dP = 2.0 * kPi / g.nphi;
-    int kl = (int)floor(P / dP - 0.5);
-    double PL = (kl + 0.5) * dP, PR = PL + dP;
-    if (g.phi_rule == 0) {
-      double a = sin(PR - P), b = sin(P - PL);
-      wk = b / (a + b);
-    } else {
-      wk = (P - PL) / dP;
-    }
-    kL = ((kl % g.nphi) + g.nphi) % g.nphi;
-    kR = (((kl + 1) % g.nphi) + g.nphi) % g.nphi;
-  }
-  // coinciding brackets (clamped or a single Phi bin) are merged so that the
-  // four records of a source have distinct targets
-  const bool oneJ = jL == jR, oneK = kL == kR;
-  const double wj0 = oneJ ? 1.0 : 1.0 - wj, wj1 = oneJ ? 0.0 : wj;
-  const double wk0 = oneK ? 1.0 : 1.0 - wk, wk1 = oneK ? 0.0 : wk;
-  const double c[4] = { wj0 * wk0, wj0 * wk1, wj1 * wk0, wj1 * wk1 };
-  const int tg[4] = { jL * g.nphi + kL, jL * g.nphi + kR, jR * g.nphi + kL, jR * g.nphi + kR };
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    // corner weights at rounding level (a direction that lands on a node up
-    // to the last bit) are dropped: they move less than 1e-15 of a bin
-    rt[r] = c[r] > 1e-15 ? tg[r] : -1;
-    rl[r] = c[r] * (1.0 - we);
-    rr[r] = c[r] * we;
-  }
-}
-
-// Gather of one remap for target direction dp over the rows r0 .. r0+CE-1 of
-// a work item.  X points at group 0 of column 0 of a direction-major buffer
-// (column stride cs, zero outside groups 0 .. ne-1).  Content that the energy
-// shift pushes below group 0 or above group ne-1 stays in that group: for
-// shifts of at most one group it lands on row -1 (kb: its position in this
-// item, folded into group 0; with SPLIT, row -1 ends the previous item,
-// the neighbouring lane, and is carried over) or on rows ne, ne+1 (the last
-// two rows of the top item, folded into group ne-1); tables with larger
-// shifts take the explicit path.  Called by all lanes of a wave together.
-template <typename T, int CE, bool SPLIT>
-__device__ __forceinline__ void gather(const Tab<T> &tb, int nd, const T *__restrict__ X, int cs, int ne,
-                                       int dp, int r0, bool top, int kb, T acc[CE])
-{
-#pragma unroll
-  for (int k = 0; k < CE; ++k) acc[k] = (T)0;
-  const int e0 = tb.start[dp], e1 = tb.start[dp + 1];
-  if ((tb.start[nd + 1] & 1) == 0) {
-    const T *base = X + (r0 - 3);
-#pragma unroll 2
-    for (int e = e0; e < e1; ++e) {
-      const T *w = base + tb.key[e];                 // window of rows r0-di-1 .. r0-di+CE-1
-      const T cl = tb.cw[2 * e], cr = tb.cw[2 * e + 1];
-      T x[CE + 1];
-#pragma unroll
-      for (int k = 0; k <= CE; ++k) x[k] = w[k];
-#pragma unroll
-      for (int k = 0; k < CE; ++k) acc[k] = fma(cl, x[k + 1], fma(cr, x[k], acc[k]));
-    }
-    if (top) acc[CE - 3] += acc[CE - 2] + acc[CE - 1];
-#pragma unroll
-    for (int k = 0; k + 1 < CE; ++k) acc[k + 1] += k == kb ? acc[k] : (T)0;
-  } else {
-    for (int e = e0; e < e1; ++e) {
-      int d, di;
-      unpack_key(tb.key[e], nd, d, di);
-      const T cl = tb.cw[2 * e], cr = tb.cw[2 * e + 1];
-      const T *col = X + d * cs;
-#pragma unroll
-      for (int k = 0; k < CE; ++k) {
-        const int i = r0 + k;
-        if (i < 0 || i >= ne) continue;
-        const int iL = i - di, iR = iL - 1;
-        T v = (T)0;
-        if (iL >= 0 && iL < ne) v += cl * col[iL];
-        if (iR >= 0 && iR < ne) v += cr * col[iR];
-        if (i == 0) {                                   // sent below group 0
-          for (int j = 0; j < ne && j + di < 0; ++j) v += cl * col[j];
-          for (int j = 0; j < ne && j + di + 1 < 0; ++j) v += cr * col[j];
-        }
-        if (i == ne - 1) {                              // sent above group ne-1
-          for (int j = max(0, ne - di); j < ne; ++j) v += cl * col[j];
-          for (int j = max(0, ne - 1 - di); j < ne; ++j) v += cr * col[j];
-        }
-        acc[k] += v;
-      }
-    }
-  }
-  if constexpr (SPLIT) {
-    const T carry = __shfl_up(acc[CE - 1], 1, 64);
-    if (r0 == 0) acc[0] += carry;
-  }
-}
-
-// MC limiter minmod(2 dm, 2 dp, (dm + dp)/2): the argument closest to zero
-// when all three have the same strict sign, else zero (branch-free form)
-template <typename T>
-__device__ inline T mc_limiter(T dm, T dp)
-{
-  const T a = (T)2 * dm, b = (T)2 * dp, m = (T)0.5 * (dm + dp);
-  const T lo = fmin(a, fmin(b, m)), hi = fmax(a, fmax(b, m));
-  return lo > (T)0 ? lo : (hi < (T)0 ? hi : (T)0);
-}
-
-__device__ inline double wave_sum(double v)
-{
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// three wave sums with their shuffles interleaved
-__device__ inline void wave_sum3(double &a, double &b, double &c)
-{
-  for (int o = 32; o > 0; o >>= 1) {
-    const double x = __shfl_xor(a, o, 64), y = __shfl_xor(b, o, 64), w = __shfl_xor(c, o, 64);
-    a += x;
-    b += y;
-    c += w;
-  }
-}
-
-// frame weight psi^6 u0 dOmega of direction d in frame k of a face
-__device__ inline double frame_weight(const DevGrid &g, const FaceAux &A, int k, int d)
-{
-  const double *nv = g.nvec + 3 * d;
-  double vdn = A.v[k][0] * nv[0] + A.v[k][1] * nv[1] + A.v[k][2] * nv[2];
-  return A.p6[k] * A.gam[k] * (1.0 + vdn) * g.dOm[d];
-}
-
-// ------------------------------------------------------------ table kernel
-
-// frames of table t (0 Lm->L, 1 R->L, 2 L->R, 3 Rp->R, 4 L->s, 5 R->s, 6 s->L,
-// 7 s->R) among 0 Lm, 1 L, 2 R, 3 Rp, 4 the interface s
-__device__ inline int tab_src(int t) { return t == 0 ? 0 : (t == 1 || t == 5) ? 2 : (t == 2 || t == 4) ? 1 : t == 3 ? 3 : 4; }
-__device__ inline int tab_dst(int t) { return (t == 0 || t == 1 || t == 6) ? 1 : (t == 2 || t == 3 || t == 7) ? 2 : 4; }
-
-// Builds the eight remap tables of one face (frame chain once per direction,
-// inverted into sorted per-target gather lists) and stores them in global
-// memory; run once per background.
-// table t: 0 Lm->L, 1 R->L, 2 L->R, 3 Rp->R, 4 L->s, 5 R->s, 6 s->L, 7 s->R
-// GTAB: the tables are built in place in global memory (grids whose tables do
-// not fit in LDS), one table at a time.
-template <typename T, bool GTAB>
-__global__ void __launch_bounds__(256)
-table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items)
-{
-  constexpr int TPR = GTAB ? 1 : 4;                 // tables per round
-  extern __shared__ __align__(16) char lds[];
-  __shared__ int flg[kTables];
-  const int2 it = items[blockIdx.x];
-  const ModelDev &M = models[it.x];
-  const DevGrid g = global_grid(M.g);
-  char *__restrict__ tabs_g = as_global(M.tabs);
-  FaceAux *__restrict__ aux = as_global(M.aux);
-  const int fid = it.y;
-  const FaceDesc &F = as_global(M.faces)[fid];
-  const int nd = g.ndir, tid = threadIdx.x, nthr = blockDim.x;
-  const size_t tstride = tab_stride(nd, sizeof(T));
-  char *p = lds;
-  char *tabs = GTAB ? tabs_g + (size_t)fid * kTables * tstride : p;
-  if (!GTAB) p += kTables * tstride;
-  Frame *frm = (Frame *)p;     p += align16(5 * sizeof(Frame));
-  char *data = p;
-  int *cnt = (int *)data;                      // TPR nd
-  int *cur = cnt + TPR * nd;                   // TPR nd
-  int *rtg = cur + TPR * nd;                   // 4 TPR nd
-  T *rcf = (T *)(rtg + 4 * TPR * nd);          // 8 TPR nd
-  // the mu nodes, searched for every direction of every table
-  double *smu = (double *)(data + align16(scratch_bytes(nd, sizeof(T), TPR)));
-  for (int q = tid; q < g.nmu; q += nthr) smu[q] = g.mu[q];
-  const int cs = col_rows(g.nch, g.ce);
-  auto tw = [&](int t, T *&cw, unsigned short *&key, unsigned short *&start) {
-    char *b = tabs + t * tstride;
-    cw = (T *)b;
-    key = (unsigned short *)(cw + 8 * nd);
-    start = key + 4 * nd;
-  };
-  if (tid < kTables) flg[tid] = 0;
-  if (tid == 0) {
-    Frame a = side_frame(g, F.L), b = side_frame(g, F.R);
-    frm[0] = side_frame(g, F.Lm);
-    frm[1] = a;
-    frm[2] = b;
-    frm[3] = side_frame(g, F.Rp);
-    Frame fs_;
-    double vl[3], vr[3];
-    change_basis(a.th, a.ph, F.ths, F.phs, a.v, vl);
-    change_basis(b.th, b.ph, F.ths, F.phs, b.v, vr);
-    for (int i = 0; i < 3; ++i) fs_.v[i] = 0.5 * (vl[i] + vr[i]);
-    fs_.alpha = 0.5 * (a.alpha + b.alpha);
-    fs_.psi = 0.5 * (a.psi + b.psi);
-    fs_.th = F.ths;
-    fs_.ph = F.phs;
-    frm[4] = fs_;
-  }
-  const bool rot = g.geom != 2;
-  const int ax = F.axis;
-  for (int round = 0; round < kTables / TPR; ++round) {
-    __syncthreads();
-    for (int q = tid; q < TPR * nd; q += nthr) cnt[q] = 0;
-    __syncthreads();
-    for (int q = tid; q < TPR * nd; q += nthr) {
-      int tl = q / nd, d = q - tl * nd, t = TPR * round + tl;
-      const Frame S = frm[tab_src(t)], D = frm[tab_dst(t)];
-      int rt[4], di;
-      double rl[4], rr[4];
-      remap_source(g, smu, S, D, ax, rot, same_frame(S, D), d, rt, rl, rr, di);
-      if (di < -1 || di > 1) atomicOr(&flg[t], 1);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        rtg[q * 4 + r] = rt[r] >= 0 ? (rt[r] | ((di + 128) << 16)) : -1;
-        rcf[(q * 4 + r) * 2] = (T)rl[r];
-        rcf[(q * 4 + r) * 2 + 1] = (T)rr[r];
-        if (rt[r] >= 0) atomicAdd(&cnt[tl * nd + rt[r]], 1);
-      }
-    }
-    __syncthreads();
-    if ((tid >> 6) < TPR) {                            // exclusive scan per table, one wave each
-      const int tl = tid >> 6, ln = tid & 63;
-      T *cw;
-      unsigned short *key, *start;
-      tw(TPR * round + tl, cw, key, start);
-      int base = 0;
-      for (int d0 = 0; d0 < nd; d0 += 64) {
-        const int d = d0 + ln;
-        const int c = d < nd ? cnt[tl * nd + d] : 0;
-        int incl = c;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const int y = __shfl_up(incl, o, 64);
-          if (ln >= o) incl += y;
-        }
-        if (d < nd) {
-          start[d] = (unsigned short)(base + incl - c);
-          cur[tl * nd + d] = base + incl - c;
-        }
-        base += __shfl(incl, 63, 64);
-      }
-      if (ln == 0) {
-        start[nd] = (unsigned short)base;
-        start[nd + 1] = (unsigned short)flg[TPR * round + tl];
-      }
-    }
-    __syncthreads();
-    for (int q = tid; q < TPR * nd; q += nthr) {       // records into their target lists
-      int tl = q / nd, d = q - tl * nd;
-      T *cw;
-      unsigned short *key, *start;
-      tw(TPR * round + tl, cw, key, start);
-      for (int r = 0; r < 4; ++r) {
-        int v = rtg[q * 4 + r];
-        if (v < 0) continue;
-        int tg = v & 0xffff, dib = v >> 16;
-        int slot = atomicAdd(&cur[tl * nd + tg], 1);
-        key[slot] = pack_key(d, dib - 128, nd);
-        cw[2 * slot] = rcf[(q * 4 + r) * 2];
-        cw[2 * slot + 1] = rcf[(q * 4 + r) * 2 + 1];
-      }
-    }
-    __syncthreads();
-    for (int q = tid; q < TPR * nd; q += nthr) {       // fixed summation order: sort by key
-      int tl = q / nd, d = q - tl * nd;
-      T *cw;
-      unsigned short *key, *start;
-      tw(TPR * round + tl, cw, key, start);
-      int a = start[d], b = start[d + 1];
-      for (int x = a + 1; x < b; ++x) {
-        unsigned short kx = key[x];
-        T c0 = cw[2 * x], c1 = cw[2 * x + 1];
-        int y = x - 1;
-        while (y >= a && key[y] > kx) {
-          key[y + 1] = key[y];
-          cw[2 * y + 2] = cw[2 * y];
-          cw[2 * y + 3] = cw[2 * y + 1];
-          --y;
-        }
-        key[y + 1] = kx;
-        cw[2 * y + 2] = c0;
-        cw[2 * y + 3] = c1;
-      }
-      // shifts within one group: keys become source window offsets
-      if (!(start[nd + 1] & 1))
-        for (int x = a; x < b; ++x) {
-          int src, di;
-          unpack_key(key[x], nd, src, di);
-          key[x] = (unsigned short)(src * cs - di + 2);
-        }
-    }
-  }
-  __syncthreads();
-
-  if (tid == 0) {
-    FaceAux A;
-    for (int k = 0; k < 5; ++k) {
-      const Frame &fr = frm[k];
-      for (int i = 0; i < 3; ++i) A.v[k][i] = fr.v[i];
-      A.alpha[k] = fr.alpha;
-      A.psi[k] = fr.psi;
-      A.gam[k] = 1.0 / sqrt(1.0 - (fr.v[0] * fr.v[0] + fr.v[1] * fr.v[1] + fr.v[2] * fr.v[2]));
-      A.p6[k] = pow(fr.psi, 6.0);
-    }
-    for (int side = 0; side < 2; ++side) {
-      const Frame &fr = frm[1 + side];
-      for (int c = 0; c < 3; ++c) {
-        double e[3] = { c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, c == 2 ? 1.0 : 0.0 }, y[3];
-        if (rot) change_basis(fr.th, fr.ph, F.ths, F.phs, e, y);
-        else { y[0] = e[0]; y[1] = e[1]; y[2] = e[2]; }
-        for (int r = 0; r < 3; ++r) A.M[side][3 * r + c] = y[r];
-      }
-    }
-    aux[fid] = A;
-  }
-  __syncthreads();
-  if (!GTAB) {
-    uint4 *dst = (uint4 *)(tabs_g + (size_t)fid * kTables * tstride);
-    const uint4 *src = (const uint4 *)tabs;
-    const int n16 = (int)(kTables * tstride / 16);
-    for (int q = tid; q < n16; q += nthr) dst[q] = src[q];
-  }
-}
-
-// ------------------------------------------------------------ time remap
-
-// LDS of the time-remap workgroup: one remap table under construction and in
-// gather form, the frame weights of both frames and one species block
-__host__ __device__ inline size_t time_lds_bytes(int nd, int ne, size_t szT)
-{
-  return align16((size_t)nd * 4) * 2 + align16((size_t)16 * nd) + align16((size_t)8 * nd * szT) * 2 +
-         align16((size_t)4 * nd * 2) + align16((size_t)(nd + 1) * 2) + align16((size_t)nd * 8) * 2 +
-         align16((size_t)nd * ne * szT);
-}
-
-// Remaps every species block of one zone from its comoving frame under the
-// current background to its comoving frame under a new one: the remap forward
-// in time of Sec. 3.2 (the closing T_{n->n+1} of a step, Sec. 3.3), at a fixed
-// place, so without rotation and with the time kick of frame_chain.  The
-// zone's gather table is built in LDS and applied in place to the number
-// content (W = psi^6 u0 G dOmega; the cell volume is unchanged).
-// nbg: the new background of the model, [5][zone] = v_r, v_theta, v_phi, alpha, psi.
-template <typename T>
-__global__ void __launch_bounds__(256)
-time_remap_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity,
-                  const double *__restrict__ nbg)
-{
-  extern __shared__ __align__(16) char lds[];
-  const int2 it = items[blockIdx.x];
-  const ModelDev &M = models[it.x];
-  const DevGrid g = global_grid(M.g);
-  T *__restrict__ f = as_global((T *)M.f[parity]);
-  const int z = it.y, nd = g.ndir, ne = g.ne, tid = threadIdx.x, nthr = blockDim.x;
-  Frame S;
-  S.v[0] = g.vr[z]; S.v[1] = g.vth[z]; S.v[2] = g.vph[z];
-  S.alpha = g.alp[z]; S.psi = g.psi[z];
-  S.th = 0.0; S.ph = 0.0;
-  Frame D = S;
-  const double *nb = as_global(nbg);
-  D.v[0] = nb[z]; D.v[1] = nb[g.nz + z]; D.v[2] = nb[2 * g.nz + z];
-  D.alpha = nb[3 * g.nz + z]; D.psi = nb[4 * g.nz + z];
-  if (same_frame(S, D)) return;                          // the whole workgroup leaves
-  char *p = lds;
-  int *cnt = (int *)p;                 p += align16((size_t)nd * 4);
-  int *cur = (int *)p;                 p += align16((size_t)nd * 4);
-  int *rtg = (int *)p;                 p += align16((size_t)16 * nd);
-  T *rcf = (T *)p;                     p += align16((size_t)8 * nd * sizeof(T));
-  T *cw = (T *)p;                      p += align16((size_t)8 * nd * sizeof(T));
-  unsigned short *key = (unsigned short *)p;  p += align16((size_t)4 * nd * 2);
-  unsigned short *start = (unsigned short *)p; p += align16((size_t)(nd + 1) * 2);
-  double *aS = (double *)p;            p += align16((size_t)nd * 8);
-  double *aD = (double *)p;            p += align16((size_t)nd * 8);
-  T *cont = (T *)p;
-  const double gS = 1.0 / sqrt(1.0 - (S.v[0] * S.v[0] + S.v[1] * S.v[1] + S.v[2] * S.v[2]));
-  const double gD = 1.0 / sqrt(1.0 - (D.v[0] * D.v[0] + D.v[1] * D.v[1] + D.v[2] * D.v[2]));
-  const double p6S = pow(S.psi, 6.0), p6D = pow(D.psi, 6.0);
-  for (int q = tid; q < nd; q += nthr) {
-    cnt[q] = 0;
-    const double *nv = g.nvec + 3 * q;
-    aS[q] = p6S * gS * (1.0 + S.v[0] * nv[0] + S.v[1] * nv[1] + S.v[2] * nv[2]) * g.dOm[q];
-    aD[q] = p6D * gD * (1.0 + D.v[0] * nv[0] + D.v[1] * nv[1] + D.v[2] * nv[2]) * g.dOm[q];
-  }
-  __syncthreads();
-  for (int q = tid; q < nd; q += nthr) {               // each source direction
-    int rt[4], di;
-    double rl[4], rr[4];
-    remap_source(g, g.mu, S, D, -1, false, false, q, rt, rl, rr, di);
-    for (int r = 0; r < 4; ++r) {
-      rtg[q * 4 + r] = rt[r] >= 0 ? (rt[r] | ((di + 128) << 16)) : -1;
-      rcf[(q * 4 + r) * 2] = (T)rl[r];
-      rcf[(q * 4 + r) * 2 + 1] = (T)rr[r];
-      if (rt[r] >= 0) atomicAdd(&cnt[rt[r]], 1);
-    }
-  }
-  __syncthreads();
-  if (tid == 0) {                                       // list starts per target
-    int acc = 0;
-    for (int d = 0; d < nd; ++d) { start[d] = (unsigned short)acc; cur[d] = acc; acc += cnt[d]; }
-    start[nd] = (unsigned short)acc;
-  }
-  __syncthreads();
-  for (int q = tid; q < nd; q += nthr)
-    for (int r = 0; r < 4; ++r) {
-      const int v = rtg[q * 4 + r];
-      if (v < 0) continue;
-      const int slot = atomicAdd(&cur[v & 0xffff], 1);
-      key[slot] = pack_key(q, (v >> 16) - 128, nd);
-      cw[2 * slot] = rcf[(q * 4 + r) * 2];
-      cw[2 * slot + 1] = rcf[(q * 4 + r) * 2 + 1];
-    }
-  __syncthreads();
-  for (int q = tid; q < nd; q += nthr) {               // fixed summation order: sort by key
-    const int a = start[q], b = start[q + 1];
-    for (int x = a + 1; x < b; ++x) {
-      const unsigned short kx = key[x];
-      const T c0 = cw[2 * x], c1 = cw[2 * x + 1];
-      int y = x - 1;
-      while (y >= a && key[y] > kx) {
-        key[y + 1] = key[y];
-        cw[2 * y + 2] = cw[2 * y];
-        cw[2 * y + 3] = cw[2 * y + 1];
-        --y;
-      }
-      key[y + 1] = kx;
-      cw[2 * y + 2] = c0;
-      cw[2 * y + 3] = c1;
-    }
-  }
-  __syncthreads();
-  for (int s = 0; s < g.ns; ++s) {
-    T *blk = f + (size_t)z * g.blk + (size_t)s * g.eblk;
-    for (int q = tid; q < ne * nd; q += nthr) {          // content, direction-major
-      const int i = q / nd, d = q - i * nd;
-      cont[d * ne + i] = (T)((double)blk[q] * g.G[i] * aS[d]);
-    }
-    __syncthreads();
-    for (int q = tid; q < ne * nd; q += nthr) {
-      const int i = q / nd, dp = q - i * nd;
-      T acc = (T)0;
-      for (int e = start[dp]; e < start[dp + 1]; ++e) {
-        int src, di;
-        unpack_key(key[e], nd, src, di);
-        const T cl = cw[2 * e], cr = cw[2 * e + 1];
-        const T *col = cont + src * ne;
-        const int iL = i - di, iR = iL - 1;
-        if (iL >= 0 && iL < ne) acc += cl * col[iL];
-        if (iR >= 0 && iR < ne) acc += cr * col[iR];
-        if (i == 0) {                                     // sent below group 0
-          for (int j = 0; j < ne && j + di < 0; ++j) acc += cl * col[j];
-          for (int j = 0; j < ne && j + di + 1 < 0; ++j) acc += cr * col[j];
-        }
-        if (i == ne - 1) {                                // sent above group ne-1
-          for (int j = max(0, ne - di); j < ne; ++j) acc += cl * col[j];
-          for (int j = max(0, ne - 1 - di); j < ne; ++j) acc += cr * col[j];
-        }
-      }
-      blk[q] = (T)((double)acc / (g.G[i] * aD[dp]));
-    }
-    __syncthreads();
-  }
-}
-
-// ------------------------------------------------------------ face kernel
-
-// one side's species-s values of a work item's load rows (li, li + NCH, ...)
-template <typename T, int NCH, int CE>
-__device__ __forceinline__ void fetch_side(const DevGrid &g, const SideDesc &sd, const T *__restrict__ f,
-                                           const T *__restrict__ feq, int s, int li, int ld, T v[CE])
-{
-  const int nd = g.ndir, ne = g.ne;
-  // one load site per row (a zone's block, or the equilibrium of a ghost), so
-  // that the loads of all rows and sides are in flight together
-  const bool data = sd.kind == btx::SIDE_ZONE || sd.kind == btx::SIDE_MIRROR;
-  const bool any = data || sd.kind == btx::SIDE_EQ;
-  const T *base = data ? f + (size_t)sd.z * g.blk + (size_t)s * g.eblk + ld : feq + ((size_t)sd.z * g.ns + s) * ne;
-  const size_t stride = data ? (size_t)nd : 1;
-#pragma unroll
-  for (int m = 0; m < CE; ++m) {
-    const int i = li + NCH * m;
-    T x = (T)0;
-    if (any && i < ne) x = base[(size_t)i * stride];
-    v[m] = x;
-  }
-}
-
-template <typename T, int NCH, int CE>
-__device__ __forceinline__ void store_side(const T v[CE], const T gl[CE], T a, int col, int li, int ne, int cs,
-                                           T *X)
-{
-#pragma unroll
-  for (int m = 0; m < CE; ++m) {
-    const int i = li + NCH * m;
-    if (i < ne) X[col * cs + i] = v[m] * gl[m] * a;
-  }
-}
-
-// One workgroup per face, NCH work items per direction.  Per species:
-//   load    the four stencil zones' blocks (coalesced rows, transposed into
-//           direction-major LDS columns as number content; three buffers,
-//           Rp taking Lm's after the slopes of L)
-//   phase 1 MC-limited slopes of both sides in their own frames (Sec. 3.3.2)
-//           and the reconstructed donor values
-//   phase 2 Lax-Wendroff half-step source in the interface frame; angle sums
-//           by wave shuffles; implicit interface collision (Eq. halfstep);
-//           blend (Sec. 3.3.3) into flux and donor contents
-//   phase 3 remapped content change of both sides (Eq. fullstep)
-// GTAB: the face's tables are read from global memory (through the caches)
-// instead of LDS, for momentum grids whose tables do not fit beside the
-// stencil blocks.
-template <typename T, int NCH, int CE, int MAXT, bool SPLIT, bool GTAB = false>
-__global__ void __launch_bounds__(MAXT)
-face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity, int sub)
-{
-  extern __shared__ __align__(16) char lds[];
-  const int2 it = items[blockIdx.x];
-  const ModelDev &M = models[it.x];
-  const DevGrid g = global_grid(M.g);
-  const char *__restrict__ tabs_g = as_global((const char *)M.tabs);
-  const FaceAux *__restrict__ aux = as_global((const FaceAux *)M.aux);
-  const T *__restrict__ f = as_global((const T *)M.f[parity]);
-  const T *__restrict__ ka = as_global((const T *)M.ka);
-  const T *__restrict__ ks = as_global((const T *)M.ks);
-  const T *__restrict__ feq = as_global((const T *)M.feq);
-  T *__restrict__ dN = as_global((T *)M.dN);
-  double *__restrict__ tally = as_global(M.tally);
-  const int fid = it.y;
-  const FaceDesc &F = as_global(M.faces)[fid];
-  // Time levels: the face steps with its finer zone, dt0 2^m; a side whose
-  // zone is at a coarser level adds this step's changes to those it already
-  // holds, unless its own step starts at this substep.
-  int lvL = 0, lvR = 0;
-  if (M.zlev) { lvL = as_global(M.zlev)[F.L.z]; lvR = as_global(M.zlev)[F.R.z]; }
-  const double dt = M.dt * (double)(1 << min(lvL, lvR));
-  const bool accL = (sub & ((1 << lvL) - 1)) != 0, accR = (sub & ((1 << lvR) - 1)) != 0;
-  const int nd = g.ndir, ne = g.ne, tid = threadIdx.x, nthr = blockDim.x;
-  T *outL = dN + (size_t)fid * 2 * g.blk, *outR = outL + g.blk;
-  if (!F.active) {
-    for (size_t q = tid; q < (size_t)g.blk; q += nthr) {
-      if (!accL) outL[q] = (T)0;
-      if (!accR) outR[q] = (T)0;
-    }
-    return;
-  }
-  const int nrow = col_rows(NCH, CE), cs = nrow, gb = NCH * CE - ne;
-  // ---- LDS carve-up
-  const size_t tstride = tab_stride(nd, sizeof(T));
-  const size_t bb = buf_bytes(nd, NCH, CE, sizeof(T));
-  char *p = lds;
-  const char *tabs = GTAB ? tabs_g + (size_t)fid * kTables * tstride : p;
-  if (!GTAB) p += kTables * tstride;
-  char *bufs = p;               p += 3 * bb;
-  T *XLm = (T *)(bufs) + gb, *XL = (T *)(bufs + bb) + gb, *XR = (T *)(bufs + 2 * bb) + gb,
-    *XRp = XLm;                   // Rp takes Lm's buffer once the slopes of L are done
-  const int nsr = g.ns * nrow;
-  T *rG = (T *)p + gb;          p += align16(nrow * sizeof(T));
-  T *riG = (T *)p + gb;         p += align16(nrow * sizeof(T));
-  T *rsrc0 = (T *)p + gb;       p += align16(nsr * sizeof(T));
-  T *rw0 = (T *)p + gb;         p += align16(nsr * sizeof(T));
-  double *rc00 = (double *)p + gb;  p += align16(nsr * 8);
-  double *rc10 = (double *)p + gb;  p += align16(nsr * 8);
-  int *rthick0 = (int *)p + gb; p += align16(nsr * 4);
-  double *spart = (double *)p;  p += align16(16 * nrow * 8);
-  double *savr = (double *)p + gb;  p += align16(nrow * 8);
-  double *tpart = (double *)p;
-
-#define TB(t) tab_at<T>(tabs + (t) * tstride, nd)
-
-  // ---- remap tables of this face (built once per background by table_kernel)
-  if (!GTAB) {
-    const uint4 *src = (const uint4 *)(tabs_g + (size_t)fid * kTables * tstride);
-    uint4 *dst = (uint4 *)lds;
-    const int n16 = (int)(kTables * tstride / 16);
-    // four loads in flight per thread: indexes past the end are clamped to
-    // the last entry (loaded and stored again), so that no load is guarded
-    for (int q0 = tid; q0 < n16; q0 += 4 * nthr) {
-      uint4 t[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) t[u] = src[min(q0 + u * nthr, n16 - 1)];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) dst[min(q0 + u * nthr, n16 - 1)] = t[u];
-    }
-  }
-  // ---- zero rows of the data buffers, per-row constants outside 0 .. ne-1
-  {
-    const int ng = nrow - ne;
-    for (int q = tid; q < 3 * nd * ng; q += nthr) {
-      int b = q / (nd * ng), rem = q - b * nd * ng, d = rem / ng, r = rem - d * ng;
-      ((T *)(bufs + b * bb))[d * cs + (r < gb ? r : r + ne)] = (T)0;
-    }
-    for (int q = tid; q < nrow; q += nthr) {
-      const int r = q - gb;
-      const bool in = r >= 0 && r < ne;
-      rG[r] = in ? (T)g.G[r] : (T)0;
-      riG[r] = in ? (T)(1.0 / g.G[r]) : (T)0;
-    }
-  }
-  const FaceAux &A = aux[fid];
-  const int ax = F.axis;
-  const bool slopeL = F.L.slope, slopeR = F.R.slope && !F.self;
-  const bool ghost = F.L.kind != btx::SIDE_ZONE || F.R.kind != btx::SIDE_ZONE;
-  const double gs = A.gam[4];
-  const double ap4 = A.alpha[4] * dsq(A.psi[4] * A.psi[4]);
-  const double vn = A.v[4][ax];
-  const double Uadv = ap4 * gs * vn;
-  const double tau = 0.5 * A.alpha[4] * dt / gs;
-  // ---- per (species, group) interface opacities and collision coefficients
-  for (int q = tid; q < nsr; q += nthr) {
-    const int sp = q / nrow, i = q - sp * nrow - gb;
-    double a_ = 0.0, b_ = 0.0, e_ = 0.0;
-    const bool in = i >= 0 && i < ne;
-    if (in && !F.zero_opacity) {
-      size_t l = ((size_t)F.L.z * g.ns + sp) * ne + i, r = ((size_t)F.R.z * g.ns + sp) * ne + i;
-      a_ = 0.5 * ((double)ka[l] + (double)ka[r]);
-      b_ = 0.5 * ((double)ks[l] + (double)ks[r]);
-      e_ = 0.5 * ((double)feq[l] + (double)feq[r]);
-    }
-    const double den = 1.0 + tau * (a_ + b_);
-    const int o = sp * nrow + i;
-    rc00[o] = in ? 1.0 / den : 0.0;
-    rc10[o] = in ? tau * b_ / (1.0 + tau * a_) / den : 0.0;
-    rsrc0[o] = (T)(tau * a_ * e_);
-    rw0[o] = in ? (T)exp(-(a_ + b_) * F.h) : (T)0;
-    rthick0[o] = sizeof(T) == 8 || tau * (a_ + b_) > g.fp64_thr;
-  }
-
-  // ---- load mapping: direction ld, rows li, li + NCH, ...
-  const bool ldown = tid < NCH * nd;
-  const int ld = ldown ? tid % nd : 0, li = ldown ? tid / nd : ne;
-  T gl[CE];
-#pragma unroll
-  for (int m = 0; m < CE; ++m) {
-    const int i = li + NCH * m;
-    const double Gi = g.G[min(i, ne - 1)];           // unguarded, so the loads overlap
-    gl[m] = i < ne ? (T)Gi : (T)0;
-  }
-  const SideDesc *sides[4] = { &F.Lm, &F.L, &F.R, &F.Rp };
-  int colS[4];
-  T aS_[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    int col = ld;
-    if (sides[k]->kind == btx::SIDE_MIRROR) {
-      int j = ld / g.nphi, kk = ld - j * g.nphi;
-      col = (g.nmu - 1 - j) * g.nphi + kk;
-    }
-    colS[k] = col;
-    aS_[k] = (T)frame_weight(g, A, k, col);
-  }
-
-  // ---- compute mapping: target direction dp, rows r0 .. r0 + CE - 1
-  const bool own = tid < NCH * nd;
-  const int dp = own ? tid / NCH : 0, ch = tid % NCH;
-  const int r0 = ne + 2 - (NCH - ch) * CE;
-  const bool top = ch == NCH - 1;
-  const int kb = -1 - r0;
-  T iaL, iaR, iaS, cv, kF, uLp, uap, uRn, uan;
-  double dOd;
-  {
-    const double *nv = g.nvec + 3 * dp;
-    const double dO = g.dOm[dp];
-    iaL = (T)(1.0 / frame_weight(g, A, 1, dp));
-    iaR = (T)(1.0 / frame_weight(g, A, 2, dp));
-    iaS = (T)(1.0 / frame_weight(g, A, 4, dp));
-    // interface speeds (flux integral with zero shift) and the donor speeds of
-    // both sides (cell-centre direction expressed in the interface basis)
-    const double kvs = gs * gs / (gs + 1.0);
-    double vdn = A.v[4][0] * nv[0] + A.v[4][1] * nv[1] + A.v[4][2] * nv[2];
-    double u0 = gs * (1.0 + vdn);
-    double un = nv[ax] + (kvs * vdn + gs) * vn;
-    const double Urad = ap4 * (nv[ax] + kvs * vdn * vn);
-    const double Vn = A.alpha[4] * un / (A.psi[4] * A.psi[4] * u0);
-    double Us[2];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const double *v = A.v[1 + side];
-      double gm = A.gam[1 + side], kv = gm * gm / (gm + 1.0);
-      double vu = v[0] * nv[0] + v[1] * nv[1] + v[2] * nv[2];
-      double a_ = kv * vu + gm;
-      double e0 = nv[0] + a_ * v[0], e1 = nv[1] + a_ * v[1], e2 = nv[2] + a_ * v[2];
-      const double *M = A.M[side];
-      Us[side] = ap4 * (M[3 * ax] * e0 + M[3 * ax + 1] * e1 + M[3 * ax + 2] * e2);
-    }
-    const double gwd = dO * dt * F.area;
-    cv = (T)(-0.5 * dt * Vn / F.h);
-    kF = (T)(Urad * gwd);
-    uLp = (T)(fmax(Us[0], 0.0) * gwd);
-    uRn = (T)(fmax(-Us[1], 0.0) * gwd);
-    uap = (T)(fmax(Uadv, 0.0) * gwd);
-    uan = (T)(fmax(-Uadv, 0.0) * gwd);
-    dOd = own ? dO : 0.0;
-  }
-  const T dL = (T)F.dL, dR = (T)F.dR, ih = (T)(1.0 / F.h);
-  const T ihLm = (T)(1.0 / F.hLm), ihRp = (T)(1.0 / F.hRp);
-  const int lane = tid & 63, wave = tid >> 6, nw = (nthr + 63) >> 6;
-  // a launch with one workgroup row per species (gridDim.y = ns, for launches
-  // with few faces) takes the species of its row; else every species in turn
-  const int s_lo = gridDim.y > 1 ? (int)blockIdx.y : 0, s_hi = gridDim.y > 1 ? s_lo + 1 : g.ns;
-
-#pragma unroll 1
-  for (int s = s_lo; s < s_hi; ++s) {
-    // ---- load the stencil blocks as content densities
-    // Rp goes into Lm's buffer after stage 0.  FP32 loads it with the other
-    // sides and holds it in registers; FP64, short of registers, loads it then.
-    constexpr bool kHoldRp = sizeof(T) == 4;
-    T v3[CE];
-    {
-      T v0[CE], v1[CE], v2[CE];
-      if (slopeL) fetch_side<T, NCH, CE>(g, F.Lm, f, feq, s, li, ld, v0);
-      fetch_side<T, NCH, CE>(g, F.L, f, feq, s, li, ld, v1);
-      fetch_side<T, NCH, CE>(g, F.R, f, feq, s, li, ld, v2);
-      if (kHoldRp && slopeR) fetch_side<T, NCH, CE>(g, F.Rp, f, feq, s, li, ld, v3);
-      if (slopeL) store_side<T, NCH, CE>(v0, gl, aS_[0], colS[0], li, ne, cs, XLm);
-      store_side<T, NCH, CE>(v1, gl, aS_[1], colS[1], li, ne, cs, XL);
-      store_side<T, NCH, CE>(v2, gl, aS_[2], colS[2], li, ne, cs, XR);
-    }
-    const T *rsrc = rsrc0 + s * nrow, *rw = rw0 + s * nrow;
-    const double *rc0 = rc00 + s * nrow, *rc1 = rc10 + s * nrow;
-    const int *rthick = rthick0 + s * nrow;
-    __syncthreads();
-    // ---- five remap stages, each the sum of two gathers a = Ta . Xa, b = Tb . Xb
-    //   0 slopes of L      T0 . Lm,  T1 . R
-    //   1 slopes of R      T2 . L,   T3 . Rp
-    //   2 interface        T4 . L,   T5 . R    -> S, <S>, collision, blend
-    //   3 content to L     T6 . FL,  T1 . ER
-    //   4 content to R     T7 . FL,  T2 . EL
-    // (buffers: 0 Lm, Rp after stage 0, FL after stage 2; 1 L (EL content
-    // after stage 2); 2 R (ER content after stage 2))
-    T EL[CE], ER[CE];
-    double sumL = 0.0, sumR = 0.0;
-#pragma unroll 1
-    for (int st = 0; st < 5; ++st) {
-      T a[CE], b[CE];
-#pragma unroll
-      for (int k = 0; k < CE; ++k) a[k] = b[k] = (T)0;
-      const int nj = (st == 0 && !slopeL) || (st == 1 && !slopeR) ? 0 : 2;
-#pragma unroll 1
-      for (int j = 0; j < nj; ++j) {
-        const int t = (int)((0x2716543210ull >> (4 * (2 * st + j))) & 0xf);
-        const int x = (int)((0x1020210120ull >> (4 * (2 * st + j))) & 0xf);
-        T c[CE];
-        gather<T, CE, SPLIT>(TB(t), nd, (const T *)(bufs + x * bb) + gb, cs, ne, dp, r0, top, kb, c);
-#pragma unroll
-        for (int k = 0; k < CE; ++k) {
-          a[k] = j == 0 ? c[k] : a[k];
-          b[k] = j == 0 ? b[k] : c[k];
-        }
-      }
-      if (st == 0) {                                   // MC-limited slope of L (Sec. 3.3.2)
-#pragma unroll
-        for (int k = 0; k < CE; ++k) {
-          const int r = r0 + k;
-          const T sc = riG[r] * iaL, fl = XL[dp * cs + r] * sc;
-          const T sl = slopeL ? mc_limiter<T>((fl - a[k] * sc) * ihLm, (b[k] * sc - fl) * ih) : (T)0;
-          EL[k] = fl + dL * sl;
-          if (F.self) ER[k] = XR[dp * cs + r] * riG[r] * iaR + dR * sl;
-        }
-        if (slopeR) {                                  // Rp into Lm's buffer
-          if (!kHoldRp) fetch_side<T, NCH, CE>(g, F.Rp, f, feq, s, li, ld, v3);
-          __syncthreads();
-          store_side<T, NCH, CE>(v3, gl, aS_[3], colS[3], li, ne, cs, XRp);
-          __syncthreads();
-        }
-      } else if (st == 1) {                            // MC-limited slope of R
-        if (!F.self) {
-#pragma unroll
-          for (int k = 0; k < CE; ++k) {
-            const int r = r0 + k;
-            const T sc = riG[r] * iaR, fr = XR[dp * cs + r] * sc;
-            ER[k] = slopeR ? fr + dR * mc_limiter<T>((fr - a[k] * sc) * ih, (b[k] * sc - fr) * ihRp) : fr;
-          }
-        }
-      } else if (st == 2) {
-        // Lax-Wendroff half-step source S in the interface frame
-        T Sv[CE];
-#pragma unroll
-        for (int k = 0; k < CE; ++k) {
-          const int r = r0 + k;
-          const T sc = riG[r] * iaS;
-          const T x = a[k] * sc, y = b[k] * sc;
-          Sv[k] = (T)0.5 * (x + y) + cv * (y - x) + rsrc[r];
-        }
-        // angle sums of S per group (FP64): lanes NCH apart share rows
-#pragma unroll
-        for (int k = 0; k < CE; ++k) {
-          double v = (double)Sv[k] * dOd;
-#pragma unroll
-          for (int o = NCH; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
-          if (lane < NCH) spart[wave * nrow + r0 + k + gb] = v;
-        }
-        __syncthreads();                               // partial sums visible, buffers free
-        if (tid < nrow) {                              // totals over the waves, fixed order
-          double t = 0.0;
-#pragma unroll 4
-          for (int w = 0; w < nw; ++w) t += spart[w * nrow + tid];
-          savr[tid - gb] = t * (1.0 / (4.0 * kPi));
-        }
-        __syncthreads();
-        // implicit interface collision, blend weights and content fluxes
-        if (own) {
-#pragma unroll
-          for (int k = 0; k < CE; ++k) {
-            const int r = r0 + k;
-            if (r < 0 || r >= ne) continue;
-            const double sav = savr[r];
-            T flw;
-            if (rthick[r]) flw = (T)((double)Sv[k] * rc0[r] + rc1[r] * sav);
-            else flw = (T)((float)Sv[k] * (float)rc0[r] + (float)rc1[r] * (float)sav);
-            const T w = rw[r], G = rG[r];
-            XLm[dp * cs + r] = ((T)1 - w) * kF * G * flw;
-            XL[dp * cs + r] = (w * (uLp - uap) + uap) * G * EL[k];
-            XR[dp * cs + r] = (w * (uRn - uan) + uan) * G * ER[k];
-          }
-        }
-        __syncthreads();
-      } else {                                         // remapped content changes
-        T *o = (st == 3 ? outL : outR) + (size_t)s * g.eblk;
-        const T *own_c = st == 3 ? XL : XR;
-        const T sg = st == 3 ? (T)-1 : (T)1;
-        const bool acc = st == 3 ? accL : accR;
-        double sum = 0.0;
-#pragma unroll
-        for (int k = 0; k < CE; ++k) {
-          const int r = r0 + k;
-          if (!own || r < 0 || r >= ne) continue;
-          const T v = sg * a[k] - own_c[dp * cs + r] + b[k];
-          o[r * nd + dp] = acc ? o[r * nd + dp] + v : v;
-          sum += (double)v;
-        }
-        if (st == 3) sumL = sum;
-        else sumR = sum;
-      }
-    }
-    if (ghost) {
-      double v = wave_sum(F.L.kind != btx::SIDE_ZONE ? sumL : sumR);
-      if (lane == 0) tpart[wave] = v;
-    }
-    __syncthreads();                                   // buffers and partials free for the next species
-    if (ghost && tid == 0) {
-      double t = 0.0;
-      for (int w = 0; w < nw; ++w) t += tpart[w];
-      tally[(size_t)fid * g.ns + s] += t;
-    }
-  }
-#undef TB
-}
-
-// ------------------------------------------------------------ zone kernel
-
-// R: directions per lane (64 R directions at most).  A direction's loads (the
-// state and the changes from every face side of the zone) all go out before
-// the first is used; at 4 waves per SIMD (not 8) the compiler keeps them in
-// registers, and the kernel is faster for it.  With 16 directions per lane
-// (above 256 directions) the register bound is that of 2 waves per SIMD: at
-// 4 the kernel spilled; it takes about 120 registers.
-template <typename T, int R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R > 4 ? 2 : 4)))
-zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity)
-{
-  const int2 it = items[blockIdx.x];
-  const ModelDev &M = models[it.x];
-  const DevGrid g = global_grid(M.g);
-  const btx::ZoneFaces *__restrict__ zf = as_global(M.zf);
-  const T *__restrict__ f = as_global((const T *)M.f[parity]);
-  T *__restrict__ fout = as_global((T *)M.f[parity ^ 1]);
-  const T *__restrict__ dN = as_global((const T *)M.dN);
-  const T *__restrict__ ka = as_global((const T *)M.ka);
-  const T *__restrict__ ks = as_global((const T *)M.ks);
-  const T *__restrict__ feq = as_global((const T *)M.feq);
-  const int z = it.y;
-  const double dt = M.zlev ? M.dt * (double)(1 << as_global(M.zlev)[z]) : M.dt;   // dt0 2^level
-  const int nd = g.ndir, ne = g.ne, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nwaves = blockDim.x >> 6;
-  const btx::ZoneFaces &L = zf[z];        // uniform: read through the scalar cache
-  const int nq = L.n;                     // at most 8 face sides
-  const double vr = g.vr[z], vt = g.vth[z], vp = g.vph[z];
-  const double gam = 1.0 / sqrt(1.0 - (vr * vr + vt * vt + vp * vp));
-  const double p6v = pow(g.psi[z], 6.0) * g.vol[z];
-  const double tau = g.alp[z] * dt / gam;
-  // per (species, group) row: the sums of S dOmega and S dOmega n (r, theta,
-  // phi), for the source terms after the update
-  extern __shared__ __align__(16) char lds[];
-  double *rs = (double *)lds;
-  // a row's opacities are loaded one row ahead, with the previous row's data
-  const int nrows = g.ns * ne;
-  const size_t kz = (size_t)z * nrows;
-  T kan = (T)0, ksn = (T)0, fen = (T)0;
-  if (wave < nrows) { kan = ka[kz + wave]; ksn = ks[kz + wave]; fen = feq[kz + wave]; }
-  for (int row = wave; row < nrows; row += nwaves) {
-    int s = row / ne, i = row - s * ne;
-    const double ka_ = (double)kan, ks_ = (double)ksn, fe_ = (double)fen;
-    {
-      const int nx = min(row + nwaves, nrows - 1);
-      kan = ka[kz + nx];
-      ksn = ks[kz + nx];
-      fen = feq[kz + nx];
-    }
-    bool wide = (sizeof(T) == 8) || tau * (ka_ + ks_) > g.fp64_thr;
-    double Sd[R];
-    double part = 0.0;
-    for (int r = 0; r < R; ++r) {
-      int d = lane + 64 * r;
-      Sd[r] = 0.0;
-      if (d >= nd) continue;
-      size_t off = (size_t)s * g.eblk + (size_t)i * nd + d;
-      const T fz = f[(size_t)z * g.blk + off];
-      T dv[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q < nq) dv[q] = dN[((size_t)L.fid[q] * 2 + L.side[q]) * g.blk + off];
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q < nq) acc += (double)dv[q];
-      const double *nv = g.nvec + 3 * d;
-      double W = p6v * gam * (1.0 + vr * nv[0] + vt * nv[1] + vp * nv[2]) * g.G[i] * g.dOm[d];
-      double S = (double)fz + tau * ka_ * fe_ + acc / W;
-      if (!wide) S = (double)(float)S;
-      Sd[r] = S;
-      part += S * g.dOm[d];
-    }
-    const double ssum = wave_sum(part);
-    double avg = ssum / (4.0 * kPi);
-    double pr = 0.0, pt = 0.0, pp = 0.0;
-    for (int r = 0; r < R; ++r) {
-      int d = lane + 64 * r;
-      if (d >= nd) continue;
-      size_t off = (size_t)s * g.eblk + (size_t)i * nd + d;
-      const double sw = Sd[r] * g.dOm[d];
-      pr += sw * g.nvec[3 * d];
-      pt += sw * g.nvec[3 * d + 1];
-      pp += sw * g.nvec[3 * d + 2];
-      double out;
-      if (wide) out = (Sd[r] + tau * ks_ * avg / (1.0 + tau * ka_)) / (1.0 + tau * (ka_ + ks_));
-      else {
-        float t = (float)tau, a = (float)ka_, b = (float)ks_;
-        out = ((float)Sd[r] + t * b * (float)avg / (1.0f + t * a)) / (1.0f + t * (a + b));
-      }
-      fout[(size_t)z * g.blk + off] = (T)out;
-    }
-    wave_sum3(pr, pt, pp);
-    if (lane == 0) { rs[5 * row] = ssum; rs[5 * row + 1] = pr; rs[5 * row + 2] = pt; rs[5 * row + 3] = pp; }
-  }
-  // Hydro source terms (Eq. hydrosource1-3), in FP64, one row per thread:
-  // the collision term at the new state (backward Euler) is
-  // C_d = ka feq + ks avg' - (ka + ks) f'_d with the new angle average
-  // avg' = avg / (1 + tau ka) and f'_d = (S_d + tau ks avg') / (1 + tau (ka + ks)),
-  // i.e. C_d = B - K S_d, so its dOmega- and dOmega n-weighted sums need only
-  // the row sums of S.  Kept out of the update loop, which is latency bound.
-  __syncthreads();
-  const int nrow = g.ns * ne;
-  for (int row = threadIdx.x; row < nrow; row += blockDim.x) {
-    const int s = row / ne, i = row - s * ne;
-    const size_t kidx = ((size_t)z * g.ns + s) * ne + i;
-    const double ka_ = (double)ka[kidx], ks_ = (double)ks[kidx], fe_ = (double)feq[kidx];
-    const double ssum = rs[5 * row], avg1 = ssum / (4.0 * kPi) / (1.0 + tau * ka_);
-    const double K = (ka_ + ks_) / (1.0 + tau * (ka_ + ks_));
-    const double B = ka_ * fe_ + ks_ * avg1 - K * tau * ks_ * avg1;
-    const double cw = B * g.om[0] - K * ssum, cr = B * g.om[1] - K * rs[5 * row + 1];
-    const double ct = B * g.om[2] - K * rs[5 * row + 2], cp = B * g.om[3] - K * rs[5 * row + 3];
-    const double ge = g.G[i] * g.eps[i], lep = s == 0 ? 1.0 : (s == 1 ? -1.0 : 0.0);
-    rs[5 * row] = -lep * g.G[i] * cw;
-    rs[5 * row + 1] = -ge * cw;
-    rs[5 * row + 2] = -ge * cr;
-    rs[5 * row + 3] = -ge * ct;
-    rs[5 * row + 4] = -ge * cp;
-  }
-  __syncthreads();
-  // component k is summed over the rows by wave k mod 4 (fixed order:
-  // lane-strided, then a wave sum), so the result does not depend on timing
-  for (int k = wave; k < 5; k += nwaves) {
-    double v = 0.0;
-    for (int row = lane; row < nrow; row += 64) v += rs[5 * row + k];
-    v = wave_sum(v);
-    if (lane == 0) as_global(M.q)[(size_t)z * 5 + k] = v;
-  }
-}
-
-// Compensated summation (Neumaier's variant of Kahan's): s + c carries the
-// sum of the added values with the rounding error of every addition kept in c.
-__device__ inline void comp_add(double &s, double &c, double x)
-{
-  const double t = s + x;
-  c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
-  s = t;
-}
-
-// per-zone moments in FP64 (paper Sec. 4.1-4.2, without 1/h^3), each a
-// compensated sum over the zone's bins (per thread, over the lanes of a wave
-// and over the waves in a fixed order):
-// zm[z][s][0..4] = N, J, H, K, number flux; ze[z][s] = energy content
-template <typename T>
-__global__ void __launch_bounds__(256)
-moments_kernel(const ModelDev *__restrict__ models, int m, int parity, double *__restrict__ zm,
-               double *__restrict__ ze)
-{
-  const ModelDev &M = models[m];
-  const DevGrid g = global_grid(M.g);
-  const T *__restrict__ f = as_global((const T *)M.f[parity]);
-  const int z = blockIdx.x;
-  __shared__ double red[6][16], redc[6][16];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  const double vr = g.vr[z], vt = g.vth[z], vp = g.vph[z];
-  const double gam = 1.0 / sqrt(1.0 - (vr * vr + vt * vt + vp * vp));
-  const double p6v = pow(g.psi[z], 6.0) * g.vol[z];
-  for (int s = 0; s < g.ns; ++s) {
-    double m[6] = { 0, 0, 0, 0, 0, 0 }, mc[6] = { 0, 0, 0, 0, 0, 0 };
-    for (int q = threadIdx.x; q < g.eblk; q += blockDim.x) {
-      int i = q / g.ndir, d = q - i * g.ndir;
-      double fv = (double)f[(size_t)z * g.blk + (size_t)s * g.eblk + q];
-      const double *nv = g.nvec + 3 * d;
-      double dG = g.G[i] * g.dOm[d], mu = nv[0], e = g.eps[i];
-      double nn = p6v * gam * (1.0 + vr * nv[0] + vt * nv[1] + vp * nv[2]) * dG * fv;
-      comp_add(m[0], mc[0], nn);
-      comp_add(m[1], mc[1], fv * e * dG);
-      comp_add(m[2], mc[2], fv * mu * e * dG);
-      comp_add(m[3], mc[3], fv * mu * mu * e * dG);
-      comp_add(m[4], mc[4], fv * mu * dG);
-      comp_add(m[5], mc[5], nn * e);
-    }
-    for (int k = 0; k < 6; ++k) {
-      double v = m[k], c = mc[k];
-      for (int o = 32; o > 0; o >>= 1) {
-        const double vo = __shfl_xor(v, o, 64), co = __shfl_xor(c, o, 64);
-        comp_add(v, c, vo);
-        c += co;
-      }
-      if (lane == 0) { red[k][wave] = v; redc[k][wave] = c; }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t[6];
-      for (int k = 0; k < 6; ++k) {
-        double v = 0.0, c = 0.0;
-        for (int w = 0; w < nwaves; ++w) {
-          comp_add(v, c, red[k][w]);
-          c += redc[k][w];
-        }
-        t[k] = v + c;
-      }
-      double *o = zm + ((size_t)z * g.ns + s) * 5;
-      o[0] = t[0];
-      for (int k = 1; k < 5; ++k) o[k] = t[k] / (4.0 * kPi);
-      ze[(size_t)z * g.ns + s] = t[5];
-    }
-    __syncthreads();
-  }
-}
-
-// Totals of btx_moments_device: block (s, k) sums, for species s, the zone
-// numbers (k = 0), the boundary tallies (k = 1) or the zone energies (k = 2)
-// as compensated sums in a fixed order (per thread over a stride, over the
-// lanes of a wave, over the waves), and writes totals[3 s + k].
-__global__ void __launch_bounds__(256)
-totals_kernel(const double *__restrict__ zm, const double *__restrict__ ze, const double *__restrict__ tally,
-              const int32_t *__restrict__ bface, int nz, int ns, int nb, double *__restrict__ totals)
-{
-  const int s = blockIdx.x / 3, k = blockIdx.x % 3;
-  const int n = k == 1 ? nb : nz;
-  __shared__ double red[2][4];
-  double v = 0.0, c = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double x = k == 0 ? zm[((size_t)i * ns + s) * 5]
-                            : (k == 1 ? tally[(size_t)bface[i] * ns + s] : ze[(size_t)i * ns + s]);
-    comp_add(v, c, x);
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    const double vo = __shfl_xor(v, o, 64), co = __shfl_xor(c, o, 64);
-    comp_add(v, c, vo);
-    c += co;
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) { red[0][wave] = v; red[1][wave] = c; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0, tc = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      comp_add(t, tc, red[0][w]);
-      tc += red[1][w];
-    }
-    totals[3 * s + k] = t + tc;
-  }
-}
-
-// Scratch of btx_moments_device (the entry point for callers that cannot
-// allocate): the energy content of every (zone, species) pair, followed by
-// room for the zone moments when the caller passes no buffer for them.  It is
-// one array per GPU, alive until the process ends, and shared by every call on
-// that GPU; every value a call reads is written earlier in the same call, so
-// nothing needs clearing, and calls that overlap on one GPU race.  Host code
-// never passes the array's name to a kernel: it passes the device address
-// that scratch_base() resolves once per device.
-constexpr size_t kScratchPairs = (size_t)1 << 19;   // (zone, species) pairs
-static __device__ __align__(256) double scratch[kScratchPairs * 6];   // 24 MiB
-
-template <typename T>
-__global__ void cast_kernel(const double *__restrict__ src, T *__restrict__ dst, size_t n)
-{
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = (T)src[i];
-}
-
 }  // namespace
+
+// ---------------------------------------------------------------- host side
 
 // ---------------------------------------------------------------- host side
 
@@ -1471,23 +73,6 @@ namespace {
 
 // face workgroups that fill the device, one per CU (256 compute units)
 constexpr int kFillFaces = 256;
-
-// Face work-item shape: nch items per direction (a power of two), CE groups
-// per item, the workgroup size bound and whether group -1 ends an item.
-// FP32 takes 8 items per direction by default (up to 96 directions in
-// workgroups of up to 768 threads, up to 128 in 1024) or 4.  FP64 takes 8 up
-// to 96 directions where its buffers fit in LDS, else 4 (up to 128
-// directions, 512 threads).  CE is the smallest instantiated value with
-// nch CE >= ne + 3.
-struct FaceShape {
-  int nch = 0, ce = 0, maxt = 0;
-  bool split = false;
-  bool gtab = false;                 // tables read from global memory
-  bool operator==(const FaceShape &o) const
-  {
-    return nch == o.nch && ce == o.ce && maxt == o.maxt && split == o.split && gtab == o.gtab;
-  }
-};
 
 constexpr int kCE8[] = { 3, 4, 5, 6, 8 };
 constexpr int kCE4[] = { 4, 5, 6, 7, 8, 12, 16 };
@@ -1532,63 +117,9 @@ FaceShape default_shape(const btx::Grid &g, size_t lds_cap)
   return make_shape(g.prec, g.ndir, g.ne, 8);
 }
 
-template <typename T, int NCH, int MAXT, bool SPLIT>
-const void *face_fn_t(int ce)
-{
-  if constexpr (NCH == 8) {
-    switch (ce) {
-    case 3: return (const void *)face_kernel<T, 8, 3, MAXT, SPLIT>;
-    case 4: return (const void *)face_kernel<T, 8, 4, MAXT, SPLIT>;
-    case 5: return (const void *)face_kernel<T, 8, 5, MAXT, SPLIT>;
-    case 6: return (const void *)face_kernel<T, 8, 6, MAXT, SPLIT>;
-    case 8: return (const void *)face_kernel<T, 8, 8, MAXT, SPLIT>;
-    default: return nullptr;
-    }
-  } else {
-    switch (ce) {
-    case 4: return (const void *)face_kernel<T, 4, 4, MAXT, SPLIT>;
-    case 5: return (const void *)face_kernel<T, 4, 5, MAXT, SPLIT>;
-    case 6: return (const void *)face_kernel<T, 4, 6, MAXT, SPLIT>;
-    case 7: return (const void *)face_kernel<T, 4, 7, MAXT, SPLIT>;
-    case 8: return (const void *)face_kernel<T, 4, 8, MAXT, SPLIT>;
-    case 12: return (const void *)face_kernel<T, 4, 12, MAXT, SPLIT>;
-    case 16: return (const void *)face_kernel<T, 4, 16, MAXT, SPLIT>;
-    default: return nullptr;
-    }
-  }
-}
-
-template <typename T, int NCH>
-const void *face_fn_g(int ce)
-{
-  switch (ce) {
-  case 4: return (const void *)face_kernel<T, NCH, 4, 1024, false, true>;
-  case 8: return (const void *)face_kernel<T, NCH, 8, 1024, false, true>;
-  case 16: return (const void *)face_kernel<T, NCH, 16, 1024, false, true>;
-  default: return nullptr;
-  }
-}
-
-// the face-kernel instance of a shape
-template <typename T>
-const void *face_fn(const FaceShape &f)
-{
-  if (f.ce == 0) return nullptr;
-  if (f.gtab) {
-    if (f.split) return nullptr;
-    return f.nch == 4 ? face_fn_g<T, 4>(f.ce) : f.nch == 2 ? face_fn_g<T, 2>(f.ce)
-                      : f.nch == 1 ? face_fn_g<T, 1>(f.ce) : nullptr;
-  }
-  if (f.nch == 4) return f.split ? face_fn_t<T, 4, 512, true>(f.ce) : face_fn_t<T, 4, 512, false>(f.ce);
-  if (f.maxt == 768) return f.split ? face_fn_t<T, 8, 768, true>(f.ce) : face_fn_t<T, 8, 768, false>(f.ce);
-  if constexpr (sizeof(T) == 4)
-    return f.split ? face_fn_t<T, 8, 1024, true>(f.ce) : face_fn_t<T, 8, 1024, false>(f.ce);
-  return nullptr;
-}
-
 const void *face_fn(size_t tsize, const FaceShape &f)
 {
-  return tsize == 8 ? face_fn<double>(f) : face_fn<float>(f);
+  return tsize == 8 ? btx::face_fn_f64(f) : btx::face_fn_f32(f);
 }
 
 template <typename X>
@@ -1807,7 +338,8 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
   };
   if (!dmalloc(&m.d_ka, nk * m.tsize) || !dmalloc(&m.d_ks, nk * m.tsize) || !dmalloc(&m.d_feq, nk * m.tsize) ||
       !dmalloc(&m.d_f[0], nz * blk * m.tsize) || !dmalloc(&m.d_f[1], nz * blk * m.tsize) ||
-      !dmalloc(&m.d_dN, nf * 2 * blk * m.tsize) || !dmalloc((void **)&m.d_tally, nf * g.ns * 8) ||
+      !dmalloc(&m.d_dN, nf * 2 * blk * m.tsize) ||
+      !dmalloc((void **)&m.d_tally, nf * g.ns * 8) ||
       !dmalloc((void **)&m.d_zm, nz * g.ns * 5 * 8) || !dmalloc((void **)&m.d_ze, nz * g.ns * 8) ||
       !dmalloc((void **)&m.d_stage, nk * 8) || !dmalloc((void **)&m.d_nbg, nz * 5 * 8) ||
       !dmalloc((void **)&m.d_q, nz * 5 * 8) ||
@@ -1945,12 +477,15 @@ btx_status launch_zones(size_t tsize, const ModelDev *d_models, const int2 *item
   if (n == 0) return BTX_OK;
   const void *zk = max_dirs > 256 ? (tsize == 8 ? (const void *)zone_kernel<double, 16> : (const void *)zone_kernel<float, 16>)
                                   : (tsize == 8 ? (const void *)zone_kernel<double, 4> : (const void *)zone_kernel<float, 4>);
+  btx_status st = raise_lds_limit(zk, zone_lds_bytes(max_rows));
+  if (st != BTX_OK) return st;
   void *args[] = { &d_models, &items, &parity };
   HIP_TRY(hipLaunchKernel(zk, dim3(n), dim3(256), args, zone_lds_bytes(max_rows), s));
   return BTX_OK;
 }
 
 int face_threads(const Model &m) { return ((m.shape.nch * m.g.ndir + 63) / 64) * 64; }
+
 
 size_t face_lds(const Model &m)
 {
@@ -2162,6 +697,7 @@ btx_status model_set_levels(Model &m, const int32_t *levels, int &parity, hipStr
   std::vector<int> lev(levels, levels + g.nz);
   for (int l : lev)
     if (l < 0 || l > 16) return fail(BTX_E_INVAL, "time levels must be in 0..16");
+
   const int lmax = *std::max_element(lev.begin(), lev.end());
   std::vector<unsigned char> l8(lev.begin(), lev.end());
   std::vector<std::pair<int, int>> fs, zs;

@@ -1137,6 +1137,21 @@ int orc_face_debug(orc_ctx *c, int fid, double dt, double *f_lw, double *flux_lw
 }
 
 
+/* Geometry of one face, for the pins: zones[2] = the zones on its L and R
+ * sides (-1 for a ghost side), info[3] = axis, area, active. */
+int orc_face_geom(const orc_ctx *c, int fid, int *zones, double *info)
+{
+  if (!c || fid < 0 || fid >= c->nf) return 1;
+  face_t F;
+  get_face(c, fid, &F);
+  zones[0] = F.active && F.L.kind == SIDE_ZONE ? F.L.z : -1;
+  zones[1] = F.active && F.R.kind == SIDE_ZONE ? F.R.z : -1;
+  info[0] = F.axis;
+  info[1] = F.active ? F.area : 0.0;
+  info[2] = F.active;
+  return 0;
+}
+
 /* ------------------------------------------------------------- moments */
 
 /* Moments of Sec. 4.1/4.2 per zone and species (the 1/h^3 normalisation is

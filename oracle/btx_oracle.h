@@ -87,6 +87,10 @@ int orc_geometry(const orc_ctx *c, double *vol, double *r_c, double *theta_c);
 int orc_face_debug(orc_ctx *c, int fid, double dt, double *f_lw, double *flux_lw,
                    double *dN, double *info);
 
+/* geometry of face fid: zones[2] on its L and R sides (-1: ghost or
+ * inactive), info[3] = axis, area, active (1) */
+int orc_face_geom(const orc_ctx *c, int fid, int *zones, double *info);
+
 /* building blocks, exposed for the pins.  A frame is packed as
  * {v_r, v_theta, v_phi, alpha, psi, theta, phi}. */
 void orc_chain(const double *S, const double *D, int axis, int rotate,

@@ -69,6 +69,7 @@ def lib():
         L.orc_n_faces.argtypes = [C.c_void_p]
         L.orc_geometry.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.orc_face_debug.argtypes = [C.c_void_p, C.c_int, C.c_double, _dp, _dp, _dp, _dp]
+        L.orc_face_geom.argtypes = [C.c_void_p, C.c_int, _ip, _dp]
         L.orc_chain.argtypes = [_dp, _dp, C.c_int, C.c_int, _dp, _dp]
         L.orc_chain.restype = None
         L.orc_remap_block.argtypes = [C.c_void_p, _dp, _dp, C.c_int, C.c_int, C.c_int, C.c_int,
@@ -226,6 +227,13 @@ class Oracle:
         vol, rc, thc = np.zeros(nz), np.zeros(nz), np.zeros(nz)
         lib().orc_geometry(self.ctx, _p(vol), _p(rc), _p(thc))
         return vol, rc, thc
+
+    def face_geom(self, fid):
+        """(zone on the L side, zone on the R side (-1: ghost or inactive), axis, area, active)"""
+        z = np.zeros(2, dtype=np.int32)
+        info = np.zeros(3)
+        assert lib().orc_face_geom(self.ctx, fid, z.ctypes.data_as(_ip), _p(info)) == 0
+        return int(z[0]), int(z[1]), int(info[0]), float(info[1]), bool(info[2])
 
     def face_debug(self, fid, dt):
         blk = self.shape[1:]

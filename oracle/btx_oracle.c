@@ -379,10 +379,13 @@ orc_ctx *orc_create(const orc_desc *d)
   if (c->geom == ORC_GEOM_AXISYM2D) memcpy(c->th_e, d->theta_edges, sizeof(double) * (nth + 1));
   else { c->th_e[0] = 0.0; c->th_e[1] = PI; }
   c->dphi = d->dphi;
-  /* Reading: the 1D column is one zone at the equator whose theta and phi
-   * widths are equal and make the lateral area of the outermost zone match
-   * its radial area: delta = (r_N - r_{N-1}) / r_N. */
-  c->delta = (c->r_e[c->nr] - c->r_e[c->nr - 1]) / c->r_e[c->nr];
+  /* Reading: the 1D column is one zone at the equator with equal theta and
+   * phi widths delta.  Sec. 3.3.4 leaves the width free and recommends
+   * faces of similar area; a column grid takes delta = dphi when given
+   * (> 0), else the width that makes the lateral area of the outermost zone
+   * match its radial area: delta = (r_N - r_{N-1}) / r_N. */
+  c->delta = (c->geom == ORC_GEOM_COLUMN && d->dphi > 0.0) ? d->dphi
+                                                           : (c->r_e[c->nr] - c->r_e[c->nr - 1]) / c->r_e[c->nr];
   c->e_e = (double *)malloc(sizeof(double) * (c->ne + 1));
   memcpy(c->e_e, d->eps_edges, sizeof(double) * (c->ne + 1));
   /* momentum grid (Sec. 3.1).  Reading: group centres are geometric means of

@@ -32,7 +32,8 @@ typedef struct {
   int geometry, phi_rule, inner_bc, outer_bc;
   const double *r_edges;     /* n_r+1 ascending (z edges in planar geometry)   */
   const double *theta_edges; /* n_theta+1 in 2D, spanning [0, pi]; unused else  */
-  double dphi;               /* 2D wedge width in phi; unused else             */
+  double dphi;               /* 2D wedge width in phi; column: its theta and phi
+                                width (0: (r_N - r_{N-1}) / r_N); unused else    */
   const double *eps_edges;   /* n_eps+1 ascending                              */
   const double *mu_nodes;    /* n_mu ascending quadrature nodes                */
   const double *mu_weights;  /* n_mu weights, summing to 2                     */

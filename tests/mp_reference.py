@@ -5,8 +5,9 @@ Python, sharing no code with it.  It serves only to show that the FP64
 reference's result is its arithmetic's rounding of the same computation.
 
 Scope: the 2D axisymmetric wedge (theta over [0, pi], one phi zone), a
-specular inner boundary and an outflow outer boundary, Gauss-Legendre mu
-nodes, the linear Phi split, any number of species and groups.
+specular inner boundary and an outflow outer boundary, Gauss-Legendre or
+Gauss-Lobatto mu nodes, the linear or the direction-preserving Phi split, any
+number of species and groups.
 """
 
 import mpmath as mp
@@ -40,6 +41,42 @@ def legendre(n):
         ws.append(2 / ((1 - x * x) * dp * dp))
     order = sorted(range(n), key=lambda i: xs[i])
     return [xs[i] for i in order], [ws[i] for i in order]
+
+
+def lobatto(n):
+    """Gauss-Lobatto nodes (-1, +1 and the zeros of the derivative of P_{n-1},
+    found by Newton's method from Chebyshev-Gauss-Lobatto guesses) and weights
+    2 / (n (n-1) P_{n-1}(x)^2)"""
+    m = n - 1
+
+    def P_and_dP(x):
+        p0, p1 = mp.mpf(1), x
+        for k in range(2, m + 1):
+            p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+        # P_m'(x) = m (x P_m - P_{m-1}) / (x^2 - 1), and P_m'' from the Legendre equation
+        d1 = m * (x * p1 - p0) / (x * x - 1)
+        d2 = (2 * x * d1 - m * (m + 1) * p1) / (1 - x * x)
+        return p1, d1, d2
+
+    xs = [mp.mpf(-1)]
+    for k in range(1, m):
+        x = -mp.cos(PI * k / m)
+        for _ in range(100):
+            _, d1, d2 = P_and_dP(x)
+            dx = d1 / d2
+            x -= dx
+            if abs(dx) < mp.mpf(10) ** -45:
+                break
+        xs.append(x)
+    xs.append(mp.mpf(1))
+    xs.sort()
+    ws = []
+    for x in xs:
+        p0, p1 = mp.mpf(1), x
+        for k in range(2, m + 1):
+            p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+        ws.append(mp.mpf(2) / (n * (n - 1) * p1 * p1))
+    return xs, ws
 
 
 def point(r, t, p):
@@ -125,7 +162,8 @@ class Grid:
         e = [mpf(x) for x in w.eps_edges]
         self.eps = [mp.sqrt(e[i] * e[i + 1]) for i in range(self.ne)]
         self.G = [(e[i + 1] ** 3 - e[i] ** 3) / 3 for i in range(self.ne)]
-        self.mu, wmu = legendre(self.nmu)
+        self.mu, wmu = lobatto(self.nmu) if w.mu_rule == "lobatto" else legendre(self.nmu)
+        self.phi_sin = w.phi_rule == 0        # Phi split keeping the direction (else linear)
         self.Phi = [(k + mp.mpf(1) / 2) * 2 * PI / self.nphi for k in range(self.nphi)]
         self.dOm, self.n = [], []
         for j in range(self.nmu):
@@ -275,7 +313,14 @@ class Grid:
             else:
                 dP = 2 * PI / nphi
                 kl = int(mp.floor(P / dP - mp.mpf(1) / 2))
-                wk = (P - (kl + mp.mpf(1) / 2) * dP) / dP
+                PL = (kl + mp.mpf(1) / 2) * dP
+                if self.phi_sin:
+                    # weights proportional to the sines of the angular distances to the
+                    # far node: the split keeps the direction of the transverse momentum
+                    a, b = mp.sin(PL + dP - P), mp.sin(P - PL)
+                    wk = b / (a + b)
+                else:
+                    wk = (P - PL) / dP
                 kL, kR = kl % nphi, (kl + 1) % nphi
             Wsd = S.psi ** 6 * self.u0(S, d) * self.dOm[d] if density else 1
             for i in range(ne):

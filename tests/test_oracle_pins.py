@@ -353,10 +353,12 @@ def test_sample_matches_full_step(oracle_mod):
 
 # --------------------------------------------------------- analytic tests
 def test_planar_diffusion_wave(oracle_mod):
-    """P-14 (Sec. 4.3, planar): Delta z = 0.01, kappa_s = 100, the exact
-    diffusion solution at t = 1 evolved to t = 2 (E = sqrt(k/t) exp(-3kz^2/4t),
-    F = z E/2t)."""
-    ks, dz = 100.0, 0.01
+    """P-14 (Sec. 4.3, planar): Delta z = 0.01, kappa_s = 100 (Pe = 1), the
+    exact diffusion solution at t = 1 (E = sqrt(k/t) exp(-3kz^2/4t),
+    F = z E/2t) evolved and sampled at t = 2, 3 and 5, as in the paper's planar
+    figure.  The paper reports excellent agreement; the bound is 1% of the
+    largest E and |F| at each sample."""
+    ks = 100.0
     n = 200
     w = W.planar(n_z=n, z_min=-1.0, z_max=1.0, n_mu=8, kappa_s=ks)
     o0 = oracle_mod.Oracle(w, state=False)
@@ -372,23 +374,23 @@ def test_planar_diffusion_wave(oracle_mod):
     w.f0 = f0[:, None, None, :].copy()
     o = oracle_mod.Oracle(w)
     dt = o.max_dt(0.4)
-    nsteps = int(round(1.0 / dt))
-    o.step(1.0 / nsteps, nsteps)
-    f = o.state()[:, 0, 0, :]
-    dOm = o.wmu * 2 * math.pi
-    E, F = f @ dOm, f @ (dOm * mu)
-    E2, F2 = EF(2.0)
-    assert np.max(np.abs(E - E2)) < 0.02 * E2.max()
-    assert np.max(np.abs(F - F2)) < 0.05 * np.abs(F2).max()
+    t = 1.0
+    for ts in (2.0, 3.0, 5.0):
+        nsteps = int(math.ceil((ts - t) / dt))
+        o.step((ts - t) / nsteps, nsteps)
+        t = ts
+        f = o.state()[:, 0, 0, :]
+        dOm = o.wmu * 2 * math.pi
+        E, F = f @ dOm, f @ (dOm * mu)
+        Ex, Fx = EF(ts)
+        assert np.max(np.abs(E - Ex)) < 0.01 * Ex.max(), ts
+        assert np.max(np.abs(F - Fx)) < 0.01 * np.abs(Fx).max(), ts
 
 
-@pytest.mark.slow
-def test_radiating_sphere(oracle_mod):
-    """P-13 (Sec. 4.1): homogeneous radiating sphere (kappa_a R = 10) on a
-    logarithmic column grid with Gauss-Lobatto mu cells, run to a stationary
-    state, against the exact H/J and K/J away from the centre and from the
-    zones on either side of the opacity jump."""
-    n_r, rmin, rmax, kap = 50, 0.02, 4.0, 10.0
+def _sphere_errors(oracle_mod, n_r, kap=10.0, rmin=0.02, rmax=4.0, radii=(0.5, 0.8, 1.2, 1.5, 2.0, 3.0)):
+    """stationary H/J and K/J of the radiating sphere minus the exact values at
+    the given radii (the numerical ratios interpolated linearly between zone
+    centres)"""
     w = W.radiating_sphere(n_r=n_r, n_eps=1, n_mu=9, n_phi=4, r_max=rmax, kappa=kap,
                            mu_rule="lobatto")
     w.r_edges = rmin * (rmax / rmin) ** (np.arange(n_r + 1) / n_r)
@@ -401,18 +403,34 @@ def test_radiating_sphere(oracle_mod):
     o.step(dt, int(7.0 / dt))
     zm, _ = o.moments()
     J, H, K = zm[:, 0, 1], zm[:, 0, 2], zm[:, 0, 3]
-    mu = np.linspace(-1, 1, 20001)
+    mu = np.linspace(-1, 1, 200001)
     mu = 0.5 * (mu[1:] + mu[:-1])
-    for r in [0.5, 0.8, 1.2, 1.5, 2.0, 3.0]:
-        a = int(np.argmin(abs(rc - r)))
-        x = rc[a]
+    eh, ek = [], []
+    for x in radii:
         g = np.sqrt(np.maximum(0, 1 - x ** 2 * (1 - mu ** 2)))
         # path length through the sphere; inside: x mu + R g (Reading of the garbled formula)
         s = x * mu + g if x < 1 else np.where(mu >= np.sqrt(1 - 1 / x ** 2), 2 * g, 0.0)
         fe = 1 - np.exp(-kap * s)
         hj, kj = np.mean(fe * mu) / np.mean(fe), np.mean(fe * mu * mu) / np.mean(fe)
-        assert abs(H[a] / J[a] - hj) < 0.03, (x, H[a] / J[a], hj)
-        assert abs(K[a] / J[a] - kj) < 0.03, (x, K[a] / J[a], kj)
+        eh.append(np.interp(x, rc, H / J) - hj)
+        ek.append(np.interp(x, rc, K / J) - kj)
+    return np.asarray(eh), np.asarray(ek)
+
+
+@pytest.mark.slow
+def test_radiating_sphere(oracle_mod):
+    """P-13 (Sec. 4.1): homogeneous radiating sphere (kappa_a R = 10) on a
+    logarithmic column grid with Gauss-Lobatto mu cells, run to a stationary
+    state, against the exact H/J and K/J inside and outside the sphere.  The
+    error falls with the radial resolution (40 -> 80 zones: rms of H/J from
+    about 0.1 to 0.006), and at 80 zones every sampled ratio is within 0.03."""
+    rms = {}
+    for n_r in (40, 80):
+        eh, ek = _sphere_errors(oracle_mod, n_r)
+        rms[n_r] = (np.sqrt(np.mean(eh ** 2)), np.sqrt(np.mean(ek ** 2)))
+        if n_r == 80:
+            assert np.max(np.abs(eh)) < 0.03 and np.max(np.abs(ek)) < 0.03, (eh, ek)
+    assert rms[80][0] < 0.5 * rms[40][0] and rms[80][1] < rms[40][1], rms
 
 
 def _beam(n_r=60, n_mu=6, r_in=1.0, r_out=3.0):
@@ -899,6 +917,29 @@ def test_mp_brute_force(oracle_mod):
     w.mu_rule = "legendre"
     rng = np.random.default_rng(4)
     w.f0 = rng.random(w.f0.shape)
+    w.v_theta = 0.1 * rng.standard_normal(w.n_zones)
+    w.v_r = w.v_r + 0.1 * rng.standard_normal(w.n_zones)
+    w.kappa_a = w.kappa_a * 10 ** rng.uniform(-2, 1, w.kappa_a.shape)
+    o = oracle_mod.Oracle(w)
+    dt = o.max_dt(0.4)
+    ref = mp_reference.run(w, dt, 2)
+    o.step(dt, 2)
+    ref = np.array([[[[float(x) for x in row] for row in blk] for blk in zb] for zb in ref])
+    assert np.max(np.abs(o.state() - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+def test_mp_lobatto_direction_preserving(oracle_mod):
+    """P-17 with Gauss-Lobatto mu nodes (mu = +-1 included, so the pole-label
+    rule of the Phi split is exercised) and the direction-preserving Phi split
+    (R-1) over 3 x 4 directions: two steps of the 50-digit second reference
+    agree with the FP64 reference to 1e-14 of the largest value."""
+    import mp_reference
+    w = W.shock_2d(n_r=3, n_theta=2, n_eps=2, n_mu=3, n_phi=4, precision=W.PREC_FP64)
+    w.n_species = 1
+    w.kappa_a, w.kappa_s, w.f_eq = w.kappa_a[:, :1], w.kappa_s[:, :1], w.f_eq[:, :1]
+    assert w.phi_rule == W.PHI_SIN and w.mu_rule == "lobatto"
+    rng = np.random.default_rng(7)
+    w.f0 = rng.random((w.n_zones, 1, w.n_eps, w.n_dir))
     w.v_theta = 0.1 * rng.standard_normal(w.n_zones)
     w.v_r = w.v_r + 0.1 * rng.standard_normal(w.n_zones)
     w.kappa_a = w.kappa_a * 10 ** rng.uniform(-2, 1, w.kappa_a.shape)

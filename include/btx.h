@@ -91,7 +91,11 @@ typedef struct {
   const double *r_edges;     /* n_r+1 ascending, >= 0 (z edges in slab geometry)    */
   const double *theta_edges; /* 2D: n_theta+1 ascending from 0 to pi (pi/2 for a
                                 disk boundary); else ignored                        */
-  double dphi;               /* 2D: wedge width in phi (> 0); else ignored          */
+  double dphi;               /* 2D: wedge width in phi (> 0).  Column: its theta and
+                                phi width, free by Sec. 3.3.4 (0: the width at which
+                                the outermost zone's lateral and radial faces have
+                                equal area, (r_N - r_{N-1}) / r_N; at most pi/2).
+                                Slab: ignored                                       */
   const double *eps_edges;   /* n_eps+1 ascending, logarithmically spaced (> 0)     */
   double fp64_threshold;     /* mixed mode: the collision solve of a (zone, species,
                                 group) runs in FP64 where dt_c (ka + ks) exceeds it;

@@ -251,6 +251,8 @@ btx_status validate_desc(const btx_grid_desc *d)
       if (!(d->theta_edges[b + 1] > d->theta_edges[b])) return fail(BTX_E_INVAL, "theta edges must ascend");
     if (!(d->dphi > 0.0) || d->dphi > kPi) return fail(BTX_E_INVAL, "dphi must be in (0, pi]");
   }
+  if (d->geometry == BTX_GEOM_COLUMN && !(d->dphi >= 0.0 && d->dphi <= 0.5 * kPi))
+    return fail(BTX_E_INVAL, "a column's width dphi must be in [0, pi/2]");
   return BTX_OK;
 }
 

@@ -140,8 +140,10 @@ std::string build_grid(Grid &g)
       g.nvec[3 * d + 2] = st * std::sin(g.Phi[k]);
     }
   }
-  // column width: the outermost zone's lateral faces match its radial face
-  g.delta = (g.r_e[g.nr] - g.r_e[g.nr - 1]) / g.r_e[g.nr];
+  // column width: free (Sec. 3.3.4 recommends faces of similar area); the
+  // grid's dphi when given, else the width at which the outermost zone's
+  // lateral faces match its radial face
+  g.delta = g.geom == 0 && g.dphi > 0.0 ? g.dphi : (g.r_e[g.nr] - g.r_e[g.nr - 1]) / g.r_e[g.nr];
   const bool planar = g.geom == 2, twod = g.geom == 1;
   auto row_angles = [&](int b, double &t0, double &t1, double &p0, double &p1) {
     if (twod) { t0 = g.th_e[b]; t1 = g.th_e[b + 1]; p0 = -0.5 * g.dphi; p1 = 0.5 * g.dphi; }

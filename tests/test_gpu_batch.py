@@ -49,6 +49,13 @@ def _batch(btx, ws, precision, **kw):
     return b
 
 
+def _single_shape(w):
+    """the face shape a single context takes (8 work items per direction, the
+    fewest groups per item of 3, 4, 5, 6, 8 covering the groups and three
+    guard rows)"""
+    return 8, min(c for c in (3, 4, 5, 6, 8) if 8 * c >= w.n_eps + 3)
+
+
 def _moments_close(zg, zr, tol):
     for k in (0, 1):
         mask = np.abs(zr[..., 1]) > 1e-8 * np.abs(zr[..., 1]).max()
@@ -94,7 +101,7 @@ def test_batch_mixed_matches_single_contexts(oracle_mod):
         nch, ce = b.shape(m)
         err = float(np.max(np.abs(batched - single)) / np.max(np.abs(single)))
         _say(f"[gpu]   model {m}: shape {nch}x{ce}, batch vs single {err:.3e}")
-        if nch == 8:                       # the single context's own shape: same arithmetic
+        if (nch, ce) == _single_shape(w):  # the single context's own shape: same arithmetic
             assert err == 0.0
         else:
             assert err <= 1e-5
@@ -107,12 +114,13 @@ def test_batch_mixed_matches_single_contexts(oracle_mod):
     b.close()
 
 
-def test_batch_graph_replays_match_direct_launches():
+def test_batch_graph_replays_match_direct_launches(tmp_path):
     btx = _btx()
     ws = _models(4, 0.04, W.PREC_MIXED, 23)
     _say("[gpu] batch graph replays vs direct launches")
-    a = _batch(btx, ws, W.PREC_MIXED)
-    d = _batch(btx, ws, W.PREC_MIXED)
+    cache = tmp_path / "tune.json"             # the second batch adopts the first one's tuning
+    a = _batch(btx, ws, W.PREC_MIXED, tune_cache=cache)
+    d = _batch(btx, ws, W.PREC_MIXED, tune_cache=cache)
     d.use_graph(False)
     dts = [a.max_dt(m, 0.4) for m in range(len(ws))]
     for rep in range(4):                    # one step per call, host reads in between
@@ -164,7 +172,7 @@ def test_full_batch_100_steps(oracle_mod, tmp_path):
         c.set_state(w.f0)
         c.step(dts[m], 100)
         single = c.get_state()
-        if shapes[m][0] == 8:
+        if tuple(shapes[m]) == _single_shape(w):
             assert np.array_equal(b.get_state(m), single), m
         else:
             zs, _ = c.moments()
@@ -184,8 +192,9 @@ def test_full_batch_100_steps(oracle_mod, tmp_path):
 def test_batch_time_levels(oracle_mod):
     """Time levels in a batch: models with different highest levels (2, 1 and
     none) step 2^L substeps of their own dt per batch step; each model's state
-    equals, bit for bit, a single context stepping the same levels as many
-    level-stepped steps, and the first matches the reference (1e-12)."""
+    equals a single context stepping the same levels as many level-stepped
+    steps (bit for bit where the batch kept the context's face shape, else to
+    1e-12), and the first matches the reference (1e-12)."""
     import torch
     btx = _btx()
     ws = _models(3, 0.03, W.PREC_FP64, 31)
@@ -206,7 +215,11 @@ def test_batch_time_levels(oracle_mod):
         if levs[m] is not None:
             c.set_time_levels(levs[m])
         c.step(dts[m], 2 * 2 ** (L - lm))
-        assert np.array_equal(b.get_state(m), c.get_state()), m
+        got, single = b.get_state(m), c.get_state()
+        if tuple(b.shape(m)) == _single_shape(w):   # the same shape: the same arithmetic
+            assert np.array_equal(got, single), m
+        else:                                        # angle sums in another order
+            assert np.max(np.abs(got - single)) <= 1e-12 * np.max(np.abs(single)), m
         c.close()
     o = oracle_mod.Oracle(ws[0])
     o.set_levels(levs[0])

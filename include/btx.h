@@ -73,7 +73,7 @@ typedef enum { BTX_PHI_DIRECTION = 0, BTX_PHI_LINEAR = 1 } btx_phi_rule;
 /* radial boundary ghosts: specular mirror (mu -> -mu), outflow (empty, zero
  * opacity at the face), equilibrium (the zone's own equilibrium occupation) */
 typedef enum { BTX_BC_REFLECT = 0, BTX_BC_OUTFLOW = 1, BTX_BC_EQUIL = 2 } btx_bc;
-/* theta range of the 2D grid (Sec. 4.4): [0, pi] with the polar axis at both
+/* theta range of the 2D grid (Sec. 4.5.2): [0, pi] with the polar axis at both
  * ends, or [0, pi/2] with the equatorial plane a boundary that is an
  * optically thick disk inside disk_radius (ghost: the isotropic equilibrium
  * occupation of the adjacent zone) and empty outside it (outflow ghost).  The
@@ -125,7 +125,7 @@ typedef struct btx_ctx btx_ctx;
  * on the host, allocate the device state.  hip_stream: a hipStream_t or NULL. */
 btx_status btx_create(const btx_grid_desc *desc, int hip_device, void *hip_stream,
                       btx_ctx **out);
-/* Fluid velocity, metric (conformally flat, zero shift, Sec. 2.4) and
+/* Fluid velocity, metric (conformally flat, zero shift, Sec. 3.1) and
  * opacities (Eq. sourceterms).  Static until the next call. */
 btx_status btx_set_background(btx_ctx *ctx, const btx_background *bg);
 /* Evolving background (Sec. 3.2, the remap applied as time advances; the
@@ -177,7 +177,7 @@ btx_status btx_moments_device(btx_ctx *ctx, double *zone_moments, double *totals
  * phi) directions (Q_M).  No 1/h^3.  Zero before the first step.  Computed
  * in FP64 by the zone update; synchronises the stream. */
 btx_status btx_source_terms(btx_ctx *ctx, double *q);
-/* Local time stepping (the saving Sec. 6 proposes over the global step set
+/* Local time stepping (the saving Sec. 5 proposes over the global step set
  * by the smallest zones; the paper gives no scheme, this is the library's).
  * btx_time_levels proposes a level per zone: zone z may take 2^l global
  * steps at once when 2^l times the smallest Courant length is within its own

@@ -554,7 +554,7 @@ static double centre_dist(double r1, double t1, double p1, double r2, double t2,
   return sqrt(sq(A[0] - B[0]) + sq(A[1] - B[1]) + sq(A[2] - B[2]));
 }
 
-/* Boundary ghost next to real zone z on the radial axis (Sec. 3.3.5).
+/* Boundary ghost next to real zone z on the radial axis (Sec. 3.3.4).
  * Reading: the inner boundary is a specular mirror (mu -> -mu, radial fluid
  * velocity reversed); the outer boundary is outflow (f = 0, zero opacity at the
  * face); "equilibrium" ghosts (tests only) hold the zone's own equilibrium. */
@@ -570,7 +570,7 @@ static side_t ghost_side(const orc_ctx *c, int z, int bc)
 }
 
 /* Ghost beyond the equatorial boundary of a theta-disk grid, next to zone z
- * of the last theta row (Sec. 4.4, radiating disk).  Reading: it sits at the
+ * of the last theta row (Sec. 4.5.2, radiating disk).  Reading: it sits at the
  * mirror position pi - theta_z and carries the zone's background expressed
  * in its own basis; inside the disk radius it holds the isotropic
  * equilibrium of the zone (an optically thick disk), outside it is empty
@@ -826,7 +826,7 @@ static void face_opacity(const orc_ctx *c, const face_t *F, int s, int i,
 
 /* Eulerian direction of comoving bin d of frame X, expressed in the basis of
  * frame s, and the corresponding number speed through a face of axis ax:
- * alpha_s psi_s^4 uhat^n (flux integral of Sec. 2.4 with zero shift). */
+ * alpha_s psi_s^4 uhat^n (flux integral of Sec. 3.1 with zero shift). */
 static double donor_speed(const orc_ctx *c, const frame_t *X, const frame_t *s, int ax,
                           int rot, int d)
 {
@@ -1270,7 +1270,7 @@ static double courant_length(const orc_ctx *c, int z)
   return m;
 }
 
-/* Time levels for local time stepping (Sec. 6 names it as the way to stop
+/* Time levels for local time stepping (Sec. 5 names it as the way to stop
  * the small central zones from setting every zone's step; the paper gives no
  * scheme).  Reading: zone z steps with 2^l dt0, l = floor(log2(L_z / L_min))
  * of its Courant length L_z, capped at max_level, then lowered until zones

@@ -653,7 +653,7 @@ std::vector<double> courant_lengths(const btx::Grid &g)
   return len;
 }
 
-// Time levels (local time stepping, Sec. 6): zone z takes 2^l global steps
+// Time levels (local time stepping, Sec. 5): zone z takes 2^l global steps
 // at once, l the largest with 2^l times the smallest Courant length within
 // its own (at most max_level); then zones that share a face are brought to
 // at most one level apart by lowering the coarser.

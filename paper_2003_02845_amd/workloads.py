@@ -167,7 +167,7 @@ def radiating_sphere(n_r=64, n_eps=8, n_mu=16, n_phi=4, r_max=3.0, R=1.0, kappa=
 
 def radiating_sphere_2d(n_r=100, n_theta=32, n_mu=16, n_phi=8, r_min=0.02, r_max=4.0, R=1.0,
                         kappa=10.0, mu_rule="lobatto"):
-    """The homogeneous radiating sphere on the axisymmetric grid (Sec. 4.4):
+    """The homogeneous radiating sphere on the axisymmetric grid (Sec. 4.5.1):
     one group, f_eq = 1 and kappa_a = kappa inside R, vacuum outside, static
     flat background, logarithmic radial zones from r_min (specular inner
     boundary), uniform theta zones over [0, pi]."""

@@ -1,4 +1,4 @@
-"""Multi-dimensional end-to-end checks on the GPU path (Sec. 4.4, tests in
+"""Multi-dimensional end-to-end checks on the GPU path (Sec. 4.5, tests in
 axisymmetry).
 
 Radiating disk: theta over [0, pi/2] with the equatorial disk boundary; a

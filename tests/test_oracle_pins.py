@@ -640,7 +640,7 @@ def test_source_terms_balance_the_step(oracle_mod):
 
 # ------------------------------------------------------- radiating disk
 def _disk_exact(x, z, R=1.0, n_r=400, n_phi=512):
-    """mean intensity above an isotropic f = 1 disk of radius R (Sec. 4.4):
+    """mean intensity above an isotropic f = 1 disk of radius R (Sec. 4.5.2):
     (1/4pi) times the solid angle of the disk seen from (x, z), by Gauss
     quadrature in r and the periodic midpoint rule in phi"""
     xr, wr = np.polynomial.legendre.leggauss(n_r)
@@ -677,7 +677,7 @@ def _disk_run(oracle_mod, n_phi):
 
 
 def test_radiating_disk(oracle_mod):
-    """P-21 (Sec. 4.4, radiating disk): the equatorial disk boundary mode.  A
+    """P-21 (Sec. 4.5.2, radiating disk): the equatorial disk boundary mode.  A
     thick f = 1 disk of radius 1 radiates into vacuum; in the stationary state
     the mean intensity approaches the exact solid-angle integral, away from
     the polar axis rows (the paper's artefact) and the plane itself.  The
@@ -710,7 +710,7 @@ def _turned(w, n_phi_zones):
 
 
 def test_3d_symmetric_equals_axisymmetric(oracle_mod):
-    """P-22 (Sec. 4.4: axisymmetric results carry over to 3D with the same
+    """P-22 (Sec. 4.5: axisymmetric results carry over to 3D with the same
     dphi): n copies of the wedge around the axis, with data independent of
     phi, step exactly like the axisymmetric wedge, bit for bit"""
     w2 = _shock_small()
@@ -805,7 +805,7 @@ def _lts_case():
 
 
 def test_time_levels_rules(oracle_mod):
-    """P-26 (local time stepping, a reading of Sec. 6): every zone's step
+    """P-26 (local time stepping, a reading of Sec. 5): every zone's step
     2^l dt0 stays within its own Courant limit (cfl times its Courant length);
     zones sharing a face are at most one level apart; levels rise outward on
     the logarithmic radial grid; all levels 0 is the global step, bit for bit."""

@@ -186,6 +186,7 @@ struct Model {
   FaceShape shape;
   double *d_mu = nullptr, *d_Phi = nullptr, *d_dOm = nullptr, *d_nvec = nullptr, *d_G = nullptr,
          *d_eps = nullptr, *d_vol = nullptr;
+  double *d_rconst = nullptr;        // q^k (k = -128 .. 128), cos and sin of the Phi nodes
   double *d_vr = nullptr, *d_vth = nullptr, *d_vph = nullptr, *d_alp = nullptr, *d_psi = nullptr;
   void *d_ka = nullptr, *d_ks = nullptr, *d_feq = nullptr, *d_f[2] = { nullptr, nullptr }, *d_dN = nullptr;
   char *d_tabs = nullptr;
@@ -258,7 +259,7 @@ btx_status validate_desc(const btx_grid_desc *d)
 
 void model_free(Model &m)
 {
-  void *ptrs[] = { m.d_mu, m.d_Phi, m.d_dOm, m.d_nvec, m.d_G, m.d_eps, m.d_vol, m.d_vr, m.d_vth, m.d_vph,
+  void *ptrs[] = { m.d_rconst, m.d_mu, m.d_Phi, m.d_dOm, m.d_nvec, m.d_G, m.d_eps, m.d_vol, m.d_vr, m.d_vth, m.d_vph,
                    m.d_alp, m.d_psi, m.d_ka, m.d_ks, m.d_feq, m.d_f[0], m.d_f[1], m.d_dN, m.d_tally,
                    m.d_zm, m.d_ze, m.d_stage, m.d_faces, m.d_zf, m.d_tabs, m.d_aux, m.d_fitems, m.d_zitems,
                    m.d_nbg, m.d_q, m.d_zlev, m.d_fitems_lts, m.d_zitems_lts, m.d_bface };
@@ -307,7 +308,7 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
   const size_t flds = face_lds_bytes(g.ndir, g.ns, m.shape.nch, m.shape.ce, m.tsize, m.shape.gtab);
   if (flds > lds_cap)
     return fail(BTX_E_UNSUPPORTED, "face workgroup needs " + std::to_string(flds) + " B of LDS");
-  m.tab_lds = (m.shape.gtab ? 0 : kTables * tab_stride(g.ndir, m.tsize)) + align16(5 * sizeof(Frame)) +
+  m.tab_lds = (m.shape.gtab ? 0 : kTables * tab_stride(g.ndir, m.tsize)) + align16(5 * sizeof(FrameP)) +
               align16(scratch_bytes(g.ndir, m.tsize, m.shape.gtab ? 1 : 4)) + align16((size_t)g.nmu * 8);
   if (m.tab_lds > lds_cap) return fail(BTX_E_UNSUPPORTED, "table build needs too much LDS");
   const size_t nz = g.nz, blk = (size_t)g.ns * g.ne * g.ndir, nk = nz * g.ns * g.ne, nf = g.faces.size();
@@ -318,6 +319,15 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
 #define TRY(x) do { st = (x); if (st != BTX_OK) { model_free(m); return st; } } while (0)
   TRY(upload(&m.d_mu, g.mu.data(), g.mu.size()));
   TRY(upload(&m.d_Phi, g.Phi.data(), g.Phi.size()));
+  {
+    std::vector<double> rc(257 + 2 * g.nphi);
+    for (int k = -128; k <= 128; ++k) rc[k + 128] = std::exp(k * g.lnq);
+    for (int k = 0; k < g.nphi; ++k) {
+      rc[257 + k] = std::cos(g.Phi[k]);
+      rc[257 + g.nphi + k] = std::sin(g.Phi[k]);
+    }
+    TRY(upload(&m.d_rconst, rc.data(), rc.size()));
+  }
   TRY(upload(&m.d_dOm, g.dOm.data(), g.dOm.size()));
   TRY(upload(&m.d_nvec, g.nvec.data(), g.nvec.size()));
   TRY(upload(&m.d_G, g.G.data(), g.G.size()));
@@ -376,6 +386,7 @@ ModelDev model_dev(const Model &m, double dt)
   d.mu = m.d_mu; d.Phi = m.d_Phi; d.dOm = m.d_dOm; d.nvec = m.d_nvec; d.G = m.d_G;
   d.eps = m.d_eps; d.vol = m.d_vol;
   d.vr = m.d_vr; d.vth = m.d_vth; d.vph = m.d_vph; d.alp = m.d_alp; d.psi = m.d_psi;
+  d.qpow = m.d_rconst; d.cphi = m.d_rconst + 257; d.sphi = m.d_rconst + 257 + g.nphi;
   M.faces = m.d_faces;
   M.zf = m.d_zf;
   M.tabs = m.d_tabs;
@@ -452,7 +463,10 @@ btx_status build_tables(const Model &m, const ModelDev *d_models, hipStream_t s)
   if (st != BTX_OK) return st;
   const int2 *items = m.d_fitems;
   void *args[] = { &d_models, &items };
-  HIP_TRY(hipLaunchKernel(tk, dim3(nf), dim3(256), args, m.tab_lds, s));
+  // one thread per (table, source direction) of a round, at least one wave per table of a round
+  const int tpr = m.shape.gtab ? 1 : 4;
+  const int threads = std::min(512, std::max(256, ((tpr * m.g.ndir + 63) / 64) * 64));
+  HIP_TRY(hipLaunchKernel(tk, dim3(nf), dim3(threads), args, m.tab_lds, s));
   return BTX_OK;
 }
 

@@ -56,6 +56,8 @@ struct DevGrid {
   double om[4];                     // sum over directions of dOmega and dOmega n (r, theta, phi)
   const double *mu, *Phi, *dOm, *nvec, *G, *eps, *vol;
   const double *vr, *vth, *vph, *alp, *psi;
+  const double *qpow;               // q^k for k = -128 .. 128 (index k + 128)
+  const double *cphi, *sphi;        // cos and sin of the Phi nodes
 };
 
 struct Frame {
@@ -110,6 +112,7 @@ __device__ __forceinline__ DevGrid global_grid(const DevGrid &src)
   g.vol = as_global(g.vol); g.vr = as_global(g.vr); g.vth = as_global(g.vth);
   g.vph = as_global(g.vph);
   g.alp = as_global(g.alp); g.psi = as_global(g.psi);
+  g.qpow = as_global(g.qpow); g.cphi = as_global(g.cphi); g.sphi = as_global(g.sphi);
   return g;
 }
 
@@ -156,15 +159,34 @@ __device__ void change_basis(double ta, double pa, double tb, double pb, const d
   for (int r = 0; r < 3; ++r) y[r] = B[0][r] * c[0] + B[1][r] * c[1] + B[2][r] * c[2];
 }
 
-// Lorentz boost by fluid velocity v (paper Sec. 3.2.2)
-__device__ void lorentz(const double v[3], const double u[4], double o[4])
+// A frame with what the chain needs of it evaluated once per frame rather
+// than once per direction: the Lorentz-factor terms of its velocity and its
+// orthonormal basis.
+struct FrameP {
+  Frame f;
+  double gam, kv;              // 1/sqrt(1 - v^2), gam^2/(gam + 1)
+  double B[3][3];              // basis_cols(th, ph)
+};
+
+__device__ inline FrameP prep_frame(const Frame &f)
 {
-  double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-  double gam = 1.0 / sqrt(1.0 - v2);
-  double kv = gam * gam / (gam + 1.0);
-  double vu = v[0] * u[1] + v[1] * u[2] + v[2] * u[3];
-  double a = kv * vu + gam * u[0];
-  o[0] = gam * (u[0] + vu);
+  FrameP p;
+  p.f = f;
+  const double v2 = f.v[0] * f.v[0] + f.v[1] * f.v[1] + f.v[2] * f.v[2];
+  p.gam = 1.0 / sqrt(1.0 - v2);
+  p.kv = p.gam * p.gam / (p.gam + 1.0);
+  basis_cols(f.th, f.ph, p.B);
+  return p;
+}
+
+// Lorentz boost by the frame's fluid velocity v (sgn -1: by -v) (paper
+// Sec. 3.2.2), with gam and kv of the frame
+__device__ inline void lorentz_p(const FrameP &F, double sgn, const double u[4], double o[4])
+{
+  const double v[3] = { sgn * F.f.v[0], sgn * F.f.v[1], sgn * F.f.v[2] };
+  const double vu = v[0] * u[1] + v[1] * u[2] + v[2] * u[3];
+  const double a = F.kv * vu + F.gam * u[0];
+  o[0] = F.gam * (u[0] + vu);
   o[1] = u[1] + a * v[0];
   o[2] = u[2] + a * v[1];
   o[3] = u[3] + a * v[2];
@@ -176,10 +198,11 @@ __device__ void lorentz(const double v[3], const double u[4], double o[4])
 // axis < 0: the remap forward in time at a fixed place, where the covariant
 // spatial momentum is kept and the covariant energy follows from the null
 // condition of the new metric.
-__device__ void frame_chain(const Frame &S, const Frame &D, int axis, bool rot, const double u[4], double o[4])
+__device__ void frame_chain_p(const FrameP &SP, const FrameP &DP, int axis, bool rot, const double u[4], double o[4])
 {
+  const Frame &S = SP.f, &D = DP.f;
   double e[4];
-  lorentz(S.v, u, e);
+  lorentz_p(SP, 1.0, u, e);
   double u0 = -S.alpha * e[0];                       // covariant time component
   double p2 = S.psi * S.psi;
   double uc[3] = { p2 * e[1], p2 * e[2], p2 * e[3] };  // covariant spatial components
@@ -199,12 +222,16 @@ __device__ void frame_chain(const Frame &S, const Frame &D, int axis, bool rot, 
     }
   }
   double ud[3];
-  if (rot) change_basis(S.th, S.ph, D.th, D.ph, uc, ud);
-  else { ud[0] = uc[0]; ud[1] = uc[1]; ud[2] = uc[2]; }
+  if (rot && !(S.th == D.th && S.ph == D.ph)) {        // change of basis, as change_basis
+    double c[3];
+    for (int r = 0; r < 3; ++r) c[r] = SP.B[r][0] * uc[0] + SP.B[r][1] * uc[1] + SP.B[r][2] * uc[2];
+    for (int r = 0; r < 3; ++r) ud[r] = DP.B[0][r] * c[0] + DP.B[1][r] * c[1] + DP.B[2][r] * c[2];
+  } else {
+    ud[0] = uc[0]; ud[1] = uc[1]; ud[2] = uc[2];
+  }
   double dp2 = D.psi * D.psi;
   double eD[4] = { -u0 / D.alpha, ud[0] / dp2, ud[1] / dp2, ud[2] / dp2 };
-  double mv[3] = { -D.v[0], -D.v[1], -D.v[2] };
-  lorentz(mv, eD, o);
+  lorentz_p(DP, -1.0, eD, o);
 }
 
 __device__ inline double u0_dir(const Frame &f, const double *n)
@@ -267,11 +294,13 @@ __host__ __device__ inline size_t buf_bytes(int nd, int nch, int ce, size_t szT)
   return align16((size_t)nd * col_rows(nch, ce) * szT);
 }
 
-// table-build scratch for one round of 4 tables
-// table build scratch for tpr tables at a time
+// table-build scratch for tpr tables at a time: counts and cursors per
+// target, four records per source (target and shift; tap weights) and the
+// records' indexes in target order
 __host__ __device__ inline size_t scratch_bytes(int nd, size_t szT, int tpr = 4)
 {
-  return (size_t)tpr * nd * 4 * 2 + (size_t)4 * tpr * nd * 4 + (size_t)8 * tpr * nd * szT;
+  return (size_t)tpr * nd * 4 * 2 + (size_t)4 * tpr * nd * 4 + (size_t)8 * tpr * nd * szT +
+         (size_t)4 * tpr * nd * 4;
 }
 
 // 16-bit gather keys before their conversion to window offsets: the source
@@ -322,7 +351,7 @@ __device__ inline void node_bracket(const double *x, int n, double v, int &L, in
 // (mu, Phi) corners.  rt[4] receive the targets (-1 unused), rl/rr the tap
 // weights times the corner weight.
 // mu: the mu nodes (the grid's, or a copy of them in LDS)
-__device__ void remap_source(const DevGrid &g, const double *mu, const Frame &S, const Frame &D, int axis,
+__device__ void remap_source(const DevGrid &g, const double *mu, const FrameP &S, const FrameP &D, int axis,
                              bool rot, bool ident, int d, int rt[4], double rl[4], double rr[4], int &di_out)
 {
   const double *n = g.nvec + 3 * d;
@@ -334,39 +363,61 @@ __device__ void remap_source(const DevGrid &g, const double *mu, const Frame &S,
     return;
   }
   double u[4] = { 1.0, n[0], n[1], n[2] }, o[4];
-  frame_chain(S, D, axis, rot, u, o);
-  // energy: eps* = rho eps_i; logarithmic groups -> one shift for every i
-  double rho = o[0];
-  int di = (int)floor(log(rho) / g.lnq);
-  double we = (rho * exp(-di * g.lnq) - 1.0) / (g.q - 1.0);
-  we = fmin(1.0, fmax(0.0, we));
+  frame_chain_p(S, D, axis, rot, u, o);
+  // energy: eps* = rho eps_i; on logarithmic groups one shift di serves every
+  // i: q^di <= rho < q^(di+1), estimated in FP32 and settled on the table of
+  // powers of q
+  const double rho = o[0];
+  int di = (int)floorf(__logf((float)rho) / (float)g.lnq);
   di = max(-127, min(127, di));
+  while (di > -127 && rho < g.qpow[di + 128]) --di;
+  while (di < 127 && rho >= g.qpow[di + 129]) ++di;
+  double we = (rho * g.qpow[128 - di] - 1.0) / (g.q - 1.0);
+  we = fmin(1.0, fmax(0.0, we));
   di_out = di;
   // direction
   double mus = fmin(1.0, fmax(-1.0, o[1] / o[0]));
   int jL, jR;
   double wj;
   node_bracket(mu, g.nmu, mus, jL, jR, wj);
-  int k0 = d % g.nphi;
-  double P;
-  if (o[2] * o[2] + o[3] * o[3] <= 1e-12 * o[0] * o[0]) {
-    P = g.Phi[k0];                                  // on the mu = +-1 axis: keep the Phi label
-  } else {
-    P = atan2(o[3], o[2]);
-    if (P < 0.0) P += 2.0 * kPi;
-  }
   int kL, kR;
   double wk;
   if (g.nphi == 1) { kL = kR = 0; wk = 0.0; }
   else {
-    double dP = 2.0 * kPi / g.nphi;
-    int kl = (int)floor(P / dP - 0.5);
-    double PL = (kl + 0.5) * dP, PR = PL + dP;
-    if (g.phi_rule == 0) {
-      double a = sin(PR - P), b = sin(P - PL);
-      wk = b / (a + b);
+    const double dP = 2.0 * kPi / g.nphi;
+    int kl;
+    if (o[2] * o[2] + o[3] * o[3] <= 1e-12 * o[0] * o[0]) {
+      kl = d % g.nphi;                              // on the mu = +-1 axis: keep the Phi label
+      wk = 0.0;
+    } else if (g.phi_rule == 0) {
+      // direction-preserving split between the nodes P_L <= P < P_R (Phi
+      // nodes (k + 1/2) dP): sin(P - P_L) / (sin(P_R - P) + sin(P - P_L)),
+      // from the unit vector (cos P, sin P) and the nodes' cos and sin.  The
+      // bracket is estimated in FP32 and settled by the signs of the sines; a
+      // sine within rounding of zero (a direction on a node, where the split
+      // is 0 or 1 either way) settles it too, so that it cannot flip between
+      // the two brackets that share the node.
+      const double rp = sqrt(o[2] * o[2] + o[3] * o[3]);
+      const double c = o[2] / rp, sn = o[3] / rp;
+      float Pf = atan2f((float)o[3], (float)o[2]);
+      if (Pf < 0.0f) Pf += 2.0f * (float)kPi;
+      kl = (int)floorf(Pf / (float)dP - 0.5f);
+      double a = 0.0, b = 0.0;
+      for (int it = 0; it < 4; ++it) {
+        const int l = ((kl % g.nphi) + g.nphi) % g.nphi, r = (((kl + 1) % g.nphi) + g.nphi) % g.nphi;
+        b = sn * g.cphi[l] - c * g.sphi[l];          // sin(P - P_L)
+        a = g.sphi[r] * c - g.cphi[r] * sn;          // sin(P_R - P)
+        if (it == 3) break;                          // (unreachable: the estimate is off by < 1 bin)
+        if (b < -1e-12) --kl;
+        else if (a < -1e-12) ++kl;
+        else break;
+      }
+      wk = fmin(1.0, fmax(0.0, b / (a + b)));
     } else {
-      wk = (P - PL) / dP;
+      double P = atan2(o[3], o[2]);
+      if (P < 0.0) P += 2.0 * kPi;
+      kl = (int)floor(P / dP - 0.5);
+      wk = (P - (kl + 0.5) * dP) / dP;
     }
     kL = ((kl % g.nphi) + g.nphi) % g.nphi;
     kR = (((kl + 1) % g.nphi) + g.nphi) % g.nphi;
@@ -500,7 +551,7 @@ __device__ inline int tab_dst(int t) { return (t == 0 || t == 1 || t == 6) ? 1 :
 // GTAB: the tables are built in place in global memory (grids whose tables do
 // not fit in LDS), one table at a time.
 template <typename T, bool GTAB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items)
 {
   constexpr int TPR = GTAB ? 1 : 4;                 // tables per round
@@ -518,12 +569,13 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
   char *p = lds;
   char *tabs = GTAB ? tabs_g + (size_t)fid * kTables * tstride : p;
   if (!GTAB) p += kTables * tstride;
-  Frame *frm = (Frame *)p;     p += align16(5 * sizeof(Frame));
+  FrameP *frm = (FrameP *)p;   p += align16(5 * sizeof(FrameP));
   char *data = p;
   int *cnt = (int *)data;                      // TPR nd
   int *cur = cnt + TPR * nd;                   // TPR nd
   int *rtg = cur + TPR * nd;                   // 4 TPR nd
   T *rcf = (T *)(rtg + 4 * TPR * nd);          // 8 TPR nd
+  int *idx = (int *)(rcf + 8 * TPR * nd);      // 4 TPR nd
   // the mu nodes, searched for every direction of every table
   double *smu = (double *)(data + align16(scratch_bytes(nd, sizeof(T), TPR)));
   for (int q = tid; q < g.nmu; q += nthr) smu[q] = g.mu[q];
@@ -535,22 +587,24 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
     start = key + 4 * nd;
   };
   if (tid < kTables) flg[tid] = 0;
-  if (tid == 0) {
-    Frame a = side_frame(g, F.L), b = side_frame(g, F.R);
-    frm[0] = side_frame(g, F.Lm);
-    frm[1] = a;
-    frm[2] = b;
-    frm[3] = side_frame(g, F.Rp);
-    Frame fs_;
-    double vl[3], vr[3];
-    change_basis(a.th, a.ph, F.ths, F.phs, a.v, vl);
-    change_basis(b.th, b.ph, F.ths, F.phs, b.v, vr);
-    for (int i = 0; i < 3; ++i) fs_.v[i] = 0.5 * (vl[i] + vr[i]);
-    fs_.alpha = 0.5 * (a.alpha + b.alpha);
-    fs_.psi = 0.5 * (a.psi + b.psi);
-    fs_.th = F.ths;
-    fs_.ph = F.phs;
-    frm[4] = fs_;
+  if (tid < 5) {                                  // the five frames, one lane each
+    const Frame a = side_frame(g, F.L), b = side_frame(g, F.R);
+    Frame fr;
+    if (tid == 0) fr = side_frame(g, F.Lm);
+    else if (tid == 1) fr = a;
+    else if (tid == 2) fr = b;
+    else if (tid == 3) fr = side_frame(g, F.Rp);
+    else {
+      double vl[3], vr[3];
+      change_basis(a.th, a.ph, F.ths, F.phs, a.v, vl);
+      change_basis(b.th, b.ph, F.ths, F.phs, b.v, vr);
+      for (int i = 0; i < 3; ++i) fr.v[i] = 0.5 * (vl[i] + vr[i]);
+      fr.alpha = 0.5 * (a.alpha + b.alpha);
+      fr.psi = 0.5 * (a.psi + b.psi);
+      fr.th = F.ths;
+      fr.ph = F.phs;
+    }
+    frm[tid] = prep_frame(fr);
   }
   const bool rot = g.geom != 2;
   const int ax = F.axis;
@@ -560,10 +614,10 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
     __syncthreads();
     for (int q = tid; q < TPR * nd; q += nthr) {
       int tl = q / nd, d = q - tl * nd, t = TPR * round + tl;
-      const Frame S = frm[tab_src(t)], D = frm[tab_dst(t)];
+      const FrameP &S = frm[tab_src(t)], &D = frm[tab_dst(t)];
       int rt[4], di;
       double rl[4], rr[4];
-      remap_source(g, smu, S, D, ax, rot, same_frame(S, D), d, rt, rl, rr, di);
+      remap_source(g, smu, S, D, ax, rot, same_frame(S.f, D.f), d, rt, rl, rr, di);
       if (di < -1 || di > 1) atomicOr(&flg[t], 1);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -601,73 +655,59 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
       }
     }
     __syncthreads();
-    for (int q = tid; q < TPR * nd; q += nthr) {       // records into their target lists
-      int tl = q / nd, d = q - tl * nd;
-      T *cw;
-      unsigned short *key, *start;
-      tw(TPR * round + tl, cw, key, start);
+    for (int q = tid; q < TPR * nd; q += nthr) {       // record indexes into their target lists
+      const int tl = q / nd;
       for (int r = 0; r < 4; ++r) {
-        int v = rtg[q * 4 + r];
+        const int v = rtg[q * 4 + r];
         if (v < 0) continue;
-        int tg = v & 0xffff, dib = v >> 16;
-        int slot = atomicAdd(&cur[tl * nd + tg], 1);
-        key[slot] = pack_key(d, dib - 128, nd);
-        cw[2 * slot] = rcf[(q * 4 + r) * 2];
-        cw[2 * slot + 1] = rcf[(q * 4 + r) * 2 + 1];
+        idx[tl * 4 * nd + atomicAdd(&cur[tl * nd + (v & 0xffff)], 1)] = q * 4 + r;
       }
     }
     __syncthreads();
-    for (int q = tid; q < TPR * nd; q += nthr) {       // fixed summation order: sort by key
-      int tl = q / nd, d = q - tl * nd;
+    // Each record takes the place of its rank by key within its target's list
+    // (keys are distinct there: a source sends at most one record to a
+    // target), which fixes the summation order whatever order the lists were
+    // filled in; with shifts within one group the key becomes the source
+    // window offset.
+    for (int x = tid; x < TPR * 4 * nd; x += nthr) {
+      const int tl = x / (4 * nd), sl = x - tl * 4 * nd;
       T *cw;
       unsigned short *key, *start;
       tw(TPR * round + tl, cw, key, start);
-      int a = start[d], b = start[d + 1];
-      for (int x = a + 1; x < b; ++x) {
-        unsigned short kx = key[x];
-        T c0 = cw[2 * x], c1 = cw[2 * x + 1];
-        int y = x - 1;
-        while (y >= a && key[y] > kx) {
-          key[y + 1] = key[y];
-          cw[2 * y + 2] = cw[2 * y];
-          cw[2 * y + 3] = cw[2 * y + 1];
-          --y;
-        }
-        key[y + 1] = kx;
-        cw[2 * y + 2] = c0;
-        cw[2 * y + 3] = c1;
+      if (sl >= start[nd]) continue;
+      const int rec = idx[x], v = rtg[rec];
+      const int tg = v & 0xffff, a = start[tg], b = start[tg + 1];
+      const unsigned kx = pack_key(rec / 4 - tl * nd, (v >> 16) - 128, nd);
+      int rank = 0;
+      for (int y = a; y < b; ++y) {
+        const int ry = idx[tl * 4 * nd + y];
+        rank += pack_key(ry / 4 - tl * nd, (rtg[ry] >> 16) - 128, nd) < kx;
       }
-      // shifts within one group: keys become source window offsets
-      if (!(start[nd + 1] & 1))
-        for (int x = a; x < b; ++x) {
-          int src, di;
-          unpack_key(key[x], nd, src, di);
-          key[x] = (unsigned short)(src * cs - di + 2);
-        }
+      const int slot = a + rank;
+      key[slot] = (start[nd + 1] & 1) ? (unsigned short)kx
+                                      : (unsigned short)((rec / 4 - tl * nd) * cs - ((v >> 16) - 128) + 2);
+      cw[2 * slot] = rcf[rec * 2];
+      cw[2 * slot + 1] = rcf[rec * 2 + 1];
     }
   }
   __syncthreads();
 
-  if (tid == 0) {
-    FaceAux A;
-    for (int k = 0; k < 5; ++k) {
-      const Frame &fr = frm[k];
-      for (int i = 0; i < 3; ++i) A.v[k][i] = fr.v[i];
-      A.alpha[k] = fr.alpha;
-      A.psi[k] = fr.psi;
-      A.gam[k] = 1.0 / sqrt(1.0 - (fr.v[0] * fr.v[0] + fr.v[1] * fr.v[1] + fr.v[2] * fr.v[2]));
-      A.p6[k] = pow(fr.psi, 6.0);
-    }
-    for (int side = 0; side < 2; ++side) {
-      const Frame &fr = frm[1 + side];
-      for (int c = 0; c < 3; ++c) {
-        double e[3] = { c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, c == 2 ? 1.0 : 0.0 }, y[3];
-        if (rot) change_basis(fr.th, fr.ph, F.ths, F.phs, e, y);
-        else { y[0] = e[0]; y[1] = e[1]; y[2] = e[2]; }
-        for (int r = 0; r < 3; ++r) A.M[side][3 * r + c] = y[r];
-      }
-    }
-    aux[fid] = A;
+  // the face's frame data, one lane per frame and one per basis column
+  FaceAux &A = aux[fid];
+  if (tid < 5) {
+    const FrameP &fr = frm[tid];
+    for (int i = 0; i < 3; ++i) A.v[tid][i] = fr.f.v[i];
+    A.alpha[tid] = fr.f.alpha;
+    A.psi[tid] = fr.f.psi;
+    A.gam[tid] = fr.gam;
+    A.p6[tid] = pow(fr.f.psi, 6.0);
+  } else if (tid < 11) {                         // column c of the basis change side -> interface
+    const int side = (tid - 5) / 3, c = (tid - 5) % 3;
+    const FrameP &fr = frm[1 + side], &fs = frm[4];
+    const bool same = !rot || (fr.f.th == fs.f.th && fr.f.ph == fs.f.ph);
+    for (int r = 0; r < 3; ++r)
+      A.M[side][3 * r + c] = same ? (r == c ? 1.0 : 0.0)
+                                  : fs.B[0][r] * fr.B[0][c] + fs.B[1][r] * fr.B[1][c] + fs.B[2][r] * fr.B[2][c];
   }
   __syncthreads();
   if (!GTAB) {
@@ -686,13 +726,13 @@ __host__ __device__ inline size_t time_lds_bytes(int nd, int ne, size_t szT)
 {
   return align16((size_t)nd * 4) * 2 + align16((size_t)16 * nd) + align16((size_t)8 * nd * szT) * 2 +
          align16((size_t)4 * nd * 2) + align16((size_t)(nd + 1) * 2) + align16((size_t)nd * 8) * 2 +
-         align16((size_t)nd * ne * szT);
+         align16((size_t)nd * ne * szT) + align16((size_t)16 * nd);
 }
 
 // Remaps every species block of one zone from its comoving frame under the
 // current background to its comoving frame under a new one: the remap forward
 // in time of Sec. 3.2 (the closing T_{n->n+1} of a step, Sec. 3.3), at a fixed
-// place, so without rotation and with the time kick of frame_chain.  The
+// place, so without rotation and with the time kick of frame_chain_p.  The
 // zone's gather table is built in LDS and applied in place to the number
 // content (W = psi^6 u0 G dOmega; the cell volume is unchanged).
 // nbg: the new background of the model, [5][zone] = v_r, v_theta, v_phi, alpha, psi.
@@ -716,6 +756,7 @@ time_remap_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ 
   D.v[0] = nb[z]; D.v[1] = nb[g.nz + z]; D.v[2] = nb[2 * g.nz + z];
   D.alpha = nb[3 * g.nz + z]; D.psi = nb[4 * g.nz + z];
   if (same_frame(S, D)) return;                          // the whole workgroup leaves
+  const FrameP SP = prep_frame(S), DP = prep_frame(D);
   char *p = lds;
   int *cnt = (int *)p;                 p += align16((size_t)nd * 4);
   int *cur = (int *)p;                 p += align16((size_t)nd * 4);
@@ -726,7 +767,8 @@ time_remap_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ 
   unsigned short *start = (unsigned short *)p; p += align16((size_t)(nd + 1) * 2);
   double *aS = (double *)p;            p += align16((size_t)nd * 8);
   double *aD = (double *)p;            p += align16((size_t)nd * 8);
-  T *cont = (T *)p;
+  T *cont = (T *)p;                    p += align16((size_t)nd * ne * sizeof(T));
+  int *idx = (int *)p;                 // record indexes in target order
   const double gS = 1.0 / sqrt(1.0 - (S.v[0] * S.v[0] + S.v[1] * S.v[1] + S.v[2] * S.v[2]));
   const double gD = 1.0 / sqrt(1.0 - (D.v[0] * D.v[0] + D.v[1] * D.v[1] + D.v[2] * D.v[2]));
   const double p6S = pow(S.psi, 6.0), p6D = pow(D.psi, 6.0);
@@ -740,7 +782,7 @@ time_remap_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ 
   for (int q = tid; q < nd; q += nthr) {               // each source direction
     int rt[4], di;
     double rl[4], rr[4];
-    remap_source(g, g.mu, S, D, -1, false, false, q, rt, rl, rr, di);
+    remap_source(g, g.mu, SP, DP, -1, false, false, q, rt, rl, rr, di);
     for (int r = 0; r < 4; ++r) {
       rtg[q * 4 + r] = rt[r] >= 0 ? (rt[r] | ((di + 128) << 16)) : -1;
       rcf[(q * 4 + r) * 2] = (T)rl[r];
@@ -749,38 +791,43 @@ time_remap_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ 
     }
   }
   __syncthreads();
-  if (tid == 0) {                                       // list starts per target
-    int acc = 0;
-    for (int d = 0; d < nd; ++d) { start[d] = (unsigned short)acc; cur[d] = acc; acc += cnt[d]; }
-    start[nd] = (unsigned short)acc;
+  if (tid < 64) {                                      // list starts per target: wave scan
+    int base = 0;
+    for (int d0 = 0; d0 < nd; d0 += 64) {
+      const int d = d0 + tid;
+      const int c = d < nd ? cnt[d] : 0;
+      int incl = c;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (tid >= o) incl += y;
+      }
+      if (d < nd) {
+        start[d] = (unsigned short)(base + incl - c);
+        cur[d] = base + incl - c;
+      }
+      base += __shfl(incl, 63, 64);
+    }
+    if (tid == 0) start[nd] = (unsigned short)base;
   }
   __syncthreads();
   for (int q = tid; q < nd; q += nthr)
     for (int r = 0; r < 4; ++r) {
       const int v = rtg[q * 4 + r];
-      if (v < 0) continue;
-      const int slot = atomicAdd(&cur[v & 0xffff], 1);
-      key[slot] = pack_key(q, (v >> 16) - 128, nd);
-      cw[2 * slot] = rcf[(q * 4 + r) * 2];
-      cw[2 * slot + 1] = rcf[(q * 4 + r) * 2 + 1];
+      if (v >= 0) idx[atomicAdd(&cur[v & 0xffff], 1)] = q * 4 + r;
     }
   __syncthreads();
-  for (int q = tid; q < nd; q += nthr) {               // fixed summation order: sort by key
-    const int a = start[q], b = start[q + 1];
-    for (int x = a + 1; x < b; ++x) {
-      const unsigned short kx = key[x];
-      const T c0 = cw[2 * x], c1 = cw[2 * x + 1];
-      int y = x - 1;
-      while (y >= a && key[y] > kx) {
-        key[y + 1] = key[y];
-        cw[2 * y + 2] = cw[2 * y];
-        cw[2 * y + 3] = cw[2 * y + 1];
-        --y;
-      }
-      key[y + 1] = kx;
-      cw[2 * y + 2] = c0;
-      cw[2 * y + 3] = c1;
-    }
+  // each record at the place of its rank by key in its target's list (a
+  // fixed summation order, whatever order the lists were filled in)
+  for (int x = tid; x < start[nd]; x += nthr) {
+    const int rec = idx[x], v = rtg[rec];
+    const int tg = v & 0xffff, a = start[tg], b = start[tg + 1];
+    const unsigned kx = pack_key(rec / 4, (v >> 16) - 128, nd);
+    int rank = 0;
+    for (int y = a; y < b; ++y) rank += pack_key(idx[y] / 4, (rtg[idx[y]] >> 16) - 128, nd) < kx;
+    key[a + rank] = (unsigned short)kx;
+    cw[2 * (a + rank)] = rcf[rec * 2];
+    cw[2 * (a + rank) + 1] = rcf[rec * 2 + 1];
   }
   __syncthreads();
   for (int s = 0; s < g.ns; ++s) {

@@ -51,6 +51,10 @@ def parse():
                     help="steps of the run whose background changes every step (0: skip it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--cpu-theta", type=int, default=256,
+                    help="theta rows of the grid the CPU reference is timed on with all threads")
+    ap.add_argument("--cpu-leg", nargs=2, type=int, metavar=("THREADS", "N_THETA"), default=None,
+                    help=argparse.SUPPRESS)    # child process: one reference step, no GPU
     return ap.parse_args()
 
 
@@ -161,21 +165,58 @@ def run_evolving(torch, btx, w, steps):
             "updates_per_s": w.n_values * steps / wall}
 
 
-def cpu_baseline(steps_note):
-    """the CPU reference on a bounded sample of the same workload shape"""
+def cpu_leg(threads, n_theta):
+    """child process of cpu_baseline: one FP64 reference step of the benchmark profile on
+    n_theta theta rows with the given OpenMP thread count (set in its environment); no GPU"""
     from oracle import oracle
     from paper_2003_02845_amd import workloads as W
-    w = W.hires_2d(n_theta=96)
+    w = W.hires_2d(n_theta=n_theta)
     o = oracle.Oracle(w)
     dt = o.max_dt(w.cfl)
     t = time.perf_counter()
     o.step(dt, 1)
     el = time.perf_counter() - t
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": w.n_values / el, "unit": "zone*group*direction updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"one FP64 step of the same profile and momentum grid on 600 r x 96 theta "
-                      f"zones ({w.n_values:.3g} values, {el:.1f} s)"}
+    print(json.dumps({"seconds": el, "values": w.n_values, "threads": threads,
+                      "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}), flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n_theta):
+    """the CPU reference (oracle) on the host cores: one FP64 step of the benchmark grid
+    (n_theta theta rows; 256 is the whole grid) with every thread the process may use, and
+    one step of an 8-row slice of it on one thread.  Each runs in a child process that
+    touches no GPU, so its OpenMP thread count is set before the library loads."""
+    import subprocess
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = int(os.environ.get("OMP_NUM_THREADS", avail))
+    runs = {}
+    for nt, rows in ((threads, n_theta), (1, 8)):
+        env = dict(os.environ, OMP_NUM_THREADS=str(nt), OMP_PROC_BIND="false")
+        res = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--cpu-leg", str(nt), str(rows)],
+                             env=env, capture_output=True, text=True, timeout=900)
+        if res.returncode != 0:
+            raise RuntimeError("CPU reference leg failed:\n" + res.stdout[-2000:] + res.stderr[-2000:])
+        runs[nt] = json.loads(res.stdout.strip().splitlines()[-1])
+        print(f"[bench] cpu: {nt} thread(s), {rows} theta rows: {runs[nt]['seconds']:.1f} s",
+              file=sys.stderr, flush=True)
+    full, one = runs[threads], runs[1]
+    return {"value": full["values"] / full["seconds"], "unit": "zone*group*direction updates/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"one FP64 step of the benchmark grid, 600 r x {n_theta} theta zones "
+                      f"({full['values']:.4g} values, {full['seconds']:.1f} s on {threads} threads)",
+            "cpu_model": cpu_model(), "cpus_available": avail,
+            "value_1thread": one["values"] / one["seconds"],
+            "sample_1thread": f"one FP64 step of 600 r x 8 theta zones of the same profile "
+                              f"({one['values']:.4g} values, {one['seconds']:.1f} s on 1 thread)"}
 
 
 def run_batch(torch, btx, W, steps):
@@ -238,42 +279,41 @@ def run_batch(torch, btx, W, steps):
                             "speedup_vs_global_step": (2 ** L) * ms_b / ms_l}}
 
 
-def face_traffic():
-    """HBM bytes per face-kernel launch from the committed counter summary, or None when the
-    kernel source has changed since the counters were taken"""
-    prof = os.path.join(ROOT, "profiles", "face_kernel_hires_2d_mixed_hbm_traffic.txt")
-    src = os.path.join(ROOT, "paper_2003_02845_amd", "csrc", "btx.hip")
-    try:
-        text = open(prof).read()
-        want = re.search(r"btx\.hip: ([0-9a-f]{16})", text).group(1)
-        have = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-        if want != have:
-            return None
-        return float(re.search(r"face_traffic_bytes ([0-9.e+]+)", text).group(1))
-    except (OSError, AttributeError, ValueError):
-        return None
+def kernel_source_hash():
+    """sha256 (first 16 hex) over the library's sources (csrc/, in name order): a counter
+    summary applies only to the kernels it was taken from"""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2003_02845_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
 
 
-def zone_traffic():
-    """HBM bytes per zone-kernel launch from the same counter summary, or None"""
-    prof = os.path.join(ROOT, "profiles", "face_kernel_hires_2d_mixed_hbm_traffic.txt")
-    src = os.path.join(ROOT, "paper_2003_02845_amd", "csrc", "btx.hip")
+def profile_values(name):
+    """key -> value lines ('# key value') of a committed counter summary under profiles/, or
+    None when the summary is missing or was taken from other kernel sources"""
     try:
-        text = open(prof).read()
-        want = re.search(r"btx\.hip: ([0-9a-f]{16})", text).group(1)
-        if want != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
-            return None
-        return float(re.search(r"^zone_kernel<float>\s+\d+\s+\d+\s+([0-9.]+)", text, re.M).group(1)) * 1e9
-    except (OSError, AttributeError, ValueError):
+        text = open(os.path.join(ROOT, "profiles", name)).read()
+    except OSError:
         return None
+    m = re.search(r"kernel sources sha256 \(first 16 hex\): ([0-9a-f]{16})", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    return {k: float(v) for k, v in re.findall(r"^# ([a-z0-9_]+) ([-0-9.e+]+)$", text, re.M)}
 
 
 def main():
     a = parse()
+    if a.cpu_leg is not None:
+        cpu_leg(*a.cpu_leg)
+        return
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
               f"(the spatial decomposition across GPUs is a design, not a build)", file=sys.stderr)
         sys.exit(2)
+    cpu = None if a.no_cpu else cpu_baseline(a.cpu_theta)    # before this process touches the GPU
     import torch
     from paper_2003_02845_amd import btx, workloads as W
     if not torch.cuda.is_available():
@@ -300,19 +340,35 @@ def main():
         y = torch.empty_like(x)
         y.copy_(x)
         torch.cuda.synchronize()
-    # algorithmic bytes (mixed): f read + f written (4 B each) + ka, ks, feq per group (FP32)
-    # + v_r, v_theta, alpha, psi per zone (FP64)
+    # algorithmic bytes of a step (mixed): f read and written once (4 B each), ka, ks, feq per
+    # (zone, species, group) (FP32) and v_r, v_theta, alpha, psi per zone (FP64)
     nz, nsg = w.n_zones, w.n_zones * w.n_species * w.n_eps
     b_step = w.n_values * 8 + nsg * 3 * 4 + nz * 4 * 8
-    # the face kernel's algorithmic share: it must read f and the opacities once
+    # the face kernel's own share: f and the opacities read once
     b_face = w.n_values * 4 + nsg * 3 * 4 + nz * 4 * 8
     t_face = mixed["kernel_ms"][0] * 1e-3
-    achieved = b_face / t_face / 1e9
-    traffic = face_traffic() if full else None
+    achieved = b_step / t_face / 1e9
     # the zone kernel: f read and written, the opacities and the zone background
     b_zone = w.n_values * 8 + nsg * 3 * 4 + nz * 4 * 8
     t_zone = mixed["kernel_ms"][1] * 1e-3
-    ztraffic = zone_traffic() if full else None
+    hbm = profile_values("face_kernel_hires_2d_mixed_hbm_traffic.txt") if full else None
+    alu = profile_values("face_kernel_hires_2d_mixed_valu_lds.txt") if full else None
+    compute = None
+    if alu is not None:
+        # VALU issue: one wave64 instruction per CU per cycle (4 SIMDs, 4 cycles each)
+        peak_inst = 256 * 2.4e9
+        inst_rate = alu["valu_insts_per_launch"] / t_face
+        compute = {"bound": "alu", "kernel": "face_kernel<float>",
+                   "achieved": inst_rate / 1e9, "peak": peak_inst / 1e9, "unit": "G wave-VALU instr/s",
+                   "frac": inst_rate / peak_inst,
+                   "valu_busy": alu["valu_busy_pct"] / 100.0,
+                   "lds_bank_conflict_of_lds_cycles": alu["lds_bank_conflict_pct_of_lds_active"] / 100.0,
+                   "lds_busy": alu["lds_active_pct"] / 100.0,
+                   "waves_per_cu": alu["mean_waves_per_cu"],
+                   "fp32_flops_est": {"per_update": 350, "achieved_tflops": 350 * w.n_values / t_face / 1e12,
+                                      "peak_tflops": 157.3,
+                                      "frac": 350 * w.n_values / t_face / 1e12 / 157.3},
+                   "source": "profiles/face_kernel_hires_2d_mixed_valu_lds.txt (rocprofv3 --pmc, full size)"}
     out = {
         "metric": "zone\u00b7group\u00b7direction updates/s, mixed FP32/FP64 vs FP64; % HBM peak",
         "value": value,
@@ -332,13 +388,18 @@ def main():
         "step_hbm_frac": b_step / (mixed["ms"] / a.steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": "face_kernel<float>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None if traffic is None else traffic / 1e9,
+                     "traffic": None if hbm is None else hbm["face_traffic_bytes"] / 1e9,
                      "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "algorithmic": b_face / 1e9, "algorithmic_unit": "GB per launch"},
+                     "algorithmic": b_step / 1e9,
+                     "algorithmic_unit": "GB per launch: the step's algorithmic bytes (f read and written "
+                                         "once, opacities, background) over the dominant kernel's time",
+                     "face_only": {"algorithmic": b_face / 1e9, "achieved": b_face / t_face / 1e9,
+                                   "frac": b_face / t_face / 1e9 / HBM_PEAK_GBS}},
+        "compute_roofline": compute,
         "zone_roofline": {"bound": "hbm", "kernel": "zone_kernel<float>", "achieved": b_zone / t_zone / 1e9,
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": b_zone / t_zone / 1e9 / HBM_PEAK_GBS,
-                          "traffic": None if ztraffic is None else ztraffic / 1e9,
-                          "traffic_rate": None if ztraffic is None else ztraffic / t_zone / 1e9,
+                          "traffic": None if hbm is None else hbm["zone_traffic_bytes"] / 1e9,
+                          "traffic_rate": None if hbm is None else hbm["zone_traffic_bytes"] / t_zone / 1e9,
                           "traffic_unit": "GB per launch; GB/s",
                           "algorithmic": b_zone / 1e9, "algorithmic_unit": "GB per launch"},
     }
@@ -390,8 +451,9 @@ def main():
               f"{out['batch']['sequential_ms_per_step']:.3f} ms/step sequential; with time levels "
               f"(max {bt['max_level']}) {bt['ms_per_step']:.3f} ms per {bt['substeps_per_step']} substeps, "
               f"{bt['speedup_vs_global_step']:.2f}x the simulated time per second", file=sys.stderr, flush=True)
-    if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(a.steps)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+        out["cpu_baseline"]["gpu_speedup"] = value / cpu["value"]
     print(json.dumps(out), flush=True)
 
 

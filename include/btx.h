@@ -136,6 +136,14 @@ btx_status btx_set_background(btx_ctx *ctx, const btx_background *bg);
  * replaces the background.  Without a state or background it acts as
  * btx_set_background.  Synchronises the stream. */
 btx_status btx_update_background(btx_ctx *ctx, const btx_background *bg);
+/* btx_update_background with every array of bg (FP64, same layouts) in device
+ * memory of the context's device (hipMalloc'd or managed; else BTX_E_INVAL):
+ * nothing crosses the host link.  The values are checked on the device
+ * (BTX_E_INVAL, background unchanged, if any is out of range); the copies,
+ * the time remap and the table rebuild are ordered on the context's stream,
+ * which the call synchronises before returning.  The arrays stay the
+ * caller's. */
+btx_status btx_update_background_device(btx_ctx *ctx, const btx_background *bg);
 /* Largest stable global step (Sec. 3.3): cfl times the smallest Courant
  * length (zone volume over its largest face on an axis) of the grid. */
 btx_status btx_max_dt(const btx_ctx *ctx, double cfl, double *dt_out);
@@ -219,6 +227,7 @@ btx_status btx_batch_create(const btx_grid_desc *descs, int32_t n_models, int hi
                             const char *tune_cache_path, btx_batch **out);
 btx_status btx_batch_set_background(btx_batch *b, int32_t model, const btx_background *bg);
 btx_status btx_batch_update_background(btx_batch *b, int32_t model, const btx_background *bg);
+btx_status btx_batch_update_background_device(btx_batch *b, int32_t model, const btx_background *bg);
 btx_status btx_batch_max_dt(const btx_batch *b, int32_t model, double cfl, double *dt_out);
 btx_status btx_batch_set_state(btx_batch *b, int32_t model, const void *f, int is_device_ptr);
 btx_status btx_batch_get_state(btx_batch *b, int32_t model, void *f, int is_device_ptr);

@@ -27,6 +27,7 @@ ABI_SYMBOLS = ["btx_create", "btx_set_background", "btx_max_dt", "btx_set_state"
                "btx_get_state", "btx_step", "btx_moments", "btx_timing", "btx_destroy",
                "btx_last_error", "btx_update_background", "btx_batch_create",
                "btx_batch_set_background", "btx_batch_update_background",
+               "btx_update_background_device", "btx_batch_update_background_device",
                "btx_batch_max_dt", "btx_batch_set_state", "btx_batch_get_state", "btx_batch_step",
                "btx_batch_use_graph", "btx_batch_shape", "btx_batch_moments", "btx_batch_destroy",
                "btx_batch_time_levels", "btx_batch_set_time_levels",
@@ -72,6 +73,8 @@ def lib():
         L.btx_set_background.argtypes = [vp, C.POINTER(Background)]
         L.btx_update_background.argtypes = [vp, C.POINTER(Background)]
         L.btx_batch_update_background.argtypes = [vp, C.c_int32, C.POINTER(Background)]
+        L.btx_update_background_device.argtypes = [vp, C.POINTER(Background)]
+        L.btx_batch_update_background_device.argtypes = [vp, C.c_int32, C.POINTER(Background)]
         L.btx_max_dt.argtypes = [vp, C.c_double, _dp]
         L.btx_set_state.argtypes = [vp, vp, C.c_int]
         L.btx_get_state.argtypes = [vp, vp, C.c_int]
@@ -152,6 +155,25 @@ def _background(w, grid):
     return Background(*[_p(a) for a in arrs]), arrs
 
 
+def _background_device(bg, grid, device):
+    """a Background of device pointers from a mapping of contiguous FP64 GPU
+    tensors (v_r, v_theta, alpha, psi, kappa_a, kappa_s, f_eq, optional
+    v_phi), checked against the sizes of grid"""
+    import torch
+    nz, nk = grid.n_zones, grid.n_zones * grid.n_species * grid.n_eps
+    names = ("v_r", "v_theta", "alpha", "psi", "kappa_a", "kappa_s", "f_eq")
+    ts = []
+    for name, n in zip(names, (nz, nz, nz, nz, nk, nk, nk)):
+        t = bg[name]
+        _device_tensor(t, n, torch.float64, device)
+        ts.append(t)
+    vph = bg.get("v_phi")
+    if vph is not None:
+        _device_tensor(vph, nz, torch.float64, device)
+        ts.append(vph)
+    return Background(*[C.cast(C.c_void_p(t.data_ptr()), _dp) for t in ts]), ts
+
+
 def _device_tensor(t, n, dtype, device):
     """a GPU tensor the library may read or write n values of dtype through"""
     _need(t.is_cuda and t.is_contiguous(), "the tensor must be a contiguous GPU tensor")
@@ -193,6 +215,12 @@ class Context:
         """evolve the background: the state is remapped into the new comoving frames"""
         bg, keep = _background(w, self.w)
         _check(lib().btx_update_background(self.h, C.byref(bg)))
+
+    def update_background_device(self, bg):
+        """update_background from FP64 GPU tensors already on this context's device
+        (a mapping: v_r, v_theta, alpha, psi, kappa_a, kappa_s, f_eq, optional v_phi)"""
+        b, keep = _background_device(bg, self.w, self.device)
+        _check(lib().btx_update_background_device(self.h, C.byref(b)))
 
     def max_dt(self, cfl=None):
         out = C.c_double()
@@ -279,6 +307,7 @@ class Batch:
     def __init__(self, workloads, device=0, stream=None, precision=None, tune_cache=None,
                  fp64_threshold=1.0):
         self.ws = list(workloads)
+        self.device = device
         self.precision = self.ws[0].precision if precision is None else precision
         self.dtype = np.float64 if self.precision == PREC_FP64 else np.float32
         descs = (GridDesc * len(self.ws))()
@@ -312,6 +341,10 @@ class Batch:
     def update_background(self, m, w):
         bg, keep = _background(w, self.ws[m])
         _check(lib().btx_batch_update_background(self.h, m, C.byref(bg)))
+
+    def update_background_device(self, m, bg):
+        b, keep = _background_device(bg, self.ws[m], self.device)
+        _check(lib().btx_batch_update_background_device(self.h, m, C.byref(b)))
 
     def max_dt(self, m, cfl=None):
         out = C.c_double()

@@ -193,6 +193,7 @@ struct Model {
   FaceAux *d_aux = nullptr;
   double *d_tally = nullptr, *d_zm = nullptr, *d_ze = nullptr, *d_stage = nullptr, *d_q = nullptr;
   double *d_nbg = nullptr;           // new v_r, v_theta, v_phi, alpha, psi of a background update
+  int *d_err = nullptr;              // result of the device-side check of a background
   FaceDesc *d_faces = nullptr;
   int32_t *d_bface = nullptr;        // faces with a ghost side (boundary tallies)
   btx::ZoneFaces *d_zf = nullptr;
@@ -262,7 +263,7 @@ void model_free(Model &m)
   void *ptrs[] = { m.d_rconst, m.d_mu, m.d_Phi, m.d_dOm, m.d_nvec, m.d_G, m.d_eps, m.d_vol, m.d_vr, m.d_vth, m.d_vph,
                    m.d_alp, m.d_psi, m.d_ka, m.d_ks, m.d_feq, m.d_f[0], m.d_f[1], m.d_dN, m.d_tally,
                    m.d_zm, m.d_ze, m.d_stage, m.d_faces, m.d_zf, m.d_tabs, m.d_aux, m.d_fitems, m.d_zitems,
-                   m.d_nbg, m.d_q, m.d_zlev, m.d_fitems_lts, m.d_zitems_lts, m.d_bface };
+                   m.d_nbg, m.d_q, m.d_zlev, m.d_fitems_lts, m.d_zitems_lts, m.d_bface, m.d_err };
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   m = Model();
@@ -354,7 +355,7 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
       !dmalloc((void **)&m.d_tally, nf * g.ns * 8) ||
       !dmalloc((void **)&m.d_zm, nz * g.ns * 5 * 8) || !dmalloc((void **)&m.d_ze, nz * g.ns * 8) ||
       !dmalloc((void **)&m.d_stage, nk * 8) || !dmalloc((void **)&m.d_nbg, nz * 5 * 8) ||
-      !dmalloc((void **)&m.d_q, nz * 5 * 8) ||
+      !dmalloc((void **)&m.d_q, nz * 5 * 8) || !dmalloc((void **)&m.d_err, 16) ||
       !dmalloc((void **)&m.d_tabs, nf * kTables * tab_stride(g.ndir, m.tsize)) ||
       !dmalloc((void **)&m.d_aux, nf * sizeof(FaceAux))) {
     model_free(m);
@@ -423,28 +424,74 @@ btx_status check_background(const Model &m, const btx_background *bg)
   return BTX_OK;
 }
 
-// copies the background into the model's buffers (storage precision)
-btx_status upload_background(Model &m, const btx_background *bg, hipStream_t s)
+// Checks a background whose arrays are in device memory: every array must be
+// device (or managed) memory of the model's device; the values are checked
+// on the device (one synchronisation).
+btx_status check_background_device(Model &m, const btx_background *bg, int device, hipStream_t s)
+{
+  if (!bg) return fail(BTX_E_INVAL, "null argument");
+  if (!bg->v_r || !bg->v_theta || !bg->alpha || !bg->psi || !bg->kappa_a || !bg->kappa_s || !bg->f_eq)
+    return fail(BTX_E_INVAL, "null background array");
+  const double *arrs[8] = { bg->v_r, bg->v_theta, bg->alpha, bg->psi, bg->kappa_a, bg->kappa_s, bg->f_eq, bg->v_phi };
+  for (const double *p : arrs) {
+    if (!p) continue;
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess || at.device != device ||
+        (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)) {
+      (void)hipGetLastError();
+      return fail(BTX_E_INVAL, "background arrays must be device memory of the context's device");
+    }
+  }
+  const size_t nz = m.g.nz, nk = nz * m.g.ns * m.g.ne;
+  HIP_TRY(hipMemsetAsync(m.d_err, 0, sizeof(int), s));
+  hipLaunchKernelGGL(bg_check_kernel, dim3(1024), dim3(256), 0, s, bg->v_r, bg->v_theta, bg->v_phi, bg->alpha,
+                     bg->psi, nz, bg->kappa_a, bg->kappa_s, bg->f_eq, nk, m.d_err);
+  HIP_TRY(hipGetLastError());
+  int h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, m.d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h & 1) return fail(BTX_E_INVAL, "background velocity/metric out of range (device arrays)");
+  if (h & 2) return fail(BTX_E_INVAL, "opacities must be finite and >= 0 (device arrays)");
+  return BTX_OK;
+}
+
+// copies the background into the model's buffers (storage precision); the
+// arrays are host memory (synchronous copies) or, with on_device, device
+// memory of the model's device (stream-ordered copies on s)
+btx_status upload_background(Model &m, const btx_background *bg, hipStream_t s, bool on_device = false)
 {
   const btx::Grid &g = m.g;
   const size_t nz = g.nz, nk = nz * g.ns * g.ne;
-  HIP_TRY(hipMemcpy(m.d_vr, bg->v_r, nz * 8, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(m.d_vth, bg->v_theta, nz * 8, hipMemcpyHostToDevice));
-  if (bg->v_phi) HIP_TRY(hipMemcpy(m.d_vph, bg->v_phi, nz * 8, hipMemcpyHostToDevice));
-  else HIP_TRY(hipMemset(m.d_vph, 0, nz * 8));
-  HIP_TRY(hipMemcpy(m.d_alp, bg->alpha, nz * 8, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(m.d_psi, bg->psi, nz * 8, hipMemcpyHostToDevice));
+  auto copy = [&](void *dst, const void *src, size_t bytes) -> btx_status {
+    if (on_device) HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+    else HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return BTX_OK;
+  };
+  btx_status st;
+  const double *zsrc[4] = { bg->v_r, bg->v_theta, bg->alpha, bg->psi };
+  double *zdst[4] = { m.d_vr, m.d_vth, m.d_alp, m.d_psi };
+  for (int k = 0; k < 4; ++k)
+    if ((st = copy(zdst[k], zsrc[k], nz * 8)) != BTX_OK) return st;
+  if (bg->v_phi) {
+    if ((st = copy(m.d_vph, bg->v_phi, nz * 8)) != BTX_OK) return st;
+  } else {
+    HIP_TRY(on_device ? hipMemsetAsync(m.d_vph, 0, nz * 8, s) : hipMemset(m.d_vph, 0, nz * 8));
+  }
   const double *src[3] = { bg->kappa_a, bg->kappa_s, bg->f_eq };
   void *dst[3] = { m.d_ka, m.d_ks, m.d_feq };
   for (int k = 0; k < 3; ++k) {
     if (m.tsize == 8) {
-      HIP_TRY(hipMemcpy(dst[k], src[k], nk * 8, hipMemcpyHostToDevice));
+      if ((st = copy(dst[k], src[k], nk * 8)) != BTX_OK) return st;
     } else {
-      HIP_TRY(hipMemcpy(m.d_stage, src[k], nk * 8, hipMemcpyHostToDevice));
+      const double *from = src[k];
+      if (!on_device) {
+        HIP_TRY(hipMemcpy(m.d_stage, src[k], nk * 8, hipMemcpyHostToDevice));
+        from = m.d_stage;
+      }
       hipLaunchKernelGGL((cast_kernel<float>), dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s,
-                         m.d_stage, (float *)dst[k], nk);
+                         from, (float *)dst[k], nk);
       HIP_TRY(hipGetLastError());
-      HIP_TRY(hipStreamSynchronize(s));
+      if (!on_device) HIP_TRY(hipStreamSynchronize(s));
     }
   }
   return BTX_OK;
@@ -519,20 +566,29 @@ btx_status set_face_lds(size_t tsize, const FaceShape &f, size_t lds)
 // background that evolves: the state is first remapped from the comoving
 // frames of the current background to those of the new one (forward in time,
 // time_remap_kernel), then the new background and its face tables are adopted.
+// on_device: every array of bg is device memory of the model's device.
 btx_status model_update_background(Model &m, const btx_background *bg, const ModelDev *d_models, int parity,
-                                   hipStream_t s)
+                                   hipStream_t s, int device = 0, bool on_device = false)
 {
-  btx_status st = check_background(m, bg);
+  btx_status st = on_device ? check_background_device(m, bg, device, s) : check_background(m, bg);
   if (st != BTX_OK) return st;
   HIP_TRY(hipStreamSynchronize(s));
   if (m.have_bg && m.have_state) {
     const size_t nz = m.g.nz;
-    HIP_TRY(hipMemcpy(m.d_nbg, bg->v_r, nz * 8, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(m.d_nbg + nz, bg->v_theta, nz * 8, hipMemcpyHostToDevice));
-    if (bg->v_phi) HIP_TRY(hipMemcpy(m.d_nbg + 2 * nz, bg->v_phi, nz * 8, hipMemcpyHostToDevice));
-    else HIP_TRY(hipMemset(m.d_nbg + 2 * nz, 0, nz * 8));
-    HIP_TRY(hipMemcpy(m.d_nbg + 3 * nz, bg->alpha, nz * 8, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(m.d_nbg + 4 * nz, bg->psi, nz * 8, hipMemcpyHostToDevice));
+    // host arrays: synchronous copies; device arrays: stream-ordered on s
+    auto copy = [&](double *dst, const double *src) -> btx_status {
+      if (on_device) HIP_TRY(hipMemcpyAsync(dst, src, nz * 8, hipMemcpyDeviceToDevice, s));
+      else HIP_TRY(hipMemcpy(dst, src, nz * 8, hipMemcpyHostToDevice));
+      return BTX_OK;
+    };
+    if ((st = copy(m.d_nbg, bg->v_r)) != BTX_OK || (st = copy(m.d_nbg + nz, bg->v_theta)) != BTX_OK ||
+        (st = copy(m.d_nbg + 3 * nz, bg->alpha)) != BTX_OK || (st = copy(m.d_nbg + 4 * nz, bg->psi)) != BTX_OK)
+      return st;
+    if (bg->v_phi) {
+      if ((st = copy(m.d_nbg + 2 * nz, bg->v_phi)) != BTX_OK) return st;
+    } else {
+      HIP_TRY(on_device ? hipMemsetAsync(m.d_nbg + 2 * nz, 0, nz * 8, s) : hipMemset(m.d_nbg + 2 * nz, 0, nz * 8));
+    }
     const void *tk = m.tsize == 8 ? (const void *)time_remap_kernel<double> : (const void *)time_remap_kernel<float>;
     const size_t lds = time_lds_bytes(m.g.ndir, m.g.ne, m.tsize);
     if ((st = raise_lds_limit(tk, lds)) != BTX_OK) return st;
@@ -540,9 +596,9 @@ btx_status model_update_background(Model &m, const btx_background *bg, const Mod
     const double *nbg = m.d_nbg;
     void *args[] = { &d_models, &items, &parity, &nbg };
     HIP_TRY(hipLaunchKernel(tk, dim3((unsigned)nz), dim3(256), args, lds, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    if (!on_device) HIP_TRY(hipStreamSynchronize(s));
   }
-  if ((st = upload_background(m, bg, s)) != BTX_OK) return st;
+  if ((st = upload_background(m, bg, s, on_device)) != BTX_OK) return st;
   if ((st = build_tables(m, d_models, s)) != BTX_OK) return st;
   HIP_TRY(hipStreamSynchronize(s));
   m.have_bg = true;
@@ -1215,6 +1271,13 @@ btx_status btx_update_background(btx_ctx *c, const btx_background *bg)
   return model_update_background(c->m, bg, c->d_model, c->parity, c->stream);
 }
 
+btx_status btx_update_background_device(btx_ctx *c, const btx_background *bg)
+{
+  if (!c) return fail(BTX_E_INVAL, "null argument");
+  HIP_TRY(hipSetDevice(c->device));
+  return model_update_background(c->m, bg, c->d_model, c->parity, c->stream, c->device, true);
+}
+
 btx_status btx_max_dt(const btx_ctx *c, double cfl, double *dt_out)
 {
   if (!c || !dt_out) return fail(BTX_E_INVAL, "null argument");
@@ -1389,6 +1452,13 @@ btx_status btx_batch_update_background(btx_batch *b, int32_t model, const btx_ba
   if (!b || model < 0 || model >= (int)b->models.size()) return fail(BTX_E_INVAL, "bad batch or model index");
   HIP_TRY(hipSetDevice(b->device));
   return model_update_background(b->models[model], bg, b->d_models, b->parity, b->stream);
+}
+
+btx_status btx_batch_update_background_device(btx_batch *b, int32_t model, const btx_background *bg)
+{
+  if (!b || model < 0 || model >= (int)b->models.size()) return fail(BTX_E_INVAL, "bad batch or model index");
+  HIP_TRY(hipSetDevice(b->device));
+  return model_update_background(b->models[model], bg, b->d_models, b->parity, b->stream, b->device, true);
 }
 
 btx_status btx_batch_max_dt(const btx_batch *b, int32_t model, double cfl, double *dt_out)

@@ -188,7 +188,7 @@ def radiating_sphere_2d(n_r=100, n_theta=32, n_mu=16, n_phi=8, r_min=0.02, r_max
 def radiating_disk(n_r=100, n_theta=32, n_mu=16, n_phi=8, r_min=0.05, r_max=4.0, R=1.0,
                    mu_rule="lobatto"):
     """A geometrically thin, optically thick disk radiating into vacuum (Sec.
-    4.4): theta over [0, pi/2], the equatorial plane an isotropic f_eq = 1
+    4.5.2): theta over [0, pi/2], the equatorial plane an isotropic f_eq = 1
     emitter inside R and empty outside, kappa = 0 everywhere, one group,
     static flat background, logarithmic radial zones from r_min."""
     r_edges = log_edges(r_min, r_max, n_r)

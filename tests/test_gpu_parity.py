@@ -309,6 +309,96 @@ def test_evolving_background_gpu(precision, oracle_mod):
     ctx.close()
 
 
+def _device_bg(w):
+    import torch
+    vph = getattr(w, "v_phi", None)
+    d = {k: torch.from_numpy(np.ascontiguousarray(getattr(w, k), float).reshape(-1)).cuda()
+         for k in ("v_r", "v_theta", "alpha", "psi", "kappa_a", "kappa_s", "f_eq")}
+    if vph is not None:
+        d["v_phi"] = torch.from_numpy(np.ascontiguousarray(vph, float).reshape(-1)).cuda()
+    return d
+
+
+@pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
+def test_background_update_from_device_arrays(precision):
+    """btx_update_background_device (background arrays already in GPU memory)
+    gives bit for bit the state of btx_update_background from host arrays,
+    after the update and after more steps; an out-of-range device array is
+    refused with the state and background unchanged, and host pointers are
+    refused by the library itself"""
+    import ctypes as C
+    import torch
+    btx = _btx()
+    w = _perturb(W.extrude_phi(W.shock_2d(n_r=8, n_theta=4, n_eps=6, n_mu=4, n_phi=4, precision=W.PREC_FP64), 3))
+    w.v_phi = 0.01 * RNG.standard_normal(w.n_zones)
+    w2 = _evolved(w)
+    w2.v_phi = w.v_phi * 0.5
+    _say(f"[gpu] background update from device arrays, precision {precision}")
+    a, b = btx.Context(w, precision=precision), btx.Context(w, precision=precision)
+    for c in (a, b):
+        c.set_background()
+        c.set_state(w.f0)
+    dt = 0.9 * a.max_dt(0.4)
+    a.step(dt, 2)
+    b.step(dt, 2)
+    a.update_background(w2)
+    b.update_background_device(_device_bg(w2))
+    assert np.array_equal(a.get_state(), b.get_state())
+    a.step(dt, 2)
+    b.step(dt, 2)
+    assert np.array_equal(a.get_state(), b.get_state())
+    before = b.get_state()
+    bad = _device_bg(_evolved(w2))
+    bad["kappa_s"][5] = -1.0
+    with pytest.raises(btx.BtxError) as e:
+        b.update_background_device(bad)
+    assert e.value.status == btx.BTX_E_INVAL and "device" in str(e.value)
+    bad = _device_bg(_evolved(w2))
+    bad["v_r"][3] = 1.5
+    with pytest.raises(btx.BtxError) as e:
+        b.update_background_device(bad)
+    assert e.value.status == btx.BTX_E_INVAL
+    assert np.array_equal(b.get_state(), before)
+    b.step(dt, 1)
+    a.step(dt, 1)
+    assert np.array_equal(a.get_state(), b.get_state())       # the background did not change
+    hb, keep = btx._background(w2, w)                           # host pointers: refused by the library
+    st = btx.lib().btx_update_background_device(b.h, C.byref(hb))
+    assert st == btx.BTX_E_INVAL and b"device memory" in btx.lib().btx_last_error()
+    a.close()
+    b.close()
+
+
+def test_batch_background_update_from_device_arrays(tmp_path):
+    btx = _btx()
+    import torch
+    ws = W.batch_models(n_models=3, size_scale=0.04)
+    for w in ws:
+        w.precision = W.PREC_MIXED
+    _say("[gpu] batch background update from device arrays")
+    bs = []
+    for k in range(2):
+        bt = btx.Batch(ws, precision=W.PREC_MIXED, stream=torch.cuda.current_stream().cuda_stream,
+                       tune_cache=tmp_path / "tune.json")       # the second adopts the first's tuning
+        for m, w in enumerate(ws):
+            bt.set_background(m)
+            bt.set_state(m, w.f0)
+        bs.append(bt)
+    dts = [0.9 * bs[0].max_dt(m, 0.4) for m in range(len(ws))]
+    for bt in bs:
+        bt.step(dts, 2)
+    for m, w in enumerate(ws):
+        bs[0].update_background(m, _evolved(w))
+        bs[1].update_background_device(m, _device_bg(_evolved(w)))
+    for bt in bs:
+        bt.step(dts, 2)
+    for m in range(len(ws)):
+        assert tuple(bs[0].shape(m)) == tuple(bs[1].shape(m))
+        assert np.array_equal(bs[0].get_state(m), bs[1].get_state(m)), m
+    for bt in bs:
+        bt.close()
+
+
 def test_batch_evolving_background_gpu(oracle_mod):
     btx = _btx()
     import torch

@@ -57,6 +57,7 @@ struct DevGrid {
   const double *mu, *Phi, *dOm, *nvec, *G, *eps, *vol;
   const double *vr, *vth, *vph, *alp, *psi;
   const double *qpow;               // q^k for k = -128 .. 128 (index k + 128)
+  double iq1;                       // 1/(q - 1)
   const double *cphi, *sphi;        // cos and sin of the Phi nodes
 };
 
@@ -165,6 +166,7 @@ __device__ void change_basis(double ta, double pa, double tb, double pb, const d
 struct FrameP {
   Frame f;
   double gam, kv;              // 1/sqrt(1 - v^2), gam^2/(gam + 1)
+  double ia, ip2;              // 1/alpha, 1/psi^2
   double B[3][3];              // basis_cols(th, ph)
 };
 
@@ -175,6 +177,8 @@ __device__ inline FrameP prep_frame(const Frame &f)
   const double v2 = f.v[0] * f.v[0] + f.v[1] * f.v[1] + f.v[2] * f.v[2];
   p.gam = 1.0 / sqrt(1.0 - v2);
   p.kv = p.gam * p.gam / (p.gam + 1.0);
+  p.ia = 1.0 / f.alpha;
+  p.ip2 = 1.0 / (f.psi * f.psi);
   basis_cols(f.th, f.ph, p.B);
   return p;
 }
@@ -207,12 +211,12 @@ __device__ void frame_chain_p(const FrameP &SP, const FrameP &DP, int axis, bool
   double p2 = S.psi * S.psi;
   double uc[3] = { p2 * e[1], p2 * e[2], p2 * e[3] };  // covariant spatial components
   if (axis < 0 && (S.alpha != D.alpha || S.psi != D.psi)) {
-    u0 = -D.alpha * sqrt(uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]) / (D.psi * D.psi);
+    u0 = -D.alpha * sqrt(uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]) * DP.ip2;
   } else if (S.alpha != D.alpha || S.psi != D.psi) {
     double tr = 0.0;
     for (int i = 0; i < 3; ++i) if (i != axis) tr += uc[i] * uc[i];
     double dp2 = D.psi * D.psi;
-    double rad = dp2 * dp2 * u0 * u0 / (D.alpha * D.alpha) - tr;
+    double rad = dp2 * dp2 * u0 * u0 * (DP.ia * DP.ia) - tr;
     if (rad >= 0.0) {
       uc[axis] = copysign(sqrt(rad), uc[axis] >= 0.0 ? 1.0 : -1.0);
     } else {                                          // no real root: reflect along the axis
@@ -229,8 +233,7 @@ __device__ void frame_chain_p(const FrameP &SP, const FrameP &DP, int axis, bool
   } else {
     ud[0] = uc[0]; ud[1] = uc[1]; ud[2] = uc[2];
   }
-  double dp2 = D.psi * D.psi;
-  double eD[4] = { -u0 / D.alpha, ud[0] / dp2, ud[1] / dp2, ud[2] / dp2 };
+  double eD[4] = { -u0 * DP.ia, ud[0] * DP.ip2, ud[1] * DP.ip2, ud[2] * DP.ip2 };
   lorentz_p(DP, -1.0, eD, o);
 }
 
@@ -295,12 +298,12 @@ __host__ __device__ inline size_t buf_bytes(int nd, int nch, int ce, size_t szT)
 }
 
 // table-build scratch for tpr tables at a time: counts and cursors per
-// target, four records per source (target and shift; tap weights) and the
-// records' indexes in target order
+// target, four records per source (target and shift; tap weights), the
+// records' indexes in target order and their keys
 __host__ __device__ inline size_t scratch_bytes(int nd, size_t szT, int tpr = 4)
 {
   return (size_t)tpr * nd * 4 * 2 + (size_t)4 * tpr * nd * 4 + (size_t)8 * tpr * nd * szT +
-         (size_t)4 * tpr * nd * 4;
+         (size_t)4 * tpr * nd * 4 + (size_t)4 * tpr * nd * 2;
 }
 
 // 16-bit gather keys before their conversion to window offsets: the source
@@ -372,11 +375,11 @@ __device__ void remap_source(const DevGrid &g, const double *mu, const FrameP &S
   di = max(-127, min(127, di));
   while (di > -127 && rho < g.qpow[di + 128]) --di;
   while (di < 127 && rho >= g.qpow[di + 129]) ++di;
-  double we = (rho * g.qpow[128 - di] - 1.0) / (g.q - 1.0);
+  double we = (rho * g.qpow[128 - di] - 1.0) * g.iq1;
   we = fmin(1.0, fmax(0.0, we));
   di_out = di;
   // direction
-  double mus = fmin(1.0, fmax(-1.0, o[1] / o[0]));
+  double mus = fmin(1.0, fmax(-1.0, o[1] / rho));
   int jL, jR;
   double wj;
   node_bracket(mu, g.nmu, mus, jL, jR, wj);
@@ -397,8 +400,8 @@ __device__ void remap_source(const DevGrid &g, const double *mu, const FrameP &S
       // sine within rounding of zero (a direction on a node, where the split
       // is 0 or 1 either way) settles it too, so that it cannot flip between
       // the two brackets that share the node.
-      const double rp = sqrt(o[2] * o[2] + o[3] * o[3]);
-      const double c = o[2] / rp, sn = o[3] / rp;
+      const double irp = 1.0 / sqrt(o[2] * o[2] + o[3] * o[3]);
+      const double c = o[2] * irp, sn = o[3] * irp;
       float Pf = atan2f((float)o[3], (float)o[2]);
       if (Pf < 0.0f) Pf += 2.0f * (float)kPi;
       kl = (int)floorf(Pf / (float)dP - 0.5f);
@@ -578,6 +581,7 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
   int *rtg = cur + TPR * nd;                   // 4 TPR nd
   T *rcf = (T *)(rtg + 4 * TPR * nd);          // 8 TPR nd
   int *idx = (int *)(rcf + 8 * TPR * nd);      // 4 TPR nd
+  unsigned short *skey = (unsigned short *)(idx + 4 * TPR * nd);  // 4 TPR nd: key of each placed record
   // the mu nodes, searched for every direction of every table
   double *smu = (double *)(data + align16(scratch_bytes(nd, sizeof(T), TPR)));
   for (int q = tid; q < g.nmu; q += nthr) smu[q] = g.mu[q];
@@ -662,7 +666,9 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
       for (int r = 0; r < 4; ++r) {
         const int v = rtg[q * 4 + r];
         if (v < 0) continue;
-        idx[tl * 4 * nd + atomicAdd(&cur[tl * nd + (v & 0xffff)], 1)] = q * 4 + r;
+        const int sl = tl * 4 * nd + atomicAdd(&cur[tl * nd + (v & 0xffff)], 1);
+        idx[sl] = q * 4 + r;
+        skey[sl] = pack_key(q - tl * nd, (v >> 16) - 128, nd);
       }
     }
     __syncthreads();
@@ -679,12 +685,10 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
       if (sl >= start[nd]) continue;
       const int rec = idx[x], v = rtg[rec];
       const int tg = v & 0xffff, a = start[tg], b = start[tg + 1];
-      const unsigned kx = pack_key(rec / 4 - tl * nd, (v >> 16) - 128, nd);
+      const unsigned kx = skey[x];
+      const unsigned short *lk = skey + tl * 4 * nd;
       int rank = 0;
-      for (int y = a; y < b; ++y) {
-        const int ry = idx[tl * 4 * nd + y];
-        rank += pack_key(ry / 4 - tl * nd, (rtg[ry] >> 16) - 128, nd) < kx;
-      }
+      for (int y = a; y < b; ++y) rank += lk[y] < kx;
       const int slot = a + rank;
       key[slot] = (start[nd + 1] & 1) ? (unsigned short)kx
                                       : (unsigned short)((rec / 4 - tl * nd) * cs - ((v >> 16) - 128) + 2);

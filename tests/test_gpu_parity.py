@@ -309,6 +309,44 @@ def test_evolving_background_gpu(precision, oracle_mod):
     ctx.close()
 
 
+def _many_rows(ns, ne, precision):
+    """a small shock-profile grid with ns species of ne groups: ns ne (species,
+    group) rows per zone, near the 2048 the library accepts"""
+    w = W.shock_2d(n_r=3, n_theta=2, n_eps=ne, n_mu=2, n_phi=4, precision=precision)
+    rep = lambda a: np.concatenate([a[:, k % 3:k % 3 + 1] * (1.0 + 0.05 * k) for k in range(ns)], axis=1)
+    w.kappa_a, w.kappa_s = rep(w.kappa_a), rep(w.kappa_s)
+    w.f_eq = np.concatenate([w.f_eq[:, k % 3:k % 3 + 1] for k in range(ns)], axis=1)
+    w.n_species = ns
+    w.f0 = np.repeat(w.f_eq[..., None], w.n_dir, axis=3) * (1.0 + 0.3 * RNG.random((w.n_zones, ns, ne, w.n_dir)))
+    return w
+
+
+@pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
+def test_rows_near_the_limit(precision, oracle_mod):
+    """34 species x 60 groups = 2040 (species, group) rows a zone, near the
+    documented limit of 2048: the zone kernel's LDS (40 B a row, 82 KB) is
+    above the default 64 KB and must be raised before its launch.  Two steps
+    against the reference."""
+    btx = _btx()
+    w = _many_rows(34, 60, precision)
+    _say(f"[gpu] 2040 rows a zone, precision {precision}")
+    ctx = btx.Context(w, precision=precision)
+    ctx.set_background()
+    ctx.set_state(w.f0)
+    dt = ctx.max_dt(0.4)
+    ctx.step(dt, 2)
+    o = oracle_mod.Oracle(w)
+    o.step(dt, 2)
+    ref, got = o.state(), ctx.get_state()
+    err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    _say(f"[gpu]   rel err {err:.3e}")
+    assert err <= (1e-12 if precision == W.PREC_FP64 else 1e-5)
+    ctx.close()
+    with pytest.raises(btx.BtxError) as e:              # 35 x 60 = 2100 rows: refused at creation
+        btx.Context(_many_rows(35, 60, precision), precision=precision)
+    assert e.value.status == btx.BTX_E_UNSUPPORTED
+
+
 def _device_bg(w):
     import torch
     vph = getattr(w, "v_phi", None)

@@ -4,10 +4,24 @@ axisymmetry).
 Radiating disk: theta over [0, pi/2] with the equatorial disk boundary; a
 thick f = 1 disk of radius 1 radiates into vacuum. The stationary mean
 intensity is compared with the exact solid-angle integral away from the
-plane itself. The paper sees an artefact at x = 0 confined to the three
-theta rows next to the pole; here it reaches into rows 3-4 with 16 x 8
-directions (measured: 0.14 there), so those rows have their own, looser
-bound and rows 0-2 are left out as in the paper.
+plane itself (z > 0.1) and from the inner boundary (r > 2.5 r_min), in three
+regions whose bounds come from a study of
+the disk on the CPU reference (N_theta 8-32, N_mu 8-16, N_Phi 4-16, both Phi
+splits, inner radius 0.1 and 0.2):
+  * the theta rows within 8.4 degrees of the pole: the axis artefact the
+    paper reports; reported, not bounded (it grows with N_theta and with
+    N_Phi at fixed N_mu, and is larger with the linear Phi split);
+  * off the axis rows, within 4 inner radii: the specular inner boundary
+    returns radiation that would pass through the centre; its error falls
+    with N_mu (0.10 -> 0.05 for N_mu 8 -> 16) and grows with N_Phi at fixed
+    N_mu (0.10 -> 0.18 for N_Phi 8 -> 16) and with N_theta (0.10 -> 0.24 for
+    16 -> 32 rows); bounded by 0.25, above the study's largest (0.24);
+  * the rest: ray effects, falling with N_Phi (0.15, 0.05-0.07, 0.04-0.06
+    for N_Phi = 4, 8, 16 at 16 rows), largest where the two other regions
+    meet (0.097 at 32 rows, N_mu = 8); bounded by 0.1, and by 0.03 in the
+    mean (the study's means: 0.021-0.025).
+The GPU runs take 16 or 17 mu nodes, which the study shows lowers the
+errors near the axis and the inner boundary.
 
 The homogeneous radiating sphere (kappa_a R = 10) is run on the axisymmetric
 grid to a stationary state in FP64. Along rays near the pole, at 45 degrees
@@ -45,6 +59,29 @@ def _pins():
     sys.path.insert(0, __import__("os").path.dirname(__file__))
     import test_oracle_pins
     return test_oracle_pins
+
+
+def _disk_regions(w, zm):
+    """|J - exact| of the radiating disk in the three regions of the module
+    docstring: {name: errors}, with the zones' (x, z) for reports"""
+    rc = np.tile(0.5 * (w.r_edges[1:] + w.r_edges[:-1]), w.n_theta)
+    thc = np.repeat(0.5 * (w.theta_edges[1:] + w.theta_edges[:-1]), w.n_r)
+    J = zm[:, 0, 1] / (np.sqrt(2.0) * 7.0 / 3.0)
+    x, z = rc * np.sin(thc), rc * np.cos(thc)
+    sel = (z > 0.1) & (rc < 2.5) & (rc > 2.5 * w.r_edges[0])
+    exact = np.array([_pins()._disk_exact(a, b) for a, b in zip(x[sel], z[sel])])
+    err = np.abs(J[sel] - exact)
+    axis = np.degrees(thc[sel]) < 8.44
+    inner = ~axis & (rc[sel] < 4.0 * w.r_edges[0])
+    rest = ~axis & ~inner
+    out = {}
+    for name, m in (("axis rows", axis), ("2.5-4 r_min", inner), ("rest", rest)):
+        e = err[m]
+        q = int(np.argmax(e))
+        _say(f"[gpu]   {name}: |J - exact| max {e.max():.4f} at x={x[sel][m][q]:.3f} z={z[sel][m][q]:.3f}, "
+             f"mean {e.mean():.4f} ({m.sum()} zones)")
+        out[name] = e
+    return out
 
 
 def _sphere_exact(x, kappa):
@@ -100,25 +137,9 @@ def test_radiating_disk_2d():
     ctx.step(dt, steps)
     zm, tot = ctx.moments()
     ctx.close()
-    rc = np.tile(0.5 * (w.r_edges[1:] + w.r_edges[:-1]), w.n_theta)
-    thc = np.repeat(0.5 * (w.theta_edges[1:] + w.theta_edges[:-1]), w.n_r)
-    J = zm[:, 0, 1] / (np.sqrt(2.0) * 7.0 / 3.0)
-    x, z = rc * np.sin(thc), rc * np.cos(thc)
-    row = np.arange(w.n_zones) // w.n_r
-    sel = (z > 0.1) & (row >= 3) & (rc < 2.5)
-    exact = np.array([_pins()._disk_exact(a, b) for a, b in zip(x[sel], z[sel])])
-    err = np.abs(J[sel] - exact)
-    for zz in (0.25, 0.5, 1.0):
-        near = np.abs(z[sel] - zz) < 0.03
-        for q in np.argsort(x[sel][near])[::3]:
-            _say(f"[gpu]   z={z[sel][near][q]:.3f} x={x[sel][near][q]:.3f} J {J[sel][near][q]:.4f} "
-                 f"exact {exact[near][q]:.4f}")
-    for lo, hi in ((3, 5), (5, w.n_theta)):
-        part = err[(row[sel] >= lo) & (row[sel] < hi)]
-        _say(f"[gpu]   theta rows {lo}-{hi - 1}: |J - exact| max {part.max():.4f}, mean {part.mean():.4f}")
-    _say(f"[gpu]   all: max {err.max():.4f}, mean {err.mean():.4f}; outflow {tot[0, 1]:.4g}")
-    assert err[row[sel] >= 5].max() < 0.07 and err.mean() < 0.03
-    assert err.max() < 0.16                          # rows 3-4: the axis artefact
+    e = _disk_regions(w, zm)
+    assert e["rest"].max() < 0.1 and e["rest"].mean() < 0.03
+    assert e["2.5-4 r_min"].max() < 0.25
 
 
 def test_3d_symmetric_equals_axisymmetric_gpu():
@@ -227,30 +248,13 @@ def test_radiating_sphere_2d_paper_resolution():
 def test_radiating_disk_paper_resolution():
     """the radiating disk at the paper's resolution (100 x 32 zones, 17 x 32
     directions) with time levels up to 5, against the exact solid-angle
-    integral.  Zones within 2.5 r_min are left out: the specular inner
-    boundary at r_min reflects radiation that would cross the centre.  The
-    mean error falls from 0.023 (16 x 8) to 0.015; the axis artefact the
-    paper reports grows with the finer Phi grid: measured 0.18 in rows 3-4
-    and 0.096 from row 5 on (bounds 0.2 and 0.11)."""
+    integral, in the regions and with the bounds of the module docstring"""
     btx = _btx()
     w = W.radiating_disk(n_r=100, n_theta=32, n_mu=17, n_phi=32, r_min=0.1, r_max=4.0,
                          mu_rule="legendre")
     _say(f"[gpu] radiating disk, {w.n_zones} zones x {w.n_dir} directions")
     zm, tot, steps, L = _levels_run(btx, w, 4.5)
-    rc = np.tile(0.5 * (w.r_edges[1:] + w.r_edges[:-1]), w.n_theta)
-    thc = np.repeat(0.5 * (w.theta_edges[1:] + w.theta_edges[:-1]), w.n_r)
-    J = zm[:, 0, 1] / (np.sqrt(2.0) * 7.0 / 3.0)
-    x, z = rc * np.sin(thc), rc * np.cos(thc)
-    row = np.arange(w.n_zones) // w.n_r
-    sel = (z > 0.1) & (row >= 3) & (rc < 2.5) & (rc > 2.5 * w.r_edges[0])
-    exact = np.array([_pins()._disk_exact(a, b) for a, b in zip(x[sel], z[sel])])
-    err = np.abs(J[sel] - exact)
-    for lo, hi in ((3, 5), (5, w.n_theta)):
-        part = err[(row[sel] >= lo) & (row[sel] < hi)]
-        _say(f"[gpu]   theta rows {lo}-{hi - 1}: |J - exact| max {part.max():.4f}, mean {part.mean():.4f}")
-    worst = np.argsort(-err)[:4]
-    for q in worst:
-        _say(f"[gpu]     x={x[sel][q]:.3f} z={z[sel][q]:.3f} J {J[sel][q]:.4f} exact {exact[q]:.4f}")
-    _say(f"[gpu]   {steps} steps of {2 ** L} substeps; all: max {err.max():.4f}, mean {err.mean():.4f}")
-    assert err[row[sel] >= 5].max() < 0.11 and err.mean() < 0.02
-    assert err.max() < 0.2
+    _say(f"[gpu]   {steps} steps of {2 ** L} substeps")
+    e = _disk_regions(w, zm)
+    assert e["rest"].max() < 0.1 and e["rest"].mean() < 0.03
+    assert e["2.5-4 r_min"].max() < 0.25

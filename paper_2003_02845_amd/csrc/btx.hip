@@ -532,19 +532,20 @@ btx_status launch_faces(const FaceShape &shape, size_t tsize, const ModelDev *d_
   return BTX_OK;
 }
 
-// zone kernel LDS: five FP64 row values per (species, group) row
-size_t zone_lds_bytes(int rows) { return (size_t)std::max(rows, 1) * 5 * sizeof(double); }
+// zone kernel LDS: five FP64 row values per (species, group) row, one FP64
+// direction weight per direction
+size_t zone_lds_bytes(int rows, int dirs) { return ((size_t)std::max(rows, 1) * 5 + (size_t)dirs) * sizeof(double); }
 
 btx_status launch_zones(size_t tsize, const ModelDev *d_models, const int2 *items, int n, int max_rows,
-                        int parity, hipStream_t s, int max_dirs = 0)
+                        int parity, hipStream_t s, int max_dirs)
 {
   if (n == 0) return BTX_OK;
   const void *zk = max_dirs > 256 ? (tsize == 8 ? (const void *)zone_kernel<double, 16> : (const void *)zone_kernel<float, 16>)
                                   : (tsize == 8 ? (const void *)zone_kernel<double, 4> : (const void *)zone_kernel<float, 4>);
-  btx_status st = raise_lds_limit(zk, zone_lds_bytes(max_rows));
+  btx_status st = raise_lds_limit(zk, zone_lds_bytes(max_rows, max_dirs));
   if (st != BTX_OK) return st;
   void *args[] = { &d_models, &items, &parity };
-  HIP_TRY(hipLaunchKernel(zk, dim3(n), dim3(256), args, zone_lds_bytes(max_rows), s));
+  HIP_TRY(hipLaunchKernel(zk, dim3(n), dim3(256), args, zone_lds_bytes(max_rows, max_dirs), s));
   return BTX_OK;
 }
 

@@ -1286,9 +1286,16 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   const double p6v = pow(g.psi[z], 6.0) * g.vol[z];
   const double tau = g.alp[z] * dt / gam;
   // per (species, group) row: the sums of S dOmega and S dOmega n (r, theta,
-  // phi), for the source terms after the update
+  // phi), for the source terms after the update; then per direction
+  // 1 / ((1 + v.n) dOmega), the direction's part of the content weight
   extern __shared__ __align__(16) char lds[];
   double *rs = (double *)lds;
+  double *iwd = rs + 5 * (size_t)g.ns * ne;
+  for (int d = threadIdx.x; d < nd; d += blockDim.x) {
+    const double *nv = g.nvec + 3 * d;
+    iwd[d] = 1.0 / ((1.0 + vr * nv[0] + vt * nv[1] + vp * nv[2]) * g.dOm[d]);
+  }
+  __syncthreads();
   // a row's opacities are loaded one row ahead, with the previous row's data
   const int nrows = g.ns * ne;
   const size_t kz = (size_t)z * nrows;
@@ -1304,6 +1311,8 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
       fen = feq[kz + nx];
     }
     bool wide = (sizeof(T) == 8) || tau * (ka_ + ks_) > g.fp64_thr;
+    const double ci = 1.0 / (p6v * gam * g.G[i]);      // the row's part of 1/W
+    const double src = tau * ka_ * fe_;
     double Sd[R];
     double part = 0.0;
     for (int r = 0; r < R; ++r) {
@@ -1320,15 +1329,19 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
 #pragma unroll
       for (int q = 0; q < 8; ++q)
         if (q < nq) acc += (double)dv[q];
-      const double *nv = g.nvec + 3 * d;
-      double W = p6v * gam * (1.0 + vr * nv[0] + vt * nv[1] + vp * nv[2]) * g.G[i] * g.dOm[d];
-      double S = (double)fz + tau * ka_ * fe_ + acc / W;
+      // content -> occupation: / W, W = psi^6 dV gamma (1 + v.n) G_i dOmega_d
+      double S = (double)fz + src + acc * (ci * iwd[d]);
       if (!wide) S = (double)(float)S;
       Sd[r] = S;
       part += S * g.dOm[d];
     }
     const double ssum = wave_sum(part);
     double avg = ssum / (4.0 * kPi);
+    // the implicit solve f' = (S + tau ks avg / (1 + tau ka)) / (1 + tau (ka + ks)),
+    // its row constants once per row (in FP32 for an optically thin row)
+    const double sh = tau * ks_ * avg / (1.0 + tau * ka_), rden = 1.0 / (1.0 + tau * (ka_ + ks_));
+    const float tf = (float)tau, af = (float)ka_, bf = (float)ks_;
+    const float shf = tf * bf * (float)avg / (1.0f + tf * af), rdenf = 1.0f / (1.0f + tf * (af + bf));
     double pr = 0.0, pt = 0.0, pp = 0.0;
     for (int r = 0; r < R; ++r) {
       int d = lane + 64 * r;
@@ -1338,12 +1351,7 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
       pr += sw * g.nvec[3 * d];
       pt += sw * g.nvec[3 * d + 1];
       pp += sw * g.nvec[3 * d + 2];
-      double out;
-      if (wide) out = (Sd[r] + tau * ks_ * avg / (1.0 + tau * ka_)) / (1.0 + tau * (ka_ + ks_));
-      else {
-        float t = (float)tau, a = (float)ka_, b = (float)ks_;
-        out = ((float)Sd[r] + t * b * (float)avg / (1.0f + t * a)) / (1.0f + t * (a + b));
-      }
+      const double out = wide ? (Sd[r] + sh) * rden : (double)(((float)Sd[r] + shf) * rdenf);
       fout[(size_t)z * g.blk + off] = (T)out;
     }
     wave_sum3(pr, pt, pp);

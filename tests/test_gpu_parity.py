@@ -309,6 +309,49 @@ def test_evolving_background_gpu(precision, oracle_mod):
     ctx.close()
 
 
+DEGENERATE = {
+    "one_zone_column": lambda: W.radiating_sphere(n_r=1, n_eps=1, n_mu=2, n_phi=4, r_max=1.0, R=2.0),
+    "one_zone_2d": lambda: _perturb(W.shock_2d(n_r=1, n_theta=1, n_eps=1, n_mu=2, n_phi=4, precision=W.PREC_FP64)),
+    "one_zone_slab": lambda: W.planar(n_z=1, n_eps=1, n_mu=2, kappa_a=1.0, f_eq=0.5),
+}
+
+
+@pytest.mark.parametrize("case", sorted(DEGENERATE))
+@pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
+def test_degenerate_grids(case, precision, oracle_mod):
+    """the smallest grids: one zone (every face a boundary or the zone's own
+    image), one group, two mu nodes; three steps against the reference, zero
+    steps leave the state untouched, and a zero state with no opacity and no
+    equilibrium stays exactly zero"""
+    btx = _btx()
+    w = DEGENERATE[case]()
+    _say(f"[gpu] degenerate grid {case}, precision {precision}")
+    ctx = btx.Context(w, precision=precision)
+    ctx.set_background()
+    ctx.set_state(w.f0)
+    dt = ctx.max_dt(0.4)
+    before = ctx.get_state()
+    ctx.step(dt, 0)
+    assert np.array_equal(ctx.get_state(), before)
+    ctx.step(dt, 3)
+    o = oracle_mod.Oracle(w)
+    o.step(dt, 3)
+    ref, got = o.state(), ctx.get_state()
+    scale = max(np.max(np.abs(ref)), 1e-300)
+    err = float(np.max(np.abs(got - ref)) / scale)
+    _say(f"[gpu]   rel err {err:.3e}")
+    assert err <= (1e-12 if precision == W.PREC_FP64 else 1e-5)
+    w0 = DEGENERATE[case]()
+    w0.kappa_a = np.zeros_like(w0.kappa_a)
+    w0.kappa_s = np.zeros_like(w0.kappa_s)
+    w0.f_eq = np.zeros_like(w0.f_eq)
+    ctx.set_background(w0)
+    ctx.set_state(np.zeros(ctx.shape))
+    ctx.step(dt, 2)
+    assert not np.any(ctx.get_state())
+    ctx.close()
+
+
 def _many_rows(ns, ne, precision):
     """a small shock-profile grid with ns species of ne groups: ns ne (species,
     group) rows per zone, near the 2048 the library accepts"""

@@ -631,6 +631,49 @@ def test_time_levels_gpu(case, precision, oracle_mod):
     ctx.close()
 
 
+@pytest.mark.parametrize("precision", [W.PREC_FP64, W.PREC_MIXED])
+def test_time_levels_with_evolving_background_device(precision, oracle_mod):
+    """the features together on the 3D grid: time levels, a background update
+    from GPU arrays between level-stepped steps (v_phi included), then more
+    steps; against the reference (FP64 1e-12 in the state, mixed 1e-5 in the
+    zone moments)"""
+    btx = _btx()
+    w = CASES["shock_3d"]()
+    w.v_phi = 0.02 * RNG.standard_normal(w.n_zones)
+    w2 = _evolved(w)
+    w2.v_phi = -0.5 * w.v_phi
+    _say(f"[gpu] time levels and an evolving background (3D), precision {precision}")
+    o = oracle_mod.Oracle(w)
+    ctx = btx.Context(w, precision=precision)
+    ctx.set_background()
+    ctx.set_state(w.f0)
+    lev = ctx.time_levels(2)
+    assert lev.max() >= 1
+    ctx.set_time_levels(lev)
+    o.set_levels(lev)
+    dt = 0.9 * o.max_dt(0.4)
+    ctx.step(dt, 1)
+    o.step(dt, 1)
+    ctx.update_background_device(_device_bg(w2))
+    o.update_background(w2)
+    ctx.step(dt, 2)
+    o.step(dt, 2)
+    if precision == W.PREC_FP64:
+        ref, got = o.state(), ctx.get_state()
+        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        _say(f"[gpu]   rel err {err:.3e}")
+        assert err <= 1e-12
+    else:
+        zr, _ = o.moments()
+        zg, _ = ctx.moments()
+        mask = np.abs(zr[..., 1]) > 1e-8 * np.abs(zr[..., 1]).max()
+        for k in (0, 1):
+            rel = np.max(np.abs(zg[..., k] - zr[..., k])[mask] / np.abs(zr[..., k][mask]))
+            _say(f"[gpu]   moment {k} rel err {rel:.3e}")
+            assert rel <= 1e-5
+    ctx.close()
+
+
 def test_evolving_background_wide_gpu(oracle_mod):
     """a background update on a grid of 544 directions (wide gather keys in the
     time remap): FP64 against the reference"""

@@ -902,6 +902,10 @@ struct btx_batch {
   size_t tsize = 8;
   hipStream_t stream = nullptr;      // caller's stream: all work is ordered on it
   hipStream_t cap = nullptr;         // library stream used only to capture graphs
+  // side streams and events of the captured graph's parallel branches (one
+  // face launch per shape group each), created with the first capture
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev;
   ModelDev *d_models = nullptr;
   std::vector<ModelDev> h_models;
   std::vector<BatchGroup> groups;
@@ -939,6 +943,8 @@ void free_batch(btx_batch *b)
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (hipStream_t x : b->side) (void)hipStreamDestroy(x);
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
   delete b;
 }
 
@@ -1202,13 +1208,48 @@ btx_status batch_launch_lts(btx_batch *b, hipStream_t s)
   return BTX_OK;
 }
 
+// One step as graph branches: the face launches of the shape groups run side
+// by side (each writes only its own faces' changes), joined before the zone
+// launch.  Called while b->cap is being captured.
+btx_status batch_launch_branches(btx_batch *b, int parity)
+{
+  const size_t ng = b->groups.size();
+  HIP_TRY(hipEventRecord(b->ev[ng], b->cap));
+  for (size_t gi = 0; gi < ng; ++gi) {
+    const BatchGroup &gr = b->groups[gi];
+    HIP_TRY(hipStreamWaitEvent(b->side[gi], b->ev[ng], 0));
+    btx_status st = launch_faces(gr.shape, b->tsize, b->d_models, b->d_gitems + gr.first, gr.count, gr.threads,
+                                 gr.lds, parity, b->side[gi]);
+    if (st != BTX_OK) return st;
+    HIP_TRY(hipEventRecord(b->ev[gi], b->side[gi]));
+    HIP_TRY(hipStreamWaitEvent(b->cap, b->ev[gi], 0));
+  }
+  int rows = 1, dirs = 0;
+  for (const Model &m : b->models) {
+    rows = std::max(rows, m.g.ns * m.g.ne);
+    dirs = std::max(dirs, m.g.ndir);
+  }
+  return launch_zones(b->tsize, b->d_models, b->d_zitems, b->nz_all, rows, parity, b->cap, dirs);
+}
+
 // the step of each parity captured once as a graph on the library's stream
 btx_status capture_graphs(btx_batch *b)
 {
+  const size_t ng = b->groups.size();
+  while (b->side.size() < ng) {                        // default priority, like every stream here
+    hipStream_t x;
+    HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    b->side.push_back(x);
+  }
+  while (b->ev.size() < ng + 1) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    b->ev.push_back(e);
+  }
   for (int p = 0; p < 2; ++p) {
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    btx_status st = batch_launch(b, p, b->cap);
+    btx_status st = batch_launch_branches(b, p);
     hipError_t he = hipStreamEndCapture(b->cap, &g);
     if (st != BTX_OK) { if (g) (void)hipGraphDestroy(g); return st; }
     if (he != hipSuccess) return fail(BTX_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(he));

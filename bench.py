@@ -211,17 +211,29 @@ def cpu_baseline(n_theta):
     import subprocess
     avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     threads = int(os.environ.get("OMP_NUM_THREADS", avail))
-    runs = {}
-    for nt, rows in ((threads, n_theta), (1, 8)):
+    def leg(nt, rows):
         env = dict(os.environ, OMP_NUM_THREADS=str(nt), OMP_PROC_BIND="false")
-        res = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--cpu-leg", str(nt), str(rows)],
-                             env=env, capture_output=True, text=True, timeout=900)
+        try:
+            res = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--cpu-leg", str(nt), str(rows)],
+                                 env=env, capture_output=True, text=True, timeout=900)
+        except subprocess.TimeoutExpired:
+            return None
         if res.returncode != 0:
-            raise RuntimeError("CPU reference leg failed:\n" + res.stdout[-2000:] + res.stderr[-2000:])
-        runs[nt] = json.loads(res.stdout.strip().splitlines()[-1])
-        print(f"[bench] cpu: {nt} thread(s), {rows} theta rows: {runs[nt]['seconds']:.1f} s",
-              file=sys.stderr, flush=True)
-    full, one = runs[threads], runs[1]
+            print(f"[bench] cpu leg ({nt} threads, {rows} rows) failed: {res.stderr[-500:]}", file=sys.stderr,
+                  flush=True)
+            return None
+        r = json.loads(res.stdout.strip().splitlines()[-1])
+        print(f"[bench] cpu: {nt} thread(s), {rows} theta rows: {r['seconds']:.1f} s", file=sys.stderr, flush=True)
+        return r
+    # the whole grid needs about 90 GB of host memory; a quarter of it if that fails
+    full = leg(threads, n_theta)
+    if full is None and n_theta > 64:
+        n_theta = 64
+        full = leg(threads, n_theta)
+    one = leg(1, 8)
+    if full is None or one is None:
+        return {"value": None, "unit": "zone*group*direction updates/s", "cores": threads, "kind": "oracle",
+                "sample": "the CPU reference legs did not complete", "cpu_model": cpu_model()}
     return {"value": full["values"] / full["seconds"], "unit": "zone*group*direction updates/s",
             "cores": threads, "kind": "oracle",
             "sample": f"one FP64 step of the benchmark grid, 600 r x {n_theta} theta zones "
@@ -468,7 +480,8 @@ def main():
               f"{bt['speedup_vs_global_step']:.2f}x the simulated time per second", file=sys.stderr, flush=True)
     if cpu is not None:
         out["cpu_baseline"] = cpu
-        out["cpu_baseline"]["gpu_speedup"] = value / cpu["value"]
+        if cpu["value"]:
+            out["cpu_baseline"]["gpu_speedup"] = value / cpu["value"]
     print(json.dumps(out), flush=True)
 
 

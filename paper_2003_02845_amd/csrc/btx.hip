@@ -916,6 +916,7 @@ struct btx_batch {
   int parity = 0;
   bool tuned = false, use_graph = true;
   hipGraphExec_t exec[2] = { nullptr, nullptr };
+  hipGraphExec_t exec_lts = nullptr;  // the time-level step (2^L substeps), once captured
   std::string tune_path;
   // local time stepping: once a model is given time levels, every model
   // updates in place and a step is 2^L substeps (L the largest level);
@@ -933,6 +934,7 @@ void drop_graphs(btx_batch *b)
 {
   for (auto &e : b->exec)
     if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
+  if (b->exec_lts) { (void)hipGraphExecDestroy(b->exec_lts); b->exec_lts = nullptr; }
 }
 
 void free_batch(btx_batch *b)
@@ -1137,6 +1139,7 @@ btx_status batch_launch(btx_batch *b, int parity, hipStream_t s)
 // (model, zone) item by its zone's level, with the counts up to each level.
 btx_status build_lts_lists(btx_batch *b)
 {
+  if (b->exec_lts) { (void)hipGraphExecDestroy(b->exec_lts); b->exec_lts = nullptr; }
   int L = 0;
   for (const Model &m : b->models) L = std::max(L, m.lmax);
   std::vector<int2> fit, zit;
@@ -1232,8 +1235,8 @@ btx_status batch_launch_branches(btx_batch *b, int parity)
   return launch_zones(b->tsize, b->d_models, b->d_zitems, b->nz_all, rows, parity, b->cap, dirs);
 }
 
-// the step of each parity captured once as a graph on the library's stream
-btx_status capture_graphs(btx_batch *b)
+// side streams and events for the branches of the captured graphs
+btx_status branch_streams(btx_batch *b)
 {
   const size_t ng = b->groups.size();
   while (b->side.size() < ng) {                        // default priority, like every stream here
@@ -1246,6 +1249,56 @@ btx_status capture_graphs(btx_batch *b)
     HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     b->ev.push_back(e);
   }
+  return BTX_OK;
+}
+
+// The time-level step (2^L substeps, as batch_launch_lts) captured once as a
+// graph: each substep's face launches as branches, joined before its zone
+// launch.  Recaptured when the level lists change.
+btx_status capture_lts_graph(btx_batch *b)
+{
+  btx_status st = branch_streams(b);
+  if (st != BTX_OK) return st;
+  const size_t ng = b->groups.size();
+  const int L = b->lts_L;
+  int rows = 1, dirs = 0;
+  for (const Model &m : b->models) {
+    rows = std::max(rows, m.g.ns * m.g.ne);
+    dirs = std::max(dirs, m.g.ndir);
+  }
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < (1 << L) && st == BTX_OK; ++k) {
+    const int lf = k == 0 ? L : std::min(L, __builtin_ctz(k));
+    const int lz = std::min(L, __builtin_ctz(k + 1));
+    hipError_t he = hipEventRecord(b->ev[ng], b->cap);
+    for (size_t gi = 0; gi < ng && st == BTX_OK && he == hipSuccess; ++gi) {
+      const BatchGroup &gr = b->groups[gi];
+      if (b->gf_lev[gi][lf] == 0) continue;
+      he = hipStreamWaitEvent(b->side[gi], b->ev[ng], 0);
+      if (he == hipSuccess)
+        st = launch_faces(gr.shape, b->tsize, b->d_models, b->d_gitems_lts + gr.first_lts, b->gf_lev[gi][lf],
+                          gr.threads, gr.lds, 0, b->side[gi], k);
+      if (st == BTX_OK && he == hipSuccess) he = hipEventRecord(b->ev[gi], b->side[gi]);
+      if (st == BTX_OK && he == hipSuccess) he = hipStreamWaitEvent(b->cap, b->ev[gi], 0);
+    }
+    if (he != hipSuccess && st == BTX_OK) st = fail(BTX_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(he));
+    if (st == BTX_OK) st = launch_zones(b->tsize, b->d_models, b->d_zitems_lts, b->z_lev[lz], rows, 0, b->cap, dirs);
+  }
+  hipError_t he = hipStreamEndCapture(b->cap, &g);
+  if (st != BTX_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+  if (he != hipSuccess) return fail(BTX_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(he));
+  he = hipGraphInstantiate(&b->exec_lts, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (he != hipSuccess) return fail(BTX_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(he));
+  return BTX_OK;
+}
+
+// the step of each parity captured once as a graph on the library's stream
+btx_status capture_graphs(btx_batch *b)
+{
+  btx_status bst = branch_streams(b);
+  if (bst != BTX_OK) return bst;
   for (int p = 0; p < 2; ++p) {
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
@@ -1545,10 +1598,15 @@ btx_status btx_batch_step(btx_batch *b, const double *dt_per_model, int32_t n_st
     if ((st = upload_descriptors(b)) != BTX_OK) return st;
   }
   if (!b->tuned && (st = tune(b)) != BTX_OK) return st;
-  if (b->lts) {                                      // time levels: in place, no graphs
+  if (b->lts) {                                      // time levels: in place
     if (b->lts_dirty && (st = build_lts_lists(b)) != BTX_OK) return st;
-    for (int t = 0; t < n_steps; ++t)
-      if ((st = batch_launch_lts(b, b->stream)) != BTX_OK) return st;
+    // a graph of 2^L substeps only up to 64 of them; deeper hierarchies launch directly
+    const bool graph = b->use_graph && b->lts_L <= 6;
+    if (graph && !b->exec_lts && (st = capture_lts_graph(b)) != BTX_OK) return st;
+    for (int t = 0; t < n_steps; ++t) {
+      if (graph) HIP_TRY(hipGraphLaunch(b->exec_lts, b->stream));
+      else if ((st = batch_launch_lts(b, b->stream)) != BTX_OK) return st;
+    }
     return BTX_OK;
   }
   if (b->use_graph && !b->exec[0] && (st = capture_graphs(b)) != BTX_OK) return st;

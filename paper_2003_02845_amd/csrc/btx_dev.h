@@ -1255,12 +1255,44 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
 
 // ------------------------------------------------------------ zone kernel
 
-// R: directions per lane (64 R directions at most).  A direction's loads (the
-// state and the changes from every face side of the zone) all go out before
-// the first is used; at 4 waves per SIMD (not 8) the compiler keeps them in
-// registers, and the kernel is faster for it.  With 16 directions per lane
-// (above 256 directions) the register bound is that of 2 waves per SIMD: at
-// 4 the kernel spilled; it takes about 120 registers.
+// segmented wave sum over aligned groups of W lanes (W a power of two)
+__device__ inline double seg_sum(double v, int W)
+{
+  for (int o = W >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline void seg_sum3(double &a, double &b, double &c, int W)
+{
+  for (int o = W >> 1; o > 0; o >>= 1) {
+    const double x = __shfl_xor(a, o, 64), y = __shfl_xor(b, o, 64), w = __shfl_xor(c, o, 64);
+    a += x;
+    b += y;
+    c += w;
+  }
+}
+
+// Lanes per (species, group) row in the zone kernel: the power of two W
+// (4 .. 64) with at most R directions per lane that leaves the fewest lanes
+// idle (the widest among equals); 64 / W rows then share a wave.
+__host__ __device__ inline int zone_row_lanes(int nd, int R)
+{
+  int W = 64, best = 64 * ((nd + 63) / 64);
+  for (int w = 32; w >= 4; w >>= 1) {
+    const int k = (nd + w - 1) / w;
+    if (k > R) break;
+    if (w * k < best) { best = w * k; W = w; }
+  }
+  return W;
+}
+
+// R: directions per lane (64 R directions at most).  W lanes take a row
+// (zone_row_lanes), lane j of them the directions j, j + W, ...  A direction's
+// loads (the state and the changes from every face side of the zone) all go
+// out before the first is used; at 4 waves per SIMD (not 8) the compiler
+// keeps them in registers, and the kernel is faster for it.  With 16
+// directions per lane (above 256 directions) the register bound is that of 2
+// waves per SIMD: at 4 the kernel spilled; it takes about 120 registers.
 template <typename T, int R>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R > 4 ? 2 : 4)))
 zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items, int parity)
@@ -1278,7 +1310,12 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   const int z = it.y;
   const double dt = M.zlev ? M.dt * (double)(1 << as_global(M.zlev)[z]) : M.dt;   // dt0 2^level
   const int nd = g.ndir, ne = g.ne, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int W = zone_row_lanes(nd, R), sh_w = __builtin_ctz(W);
+  const int dl = lane & (W - 1);                      // lane within the row's segment
+  const int rpw = 64 >> sh_w;                         // rows per wave at once
   const int nwaves = blockDim.x >> 6;
+  const int nslots = nwaves * rpw;                    // rows per pass of the workgroup
+  const int slot = wave * rpw + (lane >> sh_w);
   const btx::ZoneFaces &L = zf[z];        // uniform: read through the scalar cache
   const int nq = L.n;                     // at most 8 face sides
   const double vr = g.vr[z], vt = g.vth[z], vp = g.vph[z];
@@ -1300,12 +1337,21 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   const int nrows = g.ns * ne;
   const size_t kz = (size_t)z * nrows;
   T kan = (T)0, ksn = (T)0, fen = (T)0;
-  if (wave < nrows) { kan = ka[kz + wave]; ksn = ks[kz + wave]; fen = feq[kz + wave]; }
-  for (int row = wave; row < nrows; row += nwaves) {
-    int s = row / ne, i = row - s * ne;
+  {
+    const int r0 = min(slot, nrows - 1);
+    kan = ka[kz + r0]; ksn = ks[kz + r0]; fen = feq[kz + r0];
+  }
+  // every wave runs the same number of passes (a segment past the last row
+  // idles), so that the shuffles of a pass see all the wave's lanes
+  const int npass = (nrows + nslots - 1) / nslots;
+  for (int pass = 0; pass < npass; ++pass) {
+    const int row = pass * nslots + slot;
+    const bool live = row < nrows;
+    const int rr = live ? row : nrows - 1;
+    int s = rr / ne, i = rr - s * ne;
     const double ka_ = (double)kan, ks_ = (double)ksn, fe_ = (double)fen;
     {
-      const int nx = min(row + nwaves, nrows - 1);
+      const int nx = min(row + nslots, nrows - 1);
       kan = ka[kz + nx];
       ksn = ks[kz + nx];
       fen = feq[kz + nx];
@@ -1316,9 +1362,9 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
     double Sd[R];
     double part = 0.0;
     for (int r = 0; r < R; ++r) {
-      int d = lane + 64 * r;
+      int d = dl + W * r;
       Sd[r] = 0.0;
-      if (d >= nd) continue;
+      if (!live || d >= nd) continue;
       size_t off = (size_t)s * g.eblk + (size_t)i * nd + d;
       const T fz = f[(size_t)z * g.blk + off];
       T dv[8];
@@ -1335,7 +1381,7 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
       Sd[r] = S;
       part += S * g.dOm[d];
     }
-    const double ssum = wave_sum(part);
+    const double ssum = seg_sum(part, W);
     double avg = ssum / (4.0 * kPi);
     // the implicit solve f' = (S + tau ks avg / (1 + tau ka)) / (1 + tau (ka + ks)),
     // its row constants once per row (in FP32 for an optically thin row)
@@ -1344,8 +1390,8 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
     const float shf = tf * bf * (float)avg / (1.0f + tf * af), rdenf = 1.0f / (1.0f + tf * (af + bf));
     double pr = 0.0, pt = 0.0, pp = 0.0;
     for (int r = 0; r < R; ++r) {
-      int d = lane + 64 * r;
-      if (d >= nd) continue;
+      int d = dl + W * r;
+      if (!live || d >= nd) continue;
       size_t off = (size_t)s * g.eblk + (size_t)i * nd + d;
       const double sw = Sd[r] * g.dOm[d];
       pr += sw * g.nvec[3 * d];
@@ -1354,8 +1400,8 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
       const double out = wide ? (Sd[r] + sh) * rden : (double)(((float)Sd[r] + shf) * rdenf);
       fout[(size_t)z * g.blk + off] = (T)out;
     }
-    wave_sum3(pr, pt, pp);
-    if (lane == 0) { rs[5 * row] = ssum; rs[5 * row + 1] = pr; rs[5 * row + 2] = pt; rs[5 * row + 3] = pp; }
+    seg_sum3(pr, pt, pp, W);
+    if (live && dl == 0) { rs[5 * row] = ssum; rs[5 * row + 1] = pr; rs[5 * row + 2] = pt; rs[5 * row + 3] = pp; }
   }
   // Hydro source terms (Eq. hydrosource1-3), in FP64, one row per thread:
   // the collision term at the new state (backward Euler) is

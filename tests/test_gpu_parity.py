@@ -719,3 +719,30 @@ def test_repeatable_gpu(precision):
         ctx.close()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+
+
+# Direction counts that take each lane mapping of the zone kernel: a row's
+# directions over W lanes (W = 4, 8, 16, 32, 64; 64 / W rows share a wave), up
+# to 4 directions per lane, and the 16-per-lane kernel above 256 directions.
+ZONE_LANES = {4: (4, 1), 12: (3, 4), 20: (5, 4), 36: (9, 4), 96: (12, 8), 256: (32, 8), 260: (65, 4)}
+
+
+@pytest.mark.parametrize("nd", sorted(ZONE_LANES))
+def test_zone_lane_segments(nd, oracle_mod):
+    """FP64 parity (1e-12) at direction counts that cover every lane segment
+    width of the zone update, a partly filled last direction per lane, and
+    a pass whose last row segments lie past the zone's rows (3 species x 3
+    groups = 9 rows)."""
+    n_mu, n_phi = ZONE_LANES[nd]
+    w = _perturb(W.shock_2d(n_r=3, n_theta=2, n_eps=3, n_mu=n_mu, n_phi=n_phi, precision=W.PREC_FP64))
+    assert w.n_dir == nd
+    _say(f"[gpu] zone lane segments: {nd} directions")
+    o, ctx = _run_pair(w, 2, W.PREC_FP64, oracle_mod)
+    ref, got = o.state(), ctx.get_state()
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _say(f"[gpu]   max rel err {err:.3e}")
+    assert err <= 1e-12
+    zr, _ = o.moments()
+    zg, _ = ctx.moments()
+    assert np.allclose(zg, zr, rtol=1e-12, atol=1e-14 * np.max(np.abs(zr)))
+    ctx.close()

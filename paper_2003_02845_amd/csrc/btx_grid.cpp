@@ -351,6 +351,17 @@ std::string build_grid(Grid &g)
       add_zone_face(z, base + at(c - 1), 1);
     }
   }
+  // the sines and cosines of every basis angle, once per grid: the remap
+  // tables are built again for every background, the angles stay
+  auto trig = [](SideDesc &s) {
+    s.sth = std::sin(s.th); s.cth = std::cos(s.th);
+    s.sph = std::sin(s.ph); s.cph = std::cos(s.ph);
+  };
+  for (FaceDesc &F : g.faces) {
+    trig(F.L); trig(F.R); trig(F.Lm); trig(F.Rp);
+    F.sts = std::sin(F.ths); F.cts = std::cos(F.ths);
+    F.sps = std::sin(F.phs); F.cps = std::cos(F.phs);
+  }
   return "";
 }
 

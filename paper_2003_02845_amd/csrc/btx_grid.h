@@ -19,6 +19,7 @@ struct SideDesc {
   int32_t slope;     // 1: a real zone (or its periodic image) that is reconstructed
   int32_t pad;
   double th, ph;     // basis angles of the side's frame
+  double sth, cth, sph, cph;  // their sines and cosines (set once per grid)
 };
 
 // Everything a face kernel needs about one face.  Normal from L to R.
@@ -26,6 +27,7 @@ struct FaceDesc {
   SideDesc L, R;     // the two sides
   SideDesc Lm, Rp;   // L's neighbour away from the face, R's neighbour away from it
   double ths, phs;   // interface basis angles
+  double sts, cts, sps, cps;  // their sines and cosines (set once per grid)
   double area;       // flat quadrilateral area
   double h;          // L-R centre distance (Lax-Wendroff dx and blend optical depth)
   double dL, dR;     // signed reconstruction distances L -> face, R -> face

@@ -541,9 +541,9 @@ btx_status launch_faces(const FaceShape &shape, size_t tsize, const ModelDev *d_
   return BTX_OK;
 }
 
-// zone kernel LDS: five FP64 row values per (species, group) row, one FP64
-// direction weight per direction
-size_t zone_lds_bytes(int rows, int dirs) { return ((size_t)std::max(rows, 1) * 5 + (size_t)dirs) * sizeof(double); }
+// zone kernel LDS: five FP64 row values per (species, group) row; per
+// direction the weight 1/((1 + v.n) dOmega), dOmega and n (five FP64)
+size_t zone_lds_bytes(int rows, int dirs) { return ((size_t)std::max(rows, 1) * 5 + (size_t)dirs * 5) * sizeof(double); }
 
 btx_status launch_zones(size_t tsize, const ModelDev *d_models, const int2 *items, int n, int max_rows,
                         int parity, hipStream_t s, int max_dirs)

@@ -1519,13 +1519,27 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
   // phi), for the source terms after the update; then per direction
   // 1 / ((1 + v.n) dOmega), the direction's part of the content weight
   extern __shared__ __align__(16) char lds[];
+  // (with dOmega and n of each direction, read for every row)
   double *rs = (double *)lds;
   double *iwd = rs + 5 * (size_t)g.ns * ne;
+  double *sdo = iwd + nd;                  // dOmega_d
+  double *snv = sdo + nd;                  // n_d, 3 per direction
   for (int d = threadIdx.x; d < nd; d += blockDim.x) {
     const double *nv = g.nvec + 3 * d;
-    iwd[d] = 1.0 / ((1.0 + vr * nv[0] + vt * nv[1] + vp * nv[2]) * g.dOm[d]);
+    const double n0 = nv[0], n1 = nv[1], n2 = nv[2], dO = g.dOm[d];
+    iwd[d] = 1.0 / ((1.0 + vr * n0 + vt * n1 + vp * n2) * dO);
+    sdo[d] = dO;
+    snv[3 * d] = n0; snv[3 * d + 1] = n1; snv[3 * d + 2] = n2;
   }
   __syncthreads();
+  // the zone's blocks (its state, its next state and the change of each
+  // face side) from uniform bases: a value's place in every one of them is
+  // the same 32-bit offset
+  const T *__restrict__ fz0 = f + (size_t)z * g.blk;
+  T *__restrict__ fo0 = fout + (size_t)z * g.blk;
+  const T *__restrict__ dq[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) dq[q] = dN + ((size_t)L.fid[q] * 2 + L.side[q]) * g.blk;
   // a row's opacities are loaded one row ahead, with the previous row's data
   const int nrows = g.ns * ne;
   const size_t kz = (size_t)z * nrows;
@@ -1558,12 +1572,12 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
       int d = dl + W * r;
       Sd[r] = 0.0;
       if (!live || d >= nd) continue;
-      size_t off = (size_t)s * g.eblk + (size_t)i * nd + d;
-      const T fz = f[(size_t)z * g.blk + off];
+      const unsigned bo = (unsigned)(s * g.eblk + i * nd + d) * (unsigned)sizeof(T);   // byte offset
+      const T fz = *(const T *)((const char *)fz0 + bo);
       T dv[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        if (q < nq) dv[q] = dN[((size_t)L.fid[q] * 2 + L.side[q]) * g.blk + off];
+        if (q < nq) dv[q] = *(const T *)((const char *)dq[q] + bo);
       double acc = 0.0;
 #pragma unroll
       for (int q = 0; q < 8; ++q)
@@ -1572,7 +1586,7 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
       double S = (double)fz + src + acc * (ci * iwd[d]);
       if (!wide) S = (double)(float)S;
       Sd[r] = S;
-      part += S * g.dOm[d];
+      part += S * sdo[d];
     }
     const double ssum = seg_sum(part, W);
     double avg = ssum / (4.0 * kPi);
@@ -1585,13 +1599,13 @@ zone_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
     for (int r = 0; r < R; ++r) {
       int d = dl + W * r;
       if (!live || d >= nd) continue;
-      size_t off = (size_t)s * g.eblk + (size_t)i * nd + d;
-      const double sw = Sd[r] * g.dOm[d];
-      pr += sw * g.nvec[3 * d];
-      pt += sw * g.nvec[3 * d + 1];
-      pp += sw * g.nvec[3 * d + 2];
+      const unsigned bo = (unsigned)(s * g.eblk + i * nd + d) * (unsigned)sizeof(T);
+      const double sw = Sd[r] * sdo[d];
+      pr += sw * snv[3 * d];
+      pt += sw * snv[3 * d + 1];
+      pp += sw * snv[3 * d + 2];
       const double out = wide ? (Sd[r] + sh) * rden : (double)(((float)Sd[r] + shf) * rdenf);
-      fout[(size_t)z * g.blk + off] = (T)out;
+      *(T *)((char *)fo0 + bo) = (T)out;
     }
     seg_sum3(pr, pt, pp, W);
     if (live && dl == 0) { rs[5 * row] = ssum; rs[5 * row + 1] = pr; rs[5 * row + 2] = pt; rs[5 * row + 3] = pp; }

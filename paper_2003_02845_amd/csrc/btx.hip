@@ -208,7 +208,6 @@ struct Model {
   bool have_bg = false, have_state = false;
   double dt_max1 = 0.0;
   size_t tab_lds = 0;
-  size_t lds_cap = 0;           // the device's LDS per workgroup
 };
 
 // Checks a grid description; the message names the first problem.
@@ -296,7 +295,6 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
   m.tsize = g.prec == BTX_PREC_FP64 ? 8 : 4;
   m.dt_max1 = btx::max_dt(g, 1.0);
   m.shape = default_shape(g, lds_cap);
-  m.lds_cap = lds_cap;
   if (m.shape.ce == 0 || face_lds_bytes(g.ndir, g.ns, m.shape.nch, m.shape.ce, m.tsize) > lds_cap) {
     FaceShape fit, first;                          // tables through the caches instead of LDS
     for (int nch : { 4, 2, 1 }) {
@@ -311,9 +309,13 @@ btx_status model_init(Model &m, const btx_grid_desc *d, int index, size_t lds_ca
   const size_t flds = face_lds_bytes(g.ndir, g.ns, m.shape.nch, m.shape.ce, m.tsize, m.shape.gtab);
   if (flds > lds_cap)
     return fail(BTX_E_UNSUPPORTED, "face workgroup needs " + std::to_string(flds) + " B of LDS");
-  m.tab_lds = (m.shape.gtab ? 0 : kTables * tab_stride(g.ndir, m.tsize)) + align16(5 * sizeof(FrameP)) +
-              align16(scratch_bytes(g.ndir, m.tsize, m.shape.gtab ? 1 : 4)) + align16((size_t)g.nmu * 8) +
-              align16((size_t)kQpow * 8) + align16((size_t)2 * g.nphi * 8);
+  // the table build: one wave per table where the face kernel holds its
+  // tables in LDS (the scratch of eight waves then fits too), else one
+  // table at a time in global memory
+  m.tab_lds = m.shape.gtab ? align16(5 * sizeof(FrameP)) + align16(scratch_bytes(g.ndir, m.tsize, 1)) +
+                                 align16((size_t)g.nmu * 8) + align16((size_t)kQpow * 8) +
+                                 align16((size_t)2 * g.nphi * 8)
+                           : table_w_lds_bytes(g.ndir, g.nmu, g.nphi, m.tsize, 5 * sizeof(FrameP));
   if (m.tab_lds > lds_cap) return fail(BTX_E_UNSUPPORTED, "table build needs too much LDS");
   const size_t nz = g.nz, blk = (size_t)g.ns * g.ne * g.ndir, nk = nz * g.ns * g.ne, nf = g.faces.size();
   std::vector<int2> fit(nf), zit(nz);
@@ -507,23 +509,17 @@ btx_status build_tables(const Model &m, const ModelDev *d_models, hipStream_t s)
 {
   const int nf = (int)m.g.faces.size();
   if (nf == 0) return BTX_OK;
-  // one wave per table where its scratch fits (tables in LDS, the usual
-  // case); else four tables a round, or one at a time in global memory
-  const size_t wlds = table_w_lds_bytes(m.g.ndir, m.g.nmu, m.g.nphi, m.tsize, 5 * sizeof(FrameP));
-  const bool wave = !m.shape.gtab && wlds <= m.lds_cap;
-  const void *tk = wave ? (m.tsize == 8 ? (const void *)table_kernel_w<double> : (const void *)table_kernel_w<float>)
-                 : m.shape.gtab
-                       ? (m.tsize == 8 ? (const void *)table_kernel<double, true> : (const void *)table_kernel<float, true>)
-                       : (m.tsize == 8 ? (const void *)table_kernel<double, false> : (const void *)table_kernel<float, false>);
-  const size_t lds = wave ? wlds : m.tab_lds;
-  btx_status st = raise_lds_limit(tk, lds);
+  // one wave per table (m.tab_lds is sized for the kernel that runs)
+  const void *tk = m.shape.gtab
+                       ? (m.tsize == 8 ? (const void *)table_kernel_g<double> : (const void *)table_kernel_g<float>)
+                       : (m.tsize == 8 ? (const void *)table_kernel_w<double> : (const void *)table_kernel_w<float>);
+  btx_status st = raise_lds_limit(tk, m.tab_lds);
   if (st != BTX_OK) return st;
   const int2 *items = m.d_fitems;
   void *args[] = { &d_models, &items };
-  // 512 threads: one wave per table; for the rounds of four tables measured
-  // at 600 x 256 zones, 96 directions: 21 ms against 26 ms with 384 and
-  // 32 ms with 256, 768 or 1024 (fewer registers a thread) slower still
-  HIP_TRY(hipLaunchKernel(tk, dim3(nf), dim3(512), args, lds, s));
+  // 512 threads: eight waves, one per table (the global-memory build was
+  // measured at 21 ms against 26 ms with 384 threads and 32 ms with 256)
+  HIP_TRY(hipLaunchKernel(tk, dim3(nf), dim3(512), args, m.tab_lds, s));
   return BTX_OK;
 }
 

@@ -69,7 +69,7 @@ struct Frame {
   double st, ct, sp, cp;       // sin and cos of th and ph
 };
 
-// Per-face frame data computed once per background by table_kernel: the five
+// Per-face frame data computed once per background by the table build: the five
 // frames (0 Lm, 1 L, 2 R, 3 Rp, 4 interface) with their Lorentz factor and
 // psi^6, and the basis changes L -> interface and R -> interface.
 struct FaceAux {
@@ -606,18 +606,17 @@ __device__ __forceinline__ void face_aux(const FrameP *frm, bool rot, FaceAux &A
 }
 
 // Builds the eight remap tables of one face (frame chain once per direction,
-// inverted into sorted per-target gather lists) and stores them in global
-// memory; run once per background.  (Building them in place in global memory
-// instead, with 2.5 times less LDS, was 1.5 times slower: the records' scattered
-// stores.)
+// inverted into sorted per-target gather lists) in place in global memory,
+// one table at a time with the whole workgroup: the build for grids whose
+// face kernels read their tables through the caches (large momentum grids,
+// where one wave's scratch per table would not fit).  Run once per
+// background; table_kernel_w (below) builds the same tables elsewhere.
 // table t: 0 Lm->L, 1 R->L, 2 L->R, 3 Rp->R, 4 L->s, 5 R->s, 6 s->L, 7 s->R
-// GTAB: the tables are built in place in global memory (grids whose tables do
-// not fit in LDS), one table at a time.
-template <typename T, bool GTAB>
+template <typename T>
 __global__ void __launch_bounds__(512)
-table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items)
+table_kernel_g(const ModelDev *__restrict__ models, const int2 *__restrict__ items)
 {
-  constexpr int TPR = GTAB ? 1 : 4;                 // tables per round
+  constexpr int TPR = 1;                            // tables per round
   extern __shared__ __align__(16) char lds[];
   __shared__ int flg[kTables];
   const int2 it = items[blockIdx.x];
@@ -630,8 +629,7 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
   const int nd = g.ndir, tid = threadIdx.x, nthr = blockDim.x;
   const size_t tstride = tab_stride(nd, sizeof(T));
   char *p = lds;
-  char *tabs = GTAB ? tabs_g + (size_t)fid * kTables * tstride : p;
-  if (!GTAB) p += kTables * tstride;
+  char *tabs = tabs_g + (size_t)fid * kTables * tstride;
   FrameP *frm = (FrameP *)p;   p += align16(5 * sizeof(FrameP));
   char *data = p;
   int *cnt = (int *)data;                      // TPR nd
@@ -754,13 +752,6 @@ table_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items
 
   // the face's frame data, one lane per frame and one per basis column
   face_aux(frm, rot, aux[fid], tid);
-  __syncthreads();
-  if (!GTAB) {
-    uint4 *dst = (uint4 *)(tabs_g + (size_t)fid * kTables * tstride);
-    const uint4 *src = (const uint4 *)tabs;
-    const int n16 = (int)(kTables * tstride / 16);
-    for (int q = tid; q < n16; q += nthr) dst[q] = src[q];
-  }
 }
 
 // LDS of one wave of table_kernel_w: the counts (then cursors) per target,
@@ -787,13 +778,13 @@ __device__ __forceinline__ void wave_sync()
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The same tables as table_kernel (the same records, keys and order within
+// The same tables as table_kernel_g (the same records, keys and order within
 // each target's list), built by one wave per table: after the frames, the
 // eight waves of the workgroup go through the chains, the scan, the list
 // placement and the ranking of their own table with no workgroup barrier,
-// and write the table in place in global memory.  (The barrier-separated
-// rounds of table_kernel keep every wave of the face waiting for the slowest
-// at each of a dozen phases, most of them short and bound by latency.)
+// and write the table in place in global memory.  (Barrier-separated rounds
+// of four tables kept every wave of the face waiting for the slowest at each
+// of a dozen phases, most of them short and bound by latency.)
 // FP32: held to 80 registers, so that three workgroups share a CU (their LDS
 // allows three at 96 directions): 17.4 -> 15.2 ms at 600 x 256 zones with 14
 // registers spilled.  FP64 scratch allows two, which 4 waves per SIMD give.
@@ -891,7 +882,7 @@ table_kernel_w(const ModelDev *__restrict__ models, const int2 *__restrict__ ite
     }
   wave_sync();
   // Each record at the place of its rank by key within its target's list,
-  // as in table_kernel.  Target tg's cursor now marks the end of its list
+  // as in table_kernel_g.  Target tg's cursor now marks the end of its list
   // and tg - 1's its start.
   const int cs = col_rows(g.nch, g.ce);
   for (int q = lane; q < nd; q += 64)
@@ -1167,7 +1158,7 @@ face_kernel(const ModelDev *__restrict__ models, const int2 *__restrict__ items,
 
 #define TB(t) tab_at<T>(tabs + (t) * tstride, nd)
 
-  // ---- remap tables of this face (built once per background by table_kernel)
+  // ---- remap tables of this face (built once per background)
   if (!GTAB) {
     const uint4 *src = (const uint4 *)(tabs_g + (size_t)fid * kTables * tstride);
     uint4 *dst = (uint4 *)lds;

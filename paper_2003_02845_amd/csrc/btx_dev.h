@@ -308,10 +308,10 @@ __host__ __device__ inline size_t buf_bytes(int nd, int nch, int ce, size_t szT)
   return align16((size_t)nd * col_rows(nch, ce) * szT);
 }
 
-// table-build scratch for tpr tables at a time: counts and cursors per
+// scratch of table_kernel_g for tpr tables at a time: counts and cursors per
 // target, four records per source (target and shift; tap weights), the
 // records' indexes in target order and their keys
-__host__ __device__ inline size_t scratch_bytes(int nd, size_t szT, int tpr = 4)
+__host__ __device__ inline size_t scratch_bytes(int nd, size_t szT, int tpr)
 {
   return (size_t)tpr * nd * 4 * 2 + (size_t)4 * tpr * nd * 4 + (size_t)8 * tpr * nd * szT +
          (size_t)4 * tpr * nd * 4 + (size_t)4 * tpr * nd * 2;

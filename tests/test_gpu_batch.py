@@ -264,3 +264,40 @@ def test_batch_time_levels(oracle_mod):
     _say(f"[gpu]   model 0 against the reference: {err:.3e}")
     assert err <= 1e-12
     b.close()
+
+
+def test_batch_time_levels_after_global_steps(oracle_mod):
+    """Time levels set on a batch that has already stepped (its face launches
+    then grouped by shape and workgroup size, regrouped by shape alone): one
+    global step, then one level-stepped step; each model equals a single
+    context doing the same (bit for bit where the batch kept the context's
+    face shape, else to 1e-12)."""
+    import torch
+    btx = _btx()
+    ws = _models(3, 0.03, W.PREC_FP64, 37)
+    b = _batch(btx, ws, W.PREC_FP64)
+    dts = [b.max_dt(m, 0.4) for m in range(len(ws))]
+    _say("[gpu] batch time levels after global steps")
+    b.step(dts, 1)
+    levs = [b.time_levels(0, 2), None, b.time_levels(2, 1)]
+    b.set_time_levels(0, levs[0])
+    b.set_time_levels(2, levs[2])
+    L = max(int(l.max()) for l in levs if l is not None)
+    b.step(dts, 1)
+    torch.cuda.synchronize()
+    for m, w in enumerate(ws):
+        c = btx.Context(w, precision=W.PREC_FP64, stream=torch.cuda.current_stream().cuda_stream)
+        c.set_background()
+        c.set_state(w.f0)
+        c.step(dts[m], 1)
+        lm = 0 if levs[m] is None else int(levs[m].max())
+        if levs[m] is not None:
+            c.set_time_levels(levs[m])
+        c.step(dts[m], 2 ** (L - lm))
+        got, single = b.get_state(m), c.get_state()
+        if tuple(b.shape(m)) == _single_shape(w):
+            assert np.array_equal(got, single), m
+        else:
+            assert np.max(np.abs(got - single)) <= 1e-12 * np.max(np.abs(single)), m
+        c.close()
+    b.close()

@@ -274,14 +274,14 @@ def test_batch_time_levels_after_global_steps(oracle_mod):
     face shape, else to 1e-12)."""
     import torch
     btx = _btx()
-    ws = _models(3, 0.03, W.PREC_FP64, 37)
+    ws = _models(5, 0.03, W.PREC_FP64, 37)           # models 0-2 and 4 share a shape, 4 a smaller workgroup
     b = _batch(btx, ws, W.PREC_FP64)
     dts = [b.max_dt(m, 0.4) for m in range(len(ws))]
     _say("[gpu] batch time levels after global steps")
     b.step(dts, 1)
-    levs = [b.time_levels(0, 2), None, b.time_levels(2, 1)]
-    b.set_time_levels(0, levs[0])
-    b.set_time_levels(2, levs[2])
+    levs = [b.time_levels(0, 2), None, b.time_levels(2, 1), None, b.time_levels(4, 1)]
+    for m in (0, 2, 4):
+        b.set_time_levels(m, levs[m])
     L = max(int(l.max()) for l in levs if l is not None)
     b.step(dts, 1)
     torch.cuda.synchronize()
